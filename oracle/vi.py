@@ -1,0 +1,191 @@
+"""Scalarised value iteration, policy extraction and policy evaluation on one
+product model, in FP64 (appendix A.5, Alg. 3 and Alg. 4).
+
+Readings taken here:
+  * Both loops of Alg. 3 / Alg. 4 are do-while loops (they start with the
+    stability flag raised; the algorithm package's DoWhile form is meant).
+  * Jacobi iteration with two buffers instead of the in-place update: sweep n
+    computes y = T(x_{n-1}) from x_0 = 0 and stops at the first n with
+    max_s |y - x_{n-1}| <= eps, returning that sweep's y.  The fixed point is
+    the same; only where the iteration stops changes.
+  * The policy is extracted from the final values, not along the trajectory
+    (the trajectory rule of Alg. 3 is kept as ``policy_rule="paper"``, parity
+    unpinned).
+  * Tie rule: the eps-optimal action set A*(s) = {a : Q(s,a) >= max Q - tau}
+    with Q in FP64 at the returned values.  Done states have rank 0; an
+    unranked state gets rank l+1 when some a in A*(s) moves mass into the done
+    set or into a state of rank <= l; its action is the lowest-index such a.
+    States left unranked make the policy improper (an error).  The chosen
+    policy reaches done with probability 1 and is greedy for the values.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .product import Product
+
+
+class ImproperPolicy(RuntimeError):
+    pass
+
+
+def scalarised_rewards(prod: Product, wc, wp) -> np.ndarray:
+    """Row rewards (w . rho)(s,q,a) = wc * rho_i + wp * rho_{j+|I|} for each
+    column: ``wc`` / ``wp`` are scalars or [K] arrays.  Returns [R, K]."""
+    wc = np.atleast_1d(np.asarray(wc, dtype=np.float64))
+    wp = np.atleast_1d(np.asarray(wp, dtype=np.float64))
+    return prod.rew_cost[:, None] * wc[None, :] + prod.rew_prob[:, None] * wp[None, :]
+
+
+def _state_max(prod: Product, q: np.ndarray) -> np.ndarray:
+    return np.maximum.reduceat(q, prod.state_row[:-1], axis=0)
+
+
+def value_iteration(prod: Product, wc, wp, eps: float, max_sweeps: int = 1_000_000):
+    """Alg. 3 for K weight columns at once, each column stopping on its own.
+
+    Returns (y [S, K], sweeps [K]); column k of y is the values of the first
+    sweep whose residual max_s |y - x| is <= eps."""
+    r = scalarised_rewards(prod, wc, wp)
+    K = r.shape[1]
+    S = prod.n_states
+    x = np.zeros((S, K))
+    sweeps = np.zeros(K, dtype=np.int64)
+    if S == 0:
+        return x, sweeps
+    P = prod.P()
+    active = np.ones(K, dtype=bool)
+    n = 0
+    while active.any():
+        n += 1
+        if n > max_sweeps:
+            raise RuntimeError("value iteration did not converge")
+        cols = np.flatnonzero(active)
+        y = _state_max(prod, r[:, cols] + P @ x[:, cols])
+        res = np.abs(y - x[:, cols]).max(axis=0)
+        x[:, cols] = y
+        done = res <= eps
+        sweeps[cols[done]] = n
+        active[cols[done]] = False
+    return x, sweeps
+
+
+def q_values(prod: Product, x: np.ndarray, wc, wp) -> np.ndarray:
+    """Q(s,a) = (w . rho)(s,a) + sum_s' P(s,a,s') x(s') for every row, [R, K]."""
+    x2 = x.reshape(prod.n_states, -1)
+    return scalarised_rewards(prod, wc, wp) + prod.P() @ x2
+
+
+def extract_policy(prod: Product, x: np.ndarray, wc: float, wp: float,
+                   tau: float = 1e-9) -> np.ndarray:
+    """Attractor tie rule on the eps-optimal action sets (module doc).
+
+    ``x`` is one column of values.  Returns mu[S], the chosen row of each
+    state counted from the state's first row (int64)."""
+    S = prod.n_states
+    if S == 0:
+        return np.zeros(0, dtype=np.int64)
+    Q = q_values(prod, x, wc, wp)[:, 0]
+    row_state = prod.row_state()
+    qmax = _state_max(prod, Q[:, None])[:, 0]
+    opt = Q >= qmax[row_state] - tau
+    # structural successor matrix: B[r, s'] = 1 iff row r reaches live s'
+    B = sp.csr_matrix((np.ones(prod.nnz), prod.col, prod.row_ptr),
+                      shape=(prod.n_rows, S))
+    rank = np.full(S, -1, dtype=np.int64)
+    mu = np.full(S, -1, dtype=np.int64)
+    first_row = prod.state_row[:-1]
+    level = 0
+    while True:
+        ranked_before = (rank >= 0)
+        # a row qualifies if it is eps-optimal and moves mass into done or
+        # into a state ranked in an earlier round
+        hits = opt & (prod.to_done | (B @ ranked_before.astype(np.float64) > 0))
+        cand = hits & ~ranked_before[row_state]
+        if not cand.any():
+            break
+        level += 1
+        rows = np.flatnonzero(cand)
+        # the lowest-index qualifying row of each newly ranked state
+        states, first = np.unique(row_state[rows], return_index=True)
+        rank[states] = level
+        mu[states] = rows[first] - first_row[states]
+    if (rank < 0).any():
+        raise ImproperPolicy(f"{int((rank < 0).sum())} states cannot reach done "
+                             "through eps-optimal actions")
+    return mu
+
+
+def extract_policy_paper(prod: Product, wc: float, wp: float, eps: float,
+                         max_sweeps: int = 1_000_000) -> np.ndarray:
+    """Alg. 3 literally (Gauss-Seidel, mu updated only where |y - x| > eps,
+    mu initialised to the first action).  Parity unpinned; kept for the
+    record."""
+    S = prod.n_states
+    r = scalarised_rewards(prod, wc, wp)[:, 0]
+    x = np.zeros(S)
+    mu = np.zeros(S, dtype=np.int64)
+    for _ in range(max_sweeps):
+        stable = True
+        for s in range(S):
+            best, arg = -np.inf, 0
+            for rr in range(prod.state_row[s], prod.state_row[s + 1]):
+                a, b = prod.row_ptr[rr], prod.row_ptr[rr + 1]
+                v = r[rr] + float(np.dot(prod.prob[a:b], x[prod.col[a:b]]))
+                if v > best:
+                    best, arg = v, rr - prod.state_row[s]
+            if abs(best - x[s]) > eps:
+                stable = False
+                mu[s] = arg
+            x[s] = best
+        if stable:
+            return mu
+    raise RuntimeError("value iteration did not converge")
+
+
+def policy_rows(prod: Product, mu: np.ndarray) -> np.ndarray:
+    return prod.state_row[:-1] + mu
+
+
+def evaluate(prod: Product, mu: np.ndarray, eps: float, max_sweeps: int = 10_000_000):
+    """Alg. 4 for both objectives of the model: Jacobi from 0 on the fixed
+    policy, each objective stopping at its first sweep with residual <= eps.
+
+    Returns ((cost value, probability value) at the initial state,
+    (sweeps_cost, sweeps_prob), full value vectors [S, 2])."""
+    S = prod.n_states
+    if S == 0 or prod.init < 0:
+        return (0.0, 0.0), (0, 0), np.zeros((S, 2))
+    rows = policy_rows(prod, mu)
+    P = prod.P()[rows]
+    rho = np.stack([prod.rew_cost[rows], prod.rew_prob[rows]], axis=1)
+    x = np.zeros((S, 2))
+    sweeps = np.zeros(2, dtype=np.int64)
+    active = np.ones(2, dtype=bool)
+    n = 0
+    while active.any():
+        n += 1
+        if n > max_sweeps:
+            raise RuntimeError("policy evaluation did not converge")
+        cols = np.flatnonzero(active)
+        y = rho[:, cols] + P @ x[:, cols]
+        res = np.abs(y - x[:, cols]).max(axis=0)
+        x[:, cols] = y
+        done = res <= eps
+        sweeps[cols[done]] = n
+        active[cols[done]] = False
+    return (float(x[prod.init, 0]), float(x[prod.init, 1])), tuple(int(v) for v in sweeps), x
+
+
+def evaluate_exact(prod: Product, mu: np.ndarray) -> np.ndarray:
+    """Exact values of both objectives under mu: solve (I - P_mu) x = rho_mu.
+    Returns x [S, 2]."""
+    S = prod.n_states
+    if S == 0:
+        return np.zeros((0, 2))
+    rows = policy_rows(prod, mu)
+    A = sp.identity(S, format="csc") - prod.P()[rows].tocsc()
+    rho = np.stack([prod.rew_cost[rows], prod.rew_prob[rows]], axis=1)
+    return np.column_stack([spla.spsolve(A, rho[:, 0]), spla.spsolve(A, rho[:, 1])])

@@ -1,0 +1,609 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix:
+printed values of the worked example, closed forms, brute force over
+deterministic policies, the multi-objective LP, the centralised MDP, Dijkstra,
+exact linear solves and textbook assignment.  CPU only."""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.optimize import linprog, linear_sum_assignment, minimize
+from scipy.sparse.csgraph import dijkstra
+
+from workloads import worked_example, tiny_workload, make_workload
+from workloads.gridworld import Agent, Task, Workload, make_task_dfa, make_grid, make_agent
+from oracle import product, vi, alg, geometry
+
+HERE = os.path.dirname(__file__)
+GOLD = json.load(open(os.path.join(HERE, "golden", "worked_example.json")))
+
+
+# --------------------------------------------------------------------------
+# worked example (Sec. 3.3 Example, Fig. 3)
+# --------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def example():
+    wl = worked_example()
+    return product.build_all(wl)
+
+
+def test_example_product_structure(example):
+    p = example[0]
+    # live states (s0, q0) and (s2, q0); s1 is a trap, s3 accepts
+    assert p.states.tolist() == [[0, 0], [2, 0]]
+    assert p.state_row.tolist() == [0, 2, 3]
+    assert p.row_ptr.tolist() == [0, 2, 2, 2]
+    assert p.col.tolist() == [0, 1] and np.allclose(p.prob, [0.3, 0.5])
+    assert np.allclose(p.rew_prob, [0.0, 0.1, 1.0])
+    assert np.allclose(p.rew_cost, [-1, -1, -1]) and p.to_done.all() and p.init == 0
+
+
+def test_example_policy_points(example):
+    # policy b: one step, accept w.p. .1; policy a: cost 15/7, prob 5/7
+    rb = alg.support(example, 1, 1, np.array([1.0, 0.0]), 1e-13).r
+    ra = alg.support(example, 1, 1, np.array([0.0, 1.0]), 1e-13).r
+    assert np.allclose(rb, [-1.0, 0.1], atol=1e-12)
+    assert np.allclose(ra, [-15 / 7, 5 / 7], atol=1e-12)
+
+
+def test_example_figure_polygon(example):
+    # Fig. 3b is itself split between the two readings: its r1 vertex is the
+    # literal pre-sink point, its r2 vertex the standard-reading point
+    poly = np.array(GOLD["fig3b_polygon"])
+    r1 = (3 * poly[2, 0], poly[2, 1])
+    r2 = (3 * poly[3, 0], poly[3, 1])
+    assert np.allclose(r1, GOLD["printed_r1"], atol=0.005)
+    assert np.allclose(r2, [-15 / 7, 5 / 7], atol=0.005)
+
+
+def test_example_literal_presink_reproduces_printed_r1():
+    wl = worked_example()
+    prods = product.build_all(wl, presink_literal=True)
+    r1 = alg.support(prods, 1, 1, np.array([1.0, 0.0]), 1e-13).r
+    assert np.allclose(r1, GOLD["printed_r1"], atol=1e-12)
+
+
+def test_example_feasible_threshold(example):
+    q = alg.query(example, 1, 1, np.array(GOLD["t_a"]), GOLD["eps"], 1e-13)
+    assert q.verdict == alg.FEASIBLE and q.iterations == 2
+    w1, r1, t_up1, t_down1 = q.trace[0]
+    # after r1 the gap ||t_down - t_up|| is the printed 0.6
+    assert geometry.mnorm(t_down1 - t_up1) == pytest.approx(GOLD["printed_gap_after_r1_for_t_a"], abs=1e-12)
+    assert np.allclose(q.t_up, GOLD["t_a"]) and np.allclose(q.t_down, GOLD["t_a"])
+
+
+def test_example_infeasible_threshold(example):
+    q = alg.query(example, 1, 1, np.array(GOLD["t_u"]), GOLD["eps"], 1e-13)
+    assert q.verdict == alg.INFEASIBLE
+    assert q.iterations == 3
+    assert geometry.mnorm(q.t_down - q.t_up) <= GOLD["eps"]
+    # closest point on the segment between the two policy points
+    A, B, t = np.array([-15 / 7, 5 / 7]), np.array([-1.0, 0.1]), np.array(GOLD["t_u"])
+    n = np.array([-(B - A)[1], (B - A)[0]])
+    n = n if n @ (t - A) > 0 else -n
+    star = t - (n @ (t - A)) / (n @ n) * n
+    assert np.allclose(q.t_down, star, atol=1e-9)
+
+
+def test_example_printed_points_give_printed_closest_point():
+    # the inner projection of t_u onto the printed points is the printed t_down
+    Phi = np.array([GOLD["printed_r1"], [-15 / 7, 5 / 7]])
+    x, lam = geometry.project_inner(Phi, np.array(GOLD["t_u"]))
+    assert np.allclose(x, GOLD["printed_t_down_for_t_u"], atol=0.005)
+    assert geometry.kkt_inner(Phi, np.array(GOLD["t_u"]), x, lam) < 1e-10
+
+
+# --------------------------------------------------------------------------
+# hand-worked closed forms
+# --------------------------------------------------------------------------
+
+def _agent(succ_rows, costs, init=0):
+    """Agent from explicit rows: succ_rows[s][a] = [(s', p), ...]."""
+    nA = max(len(r) for r in succ_rows)
+    sa_ptr, succ, prob, cost = [0], [], [], []
+    for s, rows in enumerate(succ_rows):
+        for a in range(nA):
+            if a < len(rows):
+                for t, p in rows[a]:
+                    succ.append(t)
+                    prob.append(p)
+            cost.append(costs[a] if a < len(rows) else 0.0)
+            sa_ptr.append(len(succ))
+    n = len(succ_rows)
+    return Agent(width=n, height=1, cells=np.arange(n, dtype=np.int32), init=init, p_slip=0.0,
+                 action_cost=np.asarray(costs, float), n_actions=nA,
+                 sa_ptr=np.asarray(sa_ptr, np.int32), succ=np.asarray(succ, np.int32),
+                 prob=np.asarray(prob, float), cost=np.asarray(cost, float))
+
+
+def _task(kind, k):
+    n, L, q0, delta, acc = make_task_dfa(kind, k)
+    return Task(kind=kind, k=k, n_locs=n, n_letters=L, q0=q0, delta=delta, accepting=acc,
+                waypoints_uv=np.zeros((k, 2, 2)), avoid_uv=None)
+
+
+def _corridor(p, c):
+    # cells 0,1,2; action 0 "right" succeeds w.p. p else stays; action 1 stays
+    rows = [[[(1, p), (0, 1 - p)], [(0, 1.0)]],
+            [[(2, p), (1, 1 - p)], [(1, 1.0)]],
+            [[(2, 1.0)], [(2, 1.0)]]]
+    a = _agent(rows, [c, c])
+    letters = np.array([0, 0, 1], np.int32)
+    return product.build_product(a, _task("reach", 1), letters)
+
+
+@pytest.mark.parametrize("p,c", [(0.5, 1.0), (0.8, 2.5), (0.3, 1.7)])
+def test_corridor_closed_form(p, c):
+    prod = _corridor(p, c)
+    y, _ = vi.value_iteration(prod, 1.0, 0.0, 1e-13)
+    assert y[prod.init, 0] == pytest.approx(-2 * c / p, rel=1e-10)
+    mu = vi.extract_policy(prod, y[:, 0], 1.0, 0.0)
+    assert (mu == 0).all()
+    (vc, vp), _, _ = vi.evaluate(prod, mu, 1e-13)
+    assert vc == pytest.approx(-2 * c / p, rel=1e-10) and vp == pytest.approx(1.0, abs=1e-12)
+
+
+def test_corridor_probability_iterates_monotone():
+    prod = _corridor(0.4, 1.0)
+    P = prod.P()
+    x = np.zeros(prod.n_states)
+    for _ in range(60):
+        y = np.maximum.reduceat(prod.rew_prob + P @ x, prod.state_row[:-1])
+        assert (y >= x - 1e-15).all() and (y <= 1 + 1e-15).all()
+        x = y
+
+
+def _risky_safe(k, c, q):
+    # state 0 decides; safe walks the chain 1..k-1 to the goal G (k steps);
+    # risky reaches G w.p. q, else the avoid cell T
+    G, T = k, k + 1
+    rows = [[[(1 if k > 1 else G, 1.0)], [(G, q), (T, 1 - q)]]]
+    for s in range(1, k):
+        nxt = s + 1 if s + 1 < k else G
+        rows.append([[(nxt, 1.0)], [(nxt, 1.0)]])
+    rows.append([[(G, 1.0)], [(G, 1.0)]])
+    rows.append([[(T, 1.0)], [(T, 1.0)]])
+    a = _agent(rows, [c, c])
+    letters = np.zeros(k + 2, np.int32)
+    letters[G], letters[T] = 1, 2
+    return product.build_product(a, _task("avoid", 1), letters)
+
+
+def test_risky_safe_front_and_closest_point():
+    k, c, q = 3, 1.0, 0.4
+    prods = [_risky_safe(k, c, q)]
+    rs = alg.support(prods, 1, 1, np.array([0.0, 1.0]), 1e-13).r
+    rr = alg.support(prods, 1, 1, np.array([1.0, 0.0]), 1e-13).r
+    assert np.allclose(rs, [-c * k, 1.0]) and np.allclose(rr, [-c, q])
+    t = np.array([-1.5, 0.95])
+    res = alg.query(prods, 1, 1, t, 1e-10, 1e-13)
+    A, B = np.array([-c * k, 1.0]), np.array([-c, q])
+    n = np.array([(B - A)[1] * -1, (B - A)[0]])
+    n = n if n @ (t - A) > 0 else -n
+    star = t - (n @ (t - A)) / (n @ n) * n
+    assert res.verdict == alg.INFEASIBLE
+    assert np.allclose(res.t_down, star, atol=1e-8) and np.allclose(res.t_up, star, atol=1e-8)
+    # a threshold under the segment is feasible
+    res2 = alg.query(prods, 1, 1, np.array([-2.5, 0.5]), 1e-10, 1e-13)
+    assert res2.verdict == alg.FEASIBLE
+
+
+# --------------------------------------------------------------------------
+# brute force over deterministic policies
+# --------------------------------------------------------------------------
+
+def _policy_points(prod):
+    """(cost, prob) at the initial state of every proper deterministic policy."""
+    S = prod.n_states
+    counts = np.diff(prod.state_row)
+    pts, pols = [], []
+    P = prod.P().toarray()
+    for mu in itertools.product(*[range(n) for n in counts]):
+        rows = prod.state_row[:-1] + np.array(mu)
+        A = np.eye(S) - P[rows]
+        # proper iff I - P_mu is invertible with a non-negative inverse
+        try:
+            inv = np.linalg.inv(A)
+        except np.linalg.LinAlgError:
+            continue
+        if (inv < -1e-9).any() or np.abs(inv).max() > 1e9:
+            continue
+        x = inv @ np.stack([prod.rew_cost[rows], prod.rew_prob[rows]], axis=1)
+        pts.append(x[prod.init])
+        pols.append(np.array(mu))
+    return np.array(pts), pols
+
+
+@pytest.mark.parametrize("seed,w,h,kind", [(11, 3, 2, "reach"), (12, 3, 3, "avoid"), (13, 3, 3, "avoid")])
+def test_scalarised_optimum_equals_brute_force(seed, w, h, kind):
+    wl = tiny_workload(seed, 1, 1, width=w, height=h, kinds=(kind,), k=1)
+    prod = product.build_all(wl)[0]
+    pts, _ = _policy_points(prod)
+    rng = np.random.default_rng(seed)
+    for _ in range(5):
+        wv = rng.dirichlet([1.0, 1.0])
+        y, _ = vi.value_iteration(prod, wv[0], wv[1], 1e-13)
+        best = (pts @ wv).max()
+        assert y[prod.init, 0] == pytest.approx(best, abs=1e-9)
+        mu = vi.extract_policy(prod, y[:, 0], wv[0], wv[1])
+        ex = vi.evaluate_exact(prod, mu)[prod.init]
+        assert ex @ wv == pytest.approx(best, abs=1e-9)
+
+
+def _hull_top(points):
+    """Points not dominated in every weighted direction (a superset of the
+    vertices of down(conv) that matter): keep points optimal for some w."""
+    keep = []
+    for wv in np.linspace(0, 1, 201):
+        wvec = np.array([wv, 1 - wv])
+        keep.append(int(np.argmax(points @ wvec)))
+    return points[sorted(set(keep))]
+
+
+def _closest_brute(V, t):
+    """min ||t - x|| over x <= V^T lam, lam in simplex, by SLSQP (independent
+    of the least-distance route)."""
+    m, d = V.shape
+    fun = lambda z: float(np.sum(np.maximum(t - V.T @ z, 0.0) ** 2))
+    cons = [{"type": "eq", "fun": lambda z: z.sum() - 1.0}]
+    best = None
+    for start in range(m):
+        z0 = np.full(m, 0.1 / m)
+        z0[start] += 0.9
+        r = minimize(fun, z0, method="SLSQP", bounds=[(0, 1)] * m, constraints=cons,
+                     options={"ftol": 1e-15, "maxiter": 500})
+        if best is None or r.fun < best.fun:
+            best = r
+    return np.minimum(t, V.T @ best.x)
+
+
+@pytest.mark.parametrize("seed", [21, 22])
+def test_query_matches_brute_force_two_by_two(seed):
+    wl = tiny_workload(seed, 2, 2, width=3, height=3, kinds=("avoid",), k=1, p_slip=0.3)
+    prods = product.build_all(wl)
+    tops = [_hull_top(_policy_points(p)[0]) for p in prods]
+    # every point of C's generator set: per assignment, one top point per task
+    V = []
+    for f in [(0, 1), (1, 0)]:
+        for a in tops[f[0] * 2 + 0]:
+            for b in tops[f[1] * 2 + 1]:
+                r = np.zeros(4)
+                r[f[0]] += a[0]
+                r[f[1]] += b[0]
+                r[2], r[3] = a[1], b[1]
+                V.append(r)
+    V = np.array(V)
+    rng = np.random.default_rng(seed)
+    for _ in range(3):
+        base = V[rng.integers(len(V))]
+        t = base + np.array([0.3, 0.3, 0.05, 0.05]) * rng.uniform(-1, 2, 4)
+        t[2:] = np.clip(t[2:], 0, 1)
+        res = alg.query(prods, 2, 2, t, 1e-9, 1e-13, max_iter=200)
+        # feasibility by LP over the generators
+        lp = linprog(np.zeros(len(V)), A_ub=-V.T, b_ub=-t, A_eq=np.ones((1, len(V))), b_eq=[1],
+                     bounds=[(0, None)] * len(V), method="highs")
+        assert (res.verdict == alg.FEASIBLE) == (lp.status == 0)
+        if res.verdict != alg.FEASIBLE:
+            star = _closest_brute(V, t)
+            assert np.allclose(res.t_down, star, atol=1e-5)
+
+
+# --------------------------------------------------------------------------
+# multi-objective LP (Fig. 2) and centralised MDP (Def. teamMDP)
+# --------------------------------------------------------------------------
+
+def _mo_lp(prods, nI, nJ):
+    """Variables: x_{s,q,a} of every model, then x_ij.  Returns (A_eq, b_eq,
+    objective rows [d, nvar])."""
+    offs, n = [], 0
+    for p in prods:
+        offs.append(n)
+        n += p.n_rows
+    nx = n + nI * nJ
+    Aeq, beq = [], []
+    for m, p in enumerate(prods):
+        i, j = divmod(m, nJ)
+        rs = p.row_state()
+        for s in range(p.n_states):
+            row = np.zeros(nx)
+            row[offs[m] + p.state_row[s]: offs[m] + p.state_row[s + 1]] += 1.0
+            if s == p.init:
+                row[n + i * nJ + j] -= 1.0
+            for r in range(p.n_rows):
+                for e in range(p.row_ptr[r], p.row_ptr[r + 1]):
+                    if p.col[e] == s:
+                        row[offs[m] + r] -= p.prob[e]
+            Aeq.append(row)
+            beq.append(0.0)
+    for j in range(nJ):
+        row = np.zeros(nx)
+        row[n + np.arange(nI) * nJ + j] = 1
+        Aeq.append(row)
+        beq.append(1.0)
+    for i in range(nI):
+        row = np.zeros(nx)
+        row[n + i * nJ + np.arange(nJ)] = 1
+        Aeq.append(row)
+        beq.append(1.0)
+    obj = np.zeros((nI + nJ, nx))
+    for m, p in enumerate(prods):
+        i, j = divmod(m, nJ)
+        obj[i, offs[m]:offs[m] + p.n_rows] += p.rew_cost
+        obj[nI + j, offs[m]:offs[m] + p.n_rows] += p.rew_prob
+    return np.array(Aeq), np.array(beq), obj
+
+
+@pytest.mark.parametrize("seed", [31, 32])
+def test_support_equals_lp_optimum(seed):
+    wl = tiny_workload(seed, 2, 2, width=3, height=3, kinds=("avoid", "reach"), k=1, p_slip=0.2)
+    prods = product.build_all(wl)
+    Aeq, beq, obj = _mo_lp(prods, 2, 2)
+    rng = np.random.default_rng(seed)
+    for _ in range(3):
+        w = rng.dirichlet(np.ones(4))
+        s = alg.support(prods, 2, 2, w, 1e-13)
+        lp = linprog(-(w @ obj), A_eq=Aeq, b_eq=beq, bounds=[(0, None)] * Aeq.shape[1], method="highs")
+        assert lp.status == 0
+        assert w @ s.r == pytest.approx(-lp.fun, abs=1e-8)
+        # last equality of Lemma lem:face: w.r equals the assignment optimum
+        assert w @ s.r == pytest.approx(sum(s.c[s.f[j], j] for j in range(2)), abs=1e-9)
+
+
+@pytest.mark.parametrize("seed", [33])
+def test_verdict_equals_lp_feasibility(seed):
+    wl = tiny_workload(seed, 2, 2, width=3, height=3, kinds=("avoid",), k=1, p_slip=0.3)
+    prods = product.build_all(wl)
+    Aeq, beq, obj = _mo_lp(prods, 2, 2)
+    pts = alg.support(prods, 2, 2, np.full(4, 0.25), 1e-13).r
+    rng = np.random.default_rng(seed)
+    for _ in range(6):
+        t = pts + np.array([0.5, 0.5, 0.1, 0.1]) * rng.uniform(-1, 1, 4)
+        t[2:] = np.clip(t[2:], 0, 1)
+        lp = linprog(np.zeros(Aeq.shape[1]), A_ub=-obj, b_ub=-t, A_eq=Aeq, b_eq=beq,
+                     bounds=[(0, None)] * Aeq.shape[1], method="highs")
+        res = alg.query(prods, 2, 2, t, 1e-9, 1e-13, max_iter=200)
+        slack = None
+        if lp.status == 0 and res.verdict != alg.FEASIBLE:
+            slack = geometry.mnorm(res.t_down - t)
+        assert (res.verdict == alg.FEASIBLE) == (lp.status == 0) or (slack is not None and slack < 1e-6)
+
+
+def _centralised_value(wl, w):
+    """Scalarised optimum of the centralised MDP of Def. teamMDP, built as a
+    flat MDP and solved by value iteration (agents / tasks 0-based)."""
+    nI, nJ = wl.n_agents, wl.n_tasks
+    agents, tasks = wl.agents, wl.tasks
+    done = [tasks[j].accepting.astype(bool) | product.traps(tasks[j].n_locs, tasks[j].delta,
+                                                            tasks[j].accepting) for j in range(nJ)]
+    index = {}
+    states = []
+    for i in range(nI):
+        for j in range(nJ):
+            for s in range(agents[i].n_states):
+                for q in range(tasks[j].n_locs):
+                    for sharp in range(1 << nI):
+                        index[(i, j, s, q, sharp)] = len(states)
+                        states.append((i, j, s, q, sharp))
+    rows = []          # (state, reward, [(succ, p)])
+    for n, (i, j, s, q, sharp) in enumerate(states):
+        ag, tk = agents[i], tasks[j]
+        at_start = s == ag.init and q == tk.q0
+        if (sharp >> i) & 1 and not done[j][q]:
+            for a in range(ag.n_actions):
+                r = s * ag.n_actions + a
+                lo, hi = ag.sa_ptr[r], ag.sa_ptr[r + 1]
+                if hi == lo:
+                    continue
+                succ, rew_p = [], 0.0
+                for e in range(lo, hi):
+                    s2 = int(ag.succ[e])
+                    q2 = int(tk.delta[q, wl.letters[i][j][s2]])
+                    if tk.accepting[q2] and not tk.accepting[q]:
+                        rew_p += ag.prob[e]
+                    succ.append((index[(i, j, s2, q2, sharp)], ag.prob[e]))
+                rows.append((n, -w[i] * ag.cost[r] + w[nI + j] * rew_p, succ))
+        if at_start and not (sharp >> i) & 1:
+            rows.append((n, 0.0, [(index[(i, j, s, q, sharp | (1 << i))], 1.0)]))       # b1
+            nxt = [k for k in range(i + 1, nI) if not (sharp >> k) & 1]
+            if nxt:
+                k = nxt[0]
+                rows.append((n, 0.0, [(index[(k, j, agents[k].init, q, sharp)], 1.0)]))  # b2
+        if done[j][q] and (sharp >> i) & 1 and j < nJ - 1:
+            free = [k for k in range(nI) if not (sharp >> k) & 1]
+            if free:
+                k = free[0]
+                rows.append((n, 0.0, [(index[(k, j + 1, agents[k].init, tasks[j + 1].q0, sharp)], 1.0)]))  # b3
+    N = len(states)
+    has = np.zeros(N, bool)
+    for n, _, _ in rows:
+        has[n] = True
+    x = np.zeros(N)
+    for _ in range(100000):
+        y = np.where(has, -np.inf, 0.0)
+        for n, rew, succ in rows:
+            v = rew + sum(p * x[k] for k, p in succ)
+            if v > y[n]:
+                y[n] = v
+        if np.abs(y - x).max() <= 1e-12:
+            x = y
+            break
+        x = y
+    return x[index[(0, 0, agents[0].init, tasks[0].q0, 0)]]
+
+
+def test_centralised_optimum_equals_decentralised_assignment():
+    wl = tiny_workload(41, 2, 2, width=3, height=2, kinds=("reach",), k=1, p_slip=0.25)
+    prods = product.build_all(wl)
+    rng = np.random.default_rng(41)
+    for _ in range(2):
+        w = rng.dirichlet(np.ones(4))
+        s = alg.support(prods, 2, 2, w, 1e-13)
+        assert _centralised_value(wl, w) == pytest.approx(w @ s.r, abs=1e-8)
+
+
+# --------------------------------------------------------------------------
+# textbook reductions
+# --------------------------------------------------------------------------
+
+def test_assignment_equals_brute_force():
+    rng = np.random.default_rng(5)
+    for nI, nJ in [(3, 3), (4, 4), (2, 4), (3, 5), (5, 3)]:
+        for _ in range(5):
+            c = rng.normal(size=(nI, nJ))
+            f = alg.assign(c)
+            cap = max(1, -(-nJ // nI))
+            best = -np.inf
+            for g in itertools.product(range(nI), repeat=nJ):
+                if max(np.bincount(g, minlength=nI)) <= cap:
+                    best = max(best, sum(c[g[j], j] for j in range(nJ)))
+            assert sum(c[f[j], j] for j in range(nJ)) == pytest.approx(best, abs=1e-12)
+            assert max(np.bincount(f, minlength=nI)) <= cap
+
+
+def test_deterministic_grid_cost_is_dijkstra():
+    rng = np.random.default_rng(7)
+    free = make_grid(rng, 7, 5, 0.2)
+    cells = np.flatnonzero(free.ravel())
+    agent = make_agent(rng, free, int(cells[0]), 0.0, rng.uniform(1, 3, 5))
+    task = _task("reach", 2)
+    letters = np.zeros(agent.n_states, np.int32)
+    letters[[3, 4]] = 1
+    letters[[len(cells) - 1, len(cells) - 2]] = 2
+    prod = product.build_product(agent, task, letters)
+    y, _ = vi.value_iteration(prod, 1.0, 0.0, 1e-12)
+    S = prod.n_states
+    src, dst, wt = [], [], []
+    rs = prod.row_state()
+    for r in range(prod.n_rows):
+        a, b = prod.row_ptr[r], prod.row_ptr[r + 1]
+        tgt = prod.col[a] if b > a else S
+        src.append(rs[r])
+        dst.append(tgt)
+        wt.append(-prod.rew_cost[r])
+    G = sp.csr_matrix((wt, (src, dst)), shape=(S + 1, S + 1))
+    # csr_matrix sums duplicate edges; keep the cheapest parallel edge instead
+    best = {}
+    for u, v, c in zip(src, dst, wt):
+        if u != v:
+            best[(u, v)] = min(best.get((u, v), np.inf), c)
+    G = sp.csr_matrix((list(best.values()), ([k[0] for k in best], [k[1] for k in best])),
+                      shape=(S + 1, S + 1))
+    dist = dijkstra(G, indices=prod.init)[S]
+    assert y[prod.init, 0] == pytest.approx(-dist, abs=1e-9)
+
+
+@pytest.mark.parametrize("cfg", [1])
+def test_policy_evaluation_matches_exact_solve(cfg):
+    wl = make_workload(cfg)
+    prods = product.build_all(wl)
+    rng = np.random.default_rng(3)
+    for p in prods:
+        wv = rng.dirichlet([1, 1])
+        y, _ = vi.value_iteration(p, wv[0], wv[1], 1e-12)
+        mu = vi.extract_policy(p, y[:, 0], wv[0], wv[1])
+        (vc, vp), _, x = vi.evaluate(p, mu, 1e-12)
+        ex = vi.evaluate_exact(p, mu)
+        assert np.abs(x - ex).max() < 1e-8
+        assert 0.0 <= vp <= 1.0 + 1e-12
+
+
+# --------------------------------------------------------------------------
+# invariants
+# --------------------------------------------------------------------------
+
+def test_probability_values_and_monotonicity():
+    wl = make_workload(2, n_agents=2, n_tasks=3)
+    for p in product.build_all(wl):
+        P = p.P()
+        xp = np.zeros(p.n_states)
+        xc = np.zeros(p.n_states)
+        for _ in range(40):
+            yp = np.maximum.reduceat(p.rew_prob + P @ xp, p.state_row[:-1])
+            yc = np.maximum.reduceat(p.rew_cost + P @ xc, p.state_row[:-1])
+            assert (yp >= xp - 1e-15).all() and (yp <= 1 + 1e-12).all()
+            assert (yc <= xc + 1e-12).all()
+            xp, xc = yp, yc
+        # one-step mass plus kept mass never exceeds 1
+        rowsum = np.add.reduceat(p.prob, p.row_ptr[:-1]) if p.nnz else np.zeros(0)
+        rowsum = np.where(np.diff(p.row_ptr) > 0, rowsum, 0.0)
+        assert (rowsum + p.rew_prob <= 1 + 1e-12).all()
+
+
+@pytest.mark.parametrize("seed", [51, 52, 53])
+def test_alg1_invariants(seed):
+    wl = tiny_workload(seed, 2, 2, width=3, height=3, kinds=("avoid", "reach"), k=1, p_slip=0.2)
+    prods = product.build_all(wl)
+    rng = np.random.default_rng(seed)
+    base = alg.support(prods, 2, 2, np.full(4, 0.25), 1e-12).r
+    t = base + np.array([1.0, 1.0, 0.2, 0.2]) * rng.uniform(-0.5, 1.0, 4)
+    t[2:] = np.clip(t[2:], 0, 1)
+    res = alg.query(prods, 2, 2, t, 1e-7, 1e-12, max_iter=100)
+    prev_up, prev_down = np.inf, -np.inf
+    Ws, Rs = [], []
+    for w, r, t_up, t_down in res.trace:
+        assert (w >= 0).all() and w.sum() == pytest.approx(1.0, abs=1e-12)      # lem:weight-vector
+        for w2, r2 in zip(Ws, Rs):
+            assert w2 @ r2 >= w2 @ r - 1e-7                                      # supporting hyperplanes
+        Ws.append(w)
+        Rs.append(r)
+        d_up, d_down = geometry.mnorm(t - t_up), geometry.mnorm(t - t_down)
+        assert d_down <= d_up + 1e-9                                             # thm:synthesis (iii)
+        assert d_up <= prev_up + 1e-9 and d_down >= prev_down - 1e-9             # Phi, Lambda only grow
+        prev_up, prev_down = d_up, d_down
+        x, lam = geometry.project_inner(np.array(Rs), t)
+        assert geometry.kkt_inner(np.array(Rs), t, x, lam) < 1e-8                # t_up in down(Phi)
+    if res.verdict == alg.FEASIBLE:
+        assert np.allclose(res.t_down, t)                                        # thm:synthesis (ii)
+
+
+# --------------------------------------------------------------------------
+# the projections themselves
+# --------------------------------------------------------------------------
+
+def test_inner_projection_single_point_and_diagonal_norm():
+    r = np.array([[1.0, -2.0, 0.5]])
+    t = np.array([2.0, -3.0, 0.7])
+    x, lam = geometry.project_inner(r, t)
+    assert np.allclose(x, np.minimum(t, r[0])) and np.allclose(lam, [1.0])
+    M = np.diag([1.0, 4.0, 9.0])
+    x2, _ = geometry.project_inner(r, t, M)
+    assert np.allclose(x2, np.minimum(t, r[0]))
+
+
+def test_outer_projection_single_halfspace_closed_form():
+    rng = np.random.default_rng(9)
+    for _ in range(10):
+        d = 5
+        w = rng.dirichlet(np.ones(d))
+        rr = rng.normal(size=d)
+        t = rr + rng.uniform(0.1, 1.0, d)
+        A = rng.normal(size=(d, d))
+        M = A @ A.T + d * np.eye(d)
+        z = geometry.project_outer(w[None], rr[None], t, M)
+        Mi_w = np.linalg.solve(M, w)
+        star = t - (w @ t - w @ rr) / (w @ Mi_w) * Mi_w
+        assert np.allclose(z, star, atol=1e-10)
+        assert geometry.kkt_outer(w[None], rr[None], t, z, M) < 1e-10
+
+
+def test_inner_projection_general_norm_against_slsqp():
+    rng = np.random.default_rng(10)
+    for _ in range(5):
+        m, d = 4, 3
+        Phi = rng.normal(size=(m, d))
+        t = Phi.max(axis=0) + rng.uniform(0.1, 1.0, d)
+        A = rng.normal(size=(d, d))
+        M = A @ A.T + np.eye(d)
+        x, lam = geometry.project_inner(Phi, t, M)
+        assert geometry.kkt_inner(Phi, t, x, lam, M) < 1e-9
+        # independent: minimise over (lam, slack) with SLSQP
+        fun = lambda z: float((t - (Phi.T @ z[:m] - z[m:])) @ M @ (t - (Phi.T @ z[:m] - z[m:])))
+        cons = [{"type": "eq", "fun": lambda z: z[:m].sum() - 1}]
+        best = min((minimize(fun, np.r_[np.eye(m)[k], np.zeros(d)], method="SLSQP",
+                             bounds=[(0, None)] * (m + d), constraints=cons,
+                             options={"ftol": 1e-15, "maxiter": 1000}) for k in range(m)),
+                   key=lambda r: r.fun)
+        assert geometry.mnorm(t - x, M) ** 2 == pytest.approx(best.fun, abs=1e-7)
