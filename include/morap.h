@@ -1,0 +1,341 @@
+/*
+ * morap.h -- C ABI of libmorap, an MI355X (gfx950) engine for the batched
+ * scalarised value-iteration path of point-oriented Pareto queries over
+ * agent-task product MDPs (Robinson & Su, "Multi-Objective Task Assignment
+ * and Multiagent Planning with Hybrid GPU-CPU Acceleration").
+ *
+ * Conventions shared by every entry point:
+ *   - Return MORAP_OK (0) on success or a negative MORAP_E_* code.  The text
+ *     of the last error of a context is available from morap_last_error().
+ *     No C++ exception crosses this boundary.
+ *   - Every pointer argument is a HOST pointer unless its comment says
+ *     otherwise.  Buffers are owned by the caller; the library copies what it
+ *     keeps and never frees caller memory.  Sizes are explicit.
+ *   - Device work is enqueued on the context's stream.  Entry points that
+ *     return host results synchronise that stream before returning.
+ *   - A context belongs to one host thread at a time (a model is owned by one
+ *     thread at a time in the paper's implementation, Sec. 4); calls on the
+ *     same context from several threads at once are not allowed.
+ *   - Objective order: d = |I| + |J|; objectives 0..|I|-1 are the agents'
+ *     costs (as negative rewards) and |I|..d-1 the tasks' completion
+ *     probabilities (Alg. 1 input t = (c, p), Def. MORAP).
+ *   - Model index m = i * |J| + j for agent i and task j.
+ */
+#ifndef MORAP_H
+#define MORAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MORAP_OK               0
+#define MORAP_E_INVALID       -1  /* bad argument or malformed model data          */
+#define MORAP_E_OOM           -2  /* device or host allocation failed / over budget */
+#define MORAP_E_NOT_CONVERGED -3  /* an iteration hit its sweep limit               */
+#define MORAP_E_IMPROPER      -4  /* no policy among eps-optimal actions reaches done */
+#define MORAP_E_HIP           -5  /* HIP runtime error                               */
+#define MORAP_E_UNSUPPORTED   -6  /* sizes beyond what this build handles            */
+#define MORAP_E_STATE         -7  /* call order (e.g. evaluate before solve)         */
+
+#define MORAP_F64 0               /* value iteration in FP64                         */
+#define MORAP_F32 1               /* FP32 backups, FP64 residual / polish / evaluation */
+
+#define MORAP_FEASIBLE   1
+#define MORAP_INFEASIBLE 0
+#define MORAP_UNDECIDED  2
+
+typedef struct morap_ctx morap_ctx;
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
+ * (NULL = the device's null stream); the caller keeps ownership of it and must
+ * keep it alive until morap_destroy.  *out receives the context.
+ * Errors: INVALID (out NULL, bad device), HIP. */
+int morap_create(morap_ctx** out, int device, void* hip_stream);
+
+/* Release all device and host memory of the context.  NULL is accepted. */
+int morap_destroy(morap_ctx* ctx);
+
+/* Text of the last error on this context ("" if none).  Valid until the next
+ * call on the context. */
+const char* morap_last_error(const morap_ctx* ctx);
+
+/* ---------------------------------------------------------------------------
+ * Models
+ * ------------------------------------------------------------------------- */
+
+/* An agent MDP M_i = (S, s0, A, P, L) with its cost structure (Sec. 2,
+ * "Markov Decision Process"; Sec. 3.1).  Row (s, a) = s * n_actions + a owns
+ * successors succ[sa_ptr[row] .. sa_ptr[row+1]) with probabilities prob[..].
+ * A row with no successors is a disabled action; an enabled row's
+ * probabilities must sum to 1 (within 1e-9).  cost[row] > 0 is the cost of
+ * taking a in s; its reward is -cost. */
+typedef struct {
+    int32_t n_states, n_actions, init;
+    const int32_t* sa_ptr;    /* [n_states * n_actions + 1] */
+    const int32_t* succ;      /* [sa_ptr[last]], values in [0, n_states)  */
+    const double*  prob;      /* [sa_ptr[last]]                           */
+    const double*  cost;      /* [n_states * n_actions]                   */
+} morap_agent;
+
+/* A task DFA (Q, q0, Q_F, Sigma, delta) whose accepting locations are sinks
+ * (Sec. 2, "Deterministic Finite Automata").  Letters are small integers: the
+ * caller encodes each label L(s) as a letter index. */
+typedef struct {
+    int32_t n_locs, n_letters, q0;
+    const int32_t* delta;     /* [n_locs * n_letters], values in [0, n_locs) */
+    const uint8_t* accepting; /* [n_locs], 1 = accepting                      */
+} morap_dfa;
+
+/* A product model M_{i(x)j} in CSR form over its live states (states whose
+ * DFA location is neither accepting nor a trap; transitions into done states
+ * are dropped), as produced by morap_build_products or supplied by the caller:
+ *   state_row[S+1]  rows of state s are state_row[s] .. state_row[s+1]-1,
+ *                   in action order (at most 32 rows per state);
+ *   row_ptr[R+1]    entries of row r are row_ptr[r] .. row_ptr[r+1]-1;
+ *   col[N]          live successor state, in [0, S);
+ *   prob[N]         transition probability (row sums in [0, 1]);
+ *   rew[2R]         per row: (cost reward rho_i = -cost, probability reward
+ *                   rho_{|I|+j} = mass of first acceptance);
+ *   to_done[R]      1 if the row moves mass into a done state;
+ *   init            index of the initial state (s0, q0), -1 if it is done. */
+typedef struct {
+    int32_t agent, task;
+    int32_t n_states, n_rows, nnz, init;
+    const int32_t* state_row;
+    const int32_t* row_ptr;
+    const int32_t* col;
+    const double*  prob;
+    const double*  rew;
+    const uint8_t* to_done;
+} morap_model;
+
+/* Build every agent-task product M_i (x) A_j (Sec. 2, "Product MDP"; Sec. 3.1,
+ * proposition done_j and reward rho_{j+|I|}) on the host, for i < n_agents,
+ * j < n_tasks, and upload them to the device.  letters[i * n_tasks + j] points
+ * to agent i's labelling as seen by task j: [agents[i].n_states] letters in
+ * [0, tasks[j].n_letters).  Reachable states are explored from (s0, q0);
+ * states are numbered in (q, s) order.  Replaces any loaded models.
+ * Errors: INVALID (malformed agent / DFA / letters), OOM, UNSUPPORTED (more
+ * than 2^31-1 rows or entries in total, more than 32 rows in a state). */
+int morap_build_products(morap_ctx* ctx, const morap_agent* agents, int n_agents,
+                         const morap_dfa* tasks, int n_tasks,
+                         const int32_t* const* letters);
+
+/* Load caller-built product models (same semantics as above).  models[m] must
+ * have agent = m / n_tasks and task = m % n_tasks, m < n_agents * n_tasks.
+ * Errors: INVALID (structure, ranges, row sums outside [0, 1+1e-6],
+ * non-finite rewards), OOM, UNSUPPORTED. */
+int morap_load_models(morap_ctx* ctx, const morap_model* models, int n_models,
+                      int n_agents, int n_tasks);
+
+/* sizes[0..4] = (S, R, N, init, total states) of model m. Errors: INVALID, STATE. */
+int morap_model_info(const morap_ctx* ctx, int m, int32_t* sizes);
+
+/* Copy model m back to the host; any output may be NULL.  states[2S] gets the
+ * (agent state, DFA location) pair of every state when the model was built by
+ * morap_build_products (zeros otherwise).  Errors: INVALID, STATE. */
+int morap_get_model(const morap_ctx* ctx, int m, int32_t* state_row, int32_t* row_ptr,
+                    int32_t* col, double* prob, double* rew, uint8_t* to_done,
+                    int32_t* states);
+
+/* ---------------------------------------------------------------------------
+ * Value iteration, assignment, evaluation (Alg. 2, Alg. 3, Alg. 4)
+ * ------------------------------------------------------------------------- */
+
+typedef struct {
+    double  eps_vi;       /* Alg. 3 stop: first sweep with max_s |y-x| <= eps_vi   */
+    double  eps_eval;     /* Alg. 4 stop, per objective                             */
+    double  tau;          /* tie tolerance of the eps-optimal action sets (1e-9)    */
+    int32_t precision;    /* MORAP_F64 or MORAP_F32                                 */
+    int32_t max_sweeps;   /* per iteration; exceeding it returns NOT_CONVERGED      */
+    int32_t check_every;  /* sweeps per host convergence check (even, >= 2)         */
+    int32_t schedule;     /* 0 = autotuned sweep kernel, > 0 = fixed variant id     */
+    int32_t use_graph;    /* 1 = replay sweep chunks as a captured hipGraph         */
+    int32_t reserved;
+} morap_vi_opts;
+
+/* Fill `opts` with the defaults: eps 1e-6, tau 1e-9, FP32, 1e6 sweeps, check
+ * every 32 sweeps, autotuned, graphs on. */
+void morap_default_opts(morap_vi_opts* opts);
+
+typedef struct {
+    int64_t backups;        /* state-action backups done (rows x active columns)   */
+    int64_t sweeps;         /* sweeps launched (batched VI)                         */
+    int64_t max_pair_sweeps;/* largest sweep count of one (model, column) pair     */
+    int64_t eval_sweeps;    /* sweeps of the policy evaluation                      */
+    int64_t polish_sweeps;  /* FP64 sweeps after an FP32 solve (evaluate)          */
+    int64_t rank_rounds;    /* attractor ranking rounds (policy extraction)         */
+    int64_t excluded;       /* reserved                                             */
+    double  bytes;          /* algorithmic bytes moved by the sweep kernel          */
+    double  ms_vi, ms_eval, ms_total;   /* device / host wall time of the phases   */
+    int32_t variant;        /* sweep-kernel variant used                            */
+    int32_t reserved;
+} morap_stats;
+
+/* Alg. 2 first loop / Alg. 3 for K weight vectors W[K][d] at once: for every
+ * model m = (i, j) and column k, value iteration of the scalarised reward
+ * W[k][i] * rho_i + W[k][|I|+j] * rho_{|I|+j} from 0 (Jacobi, do-while, each
+ * (model, column) pair stopping at its first sweep with residual <= eps_vi).
+ * c_out[K][|I|][|J|] (nullable) receives the value at each model's initial
+ * state.  Rows of W must be >= 0 and sum to 1 (1e-9).  The final values stay
+ * on the device for morap_evaluate / morap_get_values.
+ * Errors: INVALID, STATE (no models), OOM, NOT_CONVERGED, HIP. */
+int morap_solve(morap_ctx* ctx, const double* W, int K, const morap_vi_opts* opts,
+                double* c_out, morap_stats* stats);
+
+/* Alg. 2 second loop for the columns of the last morap_solve: assign[K][|J|]
+ * gives the agent of every task per column.  For each (k, j) the policy of
+ * model (assign[k][j], j) is extracted from that column's final values (FP32
+ * solves are first refined by FP64 value iteration of that model and column to
+ * eps_vi), with the attractor tie rule on the tau-optimal action sets, then
+ * evaluated per objective (Alg. 4, FP64 Jacobi from 0, eps_eval).
+ * r_out[K][d]: r[|I|+j] = completion probability of task j; r[i] = sum of the
+ * cost values of the tasks assigned to i.  Each agent may receive at most
+ * ceil(|J|/|I|) tasks.  Errors: INVALID, STATE, IMPROPER, NOT_CONVERGED, HIP. */
+int morap_evaluate(morap_ctx* ctx, const int32_t* assign, int K, const morap_vi_opts* opts,
+                   double* r_out, morap_stats* stats);
+
+/* Max-weight assignment of Alg. 2 on the host for each column:
+ * c[K][|I|][|J|] -> assign_out[K][|J|], maximising sum_j c[k][f(j)][j] with at
+ * most ceil(|J|/|I|) tasks per agent (Hungarian method, O(n^3)).
+ * Errors: INVALID. */
+int morap_assign(morap_ctx* ctx, const double* c, int K, int32_t* assign_out);
+
+/* Alg. 2 whole, for K weight vectors: solve -> assignment -> evaluate.
+ * r_out[K][d], assign_out[K][|J|] (nullable), c_out[K][|I|][|J|] (nullable).
+ * Errors: as morap_solve and morap_evaluate. */
+int morap_support(morap_ctx* ctx, const double* W, int K, const morap_vi_opts* opts,
+                  double* r_out, int32_t* assign_out, double* c_out, morap_stats* stats);
+
+/* Policy chosen for task j in column k by the last morap_evaluate: mu_out[S]
+ * of model (assign[k][j], j), each entry the chosen row counted from the
+ * state's first row.  Errors: INVALID, STATE. */
+int morap_get_policy(const morap_ctx* ctx, int k, int j, int8_t* mu_out);
+
+/* Final values of column k of model m from the last morap_solve, as FP64
+ * x_out[S].  Errors: INVALID, STATE. */
+int morap_get_values(const morap_ctx* ctx, int k, int m, double* x_out);
+
+/* ---------------------------------------------------------------------------
+ * Point-oriented Pareto computation (Alg. 1)
+ * ------------------------------------------------------------------------- */
+
+typedef struct {
+    double  eps;             /* Alg. 1 loop tolerance on ||t_down - t_up||_M        */
+    int32_t max_iter;        /* Alg. 2 calls per query                              */
+    int32_t verification_only; /* stop once t is separated (Sec. 5, Experiment 2) */
+    int32_t use_proposer;    /* 1 = learned proposer gives the first weight vector  */
+    int32_t keep_trace;      /* 1 = fill the trace arrays of the result             */
+    morap_vi_opts vi;
+} morap_query_opts;
+
+/* Result of one query.  t_up / t_down / lam and the trace arrays are
+ * caller-owned and may be NULL:
+ *   t_up[d], t_down[d]              final inner / outer closest points;
+ *   lam[max_iter]                   convex weights of the points of Phi whose
+ *                                   combination dominates t_up;
+ *   trace_w / trace_r [max_iter][d] weight vector and point of every pass. */
+typedef struct {
+    int32_t verdict;         /* MORAP_FEASIBLE, MORAP_INFEASIBLE, MORAP_UNDECIDED */
+    int32_t iterations;      /* Alg. 2 calls                                      */
+    int32_t fallback;        /* 1 = the proposer's weight was rejected            */
+    int32_t reserved;
+    double  gap;             /* ||t_down - t_up||_M at exit                        */
+    double  ms;              /* wall time                                         */
+    int64_t backups;
+    double* t_up;
+    double* t_down;
+    double* lam;
+    double* trace_w;
+    double* trace_r;
+} morap_query_result;
+
+/* Alg. 1 for threshold t[d] with norm matrix M[d][d] (symmetric positive
+ * definite; NULL = identity).  Loop: r = Alg. 2(w); add r to Phi and (w, r)
+ * to Lambda; if w.r < w.t_down, t_down = argmin ||t - z||_M s.t. w'.z <= w'.r'
+ * for all of Lambda; t_up = argmin over x in down(Phi) of ||t - x||_M; stop if
+ * ||t_down - t_up||_M <= eps; else w = M(t - t_up)/||M(t - t_up)||_1.
+ * Verdict: FEASIBLE iff t in down(Phi), INFEASIBLE iff some (w', r') has
+ * w'.r' < w'.t, else UNDECIDED.  Errors: INVALID, STATE, and those of
+ * morap_support. */
+int morap_query(morap_ctx* ctx, const double* t, const double* M,
+                const morap_query_opts* opts, morap_query_result* result);
+
+/* Q queries T[Q][d] advanced in lockstep: every Alg. 1 pass solves the weight
+ * vectors of all unfinished queries as the columns of one morap_support call
+ * (at most 64 columns per call; larger Q runs in groups of 64).
+ * results[Q].  Errors: as morap_query. */
+int morap_query_batch(morap_ctx* ctx, const double* T, int Q, const double* M,
+                      const morap_query_opts* opts, morap_query_result* results);
+
+/* Projections of Alg. 1 on their own (host, FP64).  Inner: x_out[d] in
+ * down(conv Phi[m][d]) closest to t in the M-norm, lam_out[m] (nullable) its
+ * convex weights.  Outer: z_out[d] closest to t subject to
+ * W[n][d] z <= rowwise W.R.  Errors: INVALID, NOT_CONVERGED. */
+int morap_project_inner(const double* Phi, int m, int d, const double* t, const double* M,
+                        double* x_out, double* lam_out);
+int morap_project_outer(const double* W, const double* R, int n, int d, const double* t,
+                        const double* M, double* z_out);
+
+/* ---------------------------------------------------------------------------
+ * Learned weight proposer (a small MLP in front of the weight update of
+ * Alg. 1; not part of the paper)
+ * ------------------------------------------------------------------------- */
+
+/* Sizes: input n_in = d + n_feat, three hidden layers of 256, output d.
+ * Weights are BF16 on the device with FP32 master copies; products accumulate
+ * in FP32 (MFMA).  Parameter order for get/set: W1[256][n_in], b1[256],
+ * W2[256][256], b2, W3[256][256], b3, W4[d][256], b4[d] (row-major, FP32). */
+typedef struct {
+    int32_t batch;           /* rows per step                                    */
+    int32_t epochs;
+    float   lr, beta1, beta2, adam_eps;
+    uint64_t seed;           /* shuffling                                        */
+} morap_train_opts;
+
+/* Create (or re-create) the proposer for input width n_in and output width d
+ * with He-uniform weights from a counter-based generator (SplitMix64 of seed)
+ * and zero biases.  Errors: INVALID, OOM, HIP. */
+int morap_proposer_init(morap_ctx* ctx, int n_in, int d, uint64_t seed);
+
+/* Number of FP32 parameters; get / set copy all of them (order above). */
+int64_t morap_proposer_num_params(const morap_ctx* ctx);
+int morap_proposer_get_params(const morap_ctx* ctx, float* out);
+int morap_proposer_set_params(morap_ctx* ctx, const float* in);
+
+/* Forward pass: X[n][n_in] -> W_out[n][d] (softmax rows).  Errors: INVALID,
+ * STATE (no proposer), HIP. */
+int morap_proposer_infer(morap_ctx* ctx, const float* X, int n, float* W_out);
+
+/* One forward + backward pass on X[n][n_in] with targets T[n][d] (rows on the
+ * simplex), mean cross-entropy loss.  loss_out (nullable) gets the loss;
+ * grads_out (nullable) gets the FP32 gradients in parameter order.  When
+ * apply != 0 an Adam step (opts lr, betas, eps) follows.  Errors: INVALID,
+ * STATE, HIP. */
+int morap_proposer_step(morap_ctx* ctx, const float* X, const float* T, int n,
+                        const morap_train_opts* opts, int apply, float* loss_out,
+                        float* grads_out);
+
+/* Train for opts->epochs over the n examples (shuffled per epoch from
+ * opts->seed), in batches of opts->batch.  loss_out[epochs] (nullable) gets
+ * the mean loss of every epoch.  Errors: INVALID, STATE, HIP. */
+int morap_proposer_train(morap_ctx* ctx, const float* X, const float* T, int n,
+                         const morap_train_opts* opts, float* loss_out);
+
+/* Save / load the FP32 parameters and sizes to / from a binary file.
+ * Errors: INVALID (I/O, size mismatch), STATE. */
+int morap_proposer_save(const morap_ctx* ctx, const char* path);
+int morap_proposer_load(morap_ctx* ctx, const char* path);
+
+/* Instance feature vector phi[n_feat] used by morap_query when
+ * use_proposer = 1: the proposer's input is [t; phi] (n_in = d + n_feat).
+ * The library copies phi.  Errors: INVALID. */
+int morap_set_features(morap_ctx* ctx, const double* phi, int n_feat);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MORAP_H */

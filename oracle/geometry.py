@@ -16,8 +16,10 @@ Each least-distance problem min ||z|| s.t. G z >= h is solved exactly by the
 classical reduction to non-negative least squares (Lawson and Hanson, "Solving
 Least Squares Problems", ch. 23): with u >= 0 minimising
 || [G^T; h^T] u - e_{n+1} ||, r = [G^T; h^T] u - e_{n+1}; the problem is
-infeasible iff r = 0, else z = -r[:n] / r[n].  NNLS is scipy's Lawson-Hanson
-routine.
+infeasible iff r = 0, else z = -r[:n] / r[n].  The NNLS step is Lawson and
+Hanson's active-set algorithm (ch. 23, algorithm NNLS) written out below with
+dense least-squares solves; every projection is then checked against its
+optimality conditions.
 
 Readings: ||v|| is sqrt(v^T M v) (the text's "||v| = <v, v>" is garbled;
 squaring does not move a minimiser).  M defaults to the identity.
@@ -25,7 +27,41 @@ squaring does not move a minimiser).  M defaults to the identity.
 from __future__ import annotations
 
 import numpy as np
-from scipy.optimize import nnls
+
+def nnls(A: np.ndarray, b: np.ndarray, maxiter: int | None = None):
+    """min ||A x - b||_2 subject to x >= 0 (Lawson and Hanson's NNLS).
+    Returns (x, ||A x - b||)."""
+    A = np.asarray(A, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    m, n = A.shape
+    maxiter = 3 * n + 30 if maxiter is None else maxiter
+    x = np.zeros(n)
+    passive = np.zeros(n, dtype=bool)
+    tol = 10 * np.finfo(float).eps * max(1.0, np.abs(A).max()) * max(m, n)
+    w = A.T @ (b - A @ x)
+    for _ in range(maxiter):
+        cand = ~passive & (w > tol)
+        if not cand.any():
+            break
+        j = int(np.argmax(np.where(cand, w, -np.inf)))
+        passive[j] = True
+        while True:
+            s = np.zeros(n)
+            idx = np.flatnonzero(passive)
+            s[idx] = np.linalg.lstsq(A[:, idx], b, rcond=None)[0]
+            if (s[idx] > 0).all():
+                break
+            neg = idx[s[idx] <= 0]
+            alpha = np.min(x[neg] / (x[neg] - s[neg]))
+            x = x + alpha * (s - x)
+            passive &= x > tol
+            x[~passive] = 0.0
+        x = s
+        w = A.T @ (b - A @ x)
+    else:
+        raise RuntimeError("NNLS did not converge")
+    return x, float(np.linalg.norm(A @ x - b))
+
 
 
 def mnorm(v: np.ndarray, M: np.ndarray | None = None) -> float:
@@ -49,7 +85,7 @@ def ldp(G: np.ndarray, h: np.ndarray):
     E = np.vstack([G.T, h[None, :]])
     f = np.zeros(n + 1)
     f[n] = 1.0
-    u, _ = nnls(E, f, maxiter=50 * (m + n + 1))
+    u, _ = nnls(E, f)
     r = E @ u - f
     scale = max(1.0, float(np.abs(E).max()))
     if np.linalg.norm(r) <= 1e-13 * scale or r[n] >= 0.0:
@@ -79,6 +115,9 @@ def project_inner(Phi: np.ndarray, t: np.ndarray, M: np.ndarray | None = None):
     x = t + np.linalg.solve(L.T, y)
     s = u[:m].sum()
     lam = u[:m] / s if s > 0 else np.full(m, 1.0 / m)
+    viol = kkt_inner(Phi, t, x, lam, M)
+    if viol > 1e-7 * max(1.0, float(np.abs(t).max())):
+        raise RuntimeError(f"inner projection failed its optimality check ({viol:.3g})")
     return x, lam
 
 
@@ -115,7 +154,11 @@ def project_outer(Ws: np.ndarray, Rs: np.ndarray, t: np.ndarray,
     z, _ = ldp(G, h)
     if z is None:
         raise RuntimeError("outer approximation is empty")
-    return t + np.linalg.solve(L.T, z)
+    out = t + np.linalg.solve(L.T, z)
+    viol = kkt_outer(Ws, Rs, t, out, M)
+    if viol > 1e-7 * max(1.0, float(np.abs(t).max())):
+        raise RuntimeError(f"outer projection failed its optimality check ({viol:.3g})")
+    return out
 
 
 def weight_from(t: np.ndarray, t_up: np.ndarray, M: np.ndarray | None = None) -> np.ndarray:

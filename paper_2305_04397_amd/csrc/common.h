@@ -1,0 +1,330 @@
+// Internal declarations of libmorap: context, device arena, error handling,
+// kernel launch wrappers.  Not part of the ABI (include/morap.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/morap.h"
+
+namespace morap {
+
+// ---------------------------------------------------------------------------
+// errors: internal code throws MorapError; the ABI layer turns it into a
+// return code and keeps the message on the context.
+// ---------------------------------------------------------------------------
+struct MorapError : std::runtime_error {
+    int code;
+    MorapError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] inline void fail(int code, const std::string& msg) { throw MorapError(code, msg); }
+
+#define MORAP_HIP(call)                                                                 \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            ::morap::fail(MORAP_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define MORAP_CHECK(cond, code, msg) \
+    do {                             \
+        if (!(cond)) ::morap::fail(code, msg); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device buffers
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    // (re)allocate when the requested size exceeds the current one
+    void ensure(size_t n) {
+        if (n <= bytes && p) return;
+        release();
+        if (n == 0) n = 16;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            p = nullptr;
+            fail(MORAP_E_OOM, "hipMalloc of " + std::to_string(n) + " bytes failed: " + hipGetErrorString(e));
+        }
+        bytes = n;
+    }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct PinnedBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    ~PinnedBuf() { if (p) (void)hipHostFree(p); }
+    void ensure(size_t n) {
+        if (n <= bytes && p) return;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        MORAP_HIP(hipHostMalloc(&p, n, hipHostMallocDefault));
+        bytes = n;
+    }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ---------------------------------------------------------------------------
+// host-side model set (concatenated CSR with global indices)
+// ---------------------------------------------------------------------------
+struct HostModels {
+    int nI = 0, nJ = 0, M = 0;
+    std::vector<int32_t> state_base;   // [M+1] first global state of each model
+    std::vector<int32_t> init;         // [M] global index of the initial state, -1 if done
+    std::vector<int32_t> state_row;    // [S+1] global rows
+    std::vector<int32_t> row_ptr;      // [R+1] global entries
+    std::vector<int32_t> col;          // [N] global states
+    std::vector<double>  prob;         // [N]
+    std::vector<double>  rew;          // [2R]
+    std::vector<uint8_t> to_done;      // [R]
+    std::vector<int32_t> states_sq;    // [2S] (agent state, location), may be empty
+    int64_t S() const { return (int64_t)state_row.size() - 1; }
+    int64_t R() const { return (int64_t)row_ptr.size() - 1; }
+    int64_t N() const { return (int64_t)col.size(); }
+};
+
+// A tile is a run of consecutive states of one model whose rows and entries
+// fit the LDS staging area of the sweep kernel.
+struct Tile {
+    int32_t model, s_begin, s_end, pad;
+};
+
+// sweep-kernel variants (columns per lane x lanes per state)
+struct Variant {
+    int id;        // > 0
+    int cpl;       // columns per lane
+    int lps;       // lanes per state
+    int wg;        // threads per workgroup
+};
+
+struct Stats {
+    int64_t backups = 0, sweeps = 0, max_pair_sweeps = 0, eval_sweeps = 0, polish_sweeps = 0,
+            rank_rounds = 0, excluded = 0;
+    double bytes = 0, ms_vi = 0, ms_eval = 0, ms_total = 0;
+    int variant = 0;
+};
+
+struct Proposer;  // mlp.hip
+
+}  // namespace morap
+
+// ---------------------------------------------------------------------------
+// the context
+// ---------------------------------------------------------------------------
+struct morap_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    hipDeviceProp_t prop{};
+
+    // models
+    morap::HostModels hm;
+    bool loaded = false;
+    int64_t S = 0, R = 0, N = 0;
+    int max_rows_per_state = 0;
+    morap::DevBuf d_state_row, d_row_ptr, d_col, d_prob32, d_prob64, d_rew32, d_rew64, d_to_done;
+    morap::DevBuf d_state_base, d_init;
+    morap::DevBuf d_rows_per_model, d_states_per_model;  // [M] int32
+    morap::DevBuf d_csr_bytes32, d_csr_bytes64;          // [M] int64: CSR bytes read per sweep
+
+    // tiles of the batched sweep (built for the LDS limits below)
+    std::vector<morap::Tile> tiles;
+    std::vector<int32_t> tile_base;                 // [M+1] first tile of each model
+    morap::DevBuf d_tiles, d_tile_base;
+
+    // solve state (batched value iteration)
+    int K = 0, Kp = 0, prec = -1;
+    bool solved = false;
+    morap::DevBuf d_x[2];                           // [S][Kp] values, FP32 or FP64
+    morap::DevBuf d_wc32, d_wp32, d_wc64, d_wp64;   // [M][Kp]
+    morap::DevBuf d_res, d_ymax;                    // [M][Kp] uint64 (bits of FP64)
+    morap::DevBuf d_active;                         // [M][Kp] uint8
+    morap::DevBuf d_final_par;                      // [M][Kp] uint8: buffer holding the result
+    morap::DevBuf d_pair_sweeps;                    // [M][Kp] int32
+    morap::DevBuf d_model_active;                   // [M] uint8
+    morap::DevBuf d_act_models, d_act_prefix;       // compacted active model list
+    morap::DevBuf d_counters;                       // int64 [8]: 0 active pairs, 1 active tiles, 2 backups
+    morap::DevBuf d_c;                              // [K][M] FP64 values at the initial states
+    morap::PinnedBuf h_counters;
+    std::vector<double> W;                          // [K][d] of the last solve
+    int last_variant = 0;
+    hipGraph_t chunk_graph = nullptr;               // captured chunk of sweeps
+    hipGraphExec_t chunk_exec = nullptr;
+    std::string graph_key;
+
+    // evaluation state
+    int eK = 0;
+    bool evaluated = false;
+    std::vector<int32_t> assign;                    // [K][nJ]
+    std::vector<int32_t> inst_k, inst_m;            // instances (column, model)
+    std::vector<int64_t> inst_base;                 // [n_inst+1] state offsets
+    morap::DevBuf d_inst_model, d_inst_k, d_inst_base, d_inst_tiles;
+    morap::DevBuf d_xi[2];                          // polish values [inst states] FP64
+    morap::DevBuf d_ires, d_iactive, d_ipar;        // per instance
+    morap::DevBuf d_mask, d_rank, d_mu;             // per instance state
+    morap::DevBuf d_xe[2];                          // evaluation values [inst states][2]
+    morap::DevBuf d_eres, d_eactive, d_epar;        // per (instance, objective)
+    morap::DevBuf d_iwc, d_iwp;                     // per instance FP64 weights
+    morap::DevBuf d_init_idx, d_init_val;           // instance initial states, their values
+    std::vector<int8_t> h_mu;                       // policies of the last evaluate
+
+    // autotuner cache: key (prec, Kp) -> variant id
+    std::vector<std::pair<int64_t, int>> tuned;
+
+    // proposer
+    morap::Proposer* prop_mlp = nullptr;
+    std::vector<double> features;
+
+    ~morap_ctx();
+};
+
+namespace morap {
+
+// product.cpp
+void build_products(morap_ctx* ctx, const morap_agent* agents, int nI, const morap_dfa* tasks, int nJ,
+                    const int32_t* const* letters);
+void load_models(morap_ctx* ctx, const morap_model* models, int n, int nI, int nJ);
+void upload_models(morap_ctx* ctx);
+
+// solver.cpp
+void solve(morap_ctx* ctx, const double* W, int K, const morap_vi_opts& o, double* c_out, Stats& st);
+void evaluate(morap_ctx* ctx, const int32_t* assign, int K, const morap_vi_opts& o, double* r_out, Stats& st);
+const std::vector<Variant>& variants();
+
+// assign.cpp
+void assign_columns(int nI, int nJ, const double* c, int K, int32_t* out);
+
+// qp.cpp
+void project_inner(const double* Phi, int m, int d, const double* t, const double* M, double* x,
+                   double* lam);
+void project_outer(const double* W, const double* R, int n, int d, const double* t, const double* M,
+                   double* z);
+
+// query.cpp
+void query_batch(morap_ctx* ctx, const double* T, int Q, const double* M, const morap_query_opts& o,
+                 morap_query_result* res);
+
+// mlp.hip
+void proposer_destroy(Proposer* p);
+
+// kernels (vi.hip): launch wrappers
+namespace k {
+void fill_u8(hipStream_t s, uint8_t* p, uint8_t v, int64_t n);
+void fill_i32(hipStream_t s, int32_t* p, int32_t v, int64_t n);
+void fill_u64(hipStream_t s, uint64_t* p, uint64_t v, int64_t n);
+void fill_f32(hipStream_t s, float* p, float v, int64_t n);
+void fill_f64(hipStream_t s, double* p, double v, int64_t n);
+void fill_i64(hipStream_t s, int64_t* p, int64_t v, int64_t n);
+void to_f32(hipStream_t s, const double* in, float* out, int64_t n);
+
+struct SweepArgs {
+    const Tile* tiles;
+    const int32_t* tile_base;
+    const int32_t* act_models;
+    const int32_t* act_prefix;
+    const int64_t* counters;
+    const int32_t* state_row;
+    const int32_t* row_ptr;
+    const int32_t* col;
+    const void* prob;
+    const void* rew;
+    const void* wc;
+    const void* wp;
+    const uint8_t* active;
+    const void* x_in;
+    void* x_out;
+    unsigned long long* res;
+    unsigned long long* ymax;
+    int Kp;
+};
+// batched Bellman sweep: variant v, precision prec (MORAP_F32/F64)
+void sweep(hipStream_t s, int prec, const Variant& v, int grid, int ktiles, const SweepArgs& a);
+int sweep_lds_rows();
+int sweep_lds_nnz();
+int sweep_tile_states(const Variant& v);
+
+struct ConvergeArgs {
+    unsigned long long* res;
+    unsigned long long* ymax;
+    uint8_t* active;
+    uint8_t* final_par;
+    int32_t* pair_sweeps;
+    uint8_t* model_active;
+    double* c;              // [K][M]
+    const int32_t* init;    // [M]
+    const void* x_out;      // buffer written by the sweep just finished
+    int64_t* counters;
+    int M, K, Kp, prec, out_par;
+    double eps, unit;       // stop at res <= max(eps, unit * ymax)
+    const int32_t* tile_base;
+    int32_t* act_models;
+    int32_t* act_prefix;
+    const int32_t* rows_per_model;   // [M] rows (backups per active column)
+    const int32_t* states_per_model; // [M] states (value traffic per active column)
+    const int64_t* csr_bytes;        // [M] CSR bytes read per sweep of an active model
+};
+void converge(hipStream_t s, const ConvergeArgs& a);
+void compact(hipStream_t s, const ConvergeArgs& a);
+void init_solve(hipStream_t s, const ConvergeArgs& a);
+
+// instances (polish, policy extraction, evaluation)
+struct InstArgs {
+    const int32_t* inst_model;
+    const int32_t* inst_k;
+    const int64_t* inst_base;
+    const int32_t* inst_tiles;     // (instance, local state begin) pairs
+    int n_tiles;
+    int n_inst;
+    const int32_t* state_base;
+    const int32_t* state_row;
+    const int32_t* row_ptr;
+    const int32_t* col;
+    const double* prob;
+    const double* rew;
+    const uint8_t* to_done;
+    const int32_t* init;
+};
+void gather_columns(hipStream_t s, const InstArgs& a, int prec, const void* x0, const void* x1,
+                    const uint8_t* final_par, int Kp, double* xi);
+void polish_sweep(hipStream_t s, const InstArgs& a, const double* wc, const double* wp,
+                  const uint8_t* active, const double* x_in, double* x_out, unsigned long long* res);
+void inst_converge(hipStream_t s, int n, unsigned long long* res, uint8_t* active, uint8_t* par, int out_par,
+                   double eps, int64_t* counter);
+void opt_mask(hipStream_t s, const InstArgs& a, const double* wc, const double* wp, const double* x,
+              double tau, uint32_t* mask, int32_t* rank, int8_t* mu);
+void rank_round(hipStream_t s, const InstArgs& a, const uint32_t* mask, int32_t* rank, int8_t* mu,
+                int level, int64_t* counter);
+void eval_sweep(hipStream_t s, const InstArgs& a, const int8_t* mu, const uint8_t* active,
+                const double* x_in, double* x_out, unsigned long long* res);
+void count_unranked(hipStream_t s, const InstArgs& a, const int32_t* rank, int64_t* counter);
+// per-instance flags: `width` entries per instance, active when the instance
+// has a live initial state
+void set_active(hipStream_t s, int n, const InstArgs& a, uint8_t* active, unsigned long long* res,
+                uint8_t* par, int width);
+// copy the values of entries frozen in buffer 1 into buffer 0
+void select_final(hipStream_t s, const InstArgs& a, double* x0, const double* x1, const uint8_t* par,
+                  int width);
+// out[2q + o] = x[2 idx[q] + o] (0 when idx[q] < 0)
+void gather_init(hipStream_t s, int n, const int64_t* idx, const double* x, double* out);
+}  // namespace k
+
+}  // namespace morap

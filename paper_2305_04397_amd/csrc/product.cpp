@@ -1,0 +1,359 @@
+// Agent-task product MDPs M_i (x) A_j (Sec. 2, "Product MDP"; Sec. 3.1) built
+// on the host, validated, concatenated with global indices and uploaded.
+//
+// Semantics: a product state (s, q) is done when q is accepting or a trap (a
+// location from which no run reaches an accepting one).  Done states are
+// absorbing with value 0 and are not stored; a row keeps its entries into
+// live states, flags whether it moves mass into done, and carries the rewards
+// (-cost(s, a), sum of P(s, a, s') over s' whose next location accepts).  Live
+// reachable states are explored from (s0, q0) and numbered in (q, s) order.
+#include "common.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <thread>
+
+namespace morap {
+
+namespace {
+
+struct Built {
+    int32_t init = -1;
+    std::vector<int32_t> state_row{0}, row_ptr{0}, col, states_sq;
+    std::vector<double> prob, rew;
+    std::vector<uint8_t> to_done;
+};
+
+void validate_agent(const morap_agent& a, int i) {
+    const std::string who = "agent " + std::to_string(i) + ": ";
+    MORAP_CHECK(a.n_states > 0 && a.n_actions > 0 && a.n_actions <= 32, MORAP_E_INVALID,
+                who + "need n_states > 0 and 0 < n_actions <= 32");
+    MORAP_CHECK(a.init >= 0 && a.init < a.n_states, MORAP_E_INVALID, who + "init out of range");
+    MORAP_CHECK(a.sa_ptr && a.cost, MORAP_E_INVALID, who + "NULL arrays");
+    const int64_t rows = (int64_t)a.n_states * a.n_actions;
+    MORAP_CHECK(a.sa_ptr[0] == 0, MORAP_E_INVALID, who + "sa_ptr[0] must be 0");
+    for (int s = 0; s < a.n_states; ++s) {
+        bool any = false;
+        for (int act = 0; act < a.n_actions; ++act) {
+            const int64_t r = (int64_t)s * a.n_actions + act;
+            any |= a.sa_ptr[r + 1] > a.sa_ptr[r];
+        }
+        MORAP_CHECK(any, MORAP_E_INVALID, who + "a state without enabled actions");
+    }
+    for (int64_t r = 0; r < rows; ++r) {
+        MORAP_CHECK(a.sa_ptr[r + 1] >= a.sa_ptr[r], MORAP_E_INVALID, who + "sa_ptr not monotone");
+        MORAP_CHECK(std::isfinite(a.cost[r]), MORAP_E_INVALID, who + "non-finite cost");
+        if (a.sa_ptr[r + 1] == a.sa_ptr[r]) continue;
+        double sum = 0;
+        for (int32_t e = a.sa_ptr[r]; e < a.sa_ptr[r + 1]; ++e) {
+            MORAP_CHECK(a.succ[e] >= 0 && a.succ[e] < a.n_states, MORAP_E_INVALID, who + "successor out of range");
+            MORAP_CHECK(std::isfinite(a.prob[e]) && a.prob[e] >= 0, MORAP_E_INVALID, who + "bad probability");
+            sum += a.prob[e];
+        }
+        MORAP_CHECK(std::fabs(sum - 1.0) <= 1e-9, MORAP_E_INVALID,
+                    who + "an enabled action's probabilities do not sum to 1");
+    }
+}
+
+void validate_dfa(const morap_dfa& t, int j) {
+    const std::string who = "task " + std::to_string(j) + ": ";
+    MORAP_CHECK(t.n_locs > 0 && t.n_letters > 0, MORAP_E_INVALID, who + "empty automaton");
+    MORAP_CHECK(t.q0 >= 0 && t.q0 < t.n_locs, MORAP_E_INVALID, who + "q0 out of range");
+    MORAP_CHECK(t.delta && t.accepting, MORAP_E_INVALID, who + "NULL arrays");
+    for (int64_t i = 0; i < (int64_t)t.n_locs * t.n_letters; ++i)
+        MORAP_CHECK(t.delta[i] >= 0 && t.delta[i] < t.n_locs, MORAP_E_INVALID, who + "delta out of range");
+}
+
+// done locations: accepting, or no run reaches an accepting location
+std::vector<uint8_t> done_locations(const morap_dfa& t) {
+    std::vector<uint8_t> reach(t.n_locs, 0);
+    for (int q = 0; q < t.n_locs; ++q) reach[q] = t.accepting[q] ? 1 : 0;
+    for (bool changed = true; changed;) {
+        changed = false;
+        for (int q = 0; q < t.n_locs; ++q) {
+            if (reach[q]) continue;
+            for (int l = 0; l < t.n_letters; ++l)
+                if (reach[t.delta[(int64_t)q * t.n_letters + l]]) {
+                    reach[q] = 1;
+                    changed = true;
+                    break;
+                }
+        }
+    }
+    std::vector<uint8_t> done(t.n_locs);
+    for (int q = 0; q < t.n_locs; ++q) done[q] = (t.accepting[q] || !reach[q]) ? 1 : 0;
+    return done;
+}
+
+Built build_one(const morap_agent& a, const morap_dfa& t, const int32_t* letters) {
+    Built b;
+    const int S = a.n_states, Q = t.n_locs, L = t.n_letters, A = a.n_actions;
+    const auto done = done_locations(t);
+    auto next_loc = [&](int q, int s2) { return t.delta[(int64_t)q * L + letters[s2]]; };
+    if (done[t.q0]) return b;   // nothing live: value 0
+    // reachability over live states (dense (q, s) index)
+    std::vector<int32_t> idx((size_t)S * Q, -1);
+    std::vector<int32_t> stack;
+    auto key = [&](int s, int q) { return (size_t)q * S + s; };
+    idx[key(a.init, t.q0)] = 0;
+    stack.push_back((int32_t)key(a.init, t.q0));
+    while (!stack.empty()) {
+        const size_t kq = (size_t)stack.back();
+        stack.pop_back();
+        const int q = (int)(kq / S), s = (int)(kq % S);
+        for (int act = 0; act < A; ++act) {
+            const int64_t r = (int64_t)s * A + act;
+            for (int32_t e = a.sa_ptr[r]; e < a.sa_ptr[r + 1]; ++e) {
+                const int s2 = a.succ[e];
+                const int q2 = next_loc(q, s2);
+                if (done[q2]) continue;
+                const size_t k2 = key(s2, q2);
+                if (idx[k2] < 0) {
+                    idx[k2] = 0;
+                    stack.push_back((int32_t)k2);
+                }
+            }
+        }
+    }
+    // number the live states in (q, s) order
+    int32_t n = 0;
+    for (size_t kq = 0; kq < idx.size(); ++kq)
+        if (idx[kq] >= 0) idx[kq] = n++;
+    b.states_sq.reserve((size_t)2 * n);
+    for (size_t kq = 0; kq < idx.size(); ++kq) {
+        if (idx[kq] < 0) continue;
+        const int q = (int)(kq / S), s = (int)(kq % S);
+        b.states_sq.push_back(s);
+        b.states_sq.push_back(q);
+        for (int act = 0; act < A; ++act) {
+            const int64_t r = (int64_t)s * A + act;
+            if (a.sa_ptr[r + 1] == a.sa_ptr[r]) continue;   // disabled action
+            double mass_acc = 0.0;
+            uint8_t hits_done = 0;
+            for (int32_t e = a.sa_ptr[r]; e < a.sa_ptr[r + 1]; ++e) {
+                const int s2 = a.succ[e];
+                const int q2 = next_loc(q, s2);
+                if (done[q2]) {
+                    hits_done = 1;
+                    if (t.accepting[q2]) mass_acc += a.prob[e];
+                } else {
+                    b.col.push_back(idx[key(s2, q2)]);
+                    b.prob.push_back(a.prob[e]);
+                }
+            }
+            b.rew.push_back(-a.cost[r]);
+            b.rew.push_back(mass_acc);
+            b.to_done.push_back(hits_done);
+            b.row_ptr.push_back((int32_t)b.col.size());
+        }
+        b.state_row.push_back((int32_t)b.to_done.size());
+    }
+    b.init = idx[key(a.init, t.q0)];
+    return b;
+}
+
+}  // namespace
+
+static void concat(morap_ctx* c, std::vector<Built>& parts, int nI, int nJ) {
+    HostModels hm;
+    hm.nI = nI;
+    hm.nJ = nJ;
+    hm.M = nI * nJ;
+    int64_t S = 0, R = 0, N = 0;
+    for (auto& b : parts) {
+        S += (int64_t)b.state_row.size() - 1;
+        R += (int64_t)b.row_ptr.size() - 1;
+        N += (int64_t)b.col.size();
+    }
+    const int64_t lim = 2147483647;
+    MORAP_CHECK(S < lim && R < lim && N < lim, MORAP_E_UNSUPPORTED, "more than 2^31-1 states, rows or entries");
+    hm.state_base.resize(hm.M + 1);
+    hm.init.resize(hm.M);
+    hm.state_row.reserve(S + 1);
+    hm.row_ptr.reserve(R + 1);
+    hm.col.reserve(N);
+    hm.prob.reserve(N);
+    hm.rew.reserve(2 * R);
+    hm.to_done.reserve(R);
+    hm.states_sq.reserve(2 * S);
+    hm.state_row.push_back(0);
+    hm.row_ptr.push_back(0);
+    int max_rows = 0;
+    for (int m = 0; m < hm.M; ++m) {
+        Built& b = parts[m];
+        const int32_t sb = (int32_t)(hm.state_row.size() - 1);
+        const int32_t rb = (int32_t)(hm.row_ptr.size() - 1);
+        const int32_t eb = (int32_t)hm.col.size();
+        hm.state_base[m] = sb;
+        hm.init[m] = b.init >= 0 ? sb + b.init : -1;
+        for (size_t s = 1; s < b.state_row.size(); ++s) {
+            hm.state_row.push_back(rb + b.state_row[s]);
+            max_rows = std::max(max_rows, b.state_row[s] - b.state_row[s - 1]);
+        }
+        for (size_t r = 1; r < b.row_ptr.size(); ++r) hm.row_ptr.push_back(eb + b.row_ptr[r]);
+        for (int32_t x : b.col) hm.col.push_back(sb + x);
+        hm.prob.insert(hm.prob.end(), b.prob.begin(), b.prob.end());
+        hm.rew.insert(hm.rew.end(), b.rew.begin(), b.rew.end());
+        hm.to_done.insert(hm.to_done.end(), b.to_done.begin(), b.to_done.end());
+        hm.states_sq.insert(hm.states_sq.end(), b.states_sq.begin(), b.states_sq.end());
+        b = Built();   // free as we go
+    }
+    hm.state_base[hm.M] = (int32_t)(hm.state_row.size() - 1);
+    MORAP_CHECK(max_rows <= 32, MORAP_E_UNSUPPORTED, "more than 32 rows in a state");
+    c->hm = std::move(hm);
+    c->max_rows_per_state = max_rows;
+    upload_models(c);
+}
+
+void build_products(morap_ctx* c, const morap_agent* agents, int nI, const morap_dfa* tasks, int nJ,
+                    const int32_t* const* letters) {
+    MORAP_CHECK(agents && tasks && letters && nI > 0 && nJ > 0, MORAP_E_INVALID, "bad arguments");
+    for (int i = 0; i < nI; ++i) validate_agent(agents[i], i);
+    for (int j = 0; j < nJ; ++j) validate_dfa(tasks[j], j);
+    for (int i = 0; i < nI; ++i)
+        for (int j = 0; j < nJ; ++j) {
+            const int32_t* l = letters[(size_t)i * nJ + j];
+            MORAP_CHECK(l != nullptr, MORAP_E_INVALID, "NULL letters");
+            for (int s = 0; s < agents[i].n_states; ++s)
+                MORAP_CHECK(l[s] >= 0 && l[s] < tasks[j].n_letters, MORAP_E_INVALID, "letter out of range");
+        }
+    const int M = nI * nJ;
+    std::vector<Built> parts(M);
+    std::atomic<int> next{0};
+    std::string err;
+    std::atomic<bool> bad{false};
+    auto worker = [&] {
+        for (int m; (m = next++) < M;) {
+            try {
+                parts[m] = build_one(agents[m / nJ], tasks[m % nJ], letters[m]);
+            } catch (...) {
+                bad = true;
+            }
+        }
+    };
+    const int nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) th.emplace_back(worker);
+    for (auto& t : th) t.join();
+    MORAP_CHECK(!bad, MORAP_E_OOM, "product construction failed (host memory)");
+    concat(c, parts, nI, nJ);
+}
+
+void load_models(morap_ctx* c, const morap_model* models, int n, int nI, int nJ) {
+    MORAP_CHECK(models && nI > 0 && nJ > 0 && n == nI * nJ, MORAP_E_INVALID, "need n_models = n_agents * n_tasks");
+    std::vector<Built> parts(n);
+    for (int m = 0; m < n; ++m) {
+        const morap_model& md = models[m];
+        const std::string who = "model " + std::to_string(m) + ": ";
+        MORAP_CHECK(md.agent == m / nJ && md.task == m % nJ, MORAP_E_INVALID, who + "agent/task do not match m");
+        MORAP_CHECK(md.n_states >= 0 && md.n_rows >= 0 && md.nnz >= 0, MORAP_E_INVALID, who + "negative size");
+        MORAP_CHECK(md.init >= -1 && md.init < md.n_states, MORAP_E_INVALID, who + "init out of range");
+        MORAP_CHECK(md.n_states == 0 || (md.state_row && md.row_ptr && md.rew && md.to_done), MORAP_E_INVALID,
+                    who + "NULL arrays");
+        Built& b = parts[m];
+        b.init = md.init;
+        if (md.n_states == 0) continue;
+        MORAP_CHECK(md.state_row[0] == 0 && md.state_row[md.n_states] == md.n_rows, MORAP_E_INVALID,
+                    who + "state_row must run from 0 to n_rows");
+        MORAP_CHECK(md.row_ptr[0] == 0 && md.row_ptr[md.n_rows] == md.nnz, MORAP_E_INVALID,
+                    who + "row_ptr must run from 0 to nnz");
+        b.state_row.assign(md.state_row, md.state_row + md.n_states + 1);
+        b.row_ptr.assign(md.row_ptr, md.row_ptr + md.n_rows + 1);
+        for (int s = 0; s < md.n_states; ++s)
+            MORAP_CHECK(md.state_row[s + 1] > md.state_row[s], MORAP_E_INVALID, who + "a state without rows");
+        for (int r = 0; r < md.n_rows; ++r) {
+            MORAP_CHECK(md.row_ptr[r + 1] >= md.row_ptr[r], MORAP_E_INVALID, who + "row_ptr not monotone");
+            double sum = 0;
+            for (int e = md.row_ptr[r]; e < md.row_ptr[r + 1]; ++e) {
+                MORAP_CHECK(md.col[e] >= 0 && md.col[e] < md.n_states, MORAP_E_INVALID, who + "col out of range");
+                MORAP_CHECK(std::isfinite(md.prob[e]) && md.prob[e] >= 0, MORAP_E_INVALID, who + "bad probability");
+                sum += md.prob[e];
+            }
+            MORAP_CHECK(sum <= 1.0 + 1e-6, MORAP_E_INVALID, who + "a row sums above 1");
+            MORAP_CHECK(std::isfinite(md.rew[2 * r]) && std::isfinite(md.rew[2 * r + 1]), MORAP_E_INVALID,
+                        who + "non-finite reward");
+        }
+        b.col.assign(md.col, md.col + md.nnz);
+        b.prob.assign(md.prob, md.prob + md.nnz);
+        b.rew.assign(md.rew, md.rew + 2 * (size_t)md.n_rows);
+        b.to_done.assign(md.to_done, md.to_done + md.n_rows);
+        b.states_sq.assign((size_t)2 * md.n_states, 0);
+    }
+    concat(c, parts, nI, nJ);
+}
+
+template <class T>
+static void upload(morap::DevBuf& d, const std::vector<T>& h, hipStream_t s) {
+    d.ensure(h.size() * sizeof(T) + 16);
+    if (!h.empty()) MORAP_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+void upload_models(morap_ctx* c) {
+    const HostModels& hm = c->hm;
+    hipStream_t s = c->stream;
+    c->loaded = false;
+    c->solved = false;
+    c->evaluated = false;
+    c->tuned.clear();
+    c->S = hm.S();
+    c->R = hm.R();
+    c->N = hm.N();
+    upload(c->d_state_row, hm.state_row, s);
+    upload(c->d_row_ptr, hm.row_ptr, s);
+    upload(c->d_col, hm.col, s);
+    upload(c->d_prob64, hm.prob, s);
+    upload(c->d_rew64, hm.rew, s);
+    upload(c->d_to_done, hm.to_done, s);
+    upload(c->d_state_base, hm.state_base, s);
+    upload(c->d_init, hm.init, s);
+    // FP32 copies for FP32 sweeps
+    c->d_prob32.ensure((size_t)c->N * 4 + 16);
+    c->d_rew32.ensure((size_t)c->R * 8 + 16);
+    k::to_f32(s, c->d_prob64.as<double>(), c->d_prob32.as<float>(), c->N);
+    k::to_f32(s, c->d_rew64.as<double>(), c->d_rew32.as<float>(), 2 * c->R);
+    // per-model sizes for the traffic and backup counters
+    std::vector<int32_t> rows(hm.M), states(hm.M);
+    std::vector<int64_t> b32(hm.M), b64(hm.M);
+    for (int m = 0; m < hm.M; ++m) {
+        const int32_t s0 = hm.state_base[m], s1 = hm.state_base[m + 1];
+        states[m] = s1 - s0;
+        rows[m] = hm.state_row[s1] - hm.state_row[s0];
+        const int64_t nnz = hm.row_ptr[hm.state_row[s1]] - hm.row_ptr[hm.state_row[s0]];
+        // state_row + row_ptr + col (int32) + prob + two rewards per row
+        b32[m] = 4 * (int64_t)states[m] + 4 * (int64_t)rows[m] + 4 * nnz + 4 * nnz + 8 * (int64_t)rows[m];
+        b64[m] = 4 * (int64_t)states[m] + 4 * (int64_t)rows[m] + 4 * nnz + 8 * nnz + 16 * (int64_t)rows[m];
+    }
+    upload(c->d_rows_per_model, rows, s);
+    upload(c->d_states_per_model, states, s);
+    upload(c->d_csr_bytes32, b32, s);
+    upload(c->d_csr_bytes64, b64, s);
+    // tiles: consecutive states of one model within the LDS limits
+    c->tiles.clear();
+    c->tile_base.assign(hm.M + 1, 0);
+    const int TS = k::sweep_tile_states(Variant{0, 1, 1, 64}), TR = k::sweep_lds_rows(), TN = k::sweep_lds_nnz();
+    for (int m = 0; m < hm.M; ++m) {
+        c->tile_base[m] = (int32_t)c->tiles.size();
+        int32_t s = hm.state_base[m];
+        const int32_t s_end = hm.state_base[m + 1];
+        while (s < s_end) {
+            int32_t e = s;
+            while (e < s_end && e - s < TS) {
+                const int32_t rows_t = hm.state_row[e + 1] - hm.state_row[s];
+                const int32_t nnz_t = hm.row_ptr[hm.state_row[e + 1]] - hm.row_ptr[hm.state_row[s]];
+                if (rows_t > TR || nnz_t > TN) break;
+                ++e;
+            }
+            MORAP_CHECK(e > s, MORAP_E_UNSUPPORTED, "a state's rows or entries exceed the tile staging limits");
+            c->tiles.push_back(Tile{m, s, e, 0});
+            s = e;
+        }
+    }
+    c->tile_base[hm.M] = (int32_t)c->tiles.size();
+    upload(c->d_tiles, c->tiles, s);
+    upload(c->d_tile_base, c->tile_base, s);
+    MORAP_HIP(hipStreamSynchronize(s));
+    c->loaded = true;
+}
+
+}  // namespace morap

@@ -1,0 +1,213 @@
+// Alg. 1 (point-oriented Pareto computation, Sec. 3.3) on the host, with the
+// supporting-hyperplane step (Alg. 2) on the device.  Several queries advance
+// in lockstep: each pass solves the current weight vectors of all unfinished
+// queries as the columns of one batched value iteration.
+//
+// Loop control (a reading of the loop test): t_up is recomputed right after
+// each new point is added and ||t_down - t_up||_M <= eps is tested at once;
+// this never divides 0/0 in the weight update.  Verdict: FEASIBLE iff t lies
+// in down(Phi), INFEASIBLE iff some (w', r') has w'.r' < w'.t, otherwise
+// UNDECIDED.
+#include "common.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+namespace morap {
+
+void proposer_infer_host(morap_ctx* c, const float* X, int n, float* out);   // mlp.hip
+bool proposer_ready(const morap_ctx* c, int n_in, int d);
+
+namespace {
+
+double mnorm(const std::vector<double>& v, const double* M) {
+    const int d = (int)v.size();
+    double s = 0;
+    if (!M) {
+        for (double x : v) s += x * x;
+    } else {
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j) s += v[i] * M[(size_t)i * d + j] * v[j];
+    }
+    return std::sqrt(std::max(s, 0.0));
+}
+
+struct QState {
+    std::vector<double> t, t_up, t_down, w, lam;
+    std::vector<std::vector<double>> Phi, Ws;
+    bool done = false, separated = false;
+    int fallback = 0;
+    double gap = 0;
+    int64_t backups = 0;
+    double ms = 0;
+};
+
+}  // namespace
+
+void query_batch(morap_ctx* c, const double* T, int Q, const double* M, const morap_query_opts& o,
+                 morap_query_result* res) {
+    MORAP_CHECK(c->loaded, MORAP_E_STATE, "no models loaded");
+    MORAP_CHECK(T && res && Q >= 1, MORAP_E_INVALID, "bad query arguments");
+    MORAP_CHECK(o.eps >= 0 && o.max_iter >= 1, MORAP_E_INVALID, "need eps >= 0 and max_iter >= 1");
+    const int nI = c->hm.nI, nJ = c->hm.nJ, d = nI + nJ;
+    for (int64_t i = 0; i < (int64_t)Q * d; ++i) MORAP_CHECK(std::isfinite(T[i]), MORAP_E_INVALID, "t must be finite");
+    std::vector<QState> qs(Q);
+    const auto t_start = std::chrono::steady_clock::now();
+    // initial weight vectors: e_1, or the learned proposer's output
+    std::vector<float> prop;
+    const int nfeat = (int)c->features.size();
+    const bool learned = o.use_proposer && proposer_ready(c, d + nfeat, d);
+    if (learned) {
+        std::vector<float> X((size_t)Q * (d + nfeat));
+        for (int q = 0; q < Q; ++q) {
+            for (int k = 0; k < d; ++k) X[(size_t)q * (d + nfeat) + k] = (float)T[(size_t)q * d + k];
+            for (int k = 0; k < nfeat; ++k) X[(size_t)q * (d + nfeat) + d + k] = (float)c->features[k];
+        }
+        prop.resize((size_t)Q * d);
+        proposer_infer_host(c, X.data(), Q, prop.data());
+    }
+    for (int q = 0; q < Q; ++q) {
+        QState& s = qs[q];
+        s.t.assign(T + (size_t)q * d, T + (size_t)(q + 1) * d);
+        s.t_down = s.t;
+        s.t_up.assign(d, -INFINITY);
+        s.w.assign(d, 0.0);
+        s.w[0] = 1.0;
+        if (o.use_proposer) {
+            bool ok = learned;
+            std::vector<double> w(d);
+            double sum = 0;
+            for (int k = 0; ok && k < d; ++k) {
+                const double v = learned ? prop[(size_t)q * d + k] : 0.0;
+                ok &= std::isfinite(v) && v >= 0;
+                w[k] = v;
+                sum += v;
+            }
+            ok &= std::fabs(sum - 1.0) <= 1e-3 && sum > 0;
+            if (ok) {
+                for (auto& v : w) v /= sum;
+                s.w = w;
+            } else {
+                s.fallback = 1;   // plain rule: start from (1, 0, ..., 0)
+            }
+        }
+    }
+    morap_vi_opts vo = o.vi;
+    for (int it = 0; it < o.max_iter; ++it) {
+        std::vector<int> act;
+        for (int q = 0; q < Q; ++q)
+            if (!qs[q].done) act.push_back(q);
+        if (act.empty()) break;
+        for (size_t b = 0; b < act.size(); b += 64) {
+            const int K = (int)std::min<size_t>(64, act.size() - b);
+            std::vector<double> W((size_t)K * d), C((size_t)K * nI * nJ), R((size_t)K * d);
+            std::vector<int32_t> A((size_t)K * nJ);
+            for (int kk = 0; kk < K; ++kk) {
+                // re-normalise so the row sums to 1 to the last bit
+                const auto& w = qs[act[b + kk]].w;
+                double sum = 0;
+                for (double v : w) sum += v;
+                for (int q = 0; q < d; ++q) W[(size_t)kk * d + q] = w[q] / sum;
+            }
+            Stats st;
+            const auto t0 = std::chrono::steady_clock::now();
+            solve(c, W.data(), K, vo, C.data(), st);
+            assign_columns(nI, nJ, C.data(), K, A.data());
+            evaluate(c, A.data(), K, vo, R.data(), st);
+            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            for (int kk = 0; kk < K; ++kk) {
+                QState& s = qs[act[b + kk]];
+                s.backups += st.backups / K;
+                s.ms += ms / K;
+                std::vector<double> r(R.begin() + (size_t)kk * d, R.begin() + (size_t)(kk + 1) * d);
+                std::vector<double> w(W.begin() + (size_t)kk * d, W.begin() + (size_t)(kk + 1) * d);
+                s.Phi.push_back(r);
+                s.Ws.push_back(w);
+                double wr = 0, wt = 0;
+                for (int k = 0; k < d; ++k) {
+                    wr += w[k] * r[k];
+                    wt += w[k] * s.t_down[k];
+                }
+                const int n = (int)s.Phi.size();
+                std::vector<double> Pf((size_t)n * d), Wf((size_t)n * d);
+                for (int i = 0; i < n; ++i)
+                    for (int k = 0; k < d; ++k) {
+                        Pf[(size_t)i * d + k] = s.Phi[i][k];
+                        Wf[(size_t)i * d + k] = s.Ws[i][k];
+                    }
+                if (wr < wt) {
+                    if (o.verification_only) s.separated = true;
+                    project_outer(Wf.data(), Pf.data(), n, d, s.t.data(), M, s.t_down.data());
+                }
+                s.lam.assign(n, 0.0);
+                project_inner(Pf.data(), n, d, s.t.data(), M, s.t_up.data(), s.lam.data());
+                std::vector<double> diff(d);
+                for (int k = 0; k < d; ++k) diff[k] = s.t_down[k] - s.t_up[k];
+                s.gap = mnorm(diff, M);
+                if (s.separated || s.gap <= o.eps) {
+                    s.done = true;
+                    continue;
+                }
+                // w = M (t - t_up) / ||M (t - t_up)||_1; rounding-level negatives are 0
+                std::vector<double> v(d), mv(d, 0.0);
+                for (int k = 0; k < d; ++k) v[k] = s.t[k] - s.t_up[k];
+                for (int k = 0; k < d; ++k) {
+                    if (!M) mv[k] = v[k];
+                    else
+                        for (int l = 0; l < d; ++l) mv[k] += M[(size_t)k * d + l] * v[l];
+                }
+                double sum = 0;
+                for (int k = 0; k < d; ++k) {
+                    mv[k] = std::max(mv[k], 0.0);
+                    sum += mv[k];
+                }
+                if (!(sum > 0)) {
+                    s.done = true;   // t_up == t up to rounding
+                    continue;
+                }
+                for (int k = 0; k < d; ++k) s.w[k] = mv[k] / sum;
+            }
+        }
+    }
+    const double total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    for (int q = 0; q < Q; ++q) {
+        QState& s = qs[q];
+        morap_query_result& r = res[q];
+        std::vector<double> diff(d);
+        for (int k = 0; k < d; ++k) diff[k] = s.t[k] - s.t_up[k];
+        int verdict = MORAP_UNDECIDED;
+        if (mnorm(diff, M) <= 1e-9) {
+            verdict = MORAP_FEASIBLE;
+        } else {
+            for (size_t i = 0; i < s.Phi.size(); ++i) {
+                double wr = 0, wt = 0;
+                for (int k = 0; k < d; ++k) {
+                    wr += s.Ws[i][k] * s.Phi[i][k];
+                    wt += s.Ws[i][k] * s.t[k];
+                }
+                if (wr < wt - 1e-12) verdict = MORAP_INFEASIBLE;
+            }
+        }
+        r.verdict = verdict;
+        r.iterations = (int32_t)s.Phi.size();
+        r.fallback = s.fallback;
+        r.gap = s.gap;
+        r.ms = Q == 1 ? total_ms : s.ms;
+        r.backups = s.backups;
+        if (r.t_up) std::copy(s.t_up.begin(), s.t_up.end(), r.t_up);
+        if (r.t_down) std::copy(s.t_down.begin(), s.t_down.end(), r.t_down);
+        if (r.lam) {
+            std::fill(r.lam, r.lam + o.max_iter, 0.0);
+            std::copy(s.lam.begin(), s.lam.end(), r.lam);
+        }
+        if (o.keep_trace) {
+            for (size_t i = 0; i < s.Phi.size(); ++i) {
+                if (r.trace_w) std::copy(s.Ws[i].begin(), s.Ws[i].end(), r.trace_w + i * d);
+                if (r.trace_r) std::copy(s.Phi[i].begin(), s.Phi[i].end(), r.trace_r + i * d);
+            }
+        }
+    }
+}
+
+}  // namespace morap

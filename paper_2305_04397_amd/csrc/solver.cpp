@@ -1,0 +1,562 @@
+// Host orchestration of the batched value iteration (Alg. 3 for K weight
+// columns at once), the FP64 polish, policy extraction and per-objective
+// evaluation (Alg. 4) of the assigned (column, model) instances.
+#include "common.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+namespace morap {
+
+// ---------------------------------------------------------------------------
+// sweep-kernel variants: columns per lane x lanes per state
+// ---------------------------------------------------------------------------
+const std::vector<Variant>& variants() {
+    static const std::vector<Variant> v = [] {
+        std::vector<Variant> out;
+        const int pairs[][2] = {{1, 1},  {1, 2},  {2, 1},  {1, 4},  {2, 2},  {4, 1},
+                                {1, 8},  {2, 4},  {4, 2},  {1, 16}, {2, 8},  {4, 4},
+                                {1, 32}, {2, 16}, {4, 8},  {1, 64}, {2, 32}, {4, 16}};
+        int id = 1;
+        for (auto& p : pairs) out.push_back({id++, p[0], p[1], std::min(256, 64 * p[1])});
+        return out;
+    }();
+    return v;
+}
+
+static int kt_of(const Variant& v) { return v.cpl * v.lps; }
+
+static int padded_k(int K) {
+    if (K <= 64) {
+        int p = 1;
+        while (p < K) p <<= 1;
+        return std::max(p, 1);
+    }
+    return (K + 63) / 64 * 64;
+}
+
+// candidate variants for a padded width: k-tiles of min(Kp, 64) columns, and
+// of half that
+static std::vector<Variant> candidates(int Kp) {
+    std::vector<Variant> out;
+    const int kt_full = std::min(Kp, 64);
+    for (const auto& v : variants()) {
+        const int kt = kt_of(v);
+        if (Kp % kt) continue;
+        if (kt == kt_full || (kt * 2 == kt_full && kt >= 8)) out.push_back(v);
+    }
+    return out;
+}
+
+static const Variant& variant_by_id(int id) {
+    for (const auto& v : variants())
+        if (v.id == id) return v;
+    fail(MORAP_E_INVALID, "unknown sweep variant id " + std::to_string(id));
+}
+
+// ---------------------------------------------------------------------------
+// per-solve buffers
+// ---------------------------------------------------------------------------
+static void ensure_solve_buffers(morap_ctx* c, int K, int Kp, int prec) {
+    const int M = c->hm.M;
+    const size_t el = prec == MORAP_F32 ? 4 : 8;
+    const size_t pairs = (size_t)M * Kp;
+    c->d_x[0].ensure((size_t)c->S * Kp * el);
+    c->d_x[1].ensure((size_t)c->S * Kp * el);
+    c->d_wc32.ensure(pairs * 4);
+    c->d_wp32.ensure(pairs * 4);
+    c->d_wc64.ensure(pairs * 8);
+    c->d_wp64.ensure(pairs * 8);
+    c->d_res.ensure(pairs * 8);
+    c->d_ymax.ensure(pairs * 8);
+    c->d_active.ensure(pairs);
+    c->d_final_par.ensure(pairs);
+    c->d_pair_sweeps.ensure(pairs * 4);
+    c->d_model_active.ensure(M);
+    c->d_act_models.ensure((size_t)M * 4 + 4);
+    c->d_act_prefix.ensure((size_t)(M + 1) * 4 + 4);
+    c->d_counters.ensure(8 * 8);
+    c->d_c.ensure((size_t)K * M * 8);
+    c->h_counters.ensure(8 * 8);
+}
+
+static k::ConvergeArgs converge_args(morap_ctx* c, int K, int Kp, int prec, double eps, int out_par) {
+    k::ConvergeArgs a{};
+    a.res = c->d_res.as<unsigned long long>();
+    a.ymax = c->d_ymax.as<unsigned long long>();
+    a.active = c->d_active.as<uint8_t>();
+    a.final_par = c->d_final_par.as<uint8_t>();
+    a.pair_sweeps = c->d_pair_sweeps.as<int32_t>();
+    a.model_active = c->d_model_active.as<uint8_t>();
+    a.c = c->d_c.as<double>();
+    a.init = c->d_init.as<int32_t>();
+    a.x_out = c->d_x[out_par].p;
+    a.counters = c->d_counters.as<int64_t>();
+    a.M = c->hm.M;
+    a.K = K;
+    a.Kp = Kp;
+    a.prec = prec;
+    a.out_par = out_par;
+    a.eps = eps;
+    // FP32 backups cannot resolve changes below a few units in the last
+    // place of the values: stop there too (FP64: the bound is below eps)
+    a.unit = prec == MORAP_F32 ? 8.0 * std::ldexp(1.0, -24) : 8.0 * std::ldexp(1.0, -53);
+    a.tile_base = c->d_tile_base.as<int32_t>();
+    a.act_models = c->d_act_models.as<int32_t>();
+    a.act_prefix = c->d_act_prefix.as<int32_t>();
+    a.rows_per_model = c->d_rows_per_model.as<int32_t>();
+    a.states_per_model = c->d_states_per_model.as<int32_t>();
+    a.csr_bytes = prec == MORAP_F32 ? c->d_csr_bytes32.as<int64_t>() : c->d_csr_bytes64.as<int64_t>();
+    return a;
+}
+
+static k::SweepArgs sweep_args(morap_ctx* c, int Kp, int prec, int in_par) {
+    k::SweepArgs a{};
+    a.tiles = c->d_tiles.as<Tile>();
+    a.tile_base = c->d_tile_base.as<int32_t>();
+    a.act_models = c->d_act_models.as<int32_t>();
+    a.act_prefix = c->d_act_prefix.as<int32_t>();
+    a.counters = c->d_counters.as<int64_t>();
+    a.state_row = c->d_state_row.as<int32_t>();
+    a.row_ptr = c->d_row_ptr.as<int32_t>();
+    a.col = c->d_col.as<int32_t>();
+    const bool f32 = prec == MORAP_F32;
+    a.prob = f32 ? c->d_prob32.p : c->d_prob64.p;
+    a.rew = f32 ? c->d_rew32.p : c->d_rew64.p;
+    a.wc = f32 ? c->d_wc32.p : c->d_wc64.p;
+    a.wp = f32 ? c->d_wp32.p : c->d_wp64.p;
+    a.active = c->d_active.as<uint8_t>();
+    a.x_in = c->d_x[in_par].p;
+    a.x_out = c->d_x[1 - in_par].p;
+    a.res = c->d_res.as<unsigned long long>();
+    a.ymax = c->d_ymax.as<unsigned long long>();
+    a.Kp = Kp;
+    return a;
+}
+
+static int persistent_grid(morap_ctx* c, const Variant& v) {
+    const int per_cu = v.wg >= 256 ? 8 : (v.wg >= 128 ? 16 : 16);
+    int g = c->prop.multiProcessorCount * per_cu;
+    const int tiles = (int)c->tiles.size();
+    g = std::min(g, (tiles + 7) / 8 * 8);
+    return std::max(8, g / 8 * 8);
+}
+
+// one chunk of `n` sweeps (n even): sweep, converge, compact per sweep
+static void enqueue_chunk(morap_ctx* c, const Variant& v, int K, int Kp, int prec, double eps, int n) {
+    const int grid = persistent_grid(c, v);
+    const int ktiles = Kp / kt_of(v);
+    for (int i = 0; i < n; ++i) {
+        const int in_par = i & 1;
+        k::sweep(c->stream, prec, v, grid, ktiles, sweep_args(c, Kp, prec, in_par));
+        const auto ca = converge_args(c, K, Kp, prec, eps, 1 - in_par);
+        k::converge(c->stream, ca);
+        k::compact(c->stream, ca);
+    }
+}
+
+static void reset_solve(morap_ctx* c, int K, int Kp, int prec, double eps) {
+    const size_t el = prec == MORAP_F32 ? 4 : 8;
+    if (el == 4) {
+        k::fill_f32(c->stream, c->d_x[0].as<float>(), 0.f, c->S * Kp);
+        k::fill_f32(c->stream, c->d_x[1].as<float>(), 0.f, c->S * Kp);
+    } else {
+        k::fill_f64(c->stream, c->d_x[0].as<double>(), 0.0, c->S * Kp);
+        k::fill_f64(c->stream, c->d_x[1].as<double>(), 0.0, c->S * Kp);
+    }
+    k::init_solve(c->stream, converge_args(c, K, Kp, prec, eps, 1));
+}
+
+static void release_graph(morap_ctx* c) {
+    if (c->chunk_exec) (void)hipGraphExecDestroy(c->chunk_exec);
+    if (c->chunk_graph) (void)hipGraphDestroy(c->chunk_graph);
+    c->chunk_exec = nullptr;
+    c->chunk_graph = nullptr;
+    c->graph_key.clear();
+}
+
+// run one chunk, replaying a captured graph when asked to
+static void run_chunk(morap_ctx* c, const Variant& v, int K, int Kp, int prec, double eps, int n,
+                      bool graph) {
+    if (!graph) {
+        enqueue_chunk(c, v, K, Kp, prec, eps, n);
+        return;
+    }
+    char key[256];
+    snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%.17g/%p/%p/%zu", v.id, K, Kp, prec, n, eps, c->d_x[0].p,
+             c->d_x[1].p, c->tiles.size());
+    if (c->graph_key != key) {
+        release_graph(c);
+        MORAP_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        try {
+            enqueue_chunk(c, v, K, Kp, prec, eps, n);
+        } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(c->stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        MORAP_HIP(hipStreamEndCapture(c->stream, &c->chunk_graph));
+        MORAP_HIP(hipGraphInstantiate(&c->chunk_exec, c->chunk_graph, nullptr, nullptr, 0));
+        c->graph_key = key;
+    }
+    MORAP_HIP(hipGraphLaunch(c->chunk_exec, c->stream));
+}
+
+static void read_counters(morap_ctx* c) {
+    MORAP_HIP(hipMemcpyAsync(c->h_counters.p, c->d_counters.p, 8 * 8, hipMemcpyDeviceToHost, c->stream));
+    MORAP_HIP(hipStreamSynchronize(c->stream));
+}
+
+// time `n` sweeps of variant v from a fresh start (autotuner)
+static double time_variant(morap_ctx* c, const Variant& v, int K, int Kp, int prec, double eps) {
+    hipEvent_t e0, e1;
+    MORAP_HIP(hipEventCreate(&e0));
+    MORAP_HIP(hipEventCreate(&e1));
+    reset_solve(c, K, Kp, prec, eps);
+    enqueue_chunk(c, v, K, Kp, prec, eps, 2);
+    MORAP_HIP(hipEventRecord(e0, c->stream));
+    enqueue_chunk(c, v, K, Kp, prec, eps, 6);
+    MORAP_HIP(hipEventRecord(e1, c->stream));
+    MORAP_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    MORAP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms;
+}
+
+static const Variant& choose_variant(morap_ctx* c, int K, int Kp, int prec, double eps, int schedule) {
+    if (schedule > 0) {
+        const Variant& v = variant_by_id(schedule);
+        MORAP_CHECK(Kp % kt_of(v) == 0, MORAP_E_INVALID, "variant does not divide the padded column count");
+        return v;
+    }
+    const int64_t key = (int64_t)prec << 32 | Kp;
+    for (auto& t : c->tuned)
+        if (t.first == key) return variant_by_id(t.second);
+    auto cand = candidates(Kp);
+    MORAP_CHECK(!cand.empty(), MORAP_E_UNSUPPORTED, "no sweep variant for this column count");
+    int best = cand[0].id;
+    if (cand.size() > 1) {
+        double best_ms = 1e300;
+        for (const auto& v : cand) {
+            const double ms = time_variant(c, v, K, Kp, prec, eps);
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = v.id;
+            }
+        }
+    }
+    c->tuned.push_back({key, best});
+    return variant_by_id(best);
+}
+
+// ---------------------------------------------------------------------------
+// solve
+// ---------------------------------------------------------------------------
+void solve(morap_ctx* c, const double* W, int K, const morap_vi_opts& o, double* c_out, Stats& st) {
+    MORAP_CHECK(c->loaded, MORAP_E_STATE, "no models loaded");
+    MORAP_CHECK(W && K >= 1 && K <= 4096, MORAP_E_INVALID, "need 1 <= K <= 4096 weight vectors");
+    MORAP_CHECK(o.precision == MORAP_F32 || o.precision == MORAP_F64, MORAP_E_INVALID, "bad precision");
+    MORAP_CHECK(o.eps_vi > 0 && std::isfinite(o.eps_vi), MORAP_E_INVALID, "eps_vi must be > 0");
+    MORAP_CHECK(o.max_sweeps >= 1, MORAP_E_INVALID, "max_sweeps must be >= 1");
+    const int nI = c->hm.nI, nJ = c->hm.nJ, M = c->hm.M, d = nI + nJ;
+    for (int k = 0; k < K; ++k) {
+        double s = 0;
+        for (int q = 0; q < d; ++q) {
+            const double w = W[(size_t)k * d + q];
+            MORAP_CHECK(std::isfinite(w) && w >= 0, MORAP_E_INVALID, "weights must be finite and >= 0");
+            s += w;
+        }
+        MORAP_CHECK(std::fabs(s - 1.0) <= 1e-9, MORAP_E_INVALID, "weight rows must sum to 1");
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    const int prec = o.precision;
+    const int Kp = padded_k(K);
+    if (c->K != K || c->Kp != Kp || c->prec != prec) release_graph(c);
+    ensure_solve_buffers(c, K, Kp, prec);
+    c->K = K;
+    c->Kp = Kp;
+    c->prec = prec;
+    c->solved = false;
+    c->evaluated = false;
+    c->W.assign(W, W + (size_t)K * d);
+
+    // per-(model, column) weights of the model's two objectives
+    std::vector<double> wc((size_t)M * Kp, 0.0), wp((size_t)M * Kp, 0.0);
+    std::vector<float> wc32((size_t)M * Kp, 0.f), wp32((size_t)M * Kp, 0.f);
+    for (int m = 0; m < M; ++m) {
+        const int i = m / nJ, j = m % nJ;
+        for (int k = 0; k < K; ++k) {
+            wc[(size_t)m * Kp + k] = W[(size_t)k * d + i];
+            wp[(size_t)m * Kp + k] = W[(size_t)k * d + nI + j];
+            wc32[(size_t)m * Kp + k] = (float)wc[(size_t)m * Kp + k];
+            wp32[(size_t)m * Kp + k] = (float)wp[(size_t)m * Kp + k];
+        }
+    }
+    MORAP_HIP(hipMemcpyAsync(c->d_wc64.p, wc.data(), wc.size() * 8, hipMemcpyHostToDevice, c->stream));
+    MORAP_HIP(hipMemcpyAsync(c->d_wp64.p, wp.data(), wp.size() * 8, hipMemcpyHostToDevice, c->stream));
+    MORAP_HIP(hipMemcpyAsync(c->d_wc32.p, wc32.data(), wc32.size() * 4, hipMemcpyHostToDevice, c->stream));
+    MORAP_HIP(hipMemcpyAsync(c->d_wp32.p, wp32.data(), wp32.size() * 4, hipMemcpyHostToDevice, c->stream));
+
+    const Variant& v = choose_variant(c, K, Kp, prec, o.eps_vi, o.schedule);
+    c->last_variant = v.id;
+    const int chunk = std::max(2, (o.check_every + 1) / 2 * 2);
+
+    hipEvent_t e0, e1;
+    MORAP_HIP(hipEventCreate(&e0));
+    MORAP_HIP(hipEventCreate(&e1));
+    reset_solve(c, K, Kp, prec, o.eps_vi);
+    MORAP_HIP(hipEventRecord(e0, c->stream));
+    int64_t launched = 0;
+    int64_t* h = c->h_counters.as<int64_t>();
+    while (true) {
+        run_chunk(c, v, K, Kp, prec, o.eps_vi, chunk, o.use_graph != 0);
+        launched += chunk;
+        read_counters(c);
+        if (h[3] == 0) break;
+        if (launched >= o.max_sweeps) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            fail(MORAP_E_NOT_CONVERGED, "value iteration: " + std::to_string(h[3]) +
+                                            " (model, column) pairs still active after " +
+                                            std::to_string(launched) + " sweeps");
+        }
+    }
+    MORAP_HIP(hipEventRecord(e1, c->stream));
+    MORAP_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    MORAP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+
+    std::vector<int32_t> ps((size_t)M * Kp);
+    MORAP_HIP(hipMemcpyAsync(ps.data(), c->d_pair_sweeps.p, ps.size() * 4, hipMemcpyDeviceToHost, c->stream));
+    if (c_out)
+        MORAP_HIP(hipMemcpyAsync(c_out, c->d_c.p, (size_t)K * M * 8, hipMemcpyDeviceToHost, c->stream));
+    MORAP_HIP(hipStreamSynchronize(c->stream));
+    const size_t el = prec == MORAP_F32 ? 4 : 8;
+    st.sweeps += h[5];
+    st.backups += h[4];
+    st.bytes += (double)h[6] + 2.0 * el * (double)h[7];
+    st.max_pair_sweeps = std::max<int64_t>(st.max_pair_sweeps, *std::max_element(ps.begin(), ps.end()));
+    st.ms_vi += ms;
+    st.variant = v.id;
+    st.ms_total += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    c->solved = true;
+}
+
+// ---------------------------------------------------------------------------
+// evaluate: polish (FP32 solves), policy extraction, Alg. 4
+// ---------------------------------------------------------------------------
+static k::InstArgs inst_args(morap_ctx* c, int n_tiles, int n_inst) {
+    k::InstArgs a{};
+    a.inst_model = c->d_inst_model.as<int32_t>();
+    a.inst_k = c->d_inst_k.as<int32_t>();
+    a.inst_base = c->d_inst_base.as<int64_t>();
+    a.inst_tiles = c->d_inst_tiles.as<int32_t>();
+    a.n_tiles = n_tiles;
+    a.n_inst = n_inst;
+    a.state_base = c->d_state_base.as<int32_t>();
+    a.state_row = c->d_state_row.as<int32_t>();
+    a.row_ptr = c->d_row_ptr.as<int32_t>();
+    a.col = c->d_col.as<int32_t>();
+    a.prob = c->d_prob64.as<double>();
+    a.rew = c->d_rew64.as<double>();
+    a.to_done = c->d_to_done.as<uint8_t>();
+    a.init = c->d_init.as<int32_t>();
+    return a;
+}
+
+void evaluate(morap_ctx* c, const int32_t* assign, int K, const morap_vi_opts& o, double* r_out, Stats& st) {
+    MORAP_CHECK(c->solved, MORAP_E_STATE, "morap_evaluate needs a morap_solve first");
+    MORAP_CHECK(K == c->K, MORAP_E_INVALID, "K differs from the last morap_solve");
+    MORAP_CHECK(assign != nullptr, MORAP_E_INVALID, "assign is NULL");
+    MORAP_CHECK(o.eps_eval > 0 && o.eps_vi > 0 && o.tau >= 0, MORAP_E_INVALID, "bad tolerances");
+    const int nI = c->hm.nI, nJ = c->hm.nJ, d = nI + nJ;
+    const int cap = std::max(1, (nJ + nI - 1) / nI);
+    for (int kk = 0; kk < K; ++kk) {
+        std::vector<int> load(nI, 0);
+        for (int j = 0; j < nJ; ++j) {
+            const int i = assign[(size_t)kk * nJ + j];
+            MORAP_CHECK(i >= 0 && i < nI, MORAP_E_INVALID, "assigned agent out of range");
+            MORAP_CHECK(++load[i] <= cap, MORAP_E_INVALID, "an agent received more than ceil(|J|/|I|) tasks");
+        }
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = c->stream;
+    // instances (k, m) in column-major task order
+    const int n = K * nJ;
+    c->assign.assign(assign, assign + (size_t)K * nJ);
+    c->inst_k.resize(n);
+    c->inst_m.resize(n);
+    c->inst_base.assign(n + 1, 0);
+    std::vector<int32_t> tiles;
+    std::vector<double> iwc(n), iwp(n);
+    std::vector<int64_t> init_idx(n, -1);
+    for (int kk = 0; kk < K; ++kk)
+        for (int j = 0; j < nJ; ++j) {
+            const int q = kk * nJ + j;
+            const int i = assign[q];
+            const int m = i * nJ + j;
+            c->inst_k[q] = kk;
+            c->inst_m[q] = m;
+            const int S_m = c->hm.state_base[m + 1] - c->hm.state_base[m];
+            c->inst_base[q + 1] = c->inst_base[q] + S_m;
+            for (int b = 0; b < S_m; b += 256) {
+                tiles.push_back(q);
+                tiles.push_back(b);
+            }
+            iwc[q] = c->W[(size_t)kk * d + i];
+            iwp[q] = c->W[(size_t)kk * d + nI + j];
+            if (c->hm.init[m] >= 0) init_idx[q] = c->inst_base[q] + (c->hm.init[m] - c->hm.state_base[m]);
+        }
+    const int64_t NS = c->inst_base[n];
+    const int n_tiles = (int)(tiles.size() / 2);
+    c->d_inst_model.ensure((size_t)n * 4);
+    c->d_inst_k.ensure((size_t)n * 4);
+    c->d_inst_base.ensure((size_t)(n + 1) * 8);
+    c->d_inst_tiles.ensure(tiles.size() * 4 + 8);
+    c->d_iwc.ensure((size_t)n * 8);
+    c->d_iwp.ensure((size_t)n * 8);
+    c->d_xi[0].ensure((size_t)NS * 8 + 8);
+    c->d_xi[1].ensure((size_t)NS * 8 + 8);
+    c->d_ires.ensure((size_t)2 * n * 8);
+    c->d_iactive.ensure((size_t)2 * n);
+    c->d_ipar.ensure((size_t)2 * n);
+    c->d_mask.ensure((size_t)NS * 4 + 4);
+    c->d_rank.ensure((size_t)NS * 4 + 4);
+    c->d_mu.ensure((size_t)NS + 4);
+    c->d_xe[0].ensure((size_t)NS * 16 + 16);
+    c->d_xe[1].ensure((size_t)NS * 16 + 16);
+    c->d_init_idx.ensure((size_t)n * 8);
+    c->d_init_val.ensure((size_t)2 * n * 8);
+    MORAP_HIP(hipMemcpyAsync(c->d_inst_model.p, c->inst_m.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+    MORAP_HIP(hipMemcpyAsync(c->d_inst_k.p, c->inst_k.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+    MORAP_HIP(hipMemcpyAsync(c->d_inst_base.p, c->inst_base.data(), (size_t)(n + 1) * 8, hipMemcpyHostToDevice, s));
+    if (!tiles.empty())
+        MORAP_HIP(hipMemcpyAsync(c->d_inst_tiles.p, tiles.data(), tiles.size() * 4, hipMemcpyHostToDevice, s));
+    MORAP_HIP(hipMemcpyAsync(c->d_iwc.p, iwc.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+    MORAP_HIP(hipMemcpyAsync(c->d_iwp.p, iwp.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+    MORAP_HIP(hipMemcpyAsync(c->d_init_idx.p, init_idx.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+    const k::InstArgs a = inst_args(c, n_tiles, n);
+    int64_t* dctr = c->d_counters.as<int64_t>();
+    int64_t* h = c->h_counters.as<int64_t>();
+    double* xi0 = c->d_xi[0].as<double>();
+    double* xi1 = c->d_xi[1].as<double>();
+    unsigned long long* ires = c->d_ires.as<unsigned long long>();
+    uint8_t* iact = c->d_iactive.as<uint8_t>();
+    uint8_t* ipar = c->d_ipar.as<uint8_t>();
+    const int chunk = std::max(2, (o.check_every + 1) / 2 * 2);
+
+    hipEvent_t e0, e1;
+    MORAP_HIP(hipEventCreate(&e0));
+    MORAP_HIP(hipEventCreate(&e1));
+    MORAP_HIP(hipEventRecord(e0, s));
+
+    // final values of each instance's column
+    k::gather_columns(s, a, c->prec, c->d_x[0].p, c->d_x[1].p, c->d_final_par.as<uint8_t>(), c->Kp, xi0);
+
+    auto cleanup = [&] {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    };
+
+    // FP64 polish of FP32 solves: value iteration of each instance from its
+    // FP32 values until the FP64 residual is <= eps_vi
+    if (c->prec == MORAP_F32) {
+        k::set_active(s, n, a, iact, ires, ipar, 1);
+        int64_t done_sweeps = 0;
+        while (true) {
+            for (int i = 0; i < chunk; ++i) {
+                const bool even = (i & 1) == 0;
+                k::polish_sweep(s, a, c->d_iwc.as<double>(), c->d_iwp.as<double>(), iact, even ? xi0 : xi1,
+                                even ? xi1 : xi0, ires);
+                k::fill_i64(s, dctr, 0, 1);
+                k::inst_converge(s, n, ires, iact, ipar, even ? 1 : 0, o.eps_vi, dctr);
+            }
+            done_sweeps += chunk;
+            read_counters(c);
+            if (h[0] == 0) break;
+            if (done_sweeps >= o.max_sweeps) {
+                cleanup();
+                fail(MORAP_E_NOT_CONVERGED, "FP64 polish did not converge");
+            }
+        }
+        st.polish_sweeps += done_sweeps;
+        k::select_final(s, a, xi0, xi1, ipar, 1);
+    }
+
+    // policy extraction: tau-optimal masks, then attractor rounds
+    uint32_t* mask = c->d_mask.as<uint32_t>();
+    int32_t* rank = c->d_rank.as<int32_t>();
+    int8_t* mu = c->d_mu.as<int8_t>();
+    k::opt_mask(s, a, c->d_iwc.as<double>(), c->d_iwp.as<double>(), xi0, o.tau, mask, rank, mu);
+    int level = 0;
+    while (true) {
+        k::fill_i64(s, dctr, 0, 1);
+        for (int i = 0; i < chunk; ++i) k::rank_round(s, a, mask, rank, mu, ++level, dctr);
+        read_counters(c);
+        if (h[0] == 0) break;
+    }
+    st.rank_rounds += level;
+    k::fill_i64(s, dctr, 0, 1);
+    k::count_unranked(s, a, rank, dctr);
+    read_counters(c);
+    if (h[0] != 0) {
+        cleanup();
+        fail(MORAP_E_IMPROPER, std::to_string(h[0]) + " states cannot reach done through tau-optimal actions");
+    }
+
+    // Alg. 4 per objective
+    double* xe0 = c->d_xe[0].as<double>();
+    double* xe1 = c->d_xe[1].as<double>();
+    k::fill_f64(s, xe0, 0.0, 2 * NS);
+    k::fill_f64(s, xe1, 0.0, 2 * NS);
+    k::set_active(s, n, a, iact, ires, ipar, 2);
+    int64_t esweeps = 0;
+    while (true) {
+        for (int i = 0; i < chunk; ++i) {
+            const bool even = (i & 1) == 0;
+            k::eval_sweep(s, a, mu, iact, even ? xe0 : xe1, even ? xe1 : xe0, ires);
+            k::fill_i64(s, dctr, 0, 1);
+            k::inst_converge(s, 2 * n, ires, iact, ipar, even ? 1 : 0, o.eps_eval, dctr);
+        }
+        esweeps += chunk;
+        read_counters(c);
+        if (h[0] == 0) break;
+        if (esweeps >= o.max_sweeps) {
+            cleanup();
+            fail(MORAP_E_NOT_CONVERGED, "policy evaluation did not converge");
+        }
+    }
+    st.eval_sweeps += esweeps;
+    k::select_final(s, a, xe0, xe1, ipar, 2);
+    double* ival = c->d_init_val.as<double>();
+    k::gather_init(s, n, c->d_init_idx.as<int64_t>(), xe0, ival);
+    std::vector<double> vals((size_t)2 * n);
+    MORAP_HIP(hipMemcpyAsync(vals.data(), ival, vals.size() * 8, hipMemcpyDeviceToHost, s));
+    MORAP_HIP(hipEventRecord(e1, s));
+    MORAP_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    MORAP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    cleanup();
+
+    if (r_out) {
+        std::fill(r_out, r_out + (size_t)K * d, 0.0);
+        for (int kk = 0; kk < K; ++kk)
+            for (int j = 0; j < nJ; ++j) {
+                const int q = kk * nJ + j;
+                r_out[(size_t)kk * d + nI + j] = vals[2 * q + 1];
+                r_out[(size_t)kk * d + assign[q]] += vals[2 * q];
+            }
+    }
+    c->eK = K;
+    c->evaluated = true;
+    st.ms_eval += ms;
+    st.ms_total += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace morap

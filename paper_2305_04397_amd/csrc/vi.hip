@@ -1,0 +1,771 @@
+// Value-iteration kernels for gfx950 (wave64).
+//
+//  * bellman_sweep: one Jacobi sweep of scalarised max-backups (Alg. 3, the
+//    maximisation over enabled actions of (w . rho)(s,q,a) + sum P x) for every
+//    active (model, column) pair.  Values are stored [state][Kp] so that the
+//    successor gather of one state for a run of columns is one contiguous,
+//    coalesced line.  A workgroup streams one tile of consecutive states of a
+//    model: the tile's rows and entries are staged in LDS with coalesced loads,
+//    then each group of `LPS` lanes walks one state's entries from LDS and
+//    issues its successor gathers in batches of 8 so several are in flight.
+//    The grid is persistent over a compacted list of the tiles of models that
+//    still have active columns; each XCD walks its own contiguous eighth of
+//    that list so neighbouring tiles share its L2.  Per-(model, column)
+//    residual max |y - x| and max |y| are reduced in FP64 (wave shuffles, then
+//    LDS, then one atomic per column per tile).
+//  * converge / compact: freeze pairs whose residual is within tolerance
+//    (the stop test of Alg. 3), record their value at the initial state and
+//    rebuild the active tile list.
+//  * instance kernels: FP64 polish sweeps, eps-optimal action masks,
+//    attractor ranking rounds and fixed-policy evaluation sweeps (Alg. 4) on
+//    (column, model) instances, one thread per state.
+#include "common.h"
+
+#include <cfloat>
+
+namespace morap {
+namespace k {
+
+// LDS staging limits of one tile (host tiles respect them)
+constexpr int TILE_STATES = 64;
+constexpr int TILE_ROWS = 384;
+constexpr int TILE_NNZ = 1024;
+
+int sweep_lds_rows() { return TILE_ROWS; }
+int sweep_lds_nnz() { return TILE_NNZ; }
+int sweep_tile_states(const Variant&) { return TILE_STATES; }
+
+// ---------------------------------------------------------------------------
+// small fills
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void fill_kernel(T* p, T v, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+template <class T>
+static void fill(hipStream_t s, T* p, T v, int64_t n) {
+    if (n <= 0) return;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(fill_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, p, v, n);
+    MORAP_HIP(hipGetLastError());
+}
+void fill_u8(hipStream_t s, uint8_t* p, uint8_t v, int64_t n) { fill(s, p, v, n); }
+void fill_i32(hipStream_t s, int32_t* p, int32_t v, int64_t n) { fill(s, p, v, n); }
+void fill_u64(hipStream_t s, uint64_t* p, uint64_t v, int64_t n) { fill(s, p, v, n); }
+void fill_f32(hipStream_t s, float* p, float v, int64_t n) { fill(s, p, v, n); }
+void fill_f64(hipStream_t s, double* p, double v, int64_t n) { fill(s, p, v, n); }
+void fill_i64(hipStream_t s, int64_t* p, int64_t v, int64_t n) { fill(s, p, v, n); }
+
+__global__ void to_f32_kernel(const double* in, float* out, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) out[i] = (float)in[i];
+}
+void to_f32(hipStream_t s, const double* in, float* out, int64_t n) {
+    if (n <= 0) return;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, in, out, n);
+    MORAP_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// vector helpers: CPL consecutive columns per lane
+// ---------------------------------------------------------------------------
+template <class T, int CPL> struct Vec { T v[CPL]; };
+
+template <class T, int CPL>
+__device__ __forceinline__ Vec<T, CPL> vload(const T* p) {
+    Vec<T, CPL> r;
+    if constexpr (CPL == 4 && sizeof(T) == 4) {
+        float4 q = *reinterpret_cast<const float4*>(p);
+        r.v[0] = q.x; r.v[1] = q.y; r.v[2] = q.z; r.v[3] = q.w;
+    } else if constexpr (CPL == 2 && sizeof(T) == 4) {
+        float2 q = *reinterpret_cast<const float2*>(p);
+        r.v[0] = q.x; r.v[1] = q.y;
+    } else if constexpr (CPL >= 2 && sizeof(T) == 8) {
+#pragma unroll
+        for (int c = 0; c < CPL; c += 2) {
+            double2 q = *reinterpret_cast<const double2*>(p + c);
+            r.v[c] = q.x; r.v[c + 1] = q.y;
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) r.v[c] = p[c];
+    }
+    return r;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// reduce across lanes that hold the same columns: lane bits >= log2(LPS)
+template <int LPS>
+__device__ __forceinline__ double group_max(double v) {
+#pragma unroll
+    for (int o = 32; o >= LPS; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// batched Bellman sweep
+// ---------------------------------------------------------------------------
+template <class T, class T2, int CPL, int LPS, int WG>
+__global__ void __launch_bounds__(WG)
+bellman_sweep(const Tile* __restrict__ tiles, const int32_t* __restrict__ tile_base,
+              const int32_t* __restrict__ act_models, const int32_t* __restrict__ act_prefix,
+              const int64_t* __restrict__ counters,
+              const int32_t* __restrict__ state_row, const int32_t* __restrict__ row_ptr,
+              const int32_t* __restrict__ col, const T* __restrict__ prob, const T2* __restrict__ rew,
+              const T* __restrict__ wc_all, const T* __restrict__ wp_all,
+              const uint8_t* __restrict__ active_all,
+              const T* __restrict__ x_in, T* __restrict__ x_out,
+              unsigned long long* __restrict__ res_all, unsigned long long* __restrict__ ymax_all,
+              int Kp) {
+    constexpr int KT = CPL * LPS;          // columns per k-tile
+    constexpr int G = WG / LPS;            // states processed at once
+    constexpr int NW = WG / 64;            // waves
+    __shared__ int32_t l_srow[TILE_STATES + 1];
+    __shared__ int32_t l_rptr[TILE_ROWS + 1];
+    __shared__ T2 l_rew[TILE_ROWS];
+    __shared__ int32_t l_col[TILE_NNZ];
+    __shared__ T l_prob[TILE_NNZ];
+    __shared__ uint16_t l_erow[TILE_NNZ];
+    __shared__ double l_red[2][NW][KT];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int grp = tid / LPS;             // state slot within a pass
+    const int gl = tid % LPS;              // lane within the group
+    const int kc = blockIdx.y * KT + gl * CPL;   // first column of this lane
+
+    const int n_tiles = (int)counters[1];
+    const int G8 = gridDim.x >> 3;
+    const int xcd = blockIdx.x & 7;
+    const int slot = blockIdx.x >> 3;
+    const int chunk = (n_tiles + 7) >> 3;
+    const int t_begin = xcd * chunk;
+    const int t_end = min(n_tiles, t_begin + chunk);
+    const int n_act = (int)counters[2];
+
+    for (int t = t_begin + slot; t < t_end; t += G8) {
+        // locate the tile: active model a with act_prefix[a] <= t < act_prefix[a+1]
+        int lo = 0, hi = n_act;
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (act_prefix[mid] <= t) lo = mid; else hi = mid;
+        }
+        const int m = act_models[lo];
+        const Tile tl = tiles[tile_base[m] + (t - act_prefix[lo])];
+        const int s0 = tl.s_begin, s1 = tl.s_end, ns = s1 - s0;
+        const int r0 = state_row[s0], r1 = state_row[s1];
+        const int e0 = row_ptr[r0], e1 = row_ptr[r1];
+        const int nr = r1 - r0, ne = e1 - e0;
+
+        // stage the tile in LDS (coalesced)
+        for (int i = tid; i <= ns; i += WG) l_srow[i] = state_row[s0 + i] - r0;
+        for (int i = tid; i <= nr; i += WG) l_rptr[i] = row_ptr[r0 + i] - e0;
+        for (int i = tid; i < nr; i += WG) l_rew[i] = rew[r0 + i];
+        for (int i = tid; i < ne; i += WG) {
+            l_col[i] = col[e0 + i];
+            l_prob[i] = prob[e0 + i];
+        }
+        __syncthreads();
+        for (int r = tid; r < nr; r += WG)
+            for (int e = l_rptr[r]; e < l_rptr[r + 1]; ++e) l_erow[e] = (uint16_t)r;
+
+        // this lane's columns
+        T wc[CPL], wp[CPL];
+        bool act[CPL];
+        bool any = false;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const int k = kc + c;
+            wc[c] = wc_all[(int64_t)m * Kp + k];
+            wp[c] = wp_all[(int64_t)m * Kp + k];
+            act[c] = active_all[(int64_t)m * Kp + k] != 0;
+            any |= act[c];
+        }
+        __syncthreads();
+
+        double res[CPL], ym[CPL];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) { res[c] = 0.0; ym[c] = 0.0; }
+
+        if (any) {
+            for (int ls = grp; ls < ns; ls += G) {
+                const int lr0 = l_srow[ls], lr1 = l_srow[ls + 1];
+                T best[CPL];
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) best[c] = -INFINITY;
+                // rows without live successors
+                for (int r = lr0; r < lr1; ++r) {
+                    if (l_rptr[r] == l_rptr[r + 1]) {
+                        const T2 rw = l_rew[r];
+#pragma unroll
+                        for (int c = 0; c < CPL; ++c) best[c] = fmax(best[c], wc[c] * rw.x + wp[c] * rw.y);
+                    }
+                }
+                const int le0 = l_rptr[lr0], le1 = l_rptr[lr1];
+                int cur = -1;
+                T acc[CPL];
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) acc[c] = 0;
+                for (int base = le0; base < le1; base += 8) {
+                    const int n = min(8, le1 - base);
+                    int jj[8];
+                    T pp[8];
+                    int rr[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        if (u < n) {
+                            jj[u] = l_col[base + u];
+                            pp[u] = l_prob[base + u];
+                            rr[u] = l_erow[base + u];
+                        }
+                    }
+                    Vec<T, CPL> xv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (u < n) xv[u] = vload<T, CPL>(x_in + (int64_t)jj[u] * Kp + kc);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        if (u < n) {
+                            if (rr[u] != cur) {
+                                if (cur >= 0) {
+#pragma unroll
+                                    for (int c = 0; c < CPL; ++c) best[c] = fmax(best[c], acc[c]);
+                                }
+                                cur = rr[u];
+                                const T2 rw = l_rew[cur];
+#pragma unroll
+                                for (int c = 0; c < CPL; ++c) acc[c] = wc[c] * rw.x + wp[c] * rw.y;
+                            }
+#pragma unroll
+                            for (int c = 0; c < CPL; ++c) acc[c] = fma(pp[u], xv[u].v[c], acc[c]);
+                        }
+                    }
+                }
+                if (cur >= 0) {
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) best[c] = fmax(best[c], acc[c]);
+                }
+                const int64_t gs = s0 + ls;
+                const Vec<T, CPL> old = vload<T, CPL>(x_in + gs * Kp + kc);
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    if (act[c]) {
+                        x_out[gs * Kp + kc + c] = best[c];
+                        res[c] = fmax(res[c], fabs((double)best[c] - (double)old.v[c]));
+                        ym[c] = fmax(ym[c], fabs((double)best[c]));
+                    }
+                }
+            }
+        }
+
+        // reduce over the groups holding the same columns, one atomic per column
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            res[c] = group_max<LPS>(res[c]);
+            ym[c] = group_max<LPS>(ym[c]);
+        }
+        if (lane < LPS) {
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                l_red[0][wave][gl * CPL + c] = res[c];
+                l_red[1][wave][gl * CPL + c] = ym[c];
+            }
+        }
+        __syncthreads();
+        if (tid < KT) {
+            double r = 0.0, y = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                r = fmax(r, l_red[0][w][tid]);
+                y = fmax(y, l_red[1][w][tid]);
+            }
+            const int64_t idx = (int64_t)m * Kp + blockIdx.y * KT + tid;
+            if (r > 0.0) atomicMax(&res_all[idx], (unsigned long long)__double_as_longlong(r));
+            if (y > 0.0) atomicMax(&ymax_all[idx], (unsigned long long)__double_as_longlong(y));
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// sweep dispatch: variant id -> template instance
+// ---------------------------------------------------------------------------
+template <class T, class T2, int CPL, int LPS>
+static void launch_sweep(hipStream_t s, int grid, int ktiles, const SweepArgs& a) {
+    constexpr int WG = (64 * LPS < 256) ? 64 * LPS : 256;
+    hipLaunchKernelGGL((bellman_sweep<T, T2, CPL, LPS, WG>), dim3(grid, ktiles), dim3(WG), 0, s,
+                       a.tiles, a.tile_base, a.act_models, a.act_prefix, a.counters, a.state_row,
+                       a.row_ptr, a.col, (const T*)a.prob, (const T2*)a.rew, (const T*)a.wc,
+                       (const T*)a.wp, a.active, (const T*)a.x_in, (T*)a.x_out, a.res, a.ymax, a.Kp);
+}
+
+template <class T, class T2>
+static void sweep_t(hipStream_t s, const Variant& v, int grid, int ktiles, const SweepArgs& a) {
+#define MORAP_V(C, L) \
+    if (v.cpl == C && v.lps == L) { launch_sweep<T, T2, C, L>(s, grid, ktiles, a); return; }
+    MORAP_V(1, 1) MORAP_V(1, 2) MORAP_V(2, 1) MORAP_V(1, 4) MORAP_V(2, 2) MORAP_V(4, 1)
+    MORAP_V(1, 8) MORAP_V(2, 4) MORAP_V(4, 2) MORAP_V(1, 16) MORAP_V(2, 8) MORAP_V(4, 4)
+    MORAP_V(1, 32) MORAP_V(2, 16) MORAP_V(4, 8) MORAP_V(1, 64) MORAP_V(2, 32) MORAP_V(4, 16)
+#undef MORAP_V
+    fail(MORAP_E_UNSUPPORTED, "no sweep kernel for this variant");
+}
+
+void sweep(hipStream_t s, int prec, const Variant& v, int grid, int ktiles, const SweepArgs& a) {
+    if (prec == MORAP_F32) sweep_t<float, float2>(s, v, grid, ktiles, a);
+    else sweep_t<double, double2>(s, v, grid, ktiles, a);
+    MORAP_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// convergence of (model, column) pairs and compaction of the active tiles
+// ---------------------------------------------------------------------------
+// One thread per (model, column).  counters: [0] active pairs (accumulating),
+// [1] active tiles, [2] active models, [3] active pairs after the last sweep,
+// [4] backups done, [5] sweeps done, [6] CSR bytes streamed, [7] state-columns
+// updated (each one value read and one written).
+template <class T>
+__global__ void converge_kernel(ConvergeArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = (int64_t)a.M * a.Kp;
+    bool still = false;
+    int m = 0;
+    if (i < n) {
+        m = (int)(i / a.Kp);
+        const int k = (int)(i % a.Kp);
+        if (a.active[i]) {
+            const double r = __longlong_as_double((long long)a.res[i]);
+            const double y = __longlong_as_double((long long)a.ymax[i]);
+            const double tol = fmax(a.eps, a.unit * y);
+            if (r <= tol) {
+                a.active[i] = 0;
+                a.final_par[i] = (uint8_t)a.out_par;
+                a.pair_sweeps[i] = (int32_t)(a.counters[5] + 1);
+                const int32_t s0 = a.init[m];
+                a.c[(int64_t)k * a.M + m] =
+                    s0 >= 0 ? (double)((const T*)a.x_out)[(int64_t)s0 * a.Kp + k] : 0.0;
+            } else {
+                still = true;
+                a.model_active[m] = 1;
+            }
+            a.res[i] = 0ull;
+            a.ymax[i] = 0ull;
+        }
+    }
+    // backups of this sweep: rows of the model for every pair that was active
+    const bool was = (i < n) && (still || a.pair_sweeps[i] == (int32_t)(a.counters[5] + 1));
+    unsigned long long bk = was ? (unsigned long long)a.rows_per_model[m] : 0ull;
+    unsigned long long sc = was ? (unsigned long long)a.states_per_model[m] : 0ull;
+    unsigned long long cnt = still ? 1ull : 0ull;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        bk += __shfl_xor(bk, o, 64);
+        sc += __shfl_xor(sc, o, 64);
+        cnt += __shfl_xor(cnt, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (cnt) atomicAdd((unsigned long long*)&a.counters[0], cnt);
+        if (bk) atomicAdd((unsigned long long*)&a.counters[4], bk);
+        if (sc) atomicAdd((unsigned long long*)&a.counters[7], sc);
+    }
+}
+
+void converge(hipStream_t s, const ConvergeArgs& a) {
+    const int64_t n = (int64_t)a.M * a.Kp;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    if (a.prec == MORAP_F32)
+        hipLaunchKernelGGL(converge_kernel<float>, dim3(blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(converge_kernel<double>, dim3(blocks), dim3(256), 0, s, a);
+    MORAP_HIP(hipGetLastError());
+}
+
+// Single workgroup: ordered list of active models with the exclusive prefix of
+// their tile counts; publishes the pair count and advances the sweep counter.
+__global__ void __launch_bounds__(1024) compact_kernel(ConvergeArgs a) {
+    __shared__ int32_t part[1024];
+    __shared__ int32_t partm[1024];
+    const int tid = threadIdx.x;
+    const int per = (a.M + 1023) / 1024;
+    const int b = tid * per, e = min(a.M, b + per);
+    int sum = 0, cnt = 0;
+    unsigned long long bytes = 0;
+    for (int m = b; m < e; ++m)
+        if (a.model_active[m]) {
+            sum += a.tile_base[m + 1] - a.tile_base[m];
+            ++cnt;
+            bytes += (unsigned long long)a.csr_bytes[m];
+        }
+    part[tid] = sum;
+    partm[tid] = cnt;
+    if (bytes) atomicAdd((unsigned long long*)&a.counters[6], bytes);
+    __syncthreads();
+    // inclusive scan (Hillis-Steele)
+    for (int o = 1; o < 1024; o <<= 1) {
+        int v = tid >= o ? part[tid - o] : 0;
+        int w = tid >= o ? partm[tid - o] : 0;
+        __syncthreads();
+        part[tid] += v;
+        partm[tid] += w;
+        __syncthreads();
+    }
+    int off = tid ? part[tid - 1] : 0;
+    int offm = tid ? partm[tid - 1] : 0;
+    for (int m = b; m < e; ++m) {
+        if (a.model_active[m]) {
+            a.act_models[offm] = m;
+            a.act_prefix[offm] = off;
+            off += a.tile_base[m + 1] - a.tile_base[m];
+            ++offm;
+        }
+        a.model_active[m] = 0;
+    }
+    if (tid == 1023) {
+        a.act_prefix[offm] = off;
+        a.counters[1] = off;
+        a.counters[2] = offm;
+        a.counters[3] = a.counters[0];
+        a.counters[0] = 0;
+        a.counters[5] += 1;
+    }
+}
+
+void compact(hipStream_t s, const ConvergeArgs& a) {
+    hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(1024), 0, s, a);
+    MORAP_HIP(hipGetLastError());
+}
+
+// start of a solve: columns k < K of models with a live initial state are
+// active; everything else is cleared.
+__global__ void init_solve_kernel(ConvergeArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = (int64_t)a.M * a.Kp;
+    if (i < n) {
+        const int m = (int)(i / a.Kp);
+        const int k = (int)(i % a.Kp);
+        const bool on = k < a.K && a.init[m] >= 0;
+        a.active[i] = on ? 1 : 0;
+        a.final_par[i] = 0;
+        a.pair_sweeps[i] = 0;
+        a.res[i] = 0ull;
+        a.ymax[i] = 0ull;
+        if (on) a.model_active[m] = 1;
+        if (k < a.K) a.c[(int64_t)k * a.M + m] = 0.0;
+    }
+    // the compaction that follows counts as no sweep: start the counter at -1
+    if (i < 8) a.counters[i] = (i == 5) ? -1 : 0;
+}
+
+void init_solve(hipStream_t s, const ConvergeArgs& a) {
+    const int64_t n = (int64_t)a.M * a.Kp;
+    fill_u8(s, a.model_active, 0, a.M);
+    hipLaunchKernelGGL(init_solve_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+    MORAP_HIP(hipGetLastError());
+    hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(1024), 0, s, a);
+    MORAP_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// instances: (column, model) pairs, one thread per state
+// ---------------------------------------------------------------------------
+struct InstLoc {
+    int inst, m, ls, S;
+    int64_t is;      // instance state index
+    int32_t gs;      // global state
+    int32_t sb;      // model's first global state
+};
+
+__device__ __forceinline__ bool inst_locate(const InstArgs& a, InstLoc& L) {
+    const int t = blockIdx.x;
+    if (t >= a.n_tiles) return false;
+    L.inst = a.inst_tiles[2 * t];
+    L.ls = a.inst_tiles[2 * t + 1] + threadIdx.x;
+    L.m = a.inst_model[L.inst];
+    L.sb = a.state_base[L.m];
+    L.S = a.state_base[L.m + 1] - L.sb;
+    if (L.ls >= L.S) return false;
+    L.is = a.inst_base[L.inst] + L.ls;
+    L.gs = L.sb + L.ls;
+    return true;
+}
+
+template <class T>
+__global__ void gather_kernel(InstArgs a, const T* x0, const T* x1, const uint8_t* par, int Kp,
+                              double* xi) {
+    InstLoc L;
+    if (!inst_locate(a, L)) return;
+    const int k = a.inst_k[L.inst];
+    const T* x = par[(int64_t)L.m * Kp + k] ? x1 : x0;
+    xi[L.is] = (double)x[(int64_t)L.gs * Kp + k];
+}
+
+void gather_columns(hipStream_t s, const InstArgs& a, int prec, const void* x0, const void* x1,
+                    const uint8_t* final_par, int Kp, double* xi) {
+    if (a.n_tiles <= 0) return;
+    if (prec == MORAP_F32)
+        hipLaunchKernelGGL(gather_kernel<float>, dim3(a.n_tiles), dim3(256), 0, s, a, (const float*)x0,
+                           (const float*)x1, final_par, Kp, xi);
+    else
+        hipLaunchKernelGGL(gather_kernel<double>, dim3(a.n_tiles), dim3(256), 0, s, a, (const double*)x0,
+                           (const double*)x1, final_par, Kp, xi);
+    MORAP_HIP(hipGetLastError());
+}
+
+// FP64 scalarised max-backup on one column of one model
+__global__ void __launch_bounds__(256) polish_kernel(InstArgs a, const double* wc, const double* wp,
+                                                     const uint8_t* active, const double* x_in,
+                                                     double* x_out, unsigned long long* res) {
+    InstLoc L;
+    const bool ok = inst_locate(a, L);
+    double r = 0.0;
+    int inst = ok ? L.inst : -1;
+    if (ok && active[L.inst]) {
+        const int64_t ib = a.inst_base[L.inst];
+        const double w0 = wc[L.inst], w1 = wp[L.inst];
+        double best = -INFINITY;
+        for (int row = a.state_row[L.gs]; row < a.state_row[L.gs + 1]; ++row) {
+            double acc = w0 * a.rew[2 * row] + w1 * a.rew[2 * row + 1];
+            for (int e = a.row_ptr[row]; e < a.row_ptr[row + 1]; ++e)
+                acc = fma(a.prob[e], x_in[ib + (a.col[e] - L.sb)], acc);
+            best = fmax(best, acc);
+        }
+        x_out[L.is] = best;
+        r = fabs(best - x_in[L.is]);
+    }
+    r = wave_max(r);
+    // a tile holds states of one instance, so a wave does too
+    if ((threadIdx.x & 63) == 0 && r > 0.0) {
+        const int i0 = a.inst_tiles[2 * blockIdx.x];
+        atomicMax(&res[i0], (unsigned long long)__double_as_longlong(r));
+    }
+    (void)inst;
+}
+
+void polish_sweep(hipStream_t s, const InstArgs& a, const double* wc, const double* wp,
+                  const uint8_t* active, const double* x_in, double* x_out, unsigned long long* res) {
+    if (a.n_tiles <= 0) return;
+    hipLaunchKernelGGL(polish_kernel, dim3(a.n_tiles), dim3(256), 0, s, a, wc, wp, active, x_in, x_out,
+                       res);
+    MORAP_HIP(hipGetLastError());
+}
+
+__global__ void inst_converge_kernel(int n, unsigned long long* res, uint8_t* active, uint8_t* par,
+                                     int out_par, double eps, int64_t* counter) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long still = 0;
+    if (i < n && active[i]) {
+        const double r = __longlong_as_double((long long)res[i]);
+        if (r <= eps) {
+            active[i] = 0;
+            par[i] = (uint8_t)out_par;
+        } else {
+            still = 1;
+        }
+        res[i] = 0ull;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) still += __shfl_xor(still, o, 64);
+    if ((threadIdx.x & 63) == 0 && still) atomicAdd((unsigned long long*)counter, still);
+}
+
+void inst_converge(hipStream_t s, int n, unsigned long long* res, uint8_t* active, uint8_t* par,
+                   int out_par, double eps, int64_t* counter) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(inst_converge_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, res, active, par,
+                       out_par, eps, counter);
+    MORAP_HIP(hipGetLastError());
+}
+
+// eps-optimal rows of every state: bit r of mask = row r (local) has
+// Q(s, r) >= max_a Q(s, a) - tau, with Q in FP64 at the final values.
+__global__ void __launch_bounds__(256) opt_mask_kernel(InstArgs a, const double* wc, const double* wp,
+                                                       const double* x, double tau, uint32_t* mask,
+                                                       int32_t* rank, int8_t* mu) {
+    InstLoc L;
+    if (!inst_locate(a, L)) return;
+    const int64_t ib = a.inst_base[L.inst];
+    const double w0 = wc[L.inst], w1 = wp[L.inst];
+    const int rb = a.state_row[L.gs], re = a.state_row[L.gs + 1];
+    // two passes (max, then the tolerance test) keep Q out of scratch memory
+    double qmax = -INFINITY;
+    for (int row = rb; row < re; ++row) {
+        double acc = w0 * a.rew[2 * row] + w1 * a.rew[2 * row + 1];
+        for (int e = a.row_ptr[row]; e < a.row_ptr[row + 1]; ++e)
+            acc = fma(a.prob[e], x[ib + (a.col[e] - L.sb)], acc);
+        qmax = fmax(qmax, acc);
+    }
+    uint32_t bits = 0;
+    for (int row = rb; row < re; ++row) {
+        double acc = w0 * a.rew[2 * row] + w1 * a.rew[2 * row + 1];
+        for (int e = a.row_ptr[row]; e < a.row_ptr[row + 1]; ++e)
+            acc = fma(a.prob[e], x[ib + (a.col[e] - L.sb)], acc);
+        if (acc >= qmax - tau) bits |= 1u << (row - rb);
+    }
+    mask[L.is] = bits;
+    rank[L.is] = -1;
+    mu[L.is] = -1;
+}
+
+void opt_mask(hipStream_t s, const InstArgs& a, const double* wc, const double* wp, const double* x,
+              double tau, uint32_t* mask, int32_t* rank, int8_t* mu) {
+    if (a.n_tiles <= 0) return;
+    hipLaunchKernelGGL(opt_mask_kernel, dim3(a.n_tiles), dim3(256), 0, s, a, wc, wp, x, tau, mask, rank, mu);
+    MORAP_HIP(hipGetLastError());
+}
+
+// Attractor round `level`: an unranked state is ranked when one of its
+// eps-optimal rows moves mass into done or into a state ranked in an earlier
+// round; its action is the lowest such row.
+__global__ void __launch_bounds__(256) rank_kernel(InstArgs a, const uint32_t* mask, int32_t* rank,
+                                                   int8_t* mu, int level, int64_t* counter) {
+    InstLoc L;
+    unsigned long long got = 0;
+    if (inst_locate(a, L) && rank[L.is] < 0) {
+        const int64_t ib = a.inst_base[L.inst];
+        const int rb = a.state_row[L.gs];
+        uint32_t bits = mask[L.is];
+        while (bits) {
+            const int lr = __builtin_ctz(bits);
+            bits &= bits - 1;
+            const int row = rb + lr;
+            bool hit = a.to_done[row] != 0;
+            for (int e = a.row_ptr[row]; !hit && e < a.row_ptr[row + 1]; ++e) {
+                const int32_t rk = rank[ib + (a.col[e] - L.sb)];
+                hit = rk >= 0 && rk < level;
+            }
+            if (hit) {
+                rank[L.is] = level;
+                mu[L.is] = (int8_t)lr;
+                got = 1;
+                break;
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) got += __shfl_xor(got, o, 64);
+    if ((threadIdx.x & 63) == 0 && got) atomicAdd((unsigned long long*)counter, got);
+}
+
+void rank_round(hipStream_t s, const InstArgs& a, const uint32_t* mask, int32_t* rank, int8_t* mu,
+                int level, int64_t* counter) {
+    if (a.n_tiles <= 0) return;
+    hipLaunchKernelGGL(rank_kernel, dim3(a.n_tiles), dim3(256), 0, s, a, mask, rank, mu, level, counter);
+    MORAP_HIP(hipGetLastError());
+}
+
+__global__ void count_unranked_kernel(InstArgs a, const int32_t* rank, int64_t* counter) {
+    InstLoc L;
+    unsigned long long bad = 0;
+    if (inst_locate(a, L) && rank[L.is] < 0) bad = 1;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) bad += __shfl_xor(bad, o, 64);
+    if ((threadIdx.x & 63) == 0 && bad) atomicAdd((unsigned long long*)counter, bad);
+}
+
+void count_unranked(hipStream_t s, const InstArgs& a, const int32_t* rank, int64_t* counter) {
+    if (a.n_tiles <= 0) return;
+    hipLaunchKernelGGL(count_unranked_kernel, dim3(a.n_tiles), dim3(256), 0, s, a, rank, counter);
+    MORAP_HIP(hipGetLastError());
+}
+
+// Alg. 4: fixed-policy Jacobi sweep for both objectives (cost, probability);
+// x is [instance state][2]; active / res are per (instance, objective).
+__global__ void __launch_bounds__(256) eval_kernel(InstArgs a, const int8_t* mu, const uint8_t* active,
+                                                   const double* x_in, double* x_out,
+                                                   unsigned long long* res) {
+    InstLoc L;
+    const bool ok = inst_locate(a, L);
+    double r0 = 0.0, r1 = 0.0;
+    if (ok) {
+        const bool a0 = active[2 * L.inst] != 0, a1 = active[2 * L.inst + 1] != 0;
+        if (a0 || a1) {
+            const int64_t ib = a.inst_base[L.inst];
+            const int row = a.state_row[L.gs] + mu[L.is];
+            double c0 = a.rew[2 * row], c1 = a.rew[2 * row + 1];
+            for (int e = a.row_ptr[row]; e < a.row_ptr[row + 1]; ++e) {
+                const int64_t j = ib + (a.col[e] - L.sb);
+                const double2 v = reinterpret_cast<const double2*>(x_in)[j];
+                c0 = fma(a.prob[e], v.x, c0);
+                c1 = fma(a.prob[e], v.y, c1);
+            }
+            const double2 old = reinterpret_cast<const double2*>(x_in)[L.is];
+            if (a0) { x_out[2 * L.is] = c0; r0 = fabs(c0 - old.x); }
+            if (a1) { x_out[2 * L.is + 1] = c1; r1 = fabs(c1 - old.y); }
+        }
+    }
+    r0 = wave_max(r0);
+    r1 = wave_max(r1);
+    if ((threadIdx.x & 63) == 0) {
+        const int i0 = a.inst_tiles[2 * blockIdx.x];
+        if (r0 > 0.0) atomicMax(&res[2 * i0], (unsigned long long)__double_as_longlong(r0));
+        if (r1 > 0.0) atomicMax(&res[2 * i0 + 1], (unsigned long long)__double_as_longlong(r1));
+    }
+}
+
+void eval_sweep(hipStream_t s, const InstArgs& a, const int8_t* mu, const uint8_t* active,
+                const double* x_in, double* x_out, unsigned long long* res) {
+    if (a.n_tiles <= 0) return;
+    hipLaunchKernelGGL(eval_kernel, dim3(a.n_tiles), dim3(256), 0, s, a, mu, active, x_in, x_out, res);
+    MORAP_HIP(hipGetLastError());
+}
+
+__global__ void set_active_kernel(int n, k::InstArgs a, uint8_t* active, unsigned long long* res,
+                                  uint8_t* par, int width) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * width) return;
+    const int m = a.inst_model[i / width];
+    active[i] = a.init[m] >= 0 ? 1 : 0;
+    res[i] = 0ull;
+    par[i] = 0;
+}
+
+void set_active(hipStream_t s, int n, const InstArgs& a, uint8_t* active, unsigned long long* res,
+                uint8_t* par, int width) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(set_active_kernel, dim3((n * width + 255) / 256), dim3(256), 0, s, n, a, active, res,
+                       par, width);
+    MORAP_HIP(hipGetLastError());
+}
+
+__global__ void select_final_kernel(InstArgs a, double* x0, const double* x1, const uint8_t* par, int width) {
+    InstLoc L;
+    if (!inst_locate(a, L)) return;
+    for (int o = 0; o < width; ++o)
+        if (par[(int64_t)L.inst * width + o]) x0[L.is * width + o] = x1[L.is * width + o];
+}
+
+void select_final(hipStream_t s, const InstArgs& a, double* x0, const double* x1, const uint8_t* par,
+                  int width) {
+    if (a.n_tiles <= 0) return;
+    hipLaunchKernelGGL(select_final_kernel, dim3(a.n_tiles), dim3(256), 0, s, a, x0, x1, par, width);
+    MORAP_HIP(hipGetLastError());
+}
+
+__global__ void gather_init_kernel(int n, const int64_t* idx, const double* x, double* out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int64_t i = idx[q];
+    out[2 * q] = i >= 0 ? x[2 * i] : 0.0;
+    out[2 * q + 1] = i >= 0 ? x[2 * i + 1] : 0.0;
+}
+
+void gather_init(hipStream_t s, int n, const int64_t* idx, const double* x, double* out) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(gather_init_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, idx, x, out);
+    MORAP_HIP(hipGetLastError());
+}
+
+}  // namespace k
+}  // namespace morap

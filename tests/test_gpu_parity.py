@@ -1,0 +1,214 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars:
+  * product construction, assignment and policies: bit-exact (integer work);
+  * FP64 value iteration mirrors the oracle's arithmetic up to summation
+    order, so values agree to rounding when both stop at the same sweep; the
+    bound used is 4 eps + 1e-10 |v| (a stop one sweep apart moves a value by at
+    most one residual, <= eps);
+  * per-objective evaluation (Alg. 4) is FP64 in both: 1e-9 |v| + 4 eps_eval;
+  * FP32 sweeps: the reported scalarised values carry the FP32 stopping error
+    (the test states and checks the bound of each result).
+"""
+import numpy as np
+import pytest
+
+from workloads import make_workload, worked_example, tiny_workload, dirichlet_weights
+from oracle import product, vi, alg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def morap():
+    from paper_2305_04397_amd import morap as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(morap):
+    c = morap.Context(0)
+    yield c
+    c.close()
+
+
+def _load(ctx, wl):
+    ctx.build_products(wl)
+    return product.build_all(wl)
+
+
+def _same_product(g, o):
+    assert g["state_row"].tolist() == o.state_row.tolist()
+    assert g["row_ptr"].tolist() == o.row_ptr.tolist()
+    assert g["col"].tolist() == o.col.tolist()
+    assert np.array_equal(g["prob"], o.prob)
+    assert np.array_equal(g["rew"][:, 0], o.rew_cost) and np.array_equal(g["rew"][:, 1], o.rew_prob)
+    assert g["to_done"].astype(bool).tolist() == o.to_done.tolist()
+    assert g["init"] == o.init
+    assert g["states"].tolist() == o.states.tolist()
+
+
+@pytest.mark.parametrize("name", ["example", "cfg1", "cfg2_sub", "tiny"])
+def test_products_bit_exact(ctx, name):
+    wl = {"example": worked_example, "cfg1": lambda: make_workload(1),
+          "cfg2_sub": lambda: make_workload(2, n_agents=3, n_tasks=5),
+          "tiny": lambda: tiny_workload(5, 2, 3, width=3, height=3, kinds=("avoid", "reach"))}[name]()
+    prods = _load(ctx, wl)
+    for m, p in enumerate(prods):
+        _same_product(ctx.get_model(m), p)
+
+
+def _oracle_c(prods, nI, nJ, W, eps):
+    K = W.shape[0]
+    c = np.zeros((K, nI, nJ))
+    sw = np.zeros((K, nI, nJ), dtype=np.int64)
+    vals = {}
+    for i in range(nI):
+        for j in range(nJ):
+            p = prods[i * nJ + j]
+            y, n = vi.value_iteration(p, W[:, i], W[:, nI + j], eps)
+            vals[i * nJ + j] = y
+            if p.init >= 0:
+                c[:, i, j] = y[p.init]
+            sw[:, i, j] = n
+    return c, sw, vals
+
+
+@pytest.mark.parametrize("K", [1, 3, 16, 70])
+def test_solve_f64_matches_oracle(ctx, morap, K):
+    wl = make_workload(1)
+    prods = _load(ctx, wl)
+    nI, nJ = wl.n_agents, wl.n_tasks
+    W = dirichlet_weights(np.random.default_rng(K), K, nI + nJ)
+    W[0] = np.eye(nI + nJ)[0]          # the initial weight of Alg. 1
+    eps = 1e-8
+    c, st = ctx.solve(W, morap.Options(eps_vi=eps, precision="f64"))
+    co, sw, vals = _oracle_c(prods, nI, nJ, W, eps)
+    assert np.abs(c - co).max() <= 4 * eps + 1e-10 * np.abs(co).max()
+    assert st["max_pair_sweeps"] in (sw.max(), sw.max() + 1, sw.max() - 1)
+    for m in range(len(prods)):
+        for k in (0, K - 1):
+            x = ctx.get_values(k, m)
+            assert np.abs(x - vals[m][:, k]).max() <= 4 * eps + 1e-10 * np.abs(vals[m]).max()
+
+
+def test_every_variant_gives_identical_f64_values(ctx, morap):
+    wl = make_workload(2, n_agents=2, n_tasks=3)
+    _load(ctx, wl)
+    W = dirichlet_weights(np.random.default_rng(0), 16, 5)
+    ref = None
+    from itertools import product as iprod
+    for v in range(1, 19):
+        cpl, lps = [(1, 1), (1, 2), (2, 1), (1, 4), (2, 2), (4, 1), (1, 8), (2, 4), (4, 2), (1, 16), (2, 8),
+                    (4, 4), (1, 32), (2, 16), (4, 8), (1, 64), (2, 32), (4, 16)][v - 1]
+        if 16 % (cpl * lps):
+            continue
+        for graph in (False, True):
+            c, _ = ctx.solve(W, morap.Options(eps_vi=1e-7, precision="f64", schedule=v, use_graph=graph))
+            if ref is None:
+                ref = c
+            assert np.array_equal(c, ref), (v, graph)
+
+
+def test_support_f64_cfg1_matches_oracle(ctx, morap):
+    wl = make_workload(1)
+    prods = _load(ctx, wl)
+    nI, nJ = wl.n_agents, wl.n_tasks
+    W = np.vstack([np.eye(4), dirichlet_weights(np.random.default_rng(7), 4, 4)])
+    eps = 1e-8
+    r, A, c, st = ctx.support(W, morap.Options(eps_vi=eps, precision="f64"))
+    for k in range(W.shape[0]):
+        so = alg.support(prods, nI, nJ, W[k], eps)
+        assert np.abs(c[k] - so.c).max() <= 4 * eps + 1e-10 * np.abs(so.c).max()
+        # w.r equals the assignment optimum (Lemma lem:face)
+        assert W[k] @ r[k] == pytest.approx(sum(c[k][A[k][j], j] for j in range(nJ)), abs=1e-6)
+        assert W[k] @ r[k] == pytest.approx(W[k] @ so.r, abs=1e-6)
+        if np.array_equal(A[k], so.f):
+            for j in range(nJ):
+                p = prods[A[k][j] * nJ + j]
+                mu = ctx.get_policy(k, j, p.n_states)
+                assert mu.tolist() == so.policies[j].tolist()
+            assert np.abs(r[k] - so.r).max() <= 1e-9 * np.abs(so.r).max() + 4 * eps
+
+
+def test_example_queries(ctx, morap):
+    wl = worked_example()
+    _load(ctx, wl)
+    o = morap.Options(eps_vi=1e-12, precision="f64")
+    qa = ctx.query([-2.5, 0.7], eps=1e-3, opts=o, trace=True)
+    assert qa["verdict"] == morap.FEASIBLE and qa["iterations"] == 2
+    assert np.allclose(qa["R"], [[-1.0, 0.1], [-15 / 7, 5 / 7]], atol=1e-10)
+    qu = ctx.query([-1.8, 0.9], eps=1e-3, opts=o, trace=True)
+    assert qu["verdict"] == morap.INFEASIBLE and qu["iterations"] == 3
+    A, B, t = np.array([-15 / 7, 5 / 7]), np.array([-1.0, 0.1]), np.array([-1.8, 0.9])
+    n = np.array([-(B - A)[1], (B - A)[0]])
+    n = n if n @ (t - A) > 0 else -n
+    assert np.allclose(qu["t_down"], t - (n @ (t - A)) / (n @ n) * n, atol=1e-7)
+
+
+def test_query_cfg1_matches_oracle(ctx, morap):
+    wl = make_workload(1)
+    prods = _load(ctx, wl)
+    o = morap.Options(eps_vi=1e-8, precision="f64")
+    rng = np.random.default_rng(11)
+    base = alg.support(prods, 2, 2, np.full(4, 0.25), 1e-8).r
+    T = [np.array([-40.0, -40.0, 0.8, 0.8])]
+    for _ in range(4):
+        T.append(base + np.array([5.0, 5.0, 0.0, 0.0]) * rng.uniform(-1, 1, 4))
+    for t in T:
+        g = ctx.query(t, eps=1e-6, opts=o, trace=True)
+        q = alg.query(prods, 2, 2, t, 1e-6, 1e-8)
+        assert g["verdict"] == q.verdict
+        assert np.abs(g["t_down"] - q.t_down).max() <= 1e-6
+        assert np.abs(g["t_up"] - q.t_up).max() <= 1e-6
+        assert g["iterations"] == q.iterations
+
+
+def test_f32_solve_and_support_cfg2(ctx, morap):
+    wl = make_workload(2, n_agents=3, n_tasks=6)
+    prods = _load(ctx, wl)
+    nI, nJ = wl.n_agents, wl.n_tasks
+    W = dirichlet_weights(np.random.default_rng(3), 16, nI + nJ)
+    eps = 1e-6
+    r, A, c, st = ctx.support(W, morap.Options(eps_vi=eps, precision="f32"))
+    co, _, _ = _oracle_c(prods, nI, nJ, W, eps)
+    # FP32 stopping error: the FP32 sweep stops once its residual is below
+    # max(eps, 8 u32 |y|); each value is within that residual times the
+    # effective horizon of the oracle's, bounded here by 2e-4 relative
+    err = np.abs(c - co)
+    assert (err <= 2e-4 * np.maximum(1.0, np.abs(co))).all(), err.max()
+    for k in range(W.shape[0]):
+        so_f = alg.assign(co[k])
+        # with the same assignment the FP64-polished evaluation agrees
+        if np.array_equal(so_f, A[k]):
+            ro = np.zeros(nI + nJ)
+            for j in range(nJ):
+                p = prods[A[k][j] * nJ + j]
+                y, _ = vi.value_iteration(p, W[k, A[k][j]], W[k, nI + j], eps)
+                mu = vi.extract_policy(p, y[:, 0], W[k, A[k][j]], W[k, nI + j])
+                (vc, vp), _, _ = vi.evaluate(p, mu, eps)
+                ro[nI + j] = vp
+                ro[A[k][j]] += vc
+            assert W[k] @ r[k] == pytest.approx(W[k] @ ro, abs=1e-5 * max(1, abs(W[k] @ ro)))
+
+
+def test_edge_cases(ctx, morap):
+    wl = make_workload(1)
+    _load(ctx, wl)
+    o = morap.Options(eps_vi=1e-8, precision="f64")
+    with pytest.raises(morap.MorapError) as e:
+        ctx.solve(np.full((1, 4), 0.3), o)                # row does not sum to 1
+    assert e.value.code == morap.E_INVALID
+    with pytest.raises(morap.MorapError) as e:
+        ctx.solve(np.eye(4)[:1], morap.Options(eps_vi=1e-8, precision="f64", max_sweeps=4, check_every=2))
+    assert e.value.code == morap.E_NOT_CONVERGED
+    with pytest.raises(morap.MorapError) as e:
+        ctx.evaluate(np.zeros((2, 2), np.int32), o)       # K differs from the last solve (1)
+    assert e.value.code in (morap.E_INVALID, morap.E_STATE)
+    # a task whose initial location is already accepting: empty models
+    wl2 = worked_example()
+    wl2.tasks[0].q0 = 1
+    ctx.build_products(wl2)
+    assert ctx.model_info(0)["n_states"] == 0
+    r, A, c, _ = ctx.support(np.array([[0.5, 0.5]]), o)
+    assert np.allclose(r, 0) and np.allclose(c, 0)

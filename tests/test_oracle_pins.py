@@ -607,3 +607,34 @@ def test_inner_projection_general_norm_against_slsqp():
                              options={"ftol": 1e-15, "maxiter": 1000}) for k in range(m)),
                    key=lambda r: r.fun)
         assert geometry.mnorm(t - x, M) ** 2 == pytest.approx(best.fun, abs=1e-7)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_inner_projection_fixes_points_of_the_set(seed):
+    # a threshold built as a convex combination of the points, lowered in
+    # some coordinates, lies in down(Phi): its projection is itself, and the
+    # returned weights dominate it
+    rng = np.random.default_rng(1000 + seed)
+    for _ in range(25):
+        m, d = int(rng.integers(1, 30)), int(rng.integers(2, 60))
+        Phi = rng.normal(size=(m, d)) * rng.uniform(0.1, 50, size=d)
+        lam = rng.dirichlet(np.ones(m))
+        t = Phi.T @ lam - rng.uniform(0, 1, d) * (rng.random(d) < 0.5)
+        x, w = geometry.project_inner(Phi, t)
+        assert np.array_equal(x, t)
+        assert (Phi.T @ w >= t - 1e-9 * np.abs(t).max()).all()
+        # raised above the best point in every coordinate it is outside
+        t2 = Phi.max(0) + rng.uniform(0.1, 1.0, d)
+        x2, w2 = geometry.project_inner(Phi, t2)
+        assert geometry.kkt_inner(Phi, t2, x2, w2) <= 1e-8 * np.abs(t2).max()
+        assert np.linalg.norm(t2 - x2) > 0
+
+
+def test_nnls_against_textbook_cases():
+    # exact solutions of small non-negative least-squares problems
+    A = np.array([[1.0, 0.0], [0.0, 1.0], [1.0, 1.0]])
+    x, r = geometry.nnls(A, np.array([1.0, -1.0, 0.5]))
+    # unconstrained optimum has x2 < 0; with x2 = 0 the best x1 is 0.75
+    assert np.allclose(x, [0.75, 0.0]) and r == pytest.approx(np.sqrt(0.0625 + 1 + 0.0625))
+    x, r = geometry.nnls(np.eye(3), np.array([-1.0, 2.0, 3.0]))
+    assert np.allclose(x, [0, 2, 3]) and r == pytest.approx(1.0)
