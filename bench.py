@@ -1,0 +1,199 @@
+"""Throughput of the batched value-iteration path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload 50x100]
+
+Workload (seeded, synthetic; stands in for the paper's smart-warehouse models,
+which are not available): 50 agents on 32x32..128x128 grids with 20 %
+obstacles x 100 reach/avoid tasks of 3-12 DFA locations -> 5,000 agent-task
+product MDPs, K = 64 weight columns per pass, eps 1e-6, FP32 backups with FP64
+residual, polish, evaluation and reported values.
+
+A step is one lockstep pass of Alg. 1 for 64 queries: the learned proposer's
+first weights when present (plain: Dirichlet first weights), the batched
+value iteration of all 5,000 models for the 64 columns to convergence (Alg. 3
+and the stop test), the assignment (Alg. 2), FP64 polish, policy extraction
+and per-objective evaluation of the assigned models (Alg. 4), and both
+projections of Alg. 1 for every query.  `value` is state-action backups per
+second over the timed steps (inputs resident on the device).
+
+Extra objects on the JSON line:
+  roofline      the Bellman sweep kernel: algorithmic bytes (CSR of active
+                models + one FP32 read and one write per active state-column)
+                over its summed HIP-event durations, against 8 TB/s HBM;
+  cpu_baseline  the FP64 oracle's value iteration timed on a bounded sample of
+                models of the same workload on the host (single process);
+  ms_per_query  full Alg. 1 queries (eps 0.01) from the plain first weight
+                (1, 0, ..., 0), and from the learned proposer when one is loaded.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "state-action backups/s + ms per point-oriented Pareto query (learned vs plain)"
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def thresholds(rng, front: np.ndarray, n: int, nI: int) -> np.ndarray:
+    """t = u* + delta |u*| around points u* of the front, delta ~ U[-0.3, 0.3];
+    probabilities clipped to [0, 1]."""
+    idx = rng.integers(front.shape[0], size=n)
+    u = front[idx]
+    t = u + rng.uniform(-0.3, 0.3, size=u.shape) * np.abs(u)
+    t[:, nI:] = np.clip(t[:, nI:], 0.0, 1.0)
+    return t
+
+
+def cpu_baseline(wl, K: int, eps: float, budget_s: float, seed: int) -> dict:
+    """FP64 oracle value iteration on a sample of the workload's models."""
+    from oracle import product, vi
+    rng = np.random.default_rng(seed)
+    nI, nJ = wl.n_agents, wl.n_tasks
+    W = rng.dirichlet(np.ones(nI + nJ), size=K)
+    order = rng.permutation(nI * nJ)
+    backups, elapsed, done = 0, 0.0, 0
+    for m in order:
+        i, j = divmod(int(m), nJ)
+        if wl.agents[i].n_states > 2000:      # keep the sample bounded
+            continue
+        p = product.build_product(wl.agents[i], wl.tasks[j], wl.letters[i][j])
+        t0 = time.perf_counter()
+        _, sweeps = vi.value_iteration(p, W[:, i], W[:, nI + j], eps)
+        elapsed += time.perf_counter() - t0
+        backups += int(sweeps.sum()) * p.n_rows
+        done += 1
+        if elapsed >= budget_s:
+            break
+    return {"value": backups / elapsed, "unit": "backups/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} models drawn at random from the workload (agents on 32x32 grids), "
+                      f"K={K} Dirichlet weight columns, eps {eps:g}, FP64 Jacobi value iteration, "
+                      f"{elapsed:.1f} s of single-process CPU work"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="50x100", choices=["50x100", "10x20"])
+    ap.add_argument("--queries", type=int, default=64, help="queries for the ms-per-query measurement (0 = skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--seed", type=int, default=7)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the path runs on a single MI355X (multi-GPU sharding is "
+              "described in DESIGN.md, not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    from workloads import make_workload
+    from paper_2305_04397_amd import morap
+
+    cfg = 3 if args.workload == "50x100" else 2
+    K = 64 if cfg == 3 else 16
+    eps = 1e-6
+    t0 = time.time()
+    wl = make_workload(cfg)
+    nI, nJ = wl.n_agents, wl.n_tasks
+    d = nI + nJ
+    log(f"workload {wl.name}: generated in {time.time() - t0:.1f} s")
+    ctx = morap.Context(0)
+    t0 = time.time()
+    ctx.build_products(wl)
+    tot = ctx.model_info(0)["total_states"]
+    S = R = N = 0
+    for m in range(nI * nJ):
+        info = ctx.model_info(m)
+        S, R, N = S + info["n_states"], R + info["n_rows"], N + info["nnz"]
+    log(f"{nI * nJ} products built and uploaded in {time.time() - t0:.1f} s: S={S} R={R} N={N}")
+    opts = morap.Options(eps_vi=eps, precision=args.precision, time_kernels=True)
+    rng = np.random.default_rng(args.seed)
+
+    # warm-up (includes the sweep-kernel autotuning) and front points
+    fronts = []
+    for w in range(args.warmup):
+        Wd = rng.dirichlet(np.ones(d), size=K)
+        r, _, _, st = ctx.support(Wd, opts)
+        fronts.append(r)
+        log(f"warmup {w + 1}/{args.warmup}: {st['ms_total']:.0f} ms, variant {st['variant']}, "
+            f"{st['sweeps']} sweeps")
+    if not fronts:
+        r, _, _, _ = ctx.support(rng.dirichlet(np.ones(d), size=K), opts)
+        fronts.append(r)
+    front = np.vstack(fronts)
+
+    # timed steps: one lockstep Alg. 1 pass of K queries each
+    ctx.reset_stats()
+    step_ms = []
+    t_all = time.perf_counter()
+    for s in range(args.steps):
+        T = thresholds(rng, front, K, nI)
+        W0 = rng.dirichlet(np.ones(d), size=K)
+        ts = time.perf_counter()
+        ctx.query_batch(T, W0=W0, max_iter=1, eps=0.01, opts=opts)
+        step_ms.append((time.perf_counter() - ts) * 1e3)
+        log(f"step {s + 1}/{args.steps}: {step_ms[-1]:.0f} ms")
+    wall = time.perf_counter() - t_all
+    st = ctx.stats()
+    value = st["backups"] / wall
+    achieved = st["bytes"] / (st["ms_sweep_kernel"] / 1e3) / 1e9 if st["ms_sweep_kernel"] > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "bellman_sweep", "launches": st["sweep_launches"],
+                "avg_launch_us": round(st["ms_sweep_kernel"] * 1e3 / max(1, st["sweep_launches"]), 2),
+                "bytes_per_launch": round(st["bytes"] / max(1, st["sweep_launches"]), 0)}
+    log(f"timed: {value:.3e} backups/s, sweep kernel {achieved:.0f} GB/s "
+        f"({st['sweep_launches']} launches, {st['ms_sweep_kernel']:.0f} ms kernel of {st['ms_vi']:.0f} ms VI)")
+
+    # full queries: plain first weight
+    per_query = None
+    if args.queries > 0:
+        T = thresholds(rng, front, args.queries, nI)
+        tq = time.perf_counter()
+        res = ctx.query_batch(T, max_iter=64, eps=0.01, opts=morap.Options(eps_vi=eps, precision=args.precision))
+        wq = (time.perf_counter() - tq) * 1e3
+        its = np.array([q["iterations"] for q in res])
+        verdicts = [q["verdict"] for q in res]
+        per_query = {"plain": {"queries": len(res), "wall_ms": round(wq, 1),
+                               "ms_per_query": round(wq / len(res), 2),
+                               "passes_mean": round(float(its.mean()), 2), "passes_max": int(its.max()),
+                               "feasible": verdicts.count(morap.FEASIBLE),
+                               "infeasible": verdicts.count(morap.INFEASIBLE),
+                               "undecided": verdicts.count(morap.UNDECIDED)},
+                     "learned": None}
+        log(f"queries: {len(res)} in {wq:.0f} ms, passes mean {its.mean():.1f}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl, K, eps, args.cpu_seconds, args.seed)
+        log(f"cpu baseline: {cpu['value']:.3e} backups/s")
+
+    line = {"metric": METRIC, "value": value, "unit": "backups/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(float(np.mean(step_ms)), 2), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": args.precision,
+            "data": "synthetic: seeded grid-world agents and reach/avoid task automata",
+            "config": {"workload": f"{wl.name}: {nI * nJ} product MDPs, K={K} weight columns per pass",
+                       "states": S, "rows": R, "nnz": N, "K": K, "eps_vi": eps, "seed": args.seed,
+                       "parallelism": "1 GPU"},
+            "roofline": roofline, "cpu_baseline": cpu, "ms_per_query": per_query,
+            "stats": {k: st[k] for k in ("backups", "sweeps", "eval_sweeps", "polish_sweeps", "rank_rounds",
+                                         "ms_vi", "ms_eval", "variant")}}
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

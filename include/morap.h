@@ -153,11 +153,11 @@ typedef struct {
     int32_t check_every;  /* sweeps per host convergence check (even, >= 2)         */
     int32_t schedule;     /* 0 = autotuned sweep kernel, > 0 = fixed variant id     */
     int32_t use_graph;    /* 1 = replay sweep chunks as a captured hipGraph         */
-    int32_t reserved;
+    int32_t time_kernels; /* 1 = time every sweep kernel with HIP events (eager)    */
 } morap_vi_opts;
 
 /* Fill `opts` with the defaults: eps 1e-6, tau 1e-9, FP32, 1e6 sweeps, check
- * every 32 sweeps, autotuned, graphs on. */
+ * every 32 sweeps, autotuned, graphs on, no kernel timing. */
 void morap_default_opts(morap_vi_opts* opts);
 
 typedef struct {
@@ -170,6 +170,8 @@ typedef struct {
     int64_t excluded;       /* reserved                                             */
     double  bytes;          /* algorithmic bytes moved by the sweep kernel          */
     double  ms_vi, ms_eval, ms_total;   /* device / host wall time of the phases   */
+    double  ms_sweep_kernel;/* summed sweep-kernel time (time_kernels = 1)          */
+    int64_t sweep_launches; /* sweep kernels timed                                  */
     int32_t variant;        /* sweep-kernel variant used                            */
     int32_t reserved;
 } morap_stats;
@@ -208,6 +210,11 @@ int morap_assign(morap_ctx* ctx, const double* c, int K, int32_t* assign_out);
  * Errors: as morap_solve and morap_evaluate. */
 int morap_support(morap_ctx* ctx, const double* W, int K, const morap_vi_opts* opts,
                   double* r_out, int32_t* assign_out, double* c_out, morap_stats* stats);
+
+/* Statistics accumulated by every solve / evaluate on the context since the
+ * last reset (morap_query and morap_support included).  Errors: INVALID. */
+int morap_get_stats(const morap_ctx* ctx, morap_stats* out);
+int morap_reset_stats(morap_ctx* ctx);
 
 /* Policy chosen for task j in column k by the last morap_evaluate: mu_out[S]
  * of model (assign[k][j], j), each entry the chosen row counted from the
@@ -266,8 +273,10 @@ int morap_query(morap_ctx* ctx, const double* t, const double* M,
 /* Q queries T[Q][d] advanced in lockstep: every Alg. 1 pass solves the weight
  * vectors of all unfinished queries as the columns of one morap_support call
  * (at most 64 columns per call; larger Q runs in groups of 64).
+ * W0[Q][d] (nullable) replaces each query's first weight vector (rows >= 0,
+ * summing to 1); NULL means (1, 0, ..., 0) or the learned proposer's output.
  * results[Q].  Errors: as morap_query. */
-int morap_query_batch(morap_ctx* ctx, const double* T, int Q, const double* M,
+int morap_query_batch(morap_ctx* ctx, const double* T, const double* W0, int Q, const double* M,
                       const morap_query_opts* opts, morap_query_result* results);
 
 /* Projections of Alg. 1 on their own (host, FP64).  Inner: x_out[d] in

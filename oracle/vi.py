@@ -14,9 +14,18 @@ Readings taken here:
   * Tie rule: the eps-optimal action set A*(s) = {a : Q(s,a) >= max Q - tau}
     with Q in FP64 at the returned values.  Done states have rank 0; an
     unranked state gets rank l+1 when some a in A*(s) moves mass into the done
-    set or into a state of rank <= l; its action is the lowest-index such a.
-    States left unranked make the policy improper (an error).  The chosen
-    policy reaches done with probability 1 and is greedy for the values.
+    set or into a state of rank <= l; its action is the one among those that
+    moves the most probability into done or into states of rank <= l (masses
+    within 1e-12 count as equal; then the lowest index wins).  Taking merely the
+    lowest-index qualifying action is proper too, but may progress only through
+    a rare slip and so take tens of thousands of steps on average.
+    When the rounds stop with states left unranked (near-ties below the
+    accuracy of eps-converged values can close cycles of strict argmax
+    choices, e.g. where many actions reach the goal with probability ~1), the
+    tolerance of the unranked states only is widened tenfold, 1e-9 -> 1e-3,
+    and the rounds go on; ranked states keep their choice.  States still
+    unranked make the policy improper (an error).  The chosen policy reaches
+    done with probability 1 and is tau-greedy for the values.
 """
 from __future__ import annotations
 
@@ -78,6 +87,9 @@ def q_values(prod: Product, x: np.ndarray, wc, wp) -> np.ndarray:
     return scalarised_rewards(prod, wc, wp) + prod.P() @ x2
 
 
+TAU_STEPS = 6   # widenings of the tie tolerance: tau * 10**k, k <= 6
+
+
 def extract_policy(prod: Product, x: np.ndarray, wc: float, wp: float,
                    tau: float = 1e-9) -> np.ndarray:
     """Attractor tie rule on the eps-optimal action sets (module doc).
@@ -98,6 +110,7 @@ def extract_policy(prod: Product, x: np.ndarray, wc: float, wp: float,
     mu = np.full(S, -1, dtype=np.int64)
     first_row = prod.state_row[:-1]
     level = 0
+    widen = 0
     while True:
         ranked_before = (rank >= 0)
         # a row qualifies if it is eps-optimal and moves mass into done or
@@ -105,13 +118,32 @@ def extract_policy(prod: Product, x: np.ndarray, wc: float, wp: float,
         hits = opt & (prod.to_done | (B @ ranked_before.astype(np.float64) > 0))
         cand = hits & ~ranked_before[row_state]
         if not cand.any():
-            break
+            if ranked_before.all() or widen == TAU_STEPS:
+                break
+            widen += 1
+            loose = Q >= qmax[row_state] - tau * 10.0 ** widen
+            opt = np.where(ranked_before[row_state], opt, loose)
+            continue
         level += 1
         rows = np.flatnonzero(cand)
-        # the lowest-index qualifying row of each newly ranked state
-        states, first = np.unique(row_state[rows], return_index=True)
-        rank[states] = level
-        mu[states] = rows[first] - first_row[states]
+        # mass into done, then into earlier-ranked states, in entry order
+        for s in np.unique(row_state[rows]):
+            best_r, best_m = -1, -1.0
+            for r in rows[row_state[rows] == s]:
+                a, b = prod.row_ptr[r], prod.row_ptr[r + 1]
+                m = 0.0
+                if prod.to_done[r]:
+                    live = 0.0
+                    for e in range(a, b):
+                        live += prod.prob[e]
+                    m = 1.0 - live
+                for e in range(a, b):
+                    if ranked_before[prod.col[e]]:
+                        m += prod.prob[e]
+                if m > best_m + 1e-12:
+                    best_r, best_m = r, m
+            rank[s] = level
+            mu[s] = best_r - first_row[s]
     if (rank < 0).any():
         raise ImproperPolicy(f"{int((rank < 0).sum())} states cannot reach done "
                              "through eps-optimal actions")

@@ -9,8 +9,10 @@
 using namespace morap;
 
 morap_ctx::~morap_ctx() {
-    if (chunk_exec) (void)hipGraphExecDestroy(chunk_exec);
-    if (chunk_graph) (void)hipGraphDestroy(chunk_graph);
+    for (int g = 0; g < 2; ++g) {
+        if (chunk_exec[g]) (void)hipGraphExecDestroy(chunk_exec[g]);
+        if (chunk_graph[g]) (void)hipGraphDestroy(chunk_graph[g]);
+    }
     if (prop_mlp) proposer_destroy(prop_mlp);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
@@ -53,6 +55,8 @@ void to_abi(const Stats& s, morap_stats* out) {
     out->ms_vi = s.ms_vi;
     out->ms_eval = s.ms_eval;
     out->ms_total = s.ms_total;
+    out->ms_sweep_kernel = s.ms_sweep_kernel;
+    out->sweep_launches = s.sweep_launches;
     out->variant = s.variant;
     out->reserved = 0;
 }
@@ -159,7 +163,7 @@ void morap_default_opts(morap_vi_opts* o) {
     o->check_every = 32;
     o->schedule = 0;
     o->use_graph = 1;
-    o->reserved = 0;
+    o->time_kernels = 0;
 }
 
 int morap_solve(morap_ctx* ctx, const double* W, int K, const morap_vi_opts* opts, double* c_out,
@@ -207,6 +211,18 @@ int morap_support(morap_ctx* ctx, const double* W, int K, const morap_vi_opts* o
     });
 }
 
+int morap_get_stats(const morap_ctx* cctx, morap_stats* out) {
+    morap_ctx* ctx = const_cast<morap_ctx*>(cctx);
+    return guarded(ctx, [&] {
+        MORAP_CHECK(out, MORAP_E_INVALID, "out is NULL");
+        to_abi(ctx->cum, out);
+    });
+}
+
+int morap_reset_stats(morap_ctx* ctx) {
+    return guarded(ctx, [&] { ctx->cum = Stats(); });
+}
+
 int morap_get_policy(const morap_ctx* cctx, int k, int j, int8_t* mu_out) {
     morap_ctx* ctx = const_cast<morap_ctx*>(cctx);
     return guarded(ctx, [&] {
@@ -229,11 +245,12 @@ int morap_get_values(const morap_ctx* cctx, int k, int m, double* x_out) {
         const int32_t s0 = ctx->hm.state_base[m], s1 = ctx->hm.state_base[m + 1];
         const int Kp = ctx->Kp;
         uint8_t par = 0;
-        MORAP_HIP(hipMemcpy(&par, ctx->d_final_par.as<uint8_t>() + (size_t)m * Kp + k, 1, hipMemcpyDeviceToHost));
+        MORAP_HIP(hipMemcpy(&par, ctx->vmain.final_par.as<uint8_t>() + (size_t)m * Kp + k, 1,
+                            hipMemcpyDeviceToHost));
         const size_t el = ctx->prec == MORAP_F32 ? 4 : 8;
         std::vector<char> buf((size_t)(s1 - s0) * Kp * el + 8);
         if (s1 > s0)
-            MORAP_HIP(hipMemcpy(buf.data(), ctx->d_x[par].as<char>() + (size_t)s0 * Kp * el,
+            MORAP_HIP(hipMemcpy(buf.data(), ctx->vmain.x[par].as<char>() + (size_t)s0 * Kp * el,
                                 (size_t)(s1 - s0) * Kp * el, hipMemcpyDeviceToHost));
         for (int32_t s = 0; s < s1 - s0; ++s) {
             if (el == 4) x_out[s] = reinterpret_cast<const float*>(buf.data())[(size_t)s * Kp + k];
@@ -246,15 +263,15 @@ int morap_query(morap_ctx* ctx, const double* t, const double* M, const morap_qu
                 morap_query_result* result) {
     return guarded(ctx, [&] {
         MORAP_CHECK(opts, MORAP_E_INVALID, "opts is NULL");
-        query_batch(ctx, t, 1, M, *opts, result);
+        query_batch(ctx, t, nullptr, 1, M, *opts, result);
     });
 }
 
-int morap_query_batch(morap_ctx* ctx, const double* T, int Q, const double* M, const morap_query_opts* opts,
-                      morap_query_result* results) {
+int morap_query_batch(morap_ctx* ctx, const double* T, const double* W0, int Q, const double* M,
+                      const morap_query_opts* opts, morap_query_result* results) {
     return guarded(ctx, [&] {
         MORAP_CHECK(opts, MORAP_E_INVALID, "opts is NULL");
-        query_batch(ctx, T, Q, M, *opts, results);
+        query_batch(ctx, T, W0, Q, M, *opts, results);
     });
 }
 

@@ -118,8 +118,20 @@ struct Variant {
 struct Stats {
     int64_t backups = 0, sweeps = 0, max_pair_sweeps = 0, eval_sweeps = 0, polish_sweeps = 0,
             rank_rounds = 0, excluded = 0;
-    double bytes = 0, ms_vi = 0, ms_eval = 0, ms_total = 0;
+    double bytes = 0, ms_vi = 0, ms_eval = 0, ms_total = 0, ms_sweep_kernel = 0;
+    int64_t sweep_launches = 0;
     int variant = 0;
+};
+
+// Values of one batched value iteration: two Jacobi buffers [S][Kp], the
+// buffer holding each (model, column) pair's result, and the value at every
+// model's initial state.
+struct ValueSet {
+    DevBuf x[2];
+    DevBuf final_par;   // [M][Kp] uint8
+    DevBuf c;           // [K][M] FP64
+    int prec = -1, K = 0, Kp = 0;
+    bool valid = false;
 };
 
 struct Proposer;  // mlp.hip
@@ -154,22 +166,22 @@ struct morap_ctx {
     // solve state (batched value iteration)
     int K = 0, Kp = 0, prec = -1;
     bool solved = false;
-    morap::DevBuf d_x[2];                           // [S][Kp] values, FP32 or FP64
+    morap::ValueSet vmain;                          // the solve's values (its precision)
+    morap::ValueSet vref;                           // FP64 values of the assigned pairs after an FP32 solve
+    morap::DevBuf d_pair_mask;                      // [M][Kp] uint8: pairs of a restricted solve
     morap::DevBuf d_wc32, d_wp32, d_wc64, d_wp64;   // [M][Kp]
     morap::DevBuf d_res, d_ymax;                    // [M][Kp] uint64 (bits of FP64)
     morap::DevBuf d_active;                         // [M][Kp] uint8
-    morap::DevBuf d_final_par;                      // [M][Kp] uint8: buffer holding the result
     morap::DevBuf d_pair_sweeps;                    // [M][Kp] int32
     morap::DevBuf d_model_active;                   // [M] uint8
     morap::DevBuf d_act_models, d_act_prefix;       // compacted active model list
-    morap::DevBuf d_counters;                       // int64 [8]: 0 active pairs, 1 active tiles, 2 backups
-    morap::DevBuf d_c;                              // [K][M] FP64 values at the initial states
+    morap::DevBuf d_counters;                       // int64 [8] (see the convergence kernel)
     morap::PinnedBuf h_counters;
     std::vector<double> W;                          // [K][d] of the last solve
     int last_variant = 0;
-    hipGraph_t chunk_graph = nullptr;               // captured chunk of sweeps
-    hipGraphExec_t chunk_exec = nullptr;
-    std::string graph_key;
+    hipGraph_t chunk_graph[2] = {nullptr, nullptr}; // captured chunks of sweeps (main, FP64 refine)
+    hipGraphExec_t chunk_exec[2] = {nullptr, nullptr};
+    std::string graph_key[2];
 
     // evaluation state
     int eK = 0;
@@ -178,17 +190,19 @@ struct morap_ctx {
     std::vector<int32_t> inst_k, inst_m;            // instances (column, model)
     std::vector<int64_t> inst_base;                 // [n_inst+1] state offsets
     morap::DevBuf d_inst_model, d_inst_k, d_inst_base, d_inst_tiles;
-    morap::DevBuf d_xi[2];                          // polish values [inst states] FP64
-    morap::DevBuf d_ires, d_iactive, d_ipar;        // per instance
+    morap::DevBuf d_xi;                             // final FP64 values [inst states]
+    morap::DevBuf d_ires, d_iactive, d_ipar;        // per (instance, objective)
     morap::DevBuf d_mask, d_rank, d_mu;             // per instance state
     morap::DevBuf d_xe[2];                          // evaluation values [inst states][2]
-    morap::DevBuf d_eres, d_eactive, d_epar;        // per (instance, objective)
     morap::DevBuf d_iwc, d_iwp;                     // per instance FP64 weights
     morap::DevBuf d_init_idx, d_init_val;           // instance initial states, their values
     std::vector<int8_t> h_mu;                       // policies of the last evaluate
 
     // autotuner cache: key (prec, Kp) -> variant id
     std::vector<std::pair<int64_t, int>> tuned;
+
+    // statistics since the last reset
+    morap::Stats cum;
 
     // proposer
     morap::Proposer* prop_mlp = nullptr;
@@ -220,8 +234,8 @@ void project_outer(const double* W, const double* R, int n, int d, const double*
                    double* z);
 
 // query.cpp
-void query_batch(morap_ctx* ctx, const double* T, int Q, const double* M, const morap_query_opts& o,
-                 morap_query_result* res);
+void query_batch(morap_ctx* ctx, const double* T, const double* W0, int Q, const double* M,
+                 const morap_query_opts& o, morap_query_result* res);
 
 // mlp.hip
 void proposer_destroy(Proposer* p);
@@ -271,6 +285,7 @@ struct ConvergeArgs {
     uint8_t* model_active;
     double* c;              // [K][M]
     const int32_t* init;    // [M]
+    const uint8_t* mask;    // [M][Kp] pairs to solve (nullable: all)
     const void* x_out;      // buffer written by the sweep just finished
     int64_t* counters;
     int M, K, Kp, prec, out_par;
@@ -305,12 +320,10 @@ struct InstArgs {
 };
 void gather_columns(hipStream_t s, const InstArgs& a, int prec, const void* x0, const void* x1,
                     const uint8_t* final_par, int Kp, double* xi);
-void polish_sweep(hipStream_t s, const InstArgs& a, const double* wc, const double* wp,
-                  const uint8_t* active, const double* x_in, double* x_out, unsigned long long* res);
 void inst_converge(hipStream_t s, int n, unsigned long long* res, uint8_t* active, uint8_t* par, int out_par,
                    double eps, int64_t* counter);
 void opt_mask(hipStream_t s, const InstArgs& a, const double* wc, const double* wp, const double* x,
-              double tau, uint32_t* mask, int32_t* rank, int8_t* mu);
+              double tau, uint32_t* mask, int32_t* rank, int8_t* mu, bool only_unranked);
 void rank_round(hipStream_t s, const InstArgs& a, const uint32_t* mask, int32_t* rank, int8_t* mu,
                 int level, int64_t* counter);
 void eval_sweep(hipStream_t s, const InstArgs& a, const int8_t* mu, const uint8_t* active,
@@ -323,6 +336,8 @@ void set_active(hipStream_t s, int n, const InstArgs& a, uint8_t* active, unsign
 // copy the values of entries frozen in buffer 1 into buffer 0
 void select_final(hipStream_t s, const InstArgs& a, double* x0, const double* x1, const uint8_t* par,
                   int width);
+// pair mask of a restricted solve: mask[m][k] = 1 for the instances' pairs
+void mark_pairs(hipStream_t s, const InstArgs& a, int Kp, uint8_t* mask);
 // out[2q + o] = x[2 idx[q] + o] (0 when idx[q] < 0)
 void gather_init(hipStream_t s, int n, const int64_t* idx, const double* x, double* out);
 }  // namespace k

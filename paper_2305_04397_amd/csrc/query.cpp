@@ -45,8 +45,8 @@ struct QState {
 
 }  // namespace
 
-void query_batch(morap_ctx* c, const double* T, int Q, const double* M, const morap_query_opts& o,
-                 morap_query_result* res) {
+void query_batch(morap_ctx* c, const double* T, const double* W0, int Q, const double* M,
+                 const morap_query_opts& o, morap_query_result* res) {
     MORAP_CHECK(c->loaded, MORAP_E_STATE, "no models loaded");
     MORAP_CHECK(T && res && Q >= 1, MORAP_E_INVALID, "bad query arguments");
     MORAP_CHECK(o.eps >= 0 && o.max_iter >= 1, MORAP_E_INVALID, "need eps >= 0 and max_iter >= 1");
@@ -74,7 +74,16 @@ void query_batch(morap_ctx* c, const double* T, int Q, const double* M, const mo
         s.t_up.assign(d, -INFINITY);
         s.w.assign(d, 0.0);
         s.w[0] = 1.0;
-        if (o.use_proposer) {
+        if (W0) {
+            double sum = 0;
+            for (int k = 0; k < d; ++k) {
+                const double v = W0[(size_t)q * d + k];
+                MORAP_CHECK(std::isfinite(v) && v >= 0, MORAP_E_INVALID, "first weights must be finite and >= 0");
+                sum += v;
+            }
+            MORAP_CHECK(std::fabs(sum - 1.0) <= 1e-9, MORAP_E_INVALID, "first weight rows must sum to 1");
+            s.w.assign(W0 + (size_t)q * d, W0 + (size_t)(q + 1) * d);
+        } else if (o.use_proposer) {
             bool ok = learned;
             std::vector<double> w(d);
             double sum = 0;

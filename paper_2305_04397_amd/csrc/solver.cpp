@@ -1,6 +1,12 @@
 // Host orchestration of the batched value iteration (Alg. 3 for K weight
-// columns at once), the FP64 polish, policy extraction and per-objective
-// evaluation (Alg. 4) of the assigned (column, model) instances.
+// columns at once), policy extraction and per-objective evaluation (Alg. 4)
+// of the assigned (column, model) instances.
+//
+// Precision: an FP32 solve runs FP32 backups (FP64 residual) over every
+// (model, column) pair and yields the values that choose the assignment.  The
+// evaluation then repeats the value iteration in FP64 from 0, with the same
+// stopping rule, on the assigned pairs only (one pair per task and column);
+// policies and per-objective values come from those FP64 values.
 #include "common.h"
 
 #include <algorithm>
@@ -56,14 +62,11 @@ static const Variant& variant_by_id(int id) {
 }
 
 // ---------------------------------------------------------------------------
-// per-solve buffers
+// buffers
 // ---------------------------------------------------------------------------
-static void ensure_solve_buffers(morap_ctx* c, int K, int Kp, int prec) {
+static void ensure_scratch(morap_ctx* c, int Kp) {
     const int M = c->hm.M;
-    const size_t el = prec == MORAP_F32 ? 4 : 8;
     const size_t pairs = (size_t)M * Kp;
-    c->d_x[0].ensure((size_t)c->S * Kp * el);
-    c->d_x[1].ensure((size_t)c->S * Kp * el);
     c->d_wc32.ensure(pairs * 4);
     c->d_wp32.ensure(pairs * 4);
     c->d_wc64.ensure(pairs * 8);
@@ -71,47 +74,59 @@ static void ensure_solve_buffers(morap_ctx* c, int K, int Kp, int prec) {
     c->d_res.ensure(pairs * 8);
     c->d_ymax.ensure(pairs * 8);
     c->d_active.ensure(pairs);
-    c->d_final_par.ensure(pairs);
+    c->d_pair_mask.ensure(pairs);
     c->d_pair_sweeps.ensure(pairs * 4);
     c->d_model_active.ensure(M);
     c->d_act_models.ensure((size_t)M * 4 + 4);
     c->d_act_prefix.ensure((size_t)(M + 1) * 4 + 4);
     c->d_counters.ensure(8 * 8);
-    c->d_c.ensure((size_t)K * M * 8);
     c->h_counters.ensure(8 * 8);
 }
 
-static k::ConvergeArgs converge_args(morap_ctx* c, int K, int Kp, int prec, double eps, int out_par) {
+static void ensure_values(morap_ctx* c, ValueSet& vs, int K, int Kp, int prec) {
+    const size_t el = prec == MORAP_F32 ? 4 : 8;
+    vs.x[0].ensure((size_t)c->S * Kp * el);
+    vs.x[1].ensure((size_t)c->S * Kp * el);
+    vs.final_par.ensure((size_t)c->hm.M * Kp);
+    vs.c.ensure((size_t)K * c->hm.M * 8);
+    vs.prec = prec;
+    vs.K = K;
+    vs.Kp = Kp;
+    vs.valid = false;
+}
+
+static k::ConvergeArgs converge_args(morap_ctx* c, ValueSet& vs, const uint8_t* mask, double eps, int out_par) {
     k::ConvergeArgs a{};
     a.res = c->d_res.as<unsigned long long>();
     a.ymax = c->d_ymax.as<unsigned long long>();
     a.active = c->d_active.as<uint8_t>();
-    a.final_par = c->d_final_par.as<uint8_t>();
+    a.final_par = vs.final_par.as<uint8_t>();
     a.pair_sweeps = c->d_pair_sweeps.as<int32_t>();
     a.model_active = c->d_model_active.as<uint8_t>();
-    a.c = c->d_c.as<double>();
+    a.c = vs.c.as<double>();
     a.init = c->d_init.as<int32_t>();
-    a.x_out = c->d_x[out_par].p;
+    a.mask = mask;
+    a.x_out = vs.x[out_par].p;
     a.counters = c->d_counters.as<int64_t>();
     a.M = c->hm.M;
-    a.K = K;
-    a.Kp = Kp;
-    a.prec = prec;
+    a.K = vs.K;
+    a.Kp = vs.Kp;
+    a.prec = vs.prec;
     a.out_par = out_par;
     a.eps = eps;
     // FP32 backups cannot resolve changes below a few units in the last
     // place of the values: stop there too (FP64: the bound is below eps)
-    a.unit = prec == MORAP_F32 ? 8.0 * std::ldexp(1.0, -24) : 8.0 * std::ldexp(1.0, -53);
+    a.unit = vs.prec == MORAP_F32 ? 8.0 * std::ldexp(1.0, -24) : 8.0 * std::ldexp(1.0, -53);
     a.tile_base = c->d_tile_base.as<int32_t>();
     a.act_models = c->d_act_models.as<int32_t>();
     a.act_prefix = c->d_act_prefix.as<int32_t>();
     a.rows_per_model = c->d_rows_per_model.as<int32_t>();
     a.states_per_model = c->d_states_per_model.as<int32_t>();
-    a.csr_bytes = prec == MORAP_F32 ? c->d_csr_bytes32.as<int64_t>() : c->d_csr_bytes64.as<int64_t>();
+    a.csr_bytes = vs.prec == MORAP_F32 ? c->d_csr_bytes32.as<int64_t>() : c->d_csr_bytes64.as<int64_t>();
     return a;
 }
 
-static k::SweepArgs sweep_args(morap_ctx* c, int Kp, int prec, int in_par) {
+static k::SweepArgs sweep_args(morap_ctx* c, ValueSet& vs, int in_par) {
     k::SweepArgs a{};
     a.tiles = c->d_tiles.as<Tile>();
     a.tile_base = c->d_tile_base.as<int32_t>();
@@ -121,87 +136,98 @@ static k::SweepArgs sweep_args(morap_ctx* c, int Kp, int prec, int in_par) {
     a.state_row = c->d_state_row.as<int32_t>();
     a.row_ptr = c->d_row_ptr.as<int32_t>();
     a.col = c->d_col.as<int32_t>();
-    const bool f32 = prec == MORAP_F32;
+    const bool f32 = vs.prec == MORAP_F32;
     a.prob = f32 ? c->d_prob32.p : c->d_prob64.p;
     a.rew = f32 ? c->d_rew32.p : c->d_rew64.p;
     a.wc = f32 ? c->d_wc32.p : c->d_wc64.p;
     a.wp = f32 ? c->d_wp32.p : c->d_wp64.p;
     a.active = c->d_active.as<uint8_t>();
-    a.x_in = c->d_x[in_par].p;
-    a.x_out = c->d_x[1 - in_par].p;
+    a.x_in = vs.x[in_par].p;
+    a.x_out = vs.x[1 - in_par].p;
     a.res = c->d_res.as<unsigned long long>();
     a.ymax = c->d_ymax.as<unsigned long long>();
-    a.Kp = Kp;
+    a.Kp = vs.Kp;
     return a;
 }
 
 static int persistent_grid(morap_ctx* c, const Variant& v) {
-    const int per_cu = v.wg >= 256 ? 8 : (v.wg >= 128 ? 16 : 16);
+    const int per_cu = v.wg >= 256 ? 8 : 16;
     int g = c->prop.multiProcessorCount * per_cu;
     const int tiles = (int)c->tiles.size();
     g = std::min(g, (tiles + 7) / 8 * 8);
     return std::max(8, g / 8 * 8);
 }
 
-// one chunk of `n` sweeps (n even): sweep, converge, compact per sweep
-static void enqueue_chunk(morap_ctx* c, const Variant& v, int K, int Kp, int prec, double eps, int n) {
+using EventPairs = std::vector<std::pair<hipEvent_t, hipEvent_t>>;
+
+// one chunk of `n` sweeps (n even): sweep, converge, compact per sweep;
+// `ev` (optional) receives an event pair around every sweep kernel
+static void enqueue_chunk(morap_ctx* c, ValueSet& vs, const uint8_t* mask, const Variant& v, double eps, int n,
+                          EventPairs* ev = nullptr) {
     const int grid = persistent_grid(c, v);
-    const int ktiles = Kp / kt_of(v);
+    const int ktiles = vs.Kp / kt_of(v);
     for (int i = 0; i < n; ++i) {
         const int in_par = i & 1;
-        k::sweep(c->stream, prec, v, grid, ktiles, sweep_args(c, Kp, prec, in_par));
-        const auto ca = converge_args(c, K, Kp, prec, eps, 1 - in_par);
+        if (ev) {
+            ev->emplace_back();
+            MORAP_HIP(hipEventCreate(&ev->back().first));
+            MORAP_HIP(hipEventCreate(&ev->back().second));
+            MORAP_HIP(hipEventRecord(ev->back().first, c->stream));
+        }
+        k::sweep(c->stream, vs.prec, v, grid, ktiles, sweep_args(c, vs, in_par));
+        if (ev) MORAP_HIP(hipEventRecord(ev->back().second, c->stream));
+        const auto ca = converge_args(c, vs, mask, eps, 1 - in_par);
         k::converge(c->stream, ca);
         k::compact(c->stream, ca);
     }
 }
 
-static void reset_solve(morap_ctx* c, int K, int Kp, int prec, double eps) {
-    const size_t el = prec == MORAP_F32 ? 4 : 8;
-    if (el == 4) {
-        k::fill_f32(c->stream, c->d_x[0].as<float>(), 0.f, c->S * Kp);
-        k::fill_f32(c->stream, c->d_x[1].as<float>(), 0.f, c->S * Kp);
+static void reset_solve(morap_ctx* c, ValueSet& vs, const uint8_t* mask, double eps) {
+    const int64_t n = c->S * vs.Kp;
+    if (vs.prec == MORAP_F32) {
+        k::fill_f32(c->stream, vs.x[0].as<float>(), 0.f, n);
+        k::fill_f32(c->stream, vs.x[1].as<float>(), 0.f, n);
     } else {
-        k::fill_f64(c->stream, c->d_x[0].as<double>(), 0.0, c->S * Kp);
-        k::fill_f64(c->stream, c->d_x[1].as<double>(), 0.0, c->S * Kp);
+        k::fill_f64(c->stream, vs.x[0].as<double>(), 0.0, n);
+        k::fill_f64(c->stream, vs.x[1].as<double>(), 0.0, n);
     }
-    k::init_solve(c->stream, converge_args(c, K, Kp, prec, eps, 1));
+    k::init_solve(c->stream, converge_args(c, vs, mask, eps, 1));
 }
 
-static void release_graph(morap_ctx* c) {
-    if (c->chunk_exec) (void)hipGraphExecDestroy(c->chunk_exec);
-    if (c->chunk_graph) (void)hipGraphDestroy(c->chunk_graph);
-    c->chunk_exec = nullptr;
-    c->chunk_graph = nullptr;
-    c->graph_key.clear();
+static void release_graph(morap_ctx* c, int g) {
+    if (c->chunk_exec[g]) (void)hipGraphExecDestroy(c->chunk_exec[g]);
+    if (c->chunk_graph[g]) (void)hipGraphDestroy(c->chunk_graph[g]);
+    c->chunk_exec[g] = nullptr;
+    c->chunk_graph[g] = nullptr;
+    c->graph_key[g].clear();
 }
 
-// run one chunk, replaying a captured graph when asked to
-static void run_chunk(morap_ctx* c, const Variant& v, int K, int Kp, int prec, double eps, int n,
-                      bool graph) {
-    if (!graph) {
-        enqueue_chunk(c, v, K, Kp, prec, eps, n);
+// run one chunk, replaying a captured graph (slot g) when asked to
+static void run_chunk(morap_ctx* c, int g, ValueSet& vs, const uint8_t* mask, const Variant& v, double eps, int n,
+                      bool graph, EventPairs* ev) {
+    if (!graph || ev) {
+        enqueue_chunk(c, vs, mask, v, eps, n, ev);
         return;
     }
-    char key[256];
-    snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%.17g/%p/%p/%zu", v.id, K, Kp, prec, n, eps, c->d_x[0].p,
-             c->d_x[1].p, c->tiles.size());
-    if (c->graph_key != key) {
-        release_graph(c);
+    char key[320];
+    snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%.17g/%p/%p/%p/%p/%zu", v.id, vs.K, vs.Kp, vs.prec, n, eps,
+             vs.x[0].p, vs.x[1].p, (const void*)mask, vs.c.p, c->tiles.size());
+    if (c->graph_key[g] != key) {
+        release_graph(c, g);
         MORAP_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
         try {
-            enqueue_chunk(c, v, K, Kp, prec, eps, n);
+            enqueue_chunk(c, vs, mask, v, eps, n);
         } catch (...) {
-            hipGraph_t g = nullptr;
-            (void)hipStreamEndCapture(c->stream, &g);
-            if (g) (void)hipGraphDestroy(g);
+            hipGraph_t gr = nullptr;
+            (void)hipStreamEndCapture(c->stream, &gr);
+            if (gr) (void)hipGraphDestroy(gr);
             throw;
         }
-        MORAP_HIP(hipStreamEndCapture(c->stream, &c->chunk_graph));
-        MORAP_HIP(hipGraphInstantiate(&c->chunk_exec, c->chunk_graph, nullptr, nullptr, 0));
-        c->graph_key = key;
+        MORAP_HIP(hipStreamEndCapture(c->stream, &c->chunk_graph[g]));
+        MORAP_HIP(hipGraphInstantiate(&c->chunk_exec[g], c->chunk_graph[g], nullptr, nullptr, 0));
+        c->graph_key[g] = key;
     }
-    MORAP_HIP(hipGraphLaunch(c->chunk_exec, c->stream));
+    MORAP_HIP(hipGraphLaunch(c->chunk_exec[g], c->stream));
 }
 
 static void read_counters(morap_ctx* c) {
@@ -209,15 +235,15 @@ static void read_counters(morap_ctx* c) {
     MORAP_HIP(hipStreamSynchronize(c->stream));
 }
 
-// time `n` sweeps of variant v from a fresh start (autotuner)
-static double time_variant(morap_ctx* c, const Variant& v, int K, int Kp, int prec, double eps) {
+// time 6 sweeps of variant v from a fresh start (autotuner)
+static double time_variant(morap_ctx* c, ValueSet& vs, const uint8_t* mask, const Variant& v, double eps) {
     hipEvent_t e0, e1;
     MORAP_HIP(hipEventCreate(&e0));
     MORAP_HIP(hipEventCreate(&e1));
-    reset_solve(c, K, Kp, prec, eps);
-    enqueue_chunk(c, v, K, Kp, prec, eps, 2);
+    reset_solve(c, vs, mask, eps);
+    enqueue_chunk(c, vs, mask, v, eps, 2);
     MORAP_HIP(hipEventRecord(e0, c->stream));
-    enqueue_chunk(c, v, K, Kp, prec, eps, 6);
+    enqueue_chunk(c, vs, mask, v, eps, 6);
     MORAP_HIP(hipEventRecord(e1, c->stream));
     MORAP_HIP(hipEventSynchronize(e1));
     float ms = 0;
@@ -227,22 +253,24 @@ static double time_variant(morap_ctx* c, const Variant& v, int K, int Kp, int pr
     return ms;
 }
 
-static const Variant& choose_variant(morap_ctx* c, int K, int Kp, int prec, double eps, int schedule) {
+// autotuner: the fastest candidate variant for (precision, padded width,
+// restricted or not), timed on the loaded models and cached on the context
+static const Variant& choose_variant(morap_ctx* c, ValueSet& vs, const uint8_t* mask, double eps, int schedule) {
     if (schedule > 0) {
         const Variant& v = variant_by_id(schedule);
-        MORAP_CHECK(Kp % kt_of(v) == 0, MORAP_E_INVALID, "variant does not divide the padded column count");
+        MORAP_CHECK(vs.Kp % kt_of(v) == 0, MORAP_E_INVALID, "variant does not divide the padded column count");
         return v;
     }
-    const int64_t key = (int64_t)prec << 32 | Kp;
+    const int64_t key = ((int64_t)vs.prec << 40) | ((int64_t)(mask != nullptr) << 32) | vs.Kp;
     for (auto& t : c->tuned)
         if (t.first == key) return variant_by_id(t.second);
-    auto cand = candidates(Kp);
+    auto cand = candidates(vs.Kp);
     MORAP_CHECK(!cand.empty(), MORAP_E_UNSUPPORTED, "no sweep variant for this column count");
     int best = cand[0].id;
     if (cand.size() > 1) {
         double best_ms = 1e300;
         for (const auto& v : cand) {
-            const double ms = time_variant(c, v, K, Kp, prec, eps);
+            const double ms = time_variant(c, vs, mask, v, eps);
             if (ms < best_ms) {
                 best_ms = ms;
                 best = v.id;
@@ -253,10 +281,101 @@ static const Variant& choose_variant(morap_ctx* c, int K, int Kp, int prec, doub
     return variant_by_id(best);
 }
 
+// Batched value iteration into `vs` until every (masked) pair has converged.
+static void run_vi(morap_ctx* c, int g, ValueSet& vs, const uint8_t* mask, const morap_vi_opts& o, Stats& st) {
+    const Variant& v = choose_variant(c, vs, mask, o.eps_vi, o.schedule);
+    c->last_variant = v.id;
+    const int chunk = std::max(2, (o.check_every + 1) / 2 * 2);
+    hipEvent_t e0, e1;
+    MORAP_HIP(hipEventCreate(&e0));
+    MORAP_HIP(hipEventCreate(&e1));
+    reset_solve(c, vs, mask, o.eps_vi);
+    MORAP_HIP(hipEventRecord(e0, c->stream));
+    int64_t launched = 0;
+    int64_t* h = c->h_counters.as<int64_t>();
+    EventPairs ev;
+    auto harvest = [&] {
+        for (auto& e : ev) {
+            float t = 0;
+            MORAP_HIP(hipEventElapsedTime(&t, e.first, e.second));
+            st.ms_sweep_kernel += t;
+            st.sweep_launches += 1;
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+        ev.clear();
+    };
+    while (true) {
+        run_chunk(c, g, vs, mask, v, o.eps_vi, chunk, o.use_graph != 0, o.time_kernels ? &ev : nullptr);
+        launched += chunk;
+        read_counters(c);
+        harvest();
+        if (h[3] == 0) break;
+        if (launched >= o.max_sweeps) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            fail(MORAP_E_NOT_CONVERGED, "value iteration: " + std::to_string(h[3]) +
+                                            " (model, column) pairs still active after " +
+                                            std::to_string(launched) + " sweeps");
+        }
+    }
+    MORAP_HIP(hipEventRecord(e1, c->stream));
+    MORAP_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    MORAP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::vector<int32_t> ps((size_t)c->hm.M * vs.Kp);
+    MORAP_HIP(hipMemcpy(ps.data(), c->d_pair_sweeps.p, ps.size() * 4, hipMemcpyDeviceToHost));
+    const size_t el = vs.prec == MORAP_F32 ? 4 : 8;
+    st.backups += h[4];
+    st.bytes += (double)h[6] + 2.0 * el * (double)h[7];
+    st.max_pair_sweeps = std::max<int64_t>(st.max_pair_sweeps, *std::max_element(ps.begin(), ps.end()));
+    st.ms_vi += ms;
+    st.variant = v.id;
+    if (mask) st.polish_sweeps += h[5];
+    else st.sweeps += h[5];
+    vs.valid = true;
+}
+
 // ---------------------------------------------------------------------------
 // solve
 // ---------------------------------------------------------------------------
+static void add_stats(Stats& a, const Stats& b) {
+    a.backups += b.backups;
+    a.sweeps += b.sweeps;
+    a.max_pair_sweeps = std::max(a.max_pair_sweeps, b.max_pair_sweeps);
+    a.eval_sweeps += b.eval_sweeps;
+    a.polish_sweeps += b.polish_sweeps;
+    a.rank_rounds += b.rank_rounds;
+    a.bytes += b.bytes;
+    a.ms_vi += b.ms_vi;
+    a.ms_eval += b.ms_eval;
+    a.ms_total += b.ms_total;
+    a.ms_sweep_kernel += b.ms_sweep_kernel;
+    a.sweep_launches += b.sweep_launches;
+    a.variant = b.variant ? b.variant : a.variant;
+}
+
+static void solve_impl(morap_ctx* c, const double* W, int K, const morap_vi_opts& o, double* c_out, Stats& st);
+static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const morap_vi_opts& o, double* r_out,
+                          Stats& st);
+
 void solve(morap_ctx* c, const double* W, int K, const morap_vi_opts& o, double* c_out, Stats& st) {
+    Stats local;
+    solve_impl(c, W, K, o, c_out, local);
+    add_stats(st, local);
+    add_stats(c->cum, local);
+}
+
+void evaluate(morap_ctx* c, const int32_t* assign, int K, const morap_vi_opts& o, double* r_out, Stats& st) {
+    Stats local;
+    evaluate_impl(c, assign, K, o, r_out, local);
+    add_stats(st, local);
+    add_stats(c->cum, local);
+}
+
+static void solve_impl(morap_ctx* c, const double* W, int K, const morap_vi_opts& o, double* c_out, Stats& st) {
     MORAP_CHECK(c->loaded, MORAP_E_STATE, "no models loaded");
     MORAP_CHECK(W && K >= 1 && K <= 4096, MORAP_E_INVALID, "need 1 <= K <= 4096 weight vectors");
     MORAP_CHECK(o.precision == MORAP_F32 || o.precision == MORAP_F64, MORAP_E_INVALID, "bad precision");
@@ -275,13 +394,13 @@ void solve(morap_ctx* c, const double* W, int K, const morap_vi_opts& o, double*
     const auto t0 = std::chrono::steady_clock::now();
     const int prec = o.precision;
     const int Kp = padded_k(K);
-    if (c->K != K || c->Kp != Kp || c->prec != prec) release_graph(c);
-    ensure_solve_buffers(c, K, Kp, prec);
+    c->solved = false;
+    c->evaluated = false;
+    ensure_scratch(c, Kp);
+    ensure_values(c, c->vmain, K, Kp, prec);
     c->K = K;
     c->Kp = Kp;
     c->prec = prec;
-    c->solved = false;
-    c->evaluated = false;
     c->W.assign(W, W + (size_t)K * d);
 
     // per-(model, column) weights of the model's two objectives
@@ -301,55 +420,16 @@ void solve(morap_ctx* c, const double* W, int K, const morap_vi_opts& o, double*
     MORAP_HIP(hipMemcpyAsync(c->d_wc32.p, wc32.data(), wc32.size() * 4, hipMemcpyHostToDevice, c->stream));
     MORAP_HIP(hipMemcpyAsync(c->d_wp32.p, wp32.data(), wp32.size() * 4, hipMemcpyHostToDevice, c->stream));
 
-    const Variant& v = choose_variant(c, K, Kp, prec, o.eps_vi, o.schedule);
-    c->last_variant = v.id;
-    const int chunk = std::max(2, (o.check_every + 1) / 2 * 2);
-
-    hipEvent_t e0, e1;
-    MORAP_HIP(hipEventCreate(&e0));
-    MORAP_HIP(hipEventCreate(&e1));
-    reset_solve(c, K, Kp, prec, o.eps_vi);
-    MORAP_HIP(hipEventRecord(e0, c->stream));
-    int64_t launched = 0;
-    int64_t* h = c->h_counters.as<int64_t>();
-    while (true) {
-        run_chunk(c, v, K, Kp, prec, o.eps_vi, chunk, o.use_graph != 0);
-        launched += chunk;
-        read_counters(c);
-        if (h[3] == 0) break;
-        if (launched >= o.max_sweeps) {
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            fail(MORAP_E_NOT_CONVERGED, "value iteration: " + std::to_string(h[3]) +
-                                            " (model, column) pairs still active after " +
-                                            std::to_string(launched) + " sweeps");
-        }
-    }
-    MORAP_HIP(hipEventRecord(e1, c->stream));
-    MORAP_HIP(hipEventSynchronize(e1));
-    float ms = 0;
-    MORAP_HIP(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-
-    std::vector<int32_t> ps((size_t)M * Kp);
-    MORAP_HIP(hipMemcpyAsync(ps.data(), c->d_pair_sweeps.p, ps.size() * 4, hipMemcpyDeviceToHost, c->stream));
+    run_vi(c, 0, c->vmain, nullptr, o, st);
     if (c_out)
-        MORAP_HIP(hipMemcpyAsync(c_out, c->d_c.p, (size_t)K * M * 8, hipMemcpyDeviceToHost, c->stream));
+        MORAP_HIP(hipMemcpyAsync(c_out, c->vmain.c.p, (size_t)K * M * 8, hipMemcpyDeviceToHost, c->stream));
     MORAP_HIP(hipStreamSynchronize(c->stream));
-    const size_t el = prec == MORAP_F32 ? 4 : 8;
-    st.sweeps += h[5];
-    st.backups += h[4];
-    st.bytes += (double)h[6] + 2.0 * el * (double)h[7];
-    st.max_pair_sweeps = std::max<int64_t>(st.max_pair_sweeps, *std::max_element(ps.begin(), ps.end()));
-    st.ms_vi += ms;
-    st.variant = v.id;
     st.ms_total += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     c->solved = true;
 }
 
 // ---------------------------------------------------------------------------
-// evaluate: polish (FP32 solves), policy extraction, Alg. 4
+// evaluate: FP64 values of the assigned pairs, policy extraction, Alg. 4
 // ---------------------------------------------------------------------------
 static k::InstArgs inst_args(morap_ctx* c, int n_tiles, int n_inst) {
     k::InstArgs a{};
@@ -370,7 +450,11 @@ static k::InstArgs inst_args(morap_ctx* c, int n_tiles, int n_inst) {
     return a;
 }
 
-void evaluate(morap_ctx* c, const int32_t* assign, int K, const morap_vi_opts& o, double* r_out, Stats& st) {
+// widenings of the tie tolerance in policy extraction (tau * 10^k, k <= 6)
+constexpr int kTauSteps = 6;
+
+static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const morap_vi_opts& o, double* r_out,
+                          Stats& st) {
     MORAP_CHECK(c->solved, MORAP_E_STATE, "morap_evaluate needs a morap_solve first");
     MORAP_CHECK(K == c->K, MORAP_E_INVALID, "K differs from the last morap_solve");
     MORAP_CHECK(assign != nullptr, MORAP_E_INVALID, "assign is NULL");
@@ -387,7 +471,8 @@ void evaluate(morap_ctx* c, const int32_t* assign, int K, const morap_vi_opts& o
     }
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = c->stream;
-    // instances (k, m) in column-major task order
+    c->evaluated = false;
+    // instances (k, m), task-major within each column
     const int n = K * nJ;
     c->assign.assign(assign, assign + (size_t)K * nJ);
     c->inst_k.resize(n);
@@ -421,8 +506,7 @@ void evaluate(morap_ctx* c, const int32_t* assign, int K, const morap_vi_opts& o
     c->d_inst_tiles.ensure(tiles.size() * 4 + 8);
     c->d_iwc.ensure((size_t)n * 8);
     c->d_iwp.ensure((size_t)n * 8);
-    c->d_xi[0].ensure((size_t)NS * 8 + 8);
-    c->d_xi[1].ensure((size_t)NS * 8 + 8);
+    c->d_xi.ensure((size_t)NS * 8 + 8);
     c->d_ires.ensure((size_t)2 * n * 8);
     c->d_iactive.ensure((size_t)2 * n);
     c->d_ipar.ensure((size_t)2 * n);
@@ -444,67 +528,58 @@ void evaluate(morap_ctx* c, const int32_t* assign, int K, const morap_vi_opts& o
     const k::InstArgs a = inst_args(c, n_tiles, n);
     int64_t* dctr = c->d_counters.as<int64_t>();
     int64_t* h = c->h_counters.as<int64_t>();
-    double* xi0 = c->d_xi[0].as<double>();
-    double* xi1 = c->d_xi[1].as<double>();
     unsigned long long* ires = c->d_ires.as<unsigned long long>();
     uint8_t* iact = c->d_iactive.as<uint8_t>();
     uint8_t* ipar = c->d_ipar.as<uint8_t>();
     const int chunk = std::max(2, (o.check_every + 1) / 2 * 2);
 
+    // FP64 values of the assigned pairs: after an FP32 solve, value
+    // iteration in FP64 from 0 on exactly those pairs
+    ValueSet* src = &c->vmain;
+    if (c->prec == MORAP_F32) {
+        ensure_values(c, c->vref, K, c->Kp, MORAP_F64);
+        uint8_t* pm = c->d_pair_mask.as<uint8_t>();
+        k::fill_u8(s, pm, 0, (int64_t)c->hm.M * c->Kp);
+        k::mark_pairs(s, a, c->Kp, pm);
+        run_vi(c, 1, c->vref, pm, o, st);
+        src = &c->vref;
+    }
+
     hipEvent_t e0, e1;
     MORAP_HIP(hipEventCreate(&e0));
     MORAP_HIP(hipEventCreate(&e1));
-    MORAP_HIP(hipEventRecord(e0, s));
-
-    // final values of each instance's column
-    k::gather_columns(s, a, c->prec, c->d_x[0].p, c->d_x[1].p, c->d_final_par.as<uint8_t>(), c->Kp, xi0);
-
     auto cleanup = [&] {
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
     };
+    MORAP_HIP(hipEventRecord(e0, s));
+    double* xi = c->d_xi.as<double>();
+    k::gather_columns(s, a, MORAP_F64, src->x[0].p, src->x[1].p, src->final_par.as<uint8_t>(), src->Kp, xi);
 
-    // FP64 polish of FP32 solves: value iteration of each instance from its
-    // FP32 values until the FP64 residual is <= eps_vi
-    if (c->prec == MORAP_F32) {
-        k::set_active(s, n, a, iact, ires, ipar, 1);
-        int64_t done_sweeps = 0;
-        while (true) {
-            for (int i = 0; i < chunk; ++i) {
-                const bool even = (i & 1) == 0;
-                k::polish_sweep(s, a, c->d_iwc.as<double>(), c->d_iwp.as<double>(), iact, even ? xi0 : xi1,
-                                even ? xi1 : xi0, ires);
-                k::fill_i64(s, dctr, 0, 1);
-                k::inst_converge(s, n, ires, iact, ipar, even ? 1 : 0, o.eps_vi, dctr);
-            }
-            done_sweeps += chunk;
-            read_counters(c);
-            if (h[0] == 0) break;
-            if (done_sweeps >= o.max_sweeps) {
-                cleanup();
-                fail(MORAP_E_NOT_CONVERGED, "FP64 polish did not converge");
-            }
-        }
-        st.polish_sweeps += done_sweeps;
-        k::select_final(s, a, xi0, xi1, ipar, 1);
-    }
-
-    // policy extraction: tau-optimal masks, then attractor rounds
+    // Attractor rounds with the tolerance tau; states left unranked get the
+    // tolerance widened tenfold (up to tau * 1e6) while ranked states keep
+    // their choice.
     uint32_t* mask = c->d_mask.as<uint32_t>();
     int32_t* rank = c->d_rank.as<int32_t>();
     int8_t* mu = c->d_mu.as<int8_t>();
-    k::opt_mask(s, a, c->d_iwc.as<double>(), c->d_iwp.as<double>(), xi0, o.tau, mask, rank, mu);
+    k::opt_mask(s, a, c->d_iwc.as<double>(), c->d_iwp.as<double>(), xi, o.tau, mask, rank, mu, false);
     int level = 0;
-    while (true) {
+    double tau = o.tau;
+    for (int widen = 0;; ++widen) {
+        while (true) {
+            k::fill_i64(s, dctr, 0, 1);
+            for (int i = 0; i < chunk; ++i) k::rank_round(s, a, mask, rank, mu, ++level, dctr);
+            read_counters(c);
+            if (h[0] == 0) break;
+        }
         k::fill_i64(s, dctr, 0, 1);
-        for (int i = 0; i < chunk; ++i) k::rank_round(s, a, mask, rank, mu, ++level, dctr);
+        k::count_unranked(s, a, rank, dctr);
         read_counters(c);
-        if (h[0] == 0) break;
+        if (h[0] == 0 || widen == kTauSteps) break;
+        tau *= 10.0;
+        k::opt_mask(s, a, c->d_iwc.as<double>(), c->d_iwp.as<double>(), xi, tau, mask, rank, mu, true);
     }
     st.rank_rounds += level;
-    k::fill_i64(s, dctr, 0, 1);
-    k::count_unranked(s, a, rank, dctr);
-    read_counters(c);
     if (h[0] != 0) {
         cleanup();
         fail(MORAP_E_IMPROPER, std::to_string(h[0]) + " states cannot reach done through tau-optimal actions");
@@ -528,8 +603,23 @@ void evaluate(morap_ctx* c, const int32_t* assign, int K, const morap_vi_opts& o
         read_counters(c);
         if (h[0] == 0) break;
         if (esweeps >= o.max_sweeps) {
+            // name the (column, task, objective) entries still running; the
+            // policies stay readable through morap_get_policy
+            std::vector<uint8_t> still((size_t)2 * n);
+            MORAP_HIP(hipMemcpy(still.data(), iact, still.size(), hipMemcpyDeviceToHost));
+            std::string who;
+            int shown = 0;
+            for (int q = 0; q < 2 * n && shown < 8; ++q)
+                if (still[q]) {
+                    who += " (k=" + std::to_string(q / 2 / nJ) + ", j=" + std::to_string(q / 2 % nJ) +
+                           (q % 2 ? ", probability)" : ", cost)");
+                    ++shown;
+                }
+            c->eK = K;
+            c->evaluated = true;
             cleanup();
-            fail(MORAP_E_NOT_CONVERGED, "policy evaluation did not converge");
+            fail(MORAP_E_NOT_CONVERGED, "policy evaluation did not converge after " + std::to_string(esweeps) +
+                                            " sweeps:" + who);
         }
     }
     st.eval_sweeps += esweeps;

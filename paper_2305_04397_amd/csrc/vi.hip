@@ -16,9 +16,9 @@
 //  * converge / compact: freeze pairs whose residual is within tolerance
 //    (the stop test of Alg. 3), record their value at the initial state and
 //    rebuild the active tile list.
-//  * instance kernels: FP64 polish sweeps, eps-optimal action masks,
-//    attractor ranking rounds and fixed-policy evaluation sweeps (Alg. 4) on
-//    (column, model) instances, one thread per state.
+//  * instance kernels: eps-optimal action masks, attractor ranking rounds and
+//    fixed-policy evaluation sweeps (Alg. 4) on (column, model) instances, one
+//    thread per state.
 #include "common.h"
 
 #include <cfloat>
@@ -164,6 +164,9 @@ bellman_sweep(const Tile* __restrict__ tiles, const int32_t* __restrict__ tile_b
             if (act_prefix[mid] <= t) lo = mid; else hi = mid;
         }
         const int m = act_models[lo];
+        // nothing to do when no column of this k-tile is active for the model
+        const int tile_on = tid < KT ? active_all[(int64_t)m * Kp + blockIdx.y * KT + tid] : 0;
+        if (!__syncthreads_or(tile_on)) continue;
         const Tile tl = tiles[tile_base[m] + (t - act_prefix[lo])];
         const int s0 = tl.s_begin, s1 = tl.s_end, ns = s1 - s0;
         const int r0 = state_row[s0], r1 = state_row[s1];
@@ -455,7 +458,7 @@ __global__ void init_solve_kernel(ConvergeArgs a) {
     if (i < n) {
         const int m = (int)(i / a.Kp);
         const int k = (int)(i % a.Kp);
-        const bool on = k < a.K && a.init[m] >= 0;
+        const bool on = k < a.K && a.init[m] >= 0 && (a.mask == nullptr || a.mask[i] != 0);
         a.active[i] = on ? 1 : 0;
         a.final_par[i] = 0;
         a.pair_sweeps[i] = 0;
@@ -523,44 +526,6 @@ void gather_columns(hipStream_t s, const InstArgs& a, int prec, const void* x0, 
     MORAP_HIP(hipGetLastError());
 }
 
-// FP64 scalarised max-backup on one column of one model
-__global__ void __launch_bounds__(256) polish_kernel(InstArgs a, const double* wc, const double* wp,
-                                                     const uint8_t* active, const double* x_in,
-                                                     double* x_out, unsigned long long* res) {
-    InstLoc L;
-    const bool ok = inst_locate(a, L);
-    double r = 0.0;
-    int inst = ok ? L.inst : -1;
-    if (ok && active[L.inst]) {
-        const int64_t ib = a.inst_base[L.inst];
-        const double w0 = wc[L.inst], w1 = wp[L.inst];
-        double best = -INFINITY;
-        for (int row = a.state_row[L.gs]; row < a.state_row[L.gs + 1]; ++row) {
-            double acc = w0 * a.rew[2 * row] + w1 * a.rew[2 * row + 1];
-            for (int e = a.row_ptr[row]; e < a.row_ptr[row + 1]; ++e)
-                acc = fma(a.prob[e], x_in[ib + (a.col[e] - L.sb)], acc);
-            best = fmax(best, acc);
-        }
-        x_out[L.is] = best;
-        r = fabs(best - x_in[L.is]);
-    }
-    r = wave_max(r);
-    // a tile holds states of one instance, so a wave does too
-    if ((threadIdx.x & 63) == 0 && r > 0.0) {
-        const int i0 = a.inst_tiles[2 * blockIdx.x];
-        atomicMax(&res[i0], (unsigned long long)__double_as_longlong(r));
-    }
-    (void)inst;
-}
-
-void polish_sweep(hipStream_t s, const InstArgs& a, const double* wc, const double* wp,
-                  const uint8_t* active, const double* x_in, double* x_out, unsigned long long* res) {
-    if (a.n_tiles <= 0) return;
-    hipLaunchKernelGGL(polish_kernel, dim3(a.n_tiles), dim3(256), 0, s, a, wc, wp, active, x_in, x_out,
-                       res);
-    MORAP_HIP(hipGetLastError());
-}
-
 __global__ void inst_converge_kernel(int n, unsigned long long* res, uint8_t* active, uint8_t* par,
                                      int out_par, double eps, int64_t* counter) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -590,11 +555,14 @@ void inst_converge(hipStream_t s, int n, unsigned long long* res, uint8_t* activ
 
 // eps-optimal rows of every state: bit r of mask = row r (local) has
 // Q(s, r) >= max_a Q(s, a) - tau, with Q in FP64 at the final values.
+// With `only_unranked` the masks of ranked states are kept and only unranked
+// states get the (wider) tolerance; otherwise every state starts unranked.
 __global__ void __launch_bounds__(256) opt_mask_kernel(InstArgs a, const double* wc, const double* wp,
                                                        const double* x, double tau, uint32_t* mask,
-                                                       int32_t* rank, int8_t* mu) {
+                                                       int32_t* rank, int8_t* mu, int only_unranked) {
     InstLoc L;
     if (!inst_locate(a, L)) return;
+    if (only_unranked && rank[L.is] >= 0) return;
     const int64_t ib = a.inst_base[L.inst];
     const double w0 = wc[L.inst], w1 = wp[L.inst];
     const int rb = a.state_row[L.gs], re = a.state_row[L.gs + 1];
@@ -614,20 +582,24 @@ __global__ void __launch_bounds__(256) opt_mask_kernel(InstArgs a, const double*
         if (acc >= qmax - tau) bits |= 1u << (row - rb);
     }
     mask[L.is] = bits;
-    rank[L.is] = -1;
-    mu[L.is] = -1;
+    if (!only_unranked) {
+        rank[L.is] = -1;
+        mu[L.is] = -1;
+    }
 }
 
 void opt_mask(hipStream_t s, const InstArgs& a, const double* wc, const double* wp, const double* x,
-              double tau, uint32_t* mask, int32_t* rank, int8_t* mu) {
+              double tau, uint32_t* mask, int32_t* rank, int8_t* mu, bool only_unranked) {
     if (a.n_tiles <= 0) return;
-    hipLaunchKernelGGL(opt_mask_kernel, dim3(a.n_tiles), dim3(256), 0, s, a, wc, wp, x, tau, mask, rank, mu);
+    hipLaunchKernelGGL(opt_mask_kernel, dim3(a.n_tiles), dim3(256), 0, s, a, wc, wp, x, tau, mask, rank, mu,
+                       only_unranked ? 1 : 0);
     MORAP_HIP(hipGetLastError());
 }
 
 // Attractor round `level`: an unranked state is ranked when one of its
 // eps-optimal rows moves mass into done or into a state ranked in an earlier
-// round; its action is the lowest such row.
+// round; its action is the row moving the most probability there (masses
+// within 1e-12 are equal; then the lowest row wins).
 __global__ void __launch_bounds__(256) rank_kernel(InstArgs a, const uint32_t* mask, int32_t* rank,
                                                    int8_t* mu, int level, int64_t* counter) {
     InstLoc L;
@@ -636,21 +608,36 @@ __global__ void __launch_bounds__(256) rank_kernel(InstArgs a, const uint32_t* m
         const int64_t ib = a.inst_base[L.inst];
         const int rb = a.state_row[L.gs];
         uint32_t bits = mask[L.is];
+        int best_lr = -1;
+        double best_m = -1.0;
         while (bits) {
             const int lr = __builtin_ctz(bits);
             bits &= bits - 1;
             const int row = rb + lr;
+            const int e0 = a.row_ptr[row], e1 = a.row_ptr[row + 1];
             bool hit = a.to_done[row] != 0;
-            for (int e = a.row_ptr[row]; !hit && e < a.row_ptr[row + 1]; ++e) {
-                const int32_t rk = rank[ib + (a.col[e] - L.sb)];
-                hit = rk >= 0 && rk < level;
-            }
+            double m = 0.0;
             if (hit) {
-                rank[L.is] = level;
-                mu[L.is] = (int8_t)lr;
-                got = 1;
-                break;
+                double live = 0.0;
+                for (int e = e0; e < e1; ++e) live += a.prob[e];
+                m = 1.0 - live;
             }
+            for (int e = e0; e < e1; ++e) {
+                const int32_t rk = rank[ib + (a.col[e] - L.sb)];
+                if (rk >= 0 && rk < level) {
+                    hit = true;
+                    m += a.prob[e];
+                }
+            }
+            if (hit && m > best_m + 1e-12) {
+                best_m = m;
+                best_lr = lr;
+            }
+        }
+        if (best_lr >= 0) {
+            rank[L.is] = level;
+            mu[L.is] = (int8_t)best_lr;
+            got = 1;
         }
     }
 #pragma unroll
@@ -750,6 +737,18 @@ void select_final(hipStream_t s, const InstArgs& a, double* x0, const double* x1
                   int width) {
     if (a.n_tiles <= 0) return;
     hipLaunchKernelGGL(select_final_kernel, dim3(a.n_tiles), dim3(256), 0, s, a, x0, x1, par, width);
+    MORAP_HIP(hipGetLastError());
+}
+
+__global__ void mark_pairs_kernel(InstArgs a, int Kp, uint8_t* mask) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.n_inst) return;
+    mask[(int64_t)a.inst_model[q] * Kp + a.inst_k[q]] = 1;
+}
+
+void mark_pairs(hipStream_t s, const InstArgs& a, int Kp, uint8_t* mask) {
+    if (a.n_inst <= 0) return;
+    hipLaunchKernelGGL(mark_pairs_kernel, dim3((a.n_inst + 255) / 256), dim3(256), 0, s, a, Kp, mask);
     MORAP_HIP(hipGetLastError());
 }
 

@@ -61,15 +61,15 @@ class Model(C.Structure):
 class ViOpts(C.Structure):
     _fields_ = [("eps_vi", C.c_double), ("eps_eval", C.c_double), ("tau", C.c_double),
                 ("precision", C.c_int32), ("max_sweeps", C.c_int32), ("check_every", C.c_int32),
-                ("schedule", C.c_int32), ("use_graph", C.c_int32), ("reserved", C.c_int32)]
+                ("schedule", C.c_int32), ("use_graph", C.c_int32), ("time_kernels", C.c_int32)]
 
 
 class Stats(C.Structure):
     _fields_ = [("backups", C.c_int64), ("sweeps", C.c_int64), ("max_pair_sweeps", C.c_int64),
                 ("eval_sweeps", C.c_int64), ("polish_sweeps", C.c_int64), ("rank_rounds", C.c_int64),
                 ("excluded", C.c_int64), ("bytes", C.c_double), ("ms_vi", C.c_double),
-                ("ms_eval", C.c_double), ("ms_total", C.c_double), ("variant", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("ms_eval", C.c_double), ("ms_total", C.c_double), ("ms_sweep_kernel", C.c_double),
+                ("sweep_launches", C.c_int64), ("variant", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -112,9 +112,11 @@ _sig("morap_evaluate", C.c_int, _ctxp, _p, C.c_int, C.POINTER(ViOpts), _p, C.POI
 _sig("morap_assign", C.c_int, _ctxp, _p, C.c_int, _p)
 _sig("morap_support", C.c_int, _ctxp, _p, C.c_int, C.POINTER(ViOpts), _p, _p, _p, C.POINTER(Stats))
 _sig("morap_get_policy", C.c_int, _ctxp, C.c_int, C.c_int, _p)
+_sig("morap_get_stats", C.c_int, _ctxp, C.POINTER(Stats))
+_sig("morap_reset_stats", C.c_int, _ctxp)
 _sig("morap_get_values", C.c_int, _ctxp, C.c_int, C.c_int, _p)
 _sig("morap_query", C.c_int, _ctxp, _p, _p, C.POINTER(QueryOpts), C.POINTER(QueryResult))
-_sig("morap_query_batch", C.c_int, _ctxp, _p, C.c_int, _p, C.POINTER(QueryOpts), C.POINTER(QueryResult))
+_sig("morap_query_batch", C.c_int, _ctxp, _p, _p, C.c_int, _p, C.POINTER(QueryOpts), C.POINTER(QueryResult))
 _sig("morap_project_inner", C.c_int, _p, C.c_int, C.c_int, _p, _p, _p, _p)
 _sig("morap_project_outer", C.c_int, _p, _p, C.c_int, C.c_int, _p, _p, _p)
 _sig("morap_set_features", C.c_int, _ctxp, _p, C.c_int)
@@ -148,6 +150,7 @@ class Options:
     check_every: int = 32
     schedule: int = 0
     use_graph: bool = True
+    time_kernels: bool = False
 
     def to_c(self) -> ViOpts:
         o = ViOpts()
@@ -159,6 +162,7 @@ class Options:
         o.check_every = self.check_every
         o.schedule = self.schedule
         o.use_graph = 1 if self.use_graph else 0
+        o.time_kernels = 1 if self.time_kernels else 0
         return o
 
 
@@ -324,6 +328,14 @@ class Context:
                     "morap_support")
         return r, A, c, st.as_dict()
 
+    def stats(self) -> dict:
+        st = Stats()
+        self._check(lib.morap_get_stats(self._h, C.byref(st)), "morap_get_stats")
+        return st.as_dict()
+
+    def reset_stats(self):
+        self._check(lib.morap_reset_stats(self._h), "morap_reset_stats")
+
     def get_policy(self, k: int, j: int, n_states: int) -> np.ndarray:
         mu = np.zeros(n_states, np.int8)
         self._check(lib.morap_get_policy(self._h, k, j, _ptr(mu)), "morap_get_policy")
@@ -336,9 +348,11 @@ class Context:
 
     # -- Alg. 1 ------------------------------------------------------------
     def query_batch(self, T, M=None, eps: float = 1e-3, max_iter: int = 64, opts: Options = Options(),
-                    verification_only: bool = False, use_proposer: bool = False, trace: bool = False):
+                    verification_only: bool = False, use_proposer: bool = False, trace: bool = False,
+                    W0=None):
         T = _c(np.atleast_2d(T), np.float64)
         Q, d = T.shape
+        W0c = None if W0 is None else _c(np.atleast_2d(W0), np.float64)
         qo = QueryOpts()
         qo.eps, qo.max_iter = eps, max_iter
         qo.verification_only = int(verification_only)
@@ -354,7 +368,8 @@ class Context:
             for k, v in b.items():
                 setattr(res[q], k, _ptr(v))
         Mc = None if M is None else _c(M, np.float64)
-        self._check(lib.morap_query_batch(self._h, _ptr(T), Q, _ptr(Mc), C.byref(qo), res), "morap_query_batch")
+        self._check(lib.morap_query_batch(self._h, _ptr(T), _ptr(W0c), Q, _ptr(Mc), C.byref(qo), res),
+                    "morap_query_batch")
         out = []
         for q in range(Q):
             n = res[q].iterations
