@@ -149,14 +149,22 @@ def main():
     wall = time.perf_counter() - t_all
     st = ctx.stats()
     value = st["backups"] / wall
+    # dominant kernel: the FP32 batched sweep over all (model, column) pairs
     achieved = st["bytes"] / (st["ms_sweep_kernel"] / 1e3) / 1e9 if st["ms_sweep_kernel"] > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "bellman_sweep", "launches": st["sweep_launches"],
+                "kernel": f"bellman_sweep<{args.precision}>", "launches": st["sweep_launches"],
                 "avg_launch_us": round(st["ms_sweep_kernel"] * 1e3 / max(1, st["sweep_launches"]), 2),
                 "bytes_per_launch": round(st["bytes"] / max(1, st["sweep_launches"]), 0)}
+    if st["sweep_launches_refine"]:
+        ach_r = st["bytes_refine"] / (st["ms_sweep_kernel_refine"] / 1e3) / 1e9
+        roofline["fp64_assigned_resolve"] = {
+            "achieved": round(ach_r, 1), "launches": st["sweep_launches_refine"],
+            "avg_launch_us": round(st["ms_sweep_kernel_refine"] * 1e3 / st["sweep_launches_refine"], 2)}
     log(f"timed: {value:.3e} backups/s, sweep kernel {achieved:.0f} GB/s "
-        f"({st['sweep_launches']} launches, {st['ms_sweep_kernel']:.0f} ms kernel of {st['ms_vi']:.0f} ms VI)")
+        f"({st['sweep_launches']} launches, {st['ms_sweep_kernel']:.0f} ms); FP64 re-solve "
+        f"{st['ms_sweep_kernel_refine']:.0f} ms over {st['sweep_launches_refine']} launches; VI {st['ms_vi']:.0f} ms, "
+        f"evaluation {st['ms_eval']:.0f} ms")
 
     # full queries: plain first weight
     per_query = None
@@ -190,7 +198,7 @@ def main():
                        "parallelism": "1 GPU"},
             "roofline": roofline, "cpu_baseline": cpu, "ms_per_query": per_query,
             "stats": {k: st[k] for k in ("backups", "sweeps", "eval_sweeps", "polish_sweeps", "rank_rounds",
-                                         "ms_vi", "ms_eval", "variant")}}
+                                         "ms_vi", "ms_eval", "variant", "bytes", "bytes_refine")}}
     ctx.close()
     print(json.dumps(line), flush=True)
 

@@ -172,6 +172,9 @@ typedef struct {
     double  ms_vi, ms_eval, ms_total;   /* device / host wall time of the phases   */
     double  ms_sweep_kernel;/* summed sweep-kernel time (time_kernels = 1)          */
     int64_t sweep_launches; /* sweep kernels timed                                  */
+    double  bytes_refine;   /* the three fields above for the FP64 re-solve of the   */
+    double  ms_sweep_kernel_refine; /* assigned pairs after an FP32 solve           */
+    int64_t sweep_launches_refine;
     int32_t variant;        /* sweep-kernel variant used                            */
     int32_t reserved;
 } morap_stats;

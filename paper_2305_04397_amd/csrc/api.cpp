@@ -57,6 +57,9 @@ void to_abi(const Stats& s, morap_stats* out) {
     out->ms_total = s.ms_total;
     out->ms_sweep_kernel = s.ms_sweep_kernel;
     out->sweep_launches = s.sweep_launches;
+    out->bytes_refine = s.bytes_refine;
+    out->ms_sweep_kernel_refine = s.ms_sweep_kernel_refine;
+    out->sweep_launches_refine = s.sweep_launches_refine;
     out->variant = s.variant;
     out->reserved = 0;
 }

@@ -120,6 +120,8 @@ struct Stats {
             rank_rounds = 0, excluded = 0;
     double bytes = 0, ms_vi = 0, ms_eval = 0, ms_total = 0, ms_sweep_kernel = 0;
     int64_t sweep_launches = 0;
+    double bytes_refine = 0, ms_sweep_kernel_refine = 0;
+    int64_t sweep_launches_refine = 0;
     int variant = 0;
 };
 

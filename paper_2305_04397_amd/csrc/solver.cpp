@@ -42,15 +42,17 @@ static int padded_k(int K) {
     return (K + 63) / 64 * 64;
 }
 
-// candidate variants for a padded width: k-tiles of min(Kp, 64) columns, and
-// of half that
-static std::vector<Variant> candidates(int Kp) {
+// candidate variants for a padded width: k-tiles of min(Kp, 64) columns and
+// of half that; a restricted solve (few active columns per model) also tries
+// narrower k-tiles, which skip the k-tiles without active columns
+static std::vector<Variant> candidates(int Kp, bool restricted) {
     std::vector<Variant> out;
     const int kt_full = std::min(Kp, 64);
     for (const auto& v : variants()) {
         const int kt = kt_of(v);
         if (Kp % kt) continue;
-        if (kt == kt_full || (kt * 2 == kt_full && kt >= 8)) out.push_back(v);
+        if (kt == kt_full || (kt * 2 == kt_full && kt >= 8) || (restricted && kt >= 8 && kt <= kt_full))
+            out.push_back(v);
     }
     return out;
 }
@@ -264,7 +266,7 @@ static const Variant& choose_variant(morap_ctx* c, ValueSet& vs, const uint8_t* 
     const int64_t key = ((int64_t)vs.prec << 40) | ((int64_t)(mask != nullptr) << 32) | vs.Kp;
     for (auto& t : c->tuned)
         if (t.first == key) return variant_by_id(t.second);
-    auto cand = candidates(vs.Kp);
+    auto cand = candidates(vs.Kp, mask != nullptr);
     MORAP_CHECK(!cand.empty(), MORAP_E_UNSUPPORTED, "no sweep variant for this column count");
     int best = cand[0].id;
     if (cand.size() > 1) {
@@ -298,8 +300,13 @@ static void run_vi(morap_ctx* c, int g, ValueSet& vs, const uint8_t* mask, const
         for (auto& e : ev) {
             float t = 0;
             MORAP_HIP(hipEventElapsedTime(&t, e.first, e.second));
-            st.ms_sweep_kernel += t;
-            st.sweep_launches += 1;
+            if (mask) {
+                st.ms_sweep_kernel_refine += t;
+                st.sweep_launches_refine += 1;
+            } else {
+                st.ms_sweep_kernel += t;
+                st.sweep_launches += 1;
+            }
             (void)hipEventDestroy(e.first);
             (void)hipEventDestroy(e.second);
         }
@@ -329,7 +336,8 @@ static void run_vi(morap_ctx* c, int g, ValueSet& vs, const uint8_t* mask, const
     MORAP_HIP(hipMemcpy(ps.data(), c->d_pair_sweeps.p, ps.size() * 4, hipMemcpyDeviceToHost));
     const size_t el = vs.prec == MORAP_F32 ? 4 : 8;
     st.backups += h[4];
-    st.bytes += (double)h[6] + 2.0 * el * (double)h[7];
+    if (mask) st.bytes_refine += (double)h[6] + 2.0 * el * (double)h[7];
+    else st.bytes += (double)h[6] + 2.0 * el * (double)h[7];
     st.max_pair_sweeps = std::max<int64_t>(st.max_pair_sweeps, *std::max_element(ps.begin(), ps.end()));
     st.ms_vi += ms;
     st.variant = v.id;
@@ -354,6 +362,9 @@ static void add_stats(Stats& a, const Stats& b) {
     a.ms_total += b.ms_total;
     a.ms_sweep_kernel += b.ms_sweep_kernel;
     a.sweep_launches += b.sweep_launches;
+    a.bytes_refine += b.bytes_refine;
+    a.ms_sweep_kernel_refine += b.ms_sweep_kernel_refine;
+    a.sweep_launches_refine += b.sweep_launches_refine;
     a.variant = b.variant ? b.variant : a.variant;
 }
 

@@ -117,6 +117,46 @@ __device__ __forceinline__ double group_max(double v) {
 // ---------------------------------------------------------------------------
 // batched Bellman sweep
 // ---------------------------------------------------------------------------
+// Per-(model, column) residual and |y| maxima accumulated by a workgroup over
+// its tiles of one model, flushed with one atomic per column when the model
+// changes (and at the end).
+template <int CPL, int LPS, int NW, int KT>
+__device__ __forceinline__ void flush_residuals(double (&res)[CPL], double (&ym)[CPL], double (*l_red)[NW][KT],
+                                                int m, int Kp, unsigned long long* res_all,
+                                                unsigned long long* ymax_all, bool want_ymax) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, gl = tid % LPS;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        res[c] = group_max<LPS>(res[c]);
+        ym[c] = group_max<LPS>(ym[c]);
+    }
+    if (lane < LPS) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            l_red[0][wave][gl * CPL + c] = res[c];
+            l_red[1][wave][gl * CPL + c] = ym[c];
+        }
+    }
+    __syncthreads();
+    if (tid < KT) {
+        double r = 0.0, y = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            r = fmax(r, l_red[0][w][tid]);
+            y = fmax(y, l_red[1][w][tid]);
+        }
+        const int64_t idx = (int64_t)m * Kp + blockIdx.y * KT + tid;
+        if (r > 0.0) atomicMax(&res_all[idx], (unsigned long long)__double_as_longlong(r));
+        if (want_ymax && y > 0.0) atomicMax(&ymax_all[idx], (unsigned long long)__double_as_longlong(y));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        res[c] = 0.0;
+        ym[c] = 0.0;
+    }
+}
+
 template <class T, class T2, int CPL, int LPS, int WG>
 __global__ void __launch_bounds__(WG)
 bellman_sweep(const Tile* __restrict__ tiles, const int32_t* __restrict__ tile_base,
@@ -132,6 +172,7 @@ bellman_sweep(const Tile* __restrict__ tiles, const int32_t* __restrict__ tile_b
     constexpr int KT = CPL * LPS;          // columns per k-tile
     constexpr int G = WG / LPS;            // states processed at once
     constexpr int NW = WG / 64;            // waves
+    constexpr bool want_ymax = sizeof(T) == 4;   // |y| only bounds the FP32 stop test
     __shared__ int32_t l_srow[TILE_STATES + 1];
     __shared__ int32_t l_rptr[TILE_ROWS + 1];
     __shared__ T2 l_rew[TILE_ROWS];
@@ -141,32 +182,64 @@ bellman_sweep(const Tile* __restrict__ tiles, const int32_t* __restrict__ tile_b
     __shared__ double l_red[2][NW][KT];
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
     const int grp = tid / LPS;             // state slot within a pass
     const int gl = tid % LPS;              // lane within the group
     const int kc = blockIdx.y * KT + gl * CPL;   // first column of this lane
 
+    // Each workgroup owns a contiguous block of the active tile list; the
+    // workgroups of one XCD (blockIdx % 8) own consecutive blocks, so
+    // neighbouring tiles (which share successors) stay in that XCD's L2.
     const int n_tiles = (int)counters[1];
-    const int G8 = gridDim.x >> 3;
-    const int xcd = blockIdx.x & 7;
-    const int slot = blockIdx.x >> 3;
-    const int chunk = (n_tiles + 7) >> 3;
-    const int t_begin = xcd * chunk;
-    const int t_end = min(n_tiles, t_begin + chunk);
     const int n_act = (int)counters[2];
+    const int per_xcd = gridDim.x >> 3;
+    const int owner = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    const int per_wg = (n_tiles + gridDim.x - 1) / gridDim.x;
+    const int t_begin = owner * per_wg;
+    const int t_end = min(n_tiles, t_begin + per_wg);
+    if (t_begin >= t_end) return;
 
-    for (int t = t_begin + slot; t < t_end; t += G8) {
-        // locate the tile: active model a with act_prefix[a] <= t < act_prefix[a+1]
-        int lo = 0, hi = n_act;
+    // active model holding the first tile, then advanced tile by tile
+    int lo = 0;
+    {
+        int hi = n_act;
         while (hi - lo > 1) {
-            int mid = (lo + hi) >> 1;
-            if (act_prefix[mid] <= t) lo = mid; else hi = mid;
+            const int mid = (lo + hi) >> 1;
+            if (act_prefix[mid] <= t_begin) lo = mid; else hi = mid;
         }
+    }
+    int cur_m = -1;
+    bool tile_on = false, any = false;
+    T wc[CPL], wp[CPL];
+    bool act[CPL];
+    double res[CPL], ym[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        res[c] = 0.0;
+        ym[c] = 0.0;
+        wc[c] = wp[c] = 0;
+        act[c] = false;
+    }
+
+    for (int t = t_begin; t < t_end; ++t) {
+        while (act_prefix[lo + 1] <= t) ++lo;
         const int m = act_models[lo];
-        // nothing to do when no column of this k-tile is active for the model
-        const int tile_on = tid < KT ? active_all[(int64_t)m * Kp + blockIdx.y * KT + tid] : 0;
-        if (!__syncthreads_or(tile_on)) continue;
+        if (m != cur_m) {
+            if (cur_m >= 0)
+                flush_residuals<CPL, LPS, NW, KT>(res, ym, l_red, cur_m, Kp, res_all, ymax_all, want_ymax);
+            cur_m = m;
+            any = false;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int64_t k = (int64_t)m * Kp + kc + c;
+                wc[c] = wc_all[k];
+                wp[c] = wp_all[k];
+                act[c] = active_all[k] != 0;
+                any |= act[c];
+            }
+            // skip the model when no column of this k-tile is active
+            tile_on = __syncthreads_or(any ? 1 : 0) != 0;
+        }
+        if (!tile_on) continue;
         const Tile tl = tiles[tile_base[m] + (t - act_prefix[lo])];
         const int s0 = tl.s_begin, s1 = tl.s_end, ns = s1 - s0;
         const int r0 = state_row[s0], r1 = state_row[s1];
@@ -184,24 +257,7 @@ bellman_sweep(const Tile* __restrict__ tiles, const int32_t* __restrict__ tile_b
         __syncthreads();
         for (int r = tid; r < nr; r += WG)
             for (int e = l_rptr[r]; e < l_rptr[r + 1]; ++e) l_erow[e] = (uint16_t)r;
-
-        // this lane's columns
-        T wc[CPL], wp[CPL];
-        bool act[CPL];
-        bool any = false;
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            const int k = kc + c;
-            wc[c] = wc_all[(int64_t)m * Kp + k];
-            wp[c] = wp_all[(int64_t)m * Kp + k];
-            act[c] = active_all[(int64_t)m * Kp + k] != 0;
-            any |= act[c];
-        }
         __syncthreads();
-
-        double res[CPL], ym[CPL];
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) { res[c] = 0.0; ym[c] = 0.0; }
 
         if (any) {
             for (int ls = grp; ls < ns; ls += G) {
@@ -222,25 +278,26 @@ bellman_sweep(const Tile* __restrict__ tiles, const int32_t* __restrict__ tile_b
                 T acc[CPL];
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) acc[c] = 0;
-                for (int base = le0; base < le1; base += 8) {
-                    const int n = min(8, le1 - base);
-                    int jj[8];
-                    T pp[8];
-                    int rr[8];
+                constexpr int B = CPL >= 4 ? 4 : 8;   // gathers in flight per lane
+                for (int base = le0; base < le1; base += B) {
+                    const int n = min(B, le1 - base);
+                    int jj[B];
+                    T pp[B];
+                    int rr[B];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
+                    for (int u = 0; u < B; ++u) {
                         if (u < n) {
                             jj[u] = l_col[base + u];
                             pp[u] = l_prob[base + u];
                             rr[u] = l_erow[base + u];
                         }
                     }
-                    Vec<T, CPL> xv[8];
+                    Vec<T, CPL> xv[B];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u)
+                    for (int u = 0; u < B; ++u)
                         if (u < n) xv[u] = vload<T, CPL>(x_in + (int64_t)jj[u] * Kp + kc);
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
+                    for (int u = 0; u < B; ++u) {
                         if (u < n) {
                             if (rr[u] != cur) {
                                 if (cur >= 0) {
@@ -268,39 +325,14 @@ bellman_sweep(const Tile* __restrict__ tiles, const int32_t* __restrict__ tile_b
                     if (act[c]) {
                         x_out[gs * Kp + kc + c] = best[c];
                         res[c] = fmax(res[c], fabs((double)best[c] - (double)old.v[c]));
-                        ym[c] = fmax(ym[c], fabs((double)best[c]));
+                        if (want_ymax) ym[c] = fmax(ym[c], fabs((double)best[c]));
                     }
                 }
             }
         }
-
-        // reduce over the groups holding the same columns, one atomic per column
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            res[c] = group_max<LPS>(res[c]);
-            ym[c] = group_max<LPS>(ym[c]);
-        }
-        if (lane < LPS) {
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                l_red[0][wave][gl * CPL + c] = res[c];
-                l_red[1][wave][gl * CPL + c] = ym[c];
-            }
-        }
-        __syncthreads();
-        if (tid < KT) {
-            double r = 0.0, y = 0.0;
-#pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                r = fmax(r, l_red[0][w][tid]);
-                y = fmax(y, l_red[1][w][tid]);
-            }
-            const int64_t idx = (int64_t)m * Kp + blockIdx.y * KT + tid;
-            if (r > 0.0) atomicMax(&res_all[idx], (unsigned long long)__double_as_longlong(r));
-            if (y > 0.0) atomicMax(&ymax_all[idx], (unsigned long long)__double_as_longlong(y));
-        }
-        __syncthreads();
+        __syncthreads();   // the next tile reuses the staging area
     }
+    if (cur_m >= 0) flush_residuals<CPL, LPS, NW, KT>(res, ym, l_red, cur_m, Kp, res_all, ymax_all, want_ymax);
 }
 
 // ---------------------------------------------------------------------------

@@ -3,6 +3,10 @@ numpy arrays in and out.  Argument marshalling only: every step runs in the
 library.  Importing this module loads the in-tree libmorap.so and fails
 loudly when it is missing (build it with ``python -m
 paper_2305_04397_amd.build``).
+
+libmorap links the system ROCm HIP runtime.  PyTorch wheels bundle their own
+runtime with the same soname; whichever loads first serves the whole process,
+so import this module before torch when both are used.
 """
 from __future__ import annotations
 
@@ -69,7 +73,9 @@ class Stats(C.Structure):
                 ("eval_sweeps", C.c_int64), ("polish_sweeps", C.c_int64), ("rank_rounds", C.c_int64),
                 ("excluded", C.c_int64), ("bytes", C.c_double), ("ms_vi", C.c_double),
                 ("ms_eval", C.c_double), ("ms_total", C.c_double), ("ms_sweep_kernel", C.c_double),
-                ("sweep_launches", C.c_int64), ("variant", C.c_int32), ("reserved", C.c_int32)]
+                ("sweep_launches", C.c_int64), ("bytes_refine", C.c_double),
+                ("ms_sweep_kernel_refine", C.c_double), ("sweep_launches_refine", C.c_int64),
+                ("variant", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
