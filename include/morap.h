@@ -317,6 +317,12 @@ int64_t morap_proposer_num_params(const morap_ctx* ctx);
 int morap_proposer_get_params(const morap_ctx* ctx, float* out);
 int morap_proposer_set_params(morap_ctx* ctx, const float* in);
 
+/* Input standardisation applied before the first layer: x -> (x - mu) / sd
+ * per input column (mu[n_in], sd[n_in] > 0; the library copies them).  It is
+ * not trained and is saved with the parameters; init sets mu = 0, sd = 1.
+ * Errors: INVALID, STATE. */
+int morap_proposer_set_input_norm(morap_ctx* ctx, const float* mu, const float* sd);
+
 /* Forward pass: X[n][n_in] -> W_out[n][d] (softmax rows).  Errors: INVALID,
  * STATE (no proposer), HIP. */
 int morap_proposer_infer(morap_ctx* ctx, const float* X, int n, float* W_out);

@@ -54,8 +54,13 @@ def loss(P: np.ndarray, T: np.ndarray) -> float:
     return float(-(T * np.log(np.maximum(P, 1e-300))).sum(axis=1).mean())
 
 
-def backward(params, cache, P, T):
-    """Gradients [(dW1, db1), ...] of the mean cross-entropy."""
+def backward(params, cache, P, T, grad_round=None):
+    """Gradients [(dW1, db1), ...] of the mean cross-entropy.
+
+    ``grad_round`` (e.g. ``to_bf16``) mirrors a storage precision of the
+    back-propagated gradient: the gradient at each layer's output is rounded
+    before it enters that layer's weight, bias and input gradients."""
+    rnd = grad_round or (lambda v: v)
     acts, _ = cache
     B = P.shape[0]
     g = (P - T) / B                      # d loss / d logits
@@ -63,6 +68,7 @@ def backward(params, cache, P, T):
     for l in range(len(params) - 1, -1, -1):
         W, _ = params[l]
         h = acts[l]
+        g = rnd(g)
         grads[l] = (g.T @ h, g.sum(axis=0))
         if l > 0:
             g = (g @ W) * (acts[l] > 0)

@@ -19,29 +19,6 @@ morap_ctx::~morap_ctx() {
 
 namespace {
 
-template <class F>
-int guarded(morap_ctx* c, F&& f) {
-    if (!c) return MORAP_E_INVALID;
-    try {
-        c->err.clear();
-        MORAP_HIP(hipSetDevice(c->device));
-        f();
-        return MORAP_OK;
-    } catch (const MorapError& e) {
-        c->err = e.what();
-        return e.code;
-    } catch (const std::bad_alloc&) {
-        c->err = "host allocation failed";
-        return MORAP_E_OOM;
-    } catch (const std::exception& e) {
-        c->err = e.what();
-        return MORAP_E_INVALID;
-    } catch (...) {
-        c->err = "unknown error";
-        return MORAP_E_INVALID;
-    }
-}
-
 void to_abi(const Stats& s, morap_stats* out) {
     if (!out) return;
     out->backups = s.backups;

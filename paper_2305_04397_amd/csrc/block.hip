@@ -1,0 +1,455 @@
+// Batched Bellman sweep over the neighbourhood-block form of the products
+// (Alg. 3, one Jacobi sweep of scalarised max-backups for every active
+// (model, column) pair).
+//
+// In a product M_i (x) A_j the transition probabilities of (s, q) under an
+// action are those of the agent state s (Sec. 2, "Product MDP"); only which
+// product state each agent successor lands in, and whether it is done,
+// depends on q.  When every agent state has at most 5 actions and at most 5
+// distinct successors (the state itself counted), one product state is fully
+// described by
+//   * a 32-byte record: the global product state of each of the 5 agent
+//     successor slots (the zero row when the slot is unused or its successor
+//     is done), the index of its agent state's block, the slots that enter an
+//     accepting location and the enabled actions;
+//   * its agent state's block: P[a][d] over (action, slot) and -cost[a] (a
+//     disabled action repeats the first enabled one),
+//     shared by every location and every task of that agent.
+// A backup then reads the record, the (cached) agent block and 5 successor
+// value rows; the probability-reward column is the mass the action puts on
+// accepting slots.  There is no LDS staging and no barrier: each wave owns a
+// contiguous run of the active tiles (XCD-aware), walks its states `U` at a
+// time with all successor gathers of those states in flight, and lanes map to
+// columns.  With 64 lanes per state the record, the block and every branch are
+// wave-uniform (scalar loads and branches).
+#include "common.h"
+#include "kern.h"
+
+#include <cfloat>
+#include <type_traits>
+
+namespace morap {
+namespace k {
+
+constexpr int NSLOT = 5;
+constexpr int BLK = 32;   // values per agent block
+
+template <class T, int CPL, int LPS, int U, int WG>
+__global__ void __launch_bounds__(WG)
+bellman_block(const Tile* __restrict__ tiles, const int32_t* __restrict__ tile_base,
+              const int32_t* __restrict__ act_models, const int32_t* __restrict__ act_prefix,
+              const int64_t* __restrict__ counters, const int32_t* __restrict__ rec,
+              const T* __restrict__ ablk, const T* __restrict__ wc_all, const T* __restrict__ wp_all,
+              const uint8_t* __restrict__ active_all, const T* __restrict__ x_in, T* __restrict__ x_out,
+              unsigned long long* __restrict__ res_all, unsigned long long* __restrict__ ymax_all, int Kp,
+              int32_t zero_row) {
+    constexpr int SPW = 64 / LPS;          // states per wave step
+    constexpr int KT = CPL * LPS;          // columns per k-tile
+    constexpr int NW = WG / 64;
+    constexpr bool want_ymax = sizeof(T) == 4;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int g = lane / LPS;              // state slot within a step
+    const int gl = lane % LPS;
+    const int kc = blockIdx.y * KT + gl * CPL;
+
+    // work units: active tiles, split in `sub` parts when there are fewer
+    // tiles than waves
+    const int n_tiles = (int)counters[1];
+    const int n_act = (int)counters[2];
+    const int n_waves = gridDim.x * NW;
+    const int sub = n_tiles * 4 <= n_waves ? 4 : (n_tiles * 2 <= n_waves ? 2 : 1);
+    const int n_units = n_tiles * sub;
+    int u_begin, u_end;
+    xcd_share(n_units, blockIdx.x & 7, (blockIdx.x >> 3) * NW + wave, (gridDim.x >> 3) * NW, u_begin, u_end);
+    if (u_begin >= u_end) return;
+
+    int lo = 0;
+    {
+        const int t0 = u_begin / sub;
+        int hi = n_act;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (act_prefix[mid] <= t0) lo = mid; else hi = mid;
+        }
+    }
+    int cur_m = -1;
+    bool on = false;
+    T wc[CPL], wp[CPL];
+    bool act[CPL];
+    double res[CPL], ym[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        res[c] = ym[c] = 0.0;
+        wc[c] = wp[c] = 0;
+        act[c] = false;
+    }
+
+    auto flush = [&](int m) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            res[c] = group_max<LPS>(res[c]);
+            if (want_ymax) ym[c] = group_max<LPS>(ym[c]);
+        }
+        if (lane < LPS) {
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int64_t idx = (int64_t)m * Kp + kc + c;
+                if (res[c] > 0.0) atomicMax(&res_all[idx], (unsigned long long)__double_as_longlong(res[c]));
+                if (want_ymax && ym[c] > 0.0)
+                    atomicMax(&ymax_all[idx], (unsigned long long)__double_as_longlong(ym[c]));
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) res[c] = ym[c] = 0.0;
+    };
+
+    for (int u = u_begin; u < u_end; ++u) {
+        const int t = u / sub, part = u - t * sub;
+        while (act_prefix[lo + 1] <= t) ++lo;
+        const int m = act_models[lo];
+        if (m != cur_m) {
+            if (cur_m >= 0) flush(cur_m);
+            cur_m = m;
+            bool any = false;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int64_t kk = (int64_t)m * Kp + kc + c;
+                wc[c] = wc_all[kk];
+                wp[c] = wp_all[kk];
+                act[c] = active_all[kk] != 0;
+                any |= act[c];
+            }
+            on = __ballot(any) != 0;
+        }
+        if (!on) continue;
+        const Tile tl = tiles[tile_base[m] + (t - act_prefix[lo])];
+        const int len = tl.s_end - tl.s_begin;
+        const int sb = tl.s_begin + (len * part) / sub;
+        const int se = tl.s_begin + (len * (part + 1)) / sub;
+
+        for (int s = sb; s < se; s += U * SPW) {
+            int gs[U];
+            bool ok[U];
+            int32_t sc[U][NSLOT], bi[U], fl[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                gs[q] = s + q * SPW + g;
+                ok[q] = gs[q] < se;
+                if (ok[q]) {
+                    const int32_t* r = rec + (int64_t)gs[q] * 8;
+                    const int4 r0 = *reinterpret_cast<const int4*>(r);
+                    const int4 r1 = *reinterpret_cast<const int4*>(r + 4);
+                    sc[q][0] = r0.x; sc[q][1] = r0.y; sc[q][2] = r0.z; sc[q][3] = r0.w;
+                    sc[q][4] = r1.x; bi[q] = r1.y; fl[q] = r1.z;
+                } else {
+#pragma unroll
+                    for (int d = 0; d < NSLOT; ++d) sc[q][d] = zero_row;
+                    bi[q] = 0;
+                    fl[q] = 0;
+                }
+            }
+            // every successor gather of the U states in flight together
+            Vec<T, CPL> xv[U][NSLOT];
+#pragma unroll
+            for (int q = 0; q < U; ++q)
+#pragma unroll
+                for (int d = 0; d < NSLOT; ++d) {
+                    const T* row = x_in + (int64_t)sc[q][d] * Kp;
+                    xv[q][d] = vload<T, CPL>(row + kc);
+                }
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                if (!ok[q]) continue;
+                // the agent block: P[a][d] (25 values), then -cost[a] (5)
+                T B[BLK];
+                {
+                    using V4 = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+                    constexpr int PER = sizeof(V4) / sizeof(T);
+                    const V4* src = reinterpret_cast<const V4*>(ablk + (int64_t)bi[q] * BLK);
+#pragma unroll
+                    for (int i = 0; i < BLK / PER; ++i) {
+                        const V4 v = src[i];
+                        if constexpr (PER == 4) {
+                            B[4 * i] = v.x; B[4 * i + 1] = v.y; B[4 * i + 2] = v.z; B[4 * i + 3] = v.w;
+                        } else {
+                            B[2 * i] = v.x; B[2 * i + 1] = v.y;
+                        }
+                    }
+                }
+                const int accm = fl[q] & 31;
+                // the state's own value (slot 0 unless its self-successor
+                // changes location or is done)
+                Vec<T, CPL> old = xv[q][0];
+                if (sc[q][0] != gs[q]) old = vload<T, CPL>(x_in + (int64_t)gs[q] * Kp + kc);
+                T best[CPL];
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) best[c] = -INFINITY;
+#pragma unroll
+                for (int a = 0; a < 5; ++a) {
+                    // probability reward: the action's mass on accepting slots
+                    T rp = 0;
+                    if (accm) {
+#pragma unroll
+                        for (int d = 0; d < NSLOT; ++d)
+                            if ((accm >> d) & 1) rp += B[a * NSLOT + d];
+                    }
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        T acc = wc[c] * B[25 + a];
+                        if (accm) acc = fma(wp[c], rp, acc);
+#pragma unroll
+                        for (int d = 0; d < NSLOT; ++d) acc = fma(B[a * NSLOT + d], xv[q][d].v[c], acc);
+                        best[c] = fmax(best[c], acc);
+                    }
+                }
+                const int64_t o = (int64_t)gs[q] * Kp + kc;
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    if (act[c]) {
+                        x_out[o + c] = best[c];
+                        res[c] = fmax(res[c], fabs((double)best[c] - (double)old.v[c]));
+                        if (want_ymax) ym[c] = fmax(ym[c], fabs((double)best[c]));
+                    }
+                }
+            }
+        }
+    }
+    if (cur_m >= 0) flush(cur_m);
+}
+
+// One state per wave step, lane = column (64 columns per k-tile): the
+// record fields, the agent block and every branch are wave-uniform, so the
+// block sits in scalar registers and the vector unit only does the backup
+// arithmetic.  A work unit's records are staged with one coalesced load per
+// lane (lane i holds the record of the unit's i-th state) and the next unit's
+// records are fetched while the current one is processed; U states have their
+// successor gathers in flight together.
+struct UnitDesc {
+    int m, sb, se;
+};
+
+template <class T, int U, int WG>
+__global__ void __launch_bounds__(WG)
+bellman_block_wave(const Tile* __restrict__ tiles, const int32_t* __restrict__ tile_base,
+                   const int32_t* __restrict__ act_models, const int32_t* __restrict__ act_prefix,
+                   const int64_t* __restrict__ counters, const int32_t* __restrict__ rec,
+                   const T* __restrict__ ablk, const T* __restrict__ wc_all, const T* __restrict__ wp_all,
+                   const uint8_t* __restrict__ active_all, const T* __restrict__ x_in, T* __restrict__ x_out,
+                   unsigned long long* __restrict__ res_all, unsigned long long* __restrict__ ymax_all, int Kp,
+                   int32_t zero_row) {
+    constexpr int NW = WG / 64;
+    constexpr bool want_ymax = sizeof(T) == 4;
+    // each wave's records of its current unit (lane i wrote state i's)
+    __shared__ int4 l_rec[NW][64][2];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned kc = blockIdx.y * 64u + (unsigned)lane;
+
+    const int n_tiles = (int)counters[1];
+    const int n_act = (int)counters[2];
+    const int n_waves = gridDim.x * NW;
+    const int sub = n_tiles * 4 <= n_waves ? 4 : (n_tiles * 2 <= n_waves ? 2 : 1);
+    const int n_units = n_tiles * sub;
+    int u_begin, u_end;
+    xcd_share(n_units, blockIdx.x & 7, (blockIdx.x >> 3) * NW + wave, (gridDim.x >> 3) * NW, u_begin, u_end);
+    if (u_begin >= u_end) return;
+
+    // unit -> (model, state range); the active-model cursor only moves forward
+    int lo = 0;
+    {
+        const int t0 = u_begin / sub;
+        int hi = n_act;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (act_prefix[mid] <= t0) lo = mid; else hi = mid;
+        }
+    }
+    int bound = -1, dm = -1, tb = 0, ap = 0;
+    auto describe = [&](int u) {
+        const int t = u / sub, part = u - t * sub;
+        if (t >= bound) {
+            while (act_prefix[lo + 1] <= t) ++lo;
+            dm = act_models[lo];
+            tb = tile_base[dm];
+            ap = act_prefix[lo];
+            bound = act_prefix[lo + 1];
+        }
+        const Tile tl = tiles[tb + (t - ap)];
+        const int len = tl.s_end - tl.s_begin;
+        return UnitDesc{dm, tl.s_begin + (len * part) / sub, tl.s_begin + (len * (part + 1)) / sub};
+    };
+    auto stage = [&](const UnitDesc& d, int4& r0, int4& r1) {
+        if (lane < d.se - d.sb) {
+            const int32_t* r = rec + (int64_t)(d.sb + lane) * 8;
+            r0 = *reinterpret_cast<const int4*>(r);
+            r1 = *reinterpret_cast<const int4*>(r + 4);
+        }
+    };
+
+    int cur_m = -1;
+    bool on = false, act = false;
+    T wc = 0, wp = 0;
+    double res = 0.0, ym = 0.0;
+    auto flush = [&](int m) {
+        const int64_t idx = (int64_t)m * Kp + kc;
+        if (res > 0.0) atomicMax(&res_all[idx], (unsigned long long)__double_as_longlong(res));
+        if (want_ymax && ym > 0.0) atomicMax(&ymax_all[idx], (unsigned long long)__double_as_longlong(ym));
+        res = ym = 0.0;
+    };
+
+    UnitDesc nd = describe(u_begin);
+    int4 n0 = make_int4(0, 0, 0, 0), n1 = make_int4(0, 0, 0, 0);
+    stage(nd, n0, n1);
+    for (int u = u_begin; u < u_end; ++u) {
+        const UnitDesc d = nd;
+        // publish this unit's records to the wave's LDS slots (same-wave
+        // LDS accesses are ordered: no barrier), then fetch the next unit's
+        l_rec[wave][lane][0] = n0;
+        l_rec[wave][lane][1] = n1;
+        if (u + 1 < u_end) {
+            nd = describe(u + 1);
+            stage(nd, n0, n1);
+        }
+        if (d.m != cur_m) {
+            if (cur_m >= 0) flush(cur_m);
+            cur_m = d.m;
+            const int64_t kk = (int64_t)d.m * Kp + kc;
+            wc = wc_all[kk];
+            wp = wp_all[kk];
+            act = active_all[kk] != 0;
+            on = __ballot(act) != 0;
+        }
+        if (!on) continue;
+        const int n = d.se - d.sb;
+        for (int i = 0; i < n; i += U) {
+            int32_t sc[U][NSLOT], bi[U], fl[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int j = min(i + q, n - 1);   // past the end: repeat the last state, not stored
+                const int4 a0 = l_rec[wave][j][0], a1 = l_rec[wave][j][1];
+                sc[q][0] = __builtin_amdgcn_readfirstlane(a0.x);
+                sc[q][1] = __builtin_amdgcn_readfirstlane(a0.y);
+                sc[q][2] = __builtin_amdgcn_readfirstlane(a0.z);
+                sc[q][3] = __builtin_amdgcn_readfirstlane(a0.w);
+                sc[q][4] = __builtin_amdgcn_readfirstlane(a1.x);
+                bi[q] = __builtin_amdgcn_readfirstlane(a1.y);
+                fl[q] = __builtin_amdgcn_readfirstlane(a1.z);
+            }
+            // successor rows and the state's own row (usually slot 0 again:
+            // an L1 hit), all loads unconditional so they retire in order
+            T xv[U][NSLOT], xo[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+#pragma unroll
+                for (int dd = 0; dd < NSLOT; ++dd) {
+                    const T* row = x_in + (int64_t)sc[q][dd] * Kp;
+                    xv[q][dd] = row[kc];
+                }
+                xo[q] = (x_in + (int64_t)(d.sb + min(i + q, n - 1)) * Kp)[kc];
+            }
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                if (i + q >= n) break;
+                const int gs = d.sb + i + q;
+                T B[BLK];
+                {
+                    using V4 = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+                    constexpr int PER = sizeof(V4) / sizeof(T);
+                    const V4* src = reinterpret_cast<const V4*>(ablk + (int64_t)bi[q] * BLK);
+#pragma unroll
+                    for (int k = 0; k < 32 / PER; ++k) {
+                        const V4 v = src[k];
+                        if constexpr (PER == 4) {
+                            B[4 * k] = v.x; B[4 * k + 1] = v.y; B[4 * k + 2] = v.z; B[4 * k + 3] = v.w;
+                        } else {
+                            B[2 * k] = v.x; B[2 * k + 1] = v.y;
+                        }
+                    }
+                }
+                const int accm = fl[q] & 31;
+                const T old = xo[q];
+                T best = -INFINITY;
+#pragma unroll
+                for (int a = 0; a < 5; ++a) {
+                    T acc = wc * B[25 + a];
+                    if (accm) {
+                        T rp = 0;
+#pragma unroll
+                        for (int dd = 0; dd < NSLOT; ++dd)
+                            if ((accm >> dd) & 1) rp += B[a * NSLOT + dd];
+                        acc = fma(wp, rp, acc);
+                    }
+#pragma unroll
+                    for (int dd = 0; dd < NSLOT; ++dd) acc = fma(B[a * NSLOT + dd], xv[q][dd], acc);
+                    best = fmax(best, acc);
+                }
+                if (act) {
+                    (x_out + (int64_t)gs * Kp)[kc] = best;
+                    res = fmax(res, fabs((double)best - (double)old));
+                    if (want_ymax) ym = fmax(ym, fabs((double)best));
+                }
+            }
+        }
+    }
+    if (cur_m >= 0) flush(cur_m);
+}
+
+template <class T, int U>
+static void launch_block_wave(hipStream_t s, int grid, int ktiles, const SweepArgs& a) {
+    constexpr int WG = 256;
+    hipLaunchKernelGGL((bellman_block_wave<T, U, WG>), dim3(grid, ktiles), dim3(WG), 0, s, a.tiles,
+                       a.tile_base, a.act_models, a.act_prefix, a.counters, a.rec, (const T*)a.ablk,
+                       (const T*)a.wc, (const T*)a.wp, a.active, (const T*)a.x_in, (T*)a.x_out, a.res, a.ymax,
+                       a.Kp, a.zero_row);
+}
+
+template <class T, int CPL, int LPS, int U>
+static void launch_block(hipStream_t s, int grid, int ktiles, const SweepArgs& a) {
+    constexpr int WG = 256;
+    hipLaunchKernelGGL((bellman_block<T, CPL, LPS, U, WG>), dim3(grid, ktiles), dim3(WG), 0, s, a.tiles,
+                       a.tile_base, a.act_models, a.act_prefix, a.counters, a.rec, (const T*)a.ablk,
+                       (const T*)a.wc, (const T*)a.wp, a.active, (const T*)a.x_in, (T*)a.x_out, a.res, a.ymax,
+                       a.Kp, a.zero_row);
+}
+
+template <class T>
+static void block_t(hipStream_t s, const Variant& v, int grid, int ktiles, const SweepArgs& a) {
+#define MORAP_B(C, L) \
+    if (v.cpl == C && v.lps == L) { launch_block<T, C, L, 2>(s, grid, ktiles, a); return; }
+    MORAP_B(1, 1) MORAP_B(1, 2) MORAP_B(2, 1) MORAP_B(1, 4) MORAP_B(2, 2) MORAP_B(4, 1)
+    MORAP_B(1, 8) MORAP_B(2, 4) MORAP_B(4, 2) MORAP_B(1, 16) MORAP_B(2, 8) MORAP_B(4, 4)
+    MORAP_B(1, 32) MORAP_B(2, 16) MORAP_B(4, 8) MORAP_B(2, 32) MORAP_B(4, 16)
+    if (v.cpl == 1 && v.lps == 64) { launch_block_wave<T, 4>(s, grid, ktiles, a); return; }
+#undef MORAP_B
+    fail(MORAP_E_UNSUPPORTED, "no block sweep kernel for this variant");
+}
+
+template <class T>
+static const void* block_fn(const Variant& v) {
+#define MORAP_F(C, L) \
+    if (v.cpl == C && v.lps == L) return reinterpret_cast<const void*>(&bellman_block<T, C, L, 2, 256>);
+    MORAP_F(1, 1) MORAP_F(1, 2) MORAP_F(2, 1) MORAP_F(1, 4) MORAP_F(2, 2) MORAP_F(4, 1)
+    MORAP_F(1, 8) MORAP_F(2, 4) MORAP_F(4, 2) MORAP_F(1, 16) MORAP_F(2, 8) MORAP_F(4, 4)
+    MORAP_F(1, 32) MORAP_F(2, 16) MORAP_F(4, 8) MORAP_F(2, 32) MORAP_F(4, 16)
+#undef MORAP_F
+    if (v.cpl == 1 && v.lps == 64) return reinterpret_cast<const void*>(&bellman_block_wave<T, 4, 256>);
+    fail(MORAP_E_UNSUPPORTED, "no block sweep kernel for this variant");
+}
+
+int sweep_block_resident(int prec, const Variant& v) {
+    int n = 0;
+    MORAP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &n, prec == MORAP_F32 ? block_fn<float>(v) : block_fn<double>(v), 256, 0));
+    return n;
+}
+
+void sweep_block(hipStream_t s, int prec, const Variant& v, int grid, int ktiles, const SweepArgs& a) {
+    MORAP_CHECK(a.rec && a.ablk, MORAP_E_STATE, "the neighbourhood-block form was not built");
+    if (prec == MORAP_F32) block_t<float>(s, v, grid, ktiles, a);
+    else block_t<double>(s, v, grid, ktiles, a);
+    MORAP_HIP(hipGetLastError());
+}
+
+}  // namespace k
+}  // namespace morap

@@ -96,6 +96,17 @@ struct HostModels {
     std::vector<double>  rew;          // [2R]
     std::vector<uint8_t> to_done;      // [R]
     std::vector<int32_t> states_sq;    // [2S] (agent state, location), may be empty
+    // neighbourhood-block form (products built from agents and automata whose
+    // agent states have at most 5 actions and 5 distinct successors, the
+    // state itself counted): per product state 8 int32
+    //   [0..4] global successor state of agent slot d (S = the zero row:
+    //          slot unused, or its successor is done), slot 0 = the agent
+    //          state itself; [5] index of its agent state's block; [6] bits 0-4: slot
+    //          d enters an accepting location, bits 8-12: action a enabled;
+    // and per distinct agent-state block 32 values: P[a][d] (a-major, 25), -cost[a] (5), 0, 0,
+    // where a disabled action repeats the first enabled one.
+    std::vector<int32_t> blk_rec;      // [8S]
+    std::vector<double>  blk_agent;    // [32 * distinct blocks]
     int64_t S() const { return (int64_t)state_row.size() - 1; }
     int64_t R() const { return (int64_t)row_ptr.size() - 1; }
     int64_t N() const { return (int64_t)col.size(); }
@@ -107,12 +118,14 @@ struct Tile {
     int32_t model, s_begin, s_end, pad;
 };
 
-// sweep-kernel variants (columns per lane x lanes per state)
+// sweep-kernel variants: kernel family x columns per lane x lanes per state
+enum { SWEEP_CSR = 0, SWEEP_BLOCK = 1 };
 struct Variant {
     int id;        // > 0
     int cpl;       // columns per lane
     int lps;       // lanes per state
     int wg;        // threads per workgroup
+    int kind;      // SWEEP_CSR (LDS-staged CSR tiles) or SWEEP_BLOCK (neighbourhood blocks)
 };
 
 struct Stats {
@@ -155,6 +168,8 @@ struct morap_ctx {
     bool loaded = false;
     int64_t S = 0, R = 0, N = 0;
     int max_rows_per_state = 0;
+    bool has_blocks = false;                        // the neighbourhood-block form exists
+    morap::DevBuf d_blk_rec, d_blk32, d_blk64;
     morap::DevBuf d_state_row, d_row_ptr, d_col, d_prob32, d_prob64, d_rew32, d_rew64, d_to_done;
     morap::DevBuf d_state_base, d_init;
     morap::DevBuf d_rows_per_model, d_states_per_model;  // [M] int32
@@ -179,6 +194,7 @@ struct morap_ctx {
     morap::DevBuf d_act_models, d_act_prefix;       // compacted active model list
     morap::DevBuf d_counters;                       // int64 [8] (see the convergence kernel)
     morap::PinnedBuf h_counters;
+    morap::PinnedBuf h_log;                         // per-launch tile counts (sweep log)
     std::vector<double> W;                          // [K][d] of the last solve
     int last_variant = 0;
     hipGraph_t chunk_graph[2] = {nullptr, nullptr}; // captured chunks of sweeps (main, FP64 refine)
@@ -202,6 +218,8 @@ struct morap_ctx {
 
     // autotuner cache: key (prec, Kp) -> variant id
     std::vector<std::pair<int64_t, int>> tuned;
+    // resident workgroups per compute unit: key (variant, prec) -> count
+    std::vector<std::pair<int64_t, int>> resident;
 
     // statistics since the last reset
     morap::Stats cum;
@@ -214,6 +232,31 @@ struct morap_ctx {
 };
 
 namespace morap {
+
+// Run f with the context's device current; errors become return codes and
+// the message stays on the context (no exception crosses the ABI).
+template <class F>
+int guarded(morap_ctx* c, F&& f) {
+    if (!c) return MORAP_E_INVALID;
+    try {
+        c->err.clear();
+        MORAP_HIP(hipSetDevice(c->device));
+        f();
+        return MORAP_OK;
+    } catch (const MorapError& e) {
+        c->err = e.what();
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        c->err = "host allocation failed";
+        return MORAP_E_OOM;
+    } catch (const std::exception& e) {
+        c->err = e.what();
+        return MORAP_E_INVALID;
+    } catch (...) {
+        c->err = "unknown error";
+        return MORAP_E_INVALID;
+    }
+}
 
 // product.cpp
 void build_products(morap_ctx* ctx, const morap_agent* agents, int nI, const morap_dfa* tasks, int nJ,
@@ -271,9 +314,16 @@ struct SweepArgs {
     unsigned long long* res;
     unsigned long long* ymax;
     int Kp;
+    const int32_t* rec;     // neighbourhood-block records [8S]
+    const void* ablk;       // agent blocks [32 * agent states] (precision of the sweep)
+    int32_t zero_row;       // S: the value row that always holds 0
 };
 // batched Bellman sweep: variant v, precision prec (MORAP_F32/F64)
 void sweep(hipStream_t s, int prec, const Variant& v, int grid, int ktiles, const SweepArgs& a);
+void sweep_block(hipStream_t s, int prec, const Variant& v, int grid, int ktiles, const SweepArgs& a);
+// workgroups of the variant's kernel that fit one compute unit at once
+int sweep_resident(int prec, const Variant& v);
+int sweep_block_resident(int prec, const Variant& v);
 int sweep_lds_rows();
 int sweep_lds_nnz();
 int sweep_tile_states(const Variant& v);

@@ -13,6 +13,7 @@
 #include <atomic>
 #include <cmath>
 #include <thread>
+#include <unordered_map>
 
 namespace morap {
 
@@ -203,7 +204,128 @@ static void concat(morap_ctx* c, std::vector<Built>& parts, int nI, int nJ) {
     MORAP_CHECK(max_rows <= 32, MORAP_E_UNSUPPORTED, "more than 32 rows in a state");
     c->hm = std::move(hm);
     c->max_rows_per_state = max_rows;
-    upload_models(c);
+}
+
+// Neighbourhood-block form of built products (see the sweep over it): needs
+// at most 5 actions per agent and at most 5 distinct successors per agent
+// state, the state itself included; otherwise the form is not built and the
+// CSR sweeps serve alone.
+static void build_blocks(morap_ctx* c, const morap_agent* agents, int nI, const morap_dfa* tasks, int nJ,
+                         const int32_t* const* letters) {
+    HostModels& hm = c->hm;
+    hm.blk_rec.clear();
+    hm.blk_agent.clear();
+    constexpr int NS = 5;
+    std::vector<int64_t> abase(nI + 1, 0);
+    for (int i = 0; i < nI; ++i) {
+        if (agents[i].n_actions > NS) return;
+        abase[i + 1] = abase[i] + agents[i].n_states;
+    }
+    if (abase[nI] >= (int64_t)1 << 30) return;
+    // agent slots (slot 0 = the state itself) and blocks
+    std::vector<int32_t> slot((size_t)abase[nI] * NS, -1);
+    std::vector<uint8_t> amask((size_t)abase[nI], 0);
+    std::vector<double> blk((size_t)abase[nI] * 32, 0.0);
+    for (int i = 0; i < nI; ++i) {
+        const morap_agent& a = agents[i];
+        for (int s = 0; s < a.n_states; ++s) {
+            const int64_t ab = abase[i] + s;
+            int32_t* sl = &slot[(size_t)ab * NS];
+            int n = 1;
+            sl[0] = s;
+            double* B = &blk[(size_t)ab * 32];
+            for (int act = 0; act < a.n_actions; ++act) {
+                const int64_t r = (int64_t)s * a.n_actions + act;
+                if (a.sa_ptr[r + 1] == a.sa_ptr[r]) continue;
+                amask[ab] |= (uint8_t)(1u << act);
+                B[25 + act] = -a.cost[r];
+                for (int32_t e = a.sa_ptr[r]; e < a.sa_ptr[r + 1]; ++e) {
+                    int d = 0;
+                    while (d < n && sl[d] != a.succ[e]) ++d;
+                    if (d == n) {
+                        if (n == NS) return;   // too many successors: no block form
+                        sl[n++] = a.succ[e];
+                    }
+                    B[act * NS + d] += a.prob[e];
+                }
+            }
+            // a disabled action repeats the first enabled one: the maximum
+            // over actions is unchanged and the sweep needs no branch on it
+            int first = 0;
+            while (!((amask[ab] >> first) & 1)) ++first;
+            for (int act = 0; act < NS; ++act) {
+                if ((amask[ab] >> act) & 1) continue;
+                for (int d = 0; d < NS; ++d) B[act * NS + d] = B[first * NS + d];
+                B[25 + act] = B[25 + first];
+            }
+        }
+    }
+    // identical blocks (same probabilities and costs) are stored once: grid
+    // agents have a few dozen distinct ones, which then stay cache-resident
+    std::vector<int32_t> uniq((size_t)abase[nI]);
+    std::vector<double> ublk;
+    {
+        std::unordered_map<std::string, int32_t> seen;
+        for (int64_t ab = 0; ab < abase[nI]; ++ab) {
+            std::string key(reinterpret_cast<const char*>(&blk[(size_t)ab * 32]), 32 * sizeof(double));
+            auto it = seen.find(key);
+            if (it == seen.end()) {
+                it = seen.emplace(std::move(key), (int32_t)(ublk.size() / 32)).first;
+                ublk.insert(ublk.end(), blk.begin() + ab * 32, blk.begin() + (ab + 1) * 32);
+            }
+            uniq[(size_t)ab] = it->second;
+        }
+    }
+    // per product state records
+    const int M = hm.M;
+    const int32_t S = (int32_t)hm.S();
+    std::vector<int32_t> recs((size_t)S * 8, 0);
+    std::atomic<int> next{0};
+    auto worker = [&] {
+        std::vector<int32_t> map;
+        std::vector<uint8_t> done;
+        for (int m; (m = next++) < M;) {
+            const int i = m / nJ, j = m % nJ;
+            const morap_agent& a = agents[i];
+            const morap_dfa& t = tasks[j];
+            const int32_t* L = letters[m];
+            const int32_t s0 = hm.state_base[m], s1 = hm.state_base[m + 1];
+            if (s1 == s0) continue;
+            done = done_locations(t);
+            map.assign((size_t)a.n_states * t.n_locs, -1);
+            for (int32_t g = s0; g < s1; ++g)
+                map[(size_t)hm.states_sq[2 * (size_t)g + 1] * a.n_states + hm.states_sq[2 * (size_t)g]] = g;
+            for (int32_t g = s0; g < s1; ++g) {
+                const int s = hm.states_sq[2 * (size_t)g], q = hm.states_sq[2 * (size_t)g + 1];
+                const int64_t ab = abase[i] + s;
+                int32_t* r = &recs[(size_t)g * 8];
+                int32_t acc = 0;
+                for (int d = 0; d < NS; ++d) {
+                    const int32_t s2 = slot[(size_t)ab * NS + d];
+                    r[d] = S;
+                    if (s2 < 0) continue;
+                    const int q2 = t.delta[(int64_t)q * t.n_letters + L[s2]];
+                    if (done[q2]) {
+                        if (t.accepting[q2]) acc |= 1 << d;
+                    } else {
+                        r[d] = map[(size_t)q2 * a.n_states + s2];
+                    }
+                }
+                r[5] = uniq[(size_t)ab];
+                r[6] = acc | ((int32_t)amask[ab] << 8);
+            }
+        }
+    };
+    const int nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (int k = 0; k < nt; ++k) th.emplace_back(worker);
+    for (auto& k : th) k.join();
+    for (size_t g = 0; g < (size_t)S; ++g)
+        for (int d = 0; d < NS; ++d)
+            MORAP_CHECK(recs[g * 8 + d] >= 0 && recs[g * 8 + d] <= S, MORAP_E_INVALID,
+                        "neighbourhood block: a successor that is not a live state of the model");
+    hm.blk_rec = std::move(recs);
+    hm.blk_agent = std::move(ublk);
 }
 
 void build_products(morap_ctx* c, const morap_agent* agents, int nI, const morap_dfa* tasks, int nJ,
@@ -238,6 +360,8 @@ void build_products(morap_ctx* c, const morap_agent* agents, int nI, const morap
     for (auto& t : th) t.join();
     MORAP_CHECK(!bad, MORAP_E_OOM, "product construction failed (host memory)");
     concat(c, parts, nI, nJ);
+    build_blocks(c, agents, nI, tasks, nJ, letters);
+    upload_models(c);
 }
 
 void load_models(morap_ctx* c, const morap_model* models, int n, int nI, int nJ) {
@@ -281,6 +405,7 @@ void load_models(morap_ctx* c, const morap_model* models, int n, int nI, int nJ)
         b.states_sq.assign((size_t)2 * md.n_states, 0);
     }
     concat(c, parts, nI, nJ);
+    upload_models(c);
 }
 
 template <class T>
@@ -307,6 +432,13 @@ void upload_models(morap_ctx* c) {
     upload(c->d_to_done, hm.to_done, s);
     upload(c->d_state_base, hm.state_base, s);
     upload(c->d_init, hm.init, s);
+    c->has_blocks = !hm.blk_rec.empty();
+    if (c->has_blocks) {
+        upload(c->d_blk_rec, hm.blk_rec, s);
+        upload(c->d_blk64, hm.blk_agent, s);
+        c->d_blk32.ensure(hm.blk_agent.size() * 4 + 16);
+        k::to_f32(s, c->d_blk64.as<double>(), c->d_blk32.as<float>(), (int64_t)hm.blk_agent.size());
+    }
     // FP32 copies for FP32 sweeps
     c->d_prob32.ensure((size_t)c->N * 4 + 16);
     c->d_rew32.ensure((size_t)c->R * 8 + 16);

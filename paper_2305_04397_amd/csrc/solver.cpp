@@ -12,11 +12,15 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 namespace morap {
 
 // ---------------------------------------------------------------------------
-// sweep-kernel variants: columns per lane x lanes per state
+// sweep-kernel variants: kernel family x columns per lane x lanes per state.
+// Ids 1-18 are the CSR-tile sweep, 19-36 the same shapes of the
+// neighbourhood-block sweep.
 // ---------------------------------------------------------------------------
 const std::vector<Variant>& variants() {
     static const std::vector<Variant> v = [] {
@@ -25,7 +29,8 @@ const std::vector<Variant>& variants() {
                                 {1, 8},  {2, 4},  {4, 2},  {1, 16}, {2, 8},  {4, 4},
                                 {1, 32}, {2, 16}, {4, 8},  {1, 64}, {2, 32}, {4, 16}};
         int id = 1;
-        for (auto& p : pairs) out.push_back({id++, p[0], p[1], std::min(256, 64 * p[1])});
+        for (auto& p : pairs) out.push_back({id++, p[0], p[1], std::min(256, 64 * p[1]), SWEEP_CSR});
+        for (auto& p : pairs) out.push_back({id++, p[0], p[1], 256, SWEEP_BLOCK});
         return out;
     }();
     return v;
@@ -45,10 +50,11 @@ static int padded_k(int K) {
 // candidate variants for a padded width: k-tiles of min(Kp, 64) columns and
 // of half that; a restricted solve (few active columns per model) also tries
 // narrower k-tiles, which skip the k-tiles without active columns
-static std::vector<Variant> candidates(int Kp, bool restricted) {
+static std::vector<Variant> candidates(int Kp, bool restricted, bool blocks) {
     std::vector<Variant> out;
     const int kt_full = std::min(Kp, 64);
     for (const auto& v : variants()) {
+        if (v.kind == SWEEP_BLOCK && !blocks) continue;
         const int kt = kt_of(v);
         if (Kp % kt) continue;
         if (kt == kt_full || (kt * 2 == kt_full && kt >= 8) || (restricted && kt >= 8 && kt <= kt_full))
@@ -87,8 +93,9 @@ static void ensure_scratch(morap_ctx* c, int Kp) {
 
 static void ensure_values(morap_ctx* c, ValueSet& vs, int K, int Kp, int prec) {
     const size_t el = prec == MORAP_F32 ? 4 : 8;
-    vs.x[0].ensure((size_t)c->S * Kp * el);
-    vs.x[1].ensure((size_t)c->S * Kp * el);
+    // one row past the last state: the zero row of the block sweep
+    vs.x[0].ensure((size_t)(c->S + 1) * Kp * el);
+    vs.x[1].ensure((size_t)(c->S + 1) * Kp * el);
     vs.final_par.ensure((size_t)c->hm.M * Kp);
     vs.c.ensure((size_t)K * c->hm.M * 8);
     vs.prec = prec;
@@ -149,11 +156,26 @@ static k::SweepArgs sweep_args(morap_ctx* c, ValueSet& vs, int in_par) {
     a.res = c->d_res.as<unsigned long long>();
     a.ymax = c->d_ymax.as<unsigned long long>();
     a.Kp = vs.Kp;
+    a.rec = c->has_blocks ? c->d_blk_rec.as<int32_t>() : nullptr;
+    a.ablk = c->has_blocks ? (f32 ? c->d_blk32.p : c->d_blk64.p) : nullptr;
+    a.zero_row = (int32_t)c->S;
     return a;
 }
 
-static int persistent_grid(morap_ctx* c, const Variant& v) {
-    const int per_cu = v.wg >= 256 ? 8 : 16;
+// Persistent grid: as many workgroups as the kernel keeps resident on the
+// whole chip at once (a second, partial round of workgroups would double the
+// time of a balanced sweep), a multiple of 8 (one share per XCD), and no more
+// than the tiles need.
+static int persistent_grid(morap_ctx* c, int prec, const Variant& v) {
+    const int64_t key = ((int64_t)v.id << 8) | prec;
+    int per_cu = 0;
+    for (auto& r : c->resident)
+        if (r.first == key) per_cu = r.second;
+    if (per_cu == 0) {
+        per_cu = v.kind == SWEEP_BLOCK ? k::sweep_block_resident(prec, v) : k::sweep_resident(prec, v);
+        per_cu = std::max(1, per_cu);
+        c->resident.push_back({key, per_cu});
+    }
     int g = c->prop.multiProcessorCount * per_cu;
     const int tiles = (int)c->tiles.size();
     g = std::min(g, (tiles + 7) / 8 * 8);
@@ -162,21 +184,40 @@ static int persistent_grid(morap_ctx* c, const Variant& v) {
 
 using EventPairs = std::vector<std::pair<hipEvent_t, hipEvent_t>>;
 
+// Optional per-launch log (environment variable MORAP_SWEEP_LOG = file path):
+// the autotuner's timings and, for solves run with time_kernels, one line per
+// sweep launch with its active tile count and duration.
+static FILE* sweep_log() {
+    static FILE* f = [] {
+        const char* p = std::getenv("MORAP_SWEEP_LOG");
+        return p && *p ? std::fopen(p, "a") : nullptr;
+    }();
+    return f;
+}
+
 // one chunk of `n` sweeps (n even): sweep, converge, compact per sweep;
 // `ev` (optional) receives an event pair around every sweep kernel
 static void enqueue_chunk(morap_ctx* c, ValueSet& vs, const uint8_t* mask, const Variant& v, double eps, int n,
                           EventPairs* ev = nullptr) {
-    const int grid = persistent_grid(c, v);
+    const int grid = persistent_grid(c, vs.prec, v);
     const int ktiles = vs.Kp / kt_of(v);
     for (int i = 0; i < n; ++i) {
         const int in_par = i & 1;
         if (ev) {
+            if (sweep_log() && ev->size() < 4096) {
+                c->h_log.ensure(4096 * 8);
+                MORAP_HIP(hipMemcpyAsync(c->h_log.as<int64_t>() + ev->size(), c->d_counters.as<int64_t>() + 1, 8,
+                                         hipMemcpyDeviceToHost, c->stream));
+            }
             ev->emplace_back();
             MORAP_HIP(hipEventCreate(&ev->back().first));
             MORAP_HIP(hipEventCreate(&ev->back().second));
             MORAP_HIP(hipEventRecord(ev->back().first, c->stream));
         }
-        k::sweep(c->stream, vs.prec, v, grid, ktiles, sweep_args(c, vs, in_par));
+        if (v.kind == SWEEP_BLOCK)
+            k::sweep_block(c->stream, vs.prec, v, grid, ktiles, sweep_args(c, vs, in_par));
+        else
+            k::sweep(c->stream, vs.prec, v, grid, ktiles, sweep_args(c, vs, in_par));
         if (ev) MORAP_HIP(hipEventRecord(ev->back().second, c->stream));
         const auto ca = converge_args(c, vs, mask, eps, 1 - in_par);
         k::converge(c->stream, ca);
@@ -185,7 +226,7 @@ static void enqueue_chunk(morap_ctx* c, ValueSet& vs, const uint8_t* mask, const
 }
 
 static void reset_solve(morap_ctx* c, ValueSet& vs, const uint8_t* mask, double eps) {
-    const int64_t n = c->S * vs.Kp;
+    const int64_t n = (c->S + 1) * vs.Kp;
     if (vs.prec == MORAP_F32) {
         k::fill_f32(c->stream, vs.x[0].as<float>(), 0.f, n);
         k::fill_f32(c->stream, vs.x[1].as<float>(), 0.f, n);
@@ -261,18 +302,25 @@ static const Variant& choose_variant(morap_ctx* c, ValueSet& vs, const uint8_t* 
     if (schedule > 0) {
         const Variant& v = variant_by_id(schedule);
         MORAP_CHECK(vs.Kp % kt_of(v) == 0, MORAP_E_INVALID, "variant does not divide the padded column count");
+        MORAP_CHECK(v.kind != SWEEP_BLOCK || c->has_blocks, MORAP_E_UNSUPPORTED,
+                    "the neighbourhood-block sweep needs products built from agents with at most 5 actions "
+                    "and 5 successors per state");
         return v;
     }
     const int64_t key = ((int64_t)vs.prec << 40) | ((int64_t)(mask != nullptr) << 32) | vs.Kp;
     for (auto& t : c->tuned)
         if (t.first == key) return variant_by_id(t.second);
-    auto cand = candidates(vs.Kp, mask != nullptr);
+    auto cand = candidates(vs.Kp, mask != nullptr, c->has_blocks);
     MORAP_CHECK(!cand.empty(), MORAP_E_UNSUPPORTED, "no sweep variant for this column count");
     int best = cand[0].id;
     if (cand.size() > 1) {
         double best_ms = 1e300;
         for (const auto& v : cand) {
             const double ms = time_variant(c, vs, mask, v, eps);
+            if (sweep_log())
+                std::fprintf(sweep_log(), "tune prec=%d mask=%d Kp=%d variant=%d kind=%d cpl=%d lps=%d grid=%d ms=%.4f\n",
+                             vs.prec, mask != nullptr, vs.Kp, v.id, v.kind, v.cpl, v.lps,
+                             persistent_grid(c, vs.prec, v), ms);
             if (ms < best_ms) {
                 best_ms = ms;
                 best = v.id;
@@ -297,9 +345,13 @@ static void run_vi(morap_ctx* c, int g, ValueSet& vs, const uint8_t* mask, const
     int64_t* h = c->h_counters.as<int64_t>();
     EventPairs ev;
     auto harvest = [&] {
-        for (auto& e : ev) {
+        for (size_t i = 0; i < ev.size(); ++i) {
+            auto& e = ev[i];
             float t = 0;
             MORAP_HIP(hipEventElapsedTime(&t, e.first, e.second));
+            if (sweep_log() && i < 4096)
+                std::fprintf(sweep_log(), "sweep prec=%d mask=%d variant=%d tiles=%lld ms=%.4f\n", vs.prec,
+                             mask != nullptr, v.id, (long long)c->h_log.as<int64_t>()[i], t);
             if (mask) {
                 st.ms_sweep_kernel_refine += t;
                 st.sweep_launches_refine += 1;

@@ -20,6 +20,7 @@
 //    fixed-policy evaluation sweeps (Alg. 4) on (column, model) instances, one
 //    thread per state.
 #include "common.h"
+#include "kern.h"
 
 #include <cfloat>
 
@@ -71,47 +72,6 @@ void to_f32(hipStream_t s, const double* in, float* out, int64_t n) {
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, in, out, n);
     MORAP_HIP(hipGetLastError());
-}
-
-// ---------------------------------------------------------------------------
-// vector helpers: CPL consecutive columns per lane
-// ---------------------------------------------------------------------------
-template <class T, int CPL> struct Vec { T v[CPL]; };
-
-template <class T, int CPL>
-__device__ __forceinline__ Vec<T, CPL> vload(const T* p) {
-    Vec<T, CPL> r;
-    if constexpr (CPL == 4 && sizeof(T) == 4) {
-        float4 q = *reinterpret_cast<const float4*>(p);
-        r.v[0] = q.x; r.v[1] = q.y; r.v[2] = q.z; r.v[3] = q.w;
-    } else if constexpr (CPL == 2 && sizeof(T) == 4) {
-        float2 q = *reinterpret_cast<const float2*>(p);
-        r.v[0] = q.x; r.v[1] = q.y;
-    } else if constexpr (CPL >= 2 && sizeof(T) == 8) {
-#pragma unroll
-        for (int c = 0; c < CPL; c += 2) {
-            double2 q = *reinterpret_cast<const double2*>(p + c);
-            r.v[c] = q.x; r.v[c + 1] = q.y;
-        }
-    } else {
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) r.v[c] = p[c];
-    }
-    return r;
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-// reduce across lanes that hold the same columns: lane bits >= log2(LPS)
-template <int LPS>
-__device__ __forceinline__ double group_max(double v) {
-#pragma unroll
-    for (int o = 32; o >= LPS; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -191,11 +151,8 @@ bellman_sweep(const Tile* __restrict__ tiles, const int32_t* __restrict__ tile_b
     // neighbouring tiles (which share successors) stay in that XCD's L2.
     const int n_tiles = (int)counters[1];
     const int n_act = (int)counters[2];
-    const int per_xcd = gridDim.x >> 3;
-    const int owner = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-    const int per_wg = (n_tiles + gridDim.x - 1) / gridDim.x;
-    const int t_begin = owner * per_wg;
-    const int t_end = min(n_tiles, t_begin + per_wg);
+    int t_begin, t_end;
+    xcd_share(n_tiles, blockIdx.x & 7, blockIdx.x >> 3, gridDim.x >> 3, t_begin, t_end);
     if (t_begin >= t_end) return;
 
     // active model holding the first tile, then advanced tile by tile
@@ -356,6 +313,26 @@ static void sweep_t(hipStream_t s, const Variant& v, int grid, int ktiles, const
     MORAP_V(1, 32) MORAP_V(2, 16) MORAP_V(4, 8) MORAP_V(1, 64) MORAP_V(2, 32) MORAP_V(4, 16)
 #undef MORAP_V
     fail(MORAP_E_UNSUPPORTED, "no sweep kernel for this variant");
+}
+
+template <class T, class T2>
+static const void* sweep_fn(const Variant& v) {
+#define MORAP_F(C, L)                                                                                   \
+    if (v.cpl == C && v.lps == L)                                                                       \
+        return reinterpret_cast<const void*>(                                                           \
+            &bellman_sweep<T, T2, C, L, ((64 * L < 256) ? 64 * L : 256)>);
+    MORAP_F(1, 1) MORAP_F(1, 2) MORAP_F(2, 1) MORAP_F(1, 4) MORAP_F(2, 2) MORAP_F(4, 1)
+    MORAP_F(1, 8) MORAP_F(2, 4) MORAP_F(4, 2) MORAP_F(1, 16) MORAP_F(2, 8) MORAP_F(4, 4)
+    MORAP_F(1, 32) MORAP_F(2, 16) MORAP_F(4, 8) MORAP_F(1, 64) MORAP_F(2, 32) MORAP_F(4, 16)
+#undef MORAP_F
+    fail(MORAP_E_UNSUPPORTED, "no sweep kernel for this variant");
+}
+
+int sweep_resident(int prec, const Variant& v) {
+    int n = 0;
+    MORAP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &n, prec == MORAP_F32 ? sweep_fn<float, float2>(v) : sweep_fn<double, double2>(v), v.wg, 0));
+    return n;
 }
 
 void sweep(hipStream_t s, int prec, const Variant& v, int grid, int ktiles, const SweepArgs& a) {

@@ -130,6 +130,7 @@ _sig("morap_proposer_init", C.c_int, _ctxp, C.c_int, C.c_int, C.c_uint64)
 _sig("morap_proposer_num_params", C.c_int64, _ctxp)
 _sig("morap_proposer_get_params", C.c_int, _ctxp, _p)
 _sig("morap_proposer_set_params", C.c_int, _ctxp, _p)
+_sig("morap_proposer_set_input_norm", C.c_int, _ctxp, _p, _p)
 _sig("morap_proposer_infer", C.c_int, _ctxp, _p, C.c_int, _p)
 _sig("morap_proposer_step", C.c_int, _ctxp, _p, _p, C.c_int, C.POINTER(TrainOpts), C.c_int, _p, _p)
 _sig("morap_proposer_train", C.c_int, _ctxp, _p, _p, C.c_int, C.POINTER(TrainOpts), _p)
@@ -405,6 +406,11 @@ class Context:
     def proposer_set_params(self, flat):
         flat = _c(flat, np.float32)
         self._check(lib.morap_proposer_set_params(self._h, _ptr(flat)), "morap_proposer_set_params")
+
+    def proposer_set_input_norm(self, mu, sd):
+        mu, sd = _c(mu, np.float32), _c(sd, np.float32)
+        self._check(lib.morap_proposer_set_input_norm(self._h, _ptr(mu), _ptr(sd)),
+                    "morap_proposer_set_input_norm")
 
     def proposer_infer(self, X, d: int) -> np.ndarray:
         X = _c(np.atleast_2d(X), np.float32)

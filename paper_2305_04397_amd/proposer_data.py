@@ -1,0 +1,72 @@
+"""Training data and features for the learned weight proposer.
+
+Everything here runs through the library (the plain Alg. 1 loop on the
+device); nothing is learned from the oracle.
+
+* ``features``: the instance summary phi the proposer sees beside the threshold
+  point: the ideal point (the optimum of every single objective, one batched
+  solve with the d unit weight vectors), the mean slip probability of the
+  agents and log10 of the number of product states.
+* ``thresholds``: threshold points t = u + delta |u| around front points u
+  (delta ~ U[-0.3, 0.3] per coordinate, probabilities clipped to [0, 1]).
+* ``target_weight``: the weight vector a query should have started from: for
+  a threshold outside the achievable set, the normal M (t - t_down) of the
+  face holding the closest point; otherwise the last weight vector the plain
+  loop used.  Both normalised to sum 1.
+* ``generate``: plain-loop queries in lockstep batches, returning the network
+  inputs [t; phi], the targets and the query results.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def features(ctx, wl, opts) -> np.ndarray:
+    nI, nJ = wl.n_agents, wl.n_tasks
+    d = nI + nJ
+    r, _, _, _ = ctx.support(np.eye(d), opts)
+    ideal = np.array([r[k, k] for k in range(d)])
+    states = sum(ctx.model_info(m)["n_states"] for m in range(nI * nJ))
+    slip = float(np.mean([a.p_slip for a in wl.agents]))
+    return np.concatenate([ideal, [slip, np.log10(max(states, 1))]])
+
+
+def front_points(ctx, wl, n, rng, opts) -> np.ndarray:
+    d = wl.n_agents + wl.n_tasks
+    out = []
+    for b in range(0, n, 64):
+        k = min(64, n - b)
+        r, _, _, _ = ctx.support(rng.dirichlet(np.ones(d), size=k), opts)
+        out.append(r)
+    return np.vstack(out)
+
+
+def thresholds(rng, front: np.ndarray, n: int, nI: int) -> np.ndarray:
+    u = front[rng.integers(front.shape[0], size=n)]
+    t = u + rng.uniform(-0.3, 0.3, size=u.shape) * np.abs(u)
+    t[:, nI:] = np.clip(t[:, nI:], 0.0, 1.0)
+    return t
+
+
+def target_weight(t: np.ndarray, res: dict, M=None) -> np.ndarray:
+    diff = t - res["t_down"]
+    if np.abs(diff).max() > 1e-9:
+        w = diff if M is None else M @ diff
+    else:
+        w = res["W"][-1].copy()
+    w = np.maximum(w, 0.0)
+    s = w.sum()
+    return w / s if s > 0 else np.full(t.size, 1.0 / t.size)
+
+
+def generate(ctx, wl, T: np.ndarray, phi: np.ndarray, opts, eps: float = 0.01, max_iter: int = 64,
+             batch: int = 64):
+    """Plain-loop queries for every row of T; returns (X, Wt, results)."""
+    X, Wt, results = [], [], []
+    for b in range(0, T.shape[0], batch):
+        res = ctx.query_batch(T[b:b + batch], eps=eps, max_iter=max_iter, opts=opts, trace=True)
+        for t, q in zip(T[b:b + batch], res):
+            X.append(np.concatenate([t, phi]))
+            Wt.append(target_weight(t, q))
+            results.append(q)
+    return np.asarray(X, np.float32), np.asarray(Wt, np.float32), results

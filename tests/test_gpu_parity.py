@@ -92,22 +92,74 @@ def test_solve_f64_matches_oracle(ctx, morap, K):
             assert np.abs(x - vals[m][:, k]).max() <= 4 * eps + 1e-10 * np.abs(vals[m]).max()
 
 
+SHAPES = [(1, 1), (1, 2), (2, 1), (1, 4), (2, 2), (4, 1), (1, 8), (2, 4), (4, 2), (1, 16), (2, 8),
+          (4, 4), (1, 32), (2, 16), (4, 8), (1, 64), (2, 32), (4, 16)]
+
+
 def test_every_variant_gives_identical_f64_values(ctx, morap):
+    """Variants 1-18 (CSR tiles) share one summation order, so their values are
+    bit-identical, eager or graph-replayed; so are variants 19-36 (neighbourhood
+    blocks) among themselves.  The two families add the same products in a
+    different order: they agree to rounding."""
     wl = make_workload(2, n_agents=2, n_tasks=3)
     _load(ctx, wl)
     W = dirichlet_weights(np.random.default_rng(0), 16, 5)
-    ref = None
-    from itertools import product as iprod
-    for v in range(1, 19):
-        cpl, lps = [(1, 1), (1, 2), (2, 1), (1, 4), (2, 2), (4, 1), (1, 8), (2, 4), (4, 2), (1, 16), (2, 8),
-                    (4, 4), (1, 32), (2, 16), (4, 8), (1, 64), (2, 32), (4, 16)][v - 1]
+    ref = {}
+    for v in range(1, 37):
+        cpl, lps = SHAPES[(v - 1) % 18]
         if 16 % (cpl * lps):
             continue
+        fam = v > 18
         for graph in (False, True):
-            c, _ = ctx.solve(W, morap.Options(eps_vi=1e-7, precision="f64", schedule=v, use_graph=graph))
-            if ref is None:
-                ref = c
-            assert np.array_equal(c, ref), (v, graph)
+            c, st = ctx.solve(W, morap.Options(eps_vi=1e-7, precision="f64", schedule=v, use_graph=graph))
+            assert st["variant"] == v
+            if fam not in ref:
+                ref[fam] = c
+            assert np.array_equal(c, ref[fam]), (v, graph)
+    assert np.abs(ref[True] - ref[False]).max() <= 1e-12 * np.abs(ref[False]).max()
+
+
+@pytest.mark.parametrize("v", [28, 31, 34, 36])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_block_sweep_matches_oracle_cfg2(ctx, morap, v, prec):
+    """The neighbourhood-block sweep against the oracle's value iteration, on
+    products of uneven size (obstacles, reach and avoid automata), K = 64."""
+    wl = make_workload(2, n_agents=3, n_tasks=6)
+    prods = _load(ctx, wl)
+    nI, nJ = wl.n_agents, wl.n_tasks
+    W = dirichlet_weights(np.random.default_rng(5), 64, nI + nJ)
+    eps = 1e-8 if prec == "f64" else 1e-6
+    c, st = ctx.solve(W, morap.Options(eps_vi=eps, precision=prec, schedule=v))
+    assert st["variant"] == v
+    co, _, _ = _oracle_c(prods, nI, nJ, W, eps)
+    if prec == "f64":
+        assert np.abs(c - co).max() <= 4 * eps + 1e-10 * np.abs(co).max()
+    else:
+        assert (np.abs(c - co) <= 2e-4 * np.maximum(1.0, np.abs(co))).all()
+
+
+def test_block_sweep_self_loop_changing_location(ctx, morap):
+    """Staying on a waypoint cell advances a counting automaton (visit the cell
+    set three times), so a state's own successor is another product state: the
+    sweep must then read the state's old value separately."""
+    from workloads.gridworld import Task
+    wl = tiny_workload(3, 2, 1, width=4, height=3, kinds=("reach",), k=1)
+    delta = np.array([[0, 1], [1, 2], [2, 3], [3, 3]], dtype=np.int32)
+    wl.tasks[0] = Task(kind="count", k=3, n_locs=4, n_letters=2, q0=0, delta=delta,
+                       accepting=np.array([0, 0, 0, 1], dtype=np.uint8), waypoints_uv=np.zeros((0, 2, 2)),
+                       avoid_uv=None)
+    for i in range(wl.n_agents):
+        lab = np.zeros(wl.agents[i].n_states, dtype=np.int32)
+        lab[[1, 5]] = 1
+        lab[wl.agents[i].init] = 0
+        wl.letters[i][0] = lab
+    prods = _load(ctx, wl)
+    W = dirichlet_weights(np.random.default_rng(1), 64, 3)
+    eps = 1e-10
+    for v in (28, 34):
+        c, _ = ctx.solve(W, morap.Options(eps_vi=eps, precision="f64", schedule=v))
+        co, _, _ = _oracle_c(prods, 2, 1, W, eps)
+        assert np.abs(c - co).max() <= 4 * eps + 1e-10 * np.abs(co).max()
 
 
 def test_support_f64_cfg1_matches_oracle(ctx, morap):
@@ -218,3 +270,13 @@ def test_edge_cases(ctx, morap):
     assert ctx.model_info(0)["n_states"] == 0
     r, A, c, _ = ctx.support(np.array([[0.5, 0.5]]), o)
     assert np.allclose(r, 0) and np.allclose(c, 0)
+    # caller-built CSR products have no neighbourhood-block form
+    prods = product.build_all(make_workload(1))
+    ctx.load_models([{"state_row": p.state_row, "row_ptr": p.row_ptr, "col": p.col, "prob": p.prob,
+                      "rew": np.stack([p.rew_cost, p.rew_prob], 1), "to_done": p.to_done, "init": p.init}
+                     for p in prods], 2, 2)
+    with pytest.raises(morap.MorapError) as e:
+        ctx.solve(np.eye(4)[:1], morap.Options(eps_vi=1e-8, precision="f64", schedule=19))
+    assert e.value.code == morap.E_UNSUPPORTED
+    c, st = ctx.solve(np.eye(4)[:1], morap.Options(eps_vi=1e-8, precision="f64"))
+    assert st["variant"] <= 18
