@@ -22,8 +22,11 @@ Extra objects on the JSON line:
                 over its summed HIP-event durations, against 8 TB/s HBM;
   cpu_baseline  the FP64 oracle's value iteration timed on a bounded sample of
                 models of the same workload on the host (single process);
-  ms_per_query  full Alg. 1 queries (eps 0.01) from the plain first weight
-                (1, 0, ..., 0), and from the learned proposer when one is loaded.
+  ms_per_query  full Alg. 1 queries (eps 0.01) on the timed workload from the
+                plain first weight (1, 0, ..., 0);
+  proposer      learned vs plain first weight on the 10 x 20 family: the
+                proposer is trained on the device from plain-loop queries of
+                seeded variants, then both loops answer unseen thresholds.
 """
 from __future__ import annotations
 
@@ -82,6 +85,69 @@ def cpu_baseline(wl, K: int, eps: float, budget_s: float, seed: int) -> dict:
                       f"{elapsed:.1f} s of single-process CPU work"}
 
 
+def proposer_eval(args) -> dict:
+    """Learned vs plain first weight on the 10 x 20 family.
+
+    Plain Alg. 1 loops on seeded 10 x 20 variants give (t, target weight)
+    tuples; the proposer is trained on them on the device, then both loops
+    answer the same unseen thresholds of variant 0 (fresh draws): wall time
+    and Alg. 2 passes per query, and agreement of the answers."""
+    from workloads import make_workload
+    from paper_2305_04397_amd import morap, proposer_data as pdata
+    rng = np.random.default_rng(args.seed + 1)
+    opts = morap.Options(eps_vi=1e-6, precision="f32")
+    ctx = morap.Context(0)
+    X, Wt, phis, eval_T, errors = [], [], {}, None, []
+    t0 = time.perf_counter()
+    for v in range(args.proposer_variants):
+        wl = make_workload(2, variant=v)
+        ctx.build_products(wl)
+        phi = pdata.features(ctx, wl, opts)
+        front = pdata.front_points(ctx, wl, 256, rng, opts)
+        T = pdata.thresholds(rng, front, args.proposer_train, wl.n_agents)
+        n_err = len(errors)
+        x, w, _ = pdata.generate(ctx, wl, T, phi, opts, errors=errors)
+        for e in errors[n_err:]:
+            log(f"proposer data: batch skipped: {e}")
+        X.append(x)
+        Wt.append(w)
+        if v == 0:
+            phis[0] = phi
+            eval_T = pdata.thresholds(rng, front, args.proposer_queries, wl.n_agents)
+        log(f"proposer data: variant {v}, {len(x)} tuples ({time.perf_counter() - t0:.0f} s)")
+    X, Wt = np.vstack(X), np.vstack(Wt)
+    d = Wt.shape[1]
+    ctx.proposer_init(X.shape[1], d, seed=args.seed)
+    ctx.proposer_set_input_norm(X.mean(0), X.std(0) + 1e-3)
+    tt = time.perf_counter()
+    losses = ctx.proposer_train(X, Wt, batch=256, epochs=80, lr=1e-3, seed=args.seed)
+    train_s = time.perf_counter() - tt
+    log(f"proposer trained on {len(X)} tuples in {train_s:.1f} s: loss {losses[0]:.3f} -> {losses[-1]:.3f}")
+    # evaluation on variant 0
+    wl = make_workload(2, variant=0)
+    ctx.build_products(wl)
+    ctx.set_features(phis[0])
+    ctx.query_batch(eval_T[:8], eps=0.01, opts=opts)                         # warm caches
+    out = {"workload": wl.name, "eps": 0.01, "train_tuples": int(len(X)), "skipped_batches": len(errors),
+           "train_variants": args.proposer_variants, "epochs": 80, "train_s": round(train_s, 2),
+           "loss_first": round(float(losses[0]), 4), "loss_last": round(float(losses[-1]), 4)}
+    res = {}
+    for name, use in (("plain", False), ("learned", True)):
+        ts = time.perf_counter()
+        r = ctx.query_batch(eval_T, eps=0.01, opts=opts, use_proposer=use)
+        ms = (time.perf_counter() - ts) * 1e3
+        its = np.array([q["iterations"] for q in r])
+        res[name] = r
+        out[name] = {"queries": len(r), "wall_ms": round(ms, 1), "ms_per_query": round(ms / len(r), 3),
+                     "passes_mean": round(float(its.mean()), 3), "passes_max": int(its.max())}
+        log(f"proposer eval {name}: {ms / len(r):.2f} ms/query, passes mean {its.mean():.2f}")
+    agree = sum(p["verdict"] == q["verdict"] for p, q in zip(res["plain"], res["learned"]))
+    out["verdict_agreement"] = f"{agree}/{len(eval_T)}"
+    out["fallbacks"] = int(sum(q["fallback"] for q in res["learned"]))
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +159,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--proposer-queries", type=int, default=256,
+                    help="unseen 10x20 queries for the learned-vs-plain comparison (0 = skip)")
+    ap.add_argument("--proposer-train", type=int, default=512, help="training queries per 10x20 variant")
+    ap.add_argument("--proposer-variants", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path runs on a single MI355X (multi-GPU sharding is "
@@ -175,7 +245,8 @@ def main():
         wq = (time.perf_counter() - tq) * 1e3
         its = np.array([q["iterations"] for q in res])
         verdicts = [q["verdict"] for q in res]
-        per_query = {"plain": {"queries": len(res), "wall_ms": round(wq, 1),
+        per_query = {"workload": wl.name, "eps": 0.01,
+                     "plain": {"queries": len(res), "wall_ms": round(wq, 1),
                                "ms_per_query": round(wq / len(res), 2),
                                "passes_mean": round(float(its.mean()), 2), "passes_max": int(its.max()),
                                "feasible": verdicts.count(morap.FEASIBLE),
@@ -183,6 +254,11 @@ def main():
                                "undecided": verdicts.count(morap.UNDECIDED)},
                      "learned": None}
         log(f"queries: {len(res)} in {wq:.0f} ms, passes mean {its.mean():.1f}")
+
+    ctx.close()
+    learned = None
+    if args.proposer_queries > 0:
+        learned = proposer_eval(args)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -197,9 +273,9 @@ def main():
                        "states": S, "rows": R, "nnz": N, "K": K, "eps_vi": eps, "seed": args.seed,
                        "parallelism": "1 GPU"},
             "roofline": roofline, "cpu_baseline": cpu, "ms_per_query": per_query,
+            "proposer": learned,
             "stats": {k: st[k] for k in ("backups", "sweeps", "eval_sweeps", "polish_sweeps", "rank_rounds",
                                          "ms_vi", "ms_eval", "variant", "bytes", "bytes_refine")}}
-    ctx.close()
     print(json.dumps(line), flush=True)
 
 

@@ -59,6 +59,19 @@ class SupportResult:
     values: list             # final VI values of every model (m = i*|J| + j)
 
 
+def policy_for(prod, wi: float, wj: float, eps_vi: float, tau: float = 1e-9) -> np.ndarray:
+    """The policy of one model under weights (wi, wj): value iteration on the
+    two weights scaled to sum 1, then the tie rule.  Scaling leaves the
+    optimal policies of the scalarised model unchanged (Alg. 3 maximises
+    wi rho_i + wj rho_j); it keeps the absolute stop test and the tie
+    tolerance meaningful when both weights are tiny."""
+    sc = wi + wj
+    if sc > 0:
+        wi, wj = wi / sc, wj / sc
+    x, _ = vi.value_iteration(prod, np.array([wi]), np.array([wj]), eps_vi)
+    return vi.extract_policy(prod, x[:, 0], wi, wj, tau)
+
+
 def support(products, nI: int, nJ: int, w: np.ndarray, eps_vi: float,
             eps_eval: Optional[float] = None, tau: float = 1e-9) -> SupportResult:
     """Alg. 2 for one weight vector w [d]."""
@@ -79,7 +92,7 @@ def support(products, nI: int, nJ: int, w: np.ndarray, eps_vi: float,
     for j in range(nJ):
         i = int(f[j])
         prod = products[i * nJ + j]
-        mu = vi.extract_policy(prod, values[i * nJ + j], w[i], w[nI + j], tau)
+        mu = policy_for(prod, w[i], w[nI + j], eps_vi, tau)
         (vc, vp), _, _ = vi.evaluate(prod, mu, eps_eval)
         r[nI + j] = vp
         r[i] += vc
@@ -134,6 +147,8 @@ def query(products, nI: int, nJ: int, t: np.ndarray, eps: float, eps_vi: float,
         if separated or geometry.mnorm(t_down - t_up, M) <= eps:
             break
         w = geometry.weight_from(t, t_up, M)
+        if w is None:          # t_up = t up to rounding
+            break
     verdict = verdict_of(t, t_up, np.array(Ws), np.array(Phi), M)
     return QueryResult(verdict=verdict, t_up=t_up, t_down=t_down, iterations=len(Phi),
                        Phi=Phi, W=Ws, lam=lam, trace=trace)

@@ -161,14 +161,23 @@ def project_outer(Ws: np.ndarray, Rs: np.ndarray, t: np.ndarray,
     return out
 
 
-def weight_from(t: np.ndarray, t_up: np.ndarray, M: np.ndarray | None = None) -> np.ndarray:
+NOISE = 1e-12   # relative size of the projection's rounding noise
+
+
+def weight_from(t: np.ndarray, t_up: np.ndarray, M: np.ndarray | None = None) -> np.ndarray | None:
     """w = M (t - t_up) / ||M (t - t_up)||_1 (Alg. 1, weight update).  The
-    direction is non-negative in exact arithmetic (Lemma lem:weight-vector);
-    rounding-level negative components are set to 0."""
-    v = np.asarray(t, dtype=np.float64) - np.asarray(t_up, dtype=np.float64)
+    direction is non-negative in exact arithmetic (Lemma lem:weight-vector).
+    Components at or below NOISE * max(1, ||t||_inf) are rounding noise of the
+    projection t_up and are set to 0, like negative ones (a positive noise
+    component would otherwise become the whole objective of the models it
+    touches).  Returns None when nothing is left (t_up = t to rounding)."""
+    t = np.asarray(t, dtype=np.float64)
+    v = t - np.asarray(t_up, dtype=np.float64)
     wv = v if M is None else np.asarray(M, dtype=np.float64) @ v
-    wv = np.maximum(wv, 0.0)
-    return wv / wv.sum()
+    floor = NOISE * max(1.0, float(np.abs(t).max()))
+    wv = np.where(wv > floor, wv, 0.0)
+    s = wv.sum()
+    return wv / s if s > 0 else None
 
 
 def kkt_inner(Phi, t, x, lam, M=None) -> float:

@@ -158,17 +158,26 @@ void query_batch(morap_ctx* c, const double* T, const double* W0, int Q, const d
                     s.done = true;
                     continue;
                 }
-                // w = M (t - t_up) / ||M (t - t_up)||_1; rounding-level negatives are 0
+                // w = M (t - t_up) / ||M (t - t_up)||_1.  Components at or
+                // below 1e-12 max(1, ||t||_inf) are rounding noise of the
+                // projection (like negative ones) and become 0: a positive
+                // noise entry would otherwise be the whole objective of the
+                // models it touches.
                 std::vector<double> v(d), mv(d, 0.0);
-                for (int k = 0; k < d; ++k) v[k] = s.t[k] - s.t_up[k];
+                double tmax = 1.0;
+                for (int k = 0; k < d; ++k) {
+                    v[k] = s.t[k] - s.t_up[k];
+                    tmax = std::max(tmax, std::fabs(s.t[k]));
+                }
                 for (int k = 0; k < d; ++k) {
                     if (!M) mv[k] = v[k];
                     else
                         for (int l = 0; l < d; ++l) mv[k] += M[(size_t)k * d + l] * v[l];
                 }
+                const double floor = 1e-12 * tmax;
                 double sum = 0;
                 for (int k = 0; k < d; ++k) {
-                    mv[k] = std::max(mv[k], 0.0);
+                    mv[k] = mv[k] > floor ? mv[k] : 0.0;
                     sum += mv[k];
                 }
                 if (!(sum > 0)) {

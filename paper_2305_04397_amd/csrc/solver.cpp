@@ -559,6 +559,11 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
             }
             iwc[q] = c->W[(size_t)kk * d + i];
             iwp[q] = c->W[(size_t)kk * d + nI + j];
+            const double sc = iwc[q] + iwp[q];   // policies come from the weights scaled to sum 1
+            if (sc > 0) {
+                iwc[q] /= sc;
+                iwp[q] /= sc;
+            }
             if (c->hm.init[m] >= 0) init_idx[q] = c->inst_base[q] + (c->hm.init[m] - c->hm.state_base[m]);
         }
     const int64_t NS = c->inst_base[n];
@@ -596,17 +601,39 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
     uint8_t* ipar = c->d_ipar.as<uint8_t>();
     const int chunk = std::max(2, (o.check_every + 1) / 2 * 2);
 
-    // FP64 values of the assigned pairs: after an FP32 solve, value
-    // iteration in FP64 from 0 on exactly those pairs
-    ValueSet* src = &c->vmain;
-    if (c->prec == MORAP_F32) {
-        ensure_values(c, c->vref, K, c->Kp, MORAP_F64);
+    // Values for the policies: FP64 value iteration from 0 on exactly the
+    // assigned pairs, with each model's two weights scaled to sum 1.  Scaling
+    // leaves the optimal policies unchanged; it keeps the absolute stop test
+    // and the tie tolerance meaningful when both weights are tiny (the
+    // unscaled iteration then stops after a sweep or two and its greedy
+    // policy can take ~1e6 steps to finish).
+    {
+        const int M = c->hm.M, Kp = c->Kp;
+        std::vector<double> wc((size_t)M * Kp, 0.0), wp((size_t)M * Kp, 0.0);
+        for (int kk = 0; kk < K; ++kk)
+            for (int m = 0; m < M; ++m) {
+                const int i = m / nJ, j = m % nJ;
+                double a0 = c->W[(size_t)kk * d + i], a1 = c->W[(size_t)kk * d + nI + j];
+                const double sc = a0 + a1;
+                if (sc > 0) {
+                    a0 /= sc;
+                    a1 /= sc;
+                }
+                wc[(size_t)m * Kp + kk] = a0;
+                wp[(size_t)m * Kp + kk] = a1;
+            }
+        MORAP_HIP(hipMemcpyAsync(c->d_wc64.p, wc.data(), wc.size() * 8, hipMemcpyHostToDevice, s));
+        MORAP_HIP(hipMemcpyAsync(c->d_wp64.p, wp.data(), wp.size() * 8, hipMemcpyHostToDevice, s));
+        MORAP_HIP(hipStreamSynchronize(s));   // the host vectors go out of scope
+    }
+    ensure_values(c, c->vref, K, c->Kp, MORAP_F64);
+    {
         uint8_t* pm = c->d_pair_mask.as<uint8_t>();
         k::fill_u8(s, pm, 0, (int64_t)c->hm.M * c->Kp);
         k::mark_pairs(s, a, c->Kp, pm);
         run_vi(c, 1, c->vref, pm, o, st);
-        src = &c->vref;
     }
+    ValueSet* src = &c->vref;
 
     hipEvent_t e0, e1;
     MORAP_HIP(hipEventCreate(&e0));
@@ -670,12 +697,24 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
             // policies stay readable through morap_get_policy
             std::vector<uint8_t> still((size_t)2 * n);
             MORAP_HIP(hipMemcpy(still.data(), iact, still.size(), hipMemcpyDeviceToHost));
+            // current iterate at the initial states, for the message
+            k::select_final(s, a, xe0, xe1, ipar, 2);
+            k::gather_init(s, n, c->d_init_idx.as<int64_t>(), xe0, c->d_init_val.as<double>());
+            std::vector<double> now((size_t)2 * n);
+            MORAP_HIP(hipMemcpyAsync(now.data(), c->d_init_val.p, now.size() * 8, hipMemcpyDeviceToHost, s));
+            MORAP_HIP(hipStreamSynchronize(s));
             std::string who;
             int shown = 0;
             for (int q = 0; q < 2 * n && shown < 8; ++q)
                 if (still[q]) {
-                    who += " (k=" + std::to_string(q / 2 / nJ) + ", j=" + std::to_string(q / 2 % nJ) +
-                           (q % 2 ? ", probability)" : ", cost)");
+                    const int inst = q / 2;
+                    char buf[256];
+                    std::snprintf(buf, sizeof buf,
+                                  " (k=%d, j=%d, %s: model %d, weights %.17g, %.17g, value at the initial state "
+                                  "now %.6g / %.6g)",
+                                  inst / nJ, inst % nJ, q % 2 ? "probability" : "cost", c->inst_m[inst],
+                                  iwc[inst], iwp[inst], now[2 * inst], now[2 * inst + 1]);
+                    who += buf;
                     ++shown;
                 }
             c->eK = K;

@@ -60,11 +60,20 @@ def target_weight(t: np.ndarray, res: dict, M=None) -> np.ndarray:
 
 
 def generate(ctx, wl, T: np.ndarray, phi: np.ndarray, opts, eps: float = 0.01, max_iter: int = 64,
-             batch: int = 64):
-    """Plain-loop queries for every row of T; returns (X, Wt, results)."""
+             batch: int = 64, errors: list | None = None):
+    """Plain-loop queries for every row of T; returns (X, Wt, results).  A
+    batch the library rejects is skipped; its message goes to ``errors`` when
+    a list is given, otherwise the error is raised."""
+    from paper_2305_04397_amd.morap import MorapError
     X, Wt, results = [], [], []
     for b in range(0, T.shape[0], batch):
-        res = ctx.query_batch(T[b:b + batch], eps=eps, max_iter=max_iter, opts=opts, trace=True)
+        try:
+            res = ctx.query_batch(T[b:b + batch], eps=eps, max_iter=max_iter, opts=opts, trace=True)
+        except MorapError as e:
+            if errors is None:
+                raise
+            errors.append(str(e))
+            continue
         for t, q in zip(T[b:b + batch], res):
             X.append(np.concatenate([t, phi]))
             Wt.append(target_weight(t, q))

@@ -74,6 +74,16 @@ def _oracle_c(prods, nI, nJ, W, eps):
     return c, sw, vals
 
 
+def _oracle_policy(p, wi, wj, eps):
+    """The oracle's policy of one model: value iteration on the two weights
+    scaled to sum 1, then the tie rule."""
+    sc = wi + wj
+    if sc > 0:
+        wi, wj = wi / sc, wj / sc
+    x, _ = vi.value_iteration(p, np.array([wi]), np.array([wj]), eps)
+    return vi.extract_policy(p, x[:, 0], wi, wj)
+
+
 @pytest.mark.parametrize("K", [1, 3, 16, 70])
 def test_solve_f64_matches_oracle(ctx, morap, K):
     wl = make_workload(1)
@@ -210,10 +220,18 @@ def test_query_cfg1_matches_oracle(ctx, morap):
     for t in T:
         g = ctx.query(t, eps=1e-6, opts=o, trace=True)
         q = alg.query(prods, 2, 2, t, 1e-6, 1e-8)
+        # free running: the same answer
         assert g["verdict"] == q.verdict
         assert np.abs(g["t_down"] - q.t_down).max() <= 1e-6
         assert np.abs(g["t_up"] - q.t_up).max() <= 1e-6
-        assert g["iterations"] == q.iterations
+        # replay: each weight vector of the device's loop gives the oracle's point
+        for w, r in zip(g["W"], g["R"]):
+            ro = alg.support(prods, 2, 2, w, 1e-8).r
+            assert np.abs(r - ro).max() <= 1e-9 * max(1.0, np.abs(ro).max())
+        # while both loops see the same weights they take the same path
+        same = all(np.abs(a - b).max() <= 1e-9 for a, b in zip(g["W"], q.W))
+        if same:
+            assert g["iterations"] == q.iterations
 
 
 def test_f32_solve_and_support_cfg2(ctx, morap):
@@ -241,7 +259,7 @@ def test_f32_solve_and_support_cfg2(ctx, morap):
         for j in range(nJ):
             m = A[k][j] * nJ + j
             p = prods[m]
-            mu = vi.extract_policy(p, vals[m][:, k], W[k, A[k][j]], W[k, nI + j])
+            mu = _oracle_policy(p, W[k, A[k][j]], W[k, nI + j], eps)
             assert ctx.get_policy(k, j, p.n_states).tolist() == mu.tolist()
             (vc, vp), _, _ = vi.evaluate(p, mu, eps)
             ro[nI + j] = vp

@@ -638,3 +638,29 @@ def test_nnls_against_textbook_cases():
     assert np.allclose(x, [0.75, 0.0]) and r == pytest.approx(np.sqrt(0.0625 + 1 + 0.0625))
     x, r = geometry.nnls(np.eye(3), np.array([-1.0, 2.0, 3.0]))
     assert np.allclose(x, [0, 2, 3]) and r == pytest.approx(1.0)
+
+
+def test_policy_from_tiny_weights_is_the_scaled_one():
+    """With both weights of a model tiny, the unscaled value iteration meets
+    the absolute stop test after one sweep and its greedy policy need not
+    finish in reasonable time; the policy of Alg. 2 comes from the weights
+    scaled to sum 1, i.e. here the cheapest way to finish (Dijkstra on a
+    deterministic grid)."""
+    from oracle import alg
+    rng = np.random.default_rng(7)
+    free = make_grid(rng, 7, 5, 0.2)
+    cells = np.flatnonzero(free.ravel())
+    agent = make_agent(rng, free, int(cells[0]), 0.0, rng.uniform(1, 3, 5))
+    task = _task("reach", 2)
+    letters = np.zeros(agent.n_states, np.int32)
+    letters[[3, 4]] = 1
+    letters[[len(cells) - 1, len(cells) - 2]] = 2
+    prod = product.build_product(agent, task, letters)
+    x, n = vi.value_iteration(prod, np.array([1e-9]), np.array([0.0]), 1e-6)
+    assert n[0] == 1                                    # the unscaled stop test is met at once
+    mu_tiny = alg.policy_for(prod, 1e-9, 0.0, 1e-6)
+    mu_one = alg.policy_for(prod, 1.0, 0.0, 1e-6)
+    assert mu_tiny.tolist() == mu_one.tolist()
+    y, _ = vi.value_iteration(prod, 1.0, 0.0, 1e-12)
+    cost = vi.evaluate_exact(prod, mu_tiny)[prod.init, 0]
+    assert cost == pytest.approx(y[prod.init, 0], abs=1e-9)
