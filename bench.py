@@ -20,10 +20,13 @@ Extra objects on the JSON line:
   roofline      the Bellman sweep kernel: algorithmic bytes (CSR of active
                 models + one FP32 read and one write per active state-column)
                 over its summed HIP-event durations, against 8 TB/s HBM;
+                `traffic` = HBM bytes per launch from the committed rocprofv3
+                counter summary (profiles/sweep_traffic_50x100.txt), null when
+                the sweep sources changed since it was taken;
   cpu_baseline  the FP64 oracle's value iteration timed on a bounded sample of
                 models of the same workload on the host (single process);
-  ms_per_query  full Alg. 1 queries (eps 0.01) on the timed workload from the
-                plain first weight (1, 0, ..., 0);
+  ms_per_query  Alg. 1 queries (eps 0.01, at most --query-max-iter passes) on
+                the timed workload from the plain first weight (1, 0, ..., 0);
   proposer      learned vs plain first weight on the 10 x 20 family: the
                 proposer is trained on the device from plain-loop queries of
                 seeded variants, then both loops answer unseen thresholds.
@@ -47,6 +50,40 @@ METRIC = "state-action backups/s + ms per point-oriented Pareto query (learned v
 
 def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+SHAPES = [(1, 1), (1, 2), (2, 1), (1, 4), (2, 2), (4, 1), (1, 8), (2, 4), (4, 2), (1, 16), (2, 8),
+          (4, 4), (1, 32), (2, 16), (4, 8), (1, 64), (2, 32), (4, 16)]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic_50x100.txt")
+
+
+def kernel_name(variant: int, prec: str) -> str:
+    """Device symbol (as rocprofv3 prints it) of a sweep variant."""
+    t = "float" if prec == "f32" else "double"
+    cpl, lps = SHAPES[(variant - 1) % 18]
+    if variant > 18 and (cpl, lps) == (1, 64):
+        return f"void morap::k::bellman_block_wave<{t}, 4, 256>"
+    if variant > 18:
+        return f"void morap::k::bellman_block<{t}, {cpl}, {lps}, 2, 256>"
+    v2 = "HIP_vector_type<float, 2u>" if prec == "f32" else "HIP_vector_type<double, 2u>"
+    return f"void morap::k::bellman_sweep<{t}, {v2}, {cpl}, {lps}, {min(256, 64 * lps)}>"
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when it has none or the sweep sources changed since."""
+    from paper_2305_04397_amd.profile_summary import sources_hash
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    lines = open(TRAFFIC_FILE).read().splitlines()
+    src = [l.split(":", 1)[1].strip() for l in lines if l.startswith("kernel_source_sha256:")]
+    if not src or src[0] != sources_hash():
+        return None
+    for l in lines:
+        parts = l.split(",", 4)
+        if len(parts) == 5 and parts[4] == kernel:
+            return float(parts[3])
+    return None
 
 
 def thresholds(rng, front: np.ndarray, n: int, nI: int) -> np.ndarray:
@@ -159,6 +196,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--query-max-iter", type=int, default=16,
+                    help="Alg. 2 passes allowed per query in the ms-per-query measurement")
     ap.add_argument("--proposer-queries", type=int, default=256,
                     help="unseen 10x20 queries for the learned-vs-plain comparison (0 = skip)")
     ap.add_argument("--proposer-train", type=int, default=512, help="training queries per 10x20 variant")
@@ -221,16 +260,20 @@ def main():
     value = st["backups"] / wall
     # dominant kernel: the FP32 batched sweep over all (model, column) pairs
     achieved = st["bytes"] / (st["ms_sweep_kernel"] / 1e3) / 1e9 if st["ms_sweep_kernel"] > 0 else 0.0
+    kname = kernel_name(st["variant"], args.precision)
+    tb = measured_traffic(kname)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": f"bellman_sweep<{args.precision}>", "launches": st["sweep_launches"],
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if tb is None else round(tb, 0),
+                "kernel": kname, "variant": st["variant"], "launches": st["sweep_launches"],
                 "avg_launch_us": round(st["ms_sweep_kernel"] * 1e3 / max(1, st["sweep_launches"]), 2),
                 "bytes_per_launch": round(st["bytes"] / max(1, st["sweep_launches"]), 0)}
     if st["sweep_launches_refine"]:
         ach_r = st["bytes_refine"] / (st["ms_sweep_kernel_refine"] / 1e3) / 1e9
         roofline["fp64_assigned_resolve"] = {
             "achieved": round(ach_r, 1), "launches": st["sweep_launches_refine"],
-            "avg_launch_us": round(st["ms_sweep_kernel_refine"] * 1e3 / st["sweep_launches_refine"], 2)}
+            "avg_launch_us": round(st["ms_sweep_kernel_refine"] * 1e3 / st["sweep_launches_refine"], 2),
+            "kernel": kernel_name(st["variant_refine"], "f64")}
     log(f"timed: {value:.3e} backups/s, sweep kernel {achieved:.0f} GB/s "
         f"({st['sweep_launches']} launches, {st['ms_sweep_kernel']:.0f} ms); FP64 re-solve "
         f"{st['ms_sweep_kernel_refine']:.0f} ms over {st['sweep_launches_refine']} launches; VI {st['ms_vi']:.0f} ms, "
@@ -241,11 +284,12 @@ def main():
     if args.queries > 0:
         T = thresholds(rng, front, args.queries, nI)
         tq = time.perf_counter()
-        res = ctx.query_batch(T, max_iter=64, eps=0.01, opts=morap.Options(eps_vi=eps, precision=args.precision))
+        res = ctx.query_batch(T, max_iter=args.query_max_iter, eps=0.01,
+                              opts=morap.Options(eps_vi=eps, precision=args.precision))
         wq = (time.perf_counter() - tq) * 1e3
         its = np.array([q["iterations"] for q in res])
         verdicts = [q["verdict"] for q in res]
-        per_query = {"workload": wl.name, "eps": 0.01,
+        per_query = {"workload": wl.name, "eps": 0.01, "max_iter": args.query_max_iter,
                      "plain": {"queries": len(res), "wall_ms": round(wq, 1),
                                "ms_per_query": round(wq / len(res), 2),
                                "passes_mean": round(float(its.mean()), 2), "passes_max": int(its.max()),
@@ -275,7 +319,8 @@ def main():
             "roofline": roofline, "cpu_baseline": cpu, "ms_per_query": per_query,
             "proposer": learned,
             "stats": {k: st[k] for k in ("backups", "sweeps", "eval_sweeps", "polish_sweeps", "rank_rounds",
-                                         "ms_vi", "ms_eval", "variant", "bytes", "bytes_refine")}}
+                                         "ms_vi", "ms_eval", "variant", "variant_refine", "bytes",
+                                         "bytes_refine")}}
     print(json.dumps(line), flush=True)
 
 

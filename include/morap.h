@@ -175,8 +175,8 @@ typedef struct {
     double  bytes_refine;   /* the three fields above for the FP64 re-solve of the   */
     double  ms_sweep_kernel_refine; /* assigned pairs after an FP32 solve           */
     int64_t sweep_launches_refine;
-    int32_t variant;        /* sweep-kernel variant used                            */
-    int32_t reserved;
+    int32_t variant;        /* sweep-kernel variant of the last batched solve       */
+    int32_t variant_refine; /* variant of the last FP64 re-solve of assigned pairs  */
 } morap_stats;
 
 /* Alg. 2 first loop / Alg. 3 for K weight vectors W[K][d] at once: for every

@@ -38,7 +38,7 @@ void to_abi(const Stats& s, morap_stats* out) {
     out->ms_sweep_kernel_refine = s.ms_sweep_kernel_refine;
     out->sweep_launches_refine = s.sweep_launches_refine;
     out->variant = s.variant;
-    out->reserved = 0;
+    out->variant_refine = s.variant_refine;
 }
 
 }  // namespace

@@ -17,9 +17,11 @@
 //     shared by every location and every task of that agent.
 // A backup then reads the record, the (cached) agent block and 5 successor
 // value rows; the probability-reward column is the mass the action puts on
-// accepting slots.  There is no LDS staging and no barrier: each wave owns a
-// contiguous run of the active tiles (XCD-aware), walks its states `U` at a
-// time with all successor gathers of those states in flight, and lanes map to
+// accepting slots.  There is no barrier: each XCD takes a contiguous eighth
+// of the active tiles and its waves take every n-th of them, so neighbouring
+// tiles (which share successor rows) are processed at the same time and their
+// rows meet in that XCD's L2; a wave walks its tile's states `U` at a time
+// with all successor gathers of those states in flight, and lanes map to
 // columns.  With 64 lanes per state the record, the block and every branch are
 // wave-uniform (scalar loads and branches).
 #include "common.h"
@@ -36,9 +38,9 @@ constexpr int BLK = 32;   // values per agent block
 
 template <class T, int CPL, int LPS, int U, int WG>
 __global__ void __launch_bounds__(WG)
-bellman_block(const Tile* __restrict__ tiles, const int32_t* __restrict__ tile_base,
-              const int32_t* __restrict__ act_models, const int32_t* __restrict__ act_prefix,
-              const int64_t* __restrict__ counters, const int32_t* __restrict__ rec,
+bellman_block(const Tile* __restrict__ tiles,
+              const int32_t* __restrict__ act_tiles, const int64_t* __restrict__ counters,
+              const int32_t* __restrict__ rec,
               const T* __restrict__ ablk, const T* __restrict__ wc_all, const T* __restrict__ wp_all,
               const uint8_t* __restrict__ active_all, const T* __restrict__ x_in, T* __restrict__ x_out,
               unsigned long long* __restrict__ res_all, unsigned long long* __restrict__ ymax_all, int Kp,
@@ -56,23 +58,17 @@ bellman_block(const Tile* __restrict__ tiles, const int32_t* __restrict__ tile_b
     // work units: active tiles, split in `sub` parts when there are fewer
     // tiles than waves
     const int n_tiles = (int)counters[1];
-    const int n_act = (int)counters[2];
     const int n_waves = gridDim.x * NW;
     const int sub = n_tiles * 4 <= n_waves ? 4 : (n_tiles * 2 <= n_waves ? 2 : 1);
     const int n_units = n_tiles * sub;
-    int u_begin, u_end;
-    xcd_share(n_units, blockIdx.x & 7, (blockIdx.x >> 3) * NW + wave, (gridDim.x >> 3) * NW, u_begin, u_end);
-    if (u_begin >= u_end) return;
-
-    int lo = 0;
-    {
-        const int t0 = u_begin / sub;
-        int hi = n_act;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (act_prefix[mid] <= t0) lo = mid; else hi = mid;
-        }
-    }
+    // XCD x takes the units [xb, xe); its waves take every count-th unit of
+    // it, so neighbouring units (which share successor rows) are in flight
+    // together and their rows meet in the XCD's L2
+    const int count = (gridDim.x >> 3) * NW;
+    const int xb = (int)((int64_t)n_units * (blockIdx.x & 7) / 8);
+    const int xe = (int)((int64_t)n_units * ((blockIdx.x & 7) + 1) / 8);
+    const int u_begin = xb + (int)(blockIdx.x >> 3) * NW + wave;
+    if (u_begin >= xe) return;
     int cur_m = -1;
     bool on = false;
     T wc[CPL], wp[CPL];
@@ -104,10 +100,10 @@ bellman_block(const Tile* __restrict__ tiles, const int32_t* __restrict__ tile_b
         for (int c = 0; c < CPL; ++c) res[c] = ym[c] = 0.0;
     };
 
-    for (int u = u_begin; u < u_end; ++u) {
+    for (int u = u_begin; u < xe; u += count) {
         const int t = u / sub, part = u - t * sub;
-        while (act_prefix[lo + 1] <= t) ++lo;
-        const int m = act_models[lo];
+        const Tile tl = tiles[act_tiles[t]];
+        const int m = tl.model;
         if (m != cur_m) {
             if (cur_m >= 0) flush(cur_m);
             cur_m = m;
@@ -123,7 +119,6 @@ bellman_block(const Tile* __restrict__ tiles, const int32_t* __restrict__ tile_b
             on = __ballot(any) != 0;
         }
         if (!on) continue;
-        const Tile tl = tiles[tile_base[m] + (t - act_prefix[lo])];
         const int len = tl.s_end - tl.s_begin;
         const int sb = tl.s_begin + (len * part) / sub;
         const int se = tl.s_begin + (len * (part + 1)) / sub;
@@ -231,9 +226,9 @@ struct UnitDesc {
 
 template <class T, int U, int WG>
 __global__ void __launch_bounds__(WG)
-bellman_block_wave(const Tile* __restrict__ tiles, const int32_t* __restrict__ tile_base,
-                   const int32_t* __restrict__ act_models, const int32_t* __restrict__ act_prefix,
-                   const int64_t* __restrict__ counters, const int32_t* __restrict__ rec,
+bellman_block_wave(const Tile* __restrict__ tiles,
+                   const int32_t* __restrict__ act_tiles, const int64_t* __restrict__ counters,
+                   const int32_t* __restrict__ rec,
                    const T* __restrict__ ablk, const T* __restrict__ wc_all, const T* __restrict__ wp_all,
                    const uint8_t* __restrict__ active_all, const T* __restrict__ x_in, T* __restrict__ x_out,
                    unsigned long long* __restrict__ res_all, unsigned long long* __restrict__ ymax_all, int Kp,
@@ -247,37 +242,24 @@ bellman_block_wave(const Tile* __restrict__ tiles, const int32_t* __restrict__ t
     const unsigned kc = blockIdx.y * 64u + (unsigned)lane;
 
     const int n_tiles = (int)counters[1];
-    const int n_act = (int)counters[2];
     const int n_waves = gridDim.x * NW;
     const int sub = n_tiles * 4 <= n_waves ? 4 : (n_tiles * 2 <= n_waves ? 2 : 1);
     const int n_units = n_tiles * sub;
-    int u_begin, u_end;
-    xcd_share(n_units, blockIdx.x & 7, (blockIdx.x >> 3) * NW + wave, (gridDim.x >> 3) * NW, u_begin, u_end);
-    if (u_begin >= u_end) return;
+    // XCD x takes the units [xb, xe); its waves take every count-th unit of
+    // it, so neighbouring units (which share successor rows) are in flight
+    // together and their rows meet in the XCD's L2
+    const int count = (gridDim.x >> 3) * NW;
+    const int xb = (int)((int64_t)n_units * (blockIdx.x & 7) / 8);
+    const int xe = (int)((int64_t)n_units * ((blockIdx.x & 7) + 1) / 8);
+    const int u_begin = xb + (int)(blockIdx.x >> 3) * NW + wave;
+    if (u_begin >= xe) return;
 
-    // unit -> (model, state range); the active-model cursor only moves forward
-    int lo = 0;
-    {
-        const int t0 = u_begin / sub;
-        int hi = n_act;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (act_prefix[mid] <= t0) lo = mid; else hi = mid;
-        }
-    }
-    int bound = -1, dm = -1, tb = 0, ap = 0;
+    // unit -> (model, state range)
     auto describe = [&](int u) {
         const int t = u / sub, part = u - t * sub;
-        if (t >= bound) {
-            while (act_prefix[lo + 1] <= t) ++lo;
-            dm = act_models[lo];
-            tb = tile_base[dm];
-            ap = act_prefix[lo];
-            bound = act_prefix[lo + 1];
-        }
-        const Tile tl = tiles[tb + (t - ap)];
+        const Tile tl = tiles[act_tiles[t]];
         const int len = tl.s_end - tl.s_begin;
-        return UnitDesc{dm, tl.s_begin + (len * part) / sub, tl.s_begin + (len * (part + 1)) / sub};
+        return UnitDesc{tl.model, tl.s_begin + (len * part) / sub, tl.s_begin + (len * (part + 1)) / sub};
     };
     auto stage = [&](const UnitDesc& d, int4& r0, int4& r1) {
         if (lane < d.se - d.sb) {
@@ -301,14 +283,14 @@ bellman_block_wave(const Tile* __restrict__ tiles, const int32_t* __restrict__ t
     UnitDesc nd = describe(u_begin);
     int4 n0 = make_int4(0, 0, 0, 0), n1 = make_int4(0, 0, 0, 0);
     stage(nd, n0, n1);
-    for (int u = u_begin; u < u_end; ++u) {
+    for (int u = u_begin; u < xe; u += count) {
         const UnitDesc d = nd;
         // publish this unit's records to the wave's LDS slots (same-wave
         // LDS accesses are ordered: no barrier), then fetch the next unit's
         l_rec[wave][lane][0] = n0;
         l_rec[wave][lane][1] = n1;
-        if (u + 1 < u_end) {
-            nd = describe(u + 1);
+        if (u + count < xe) {
+            nd = describe(u + count);
             stage(nd, n0, n1);
         }
         if (d.m != cur_m) {
@@ -399,7 +381,7 @@ template <class T, int U>
 static void launch_block_wave(hipStream_t s, int grid, int ktiles, const SweepArgs& a) {
     constexpr int WG = 256;
     hipLaunchKernelGGL((bellman_block_wave<T, U, WG>), dim3(grid, ktiles), dim3(WG), 0, s, a.tiles,
-                       a.tile_base, a.act_models, a.act_prefix, a.counters, a.rec, (const T*)a.ablk,
+                       a.act_tiles, a.counters, a.rec, (const T*)a.ablk,
                        (const T*)a.wc, (const T*)a.wp, a.active, (const T*)a.x_in, (T*)a.x_out, a.res, a.ymax,
                        a.Kp, a.zero_row);
 }
@@ -408,7 +390,7 @@ template <class T, int CPL, int LPS, int U>
 static void launch_block(hipStream_t s, int grid, int ktiles, const SweepArgs& a) {
     constexpr int WG = 256;
     hipLaunchKernelGGL((bellman_block<T, CPL, LPS, U, WG>), dim3(grid, ktiles), dim3(WG), 0, s, a.tiles,
-                       a.tile_base, a.act_models, a.act_prefix, a.counters, a.rec, (const T*)a.ablk,
+                       a.act_tiles, a.counters, a.rec, (const T*)a.ablk,
                        (const T*)a.wc, (const T*)a.wp, a.active, (const T*)a.x_in, (T*)a.x_out, a.res, a.ymax,
                        a.Kp, a.zero_row);
 }

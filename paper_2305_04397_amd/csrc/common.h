@@ -135,7 +135,7 @@ struct Stats {
     int64_t sweep_launches = 0;
     double bytes_refine = 0, ms_sweep_kernel_refine = 0;
     int64_t sweep_launches_refine = 0;
-    int variant = 0;
+    int variant = 0, variant_refine = 0;
 };
 
 // Values of one batched value iteration: two Jacobi buffers [S][Kp], the
@@ -192,6 +192,7 @@ struct morap_ctx {
     morap::DevBuf d_pair_sweeps;                    // [M][Kp] int32
     morap::DevBuf d_model_active;                   // [M] uint8
     morap::DevBuf d_act_models, d_act_prefix;       // compacted active model list
+    morap::DevBuf d_act_tiles;                      // the active models' tiles, in order
     morap::DevBuf d_counters;                       // int64 [8] (see the convergence kernel)
     morap::PinnedBuf h_counters;
     morap::PinnedBuf h_log;                         // per-launch tile counts (sweep log)
@@ -317,6 +318,7 @@ struct SweepArgs {
     const int32_t* rec;     // neighbourhood-block records [8S]
     const void* ablk;       // agent blocks [32 * agent states] (precision of the sweep)
     int32_t zero_row;       // S: the value row that always holds 0
+    const int32_t* act_tiles;  // global index of every active tile, in order
 };
 // batched Bellman sweep: variant v, precision prec (MORAP_F32/F64)
 void sweep(hipStream_t s, int prec, const Variant& v, int grid, int ktiles, const SweepArgs& a);
@@ -348,6 +350,7 @@ struct ConvergeArgs {
     const int32_t* rows_per_model;   // [M] rows (backups per active column)
     const int32_t* states_per_model; // [M] states (value traffic per active column)
     const int64_t* csr_bytes;        // [M] CSR bytes read per sweep of an active model
+    int32_t* act_tiles;              // [tiles] global index of every active tile, in order
 };
 void converge(hipStream_t s, const ConvergeArgs& a);
 void compact(hipStream_t s, const ConvergeArgs& a);

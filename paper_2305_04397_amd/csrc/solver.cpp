@@ -87,6 +87,7 @@ static void ensure_scratch(morap_ctx* c, int Kp) {
     c->d_model_active.ensure(M);
     c->d_act_models.ensure((size_t)M * 4 + 4);
     c->d_act_prefix.ensure((size_t)(M + 1) * 4 + 4);
+    c->d_act_tiles.ensure(c->tiles.size() * 4 + 4);
     c->d_counters.ensure(8 * 8);
     c->h_counters.ensure(8 * 8);
 }
@@ -132,6 +133,7 @@ static k::ConvergeArgs converge_args(morap_ctx* c, ValueSet& vs, const uint8_t* 
     a.rows_per_model = c->d_rows_per_model.as<int32_t>();
     a.states_per_model = c->d_states_per_model.as<int32_t>();
     a.csr_bytes = vs.prec == MORAP_F32 ? c->d_csr_bytes32.as<int64_t>() : c->d_csr_bytes64.as<int64_t>();
+    a.act_tiles = c->d_act_tiles.as<int32_t>();
     return a;
 }
 
@@ -159,6 +161,7 @@ static k::SweepArgs sweep_args(morap_ctx* c, ValueSet& vs, int in_par) {
     a.rec = c->has_blocks ? c->d_blk_rec.as<int32_t>() : nullptr;
     a.ablk = c->has_blocks ? (f32 ? c->d_blk32.p : c->d_blk64.p) : nullptr;
     a.zero_row = (int32_t)c->S;
+    a.act_tiles = c->d_act_tiles.as<int32_t>();
     return a;
 }
 
@@ -392,7 +395,8 @@ static void run_vi(morap_ctx* c, int g, ValueSet& vs, const uint8_t* mask, const
     else st.bytes += (double)h[6] + 2.0 * el * (double)h[7];
     st.max_pair_sweeps = std::max<int64_t>(st.max_pair_sweeps, *std::max_element(ps.begin(), ps.end()));
     st.ms_vi += ms;
-    st.variant = v.id;
+    if (mask) st.variant_refine = v.id;
+    else st.variant = v.id;
     if (mask) st.polish_sweeps += h[5];
     else st.sweeps += h[5];
     vs.valid = true;
@@ -418,6 +422,7 @@ static void add_stats(Stats& a, const Stats& b) {
     a.ms_sweep_kernel_refine += b.ms_sweep_kernel_refine;
     a.sweep_launches_refine += b.sweep_launches_refine;
     a.variant = b.variant ? b.variant : a.variant;
+    a.variant_refine = b.variant_refine ? b.variant_refine : a.variant_refine;
 }
 
 static void solve_impl(morap_ctx* c, const double* W, int K, const morap_vi_opts& o, double* c_out, Stats& st);

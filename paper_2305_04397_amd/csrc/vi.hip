@@ -454,8 +454,21 @@ __global__ void __launch_bounds__(1024) compact_kernel(ConvergeArgs a) {
     }
 }
 
+// The active models' tiles as one ordered list (one workgroup per active
+// model), so a sweep finds the tile of any position with one load.
+__global__ void __launch_bounds__(64) expand_kernel(ConvergeArgs a) {
+    const int b = blockIdx.x;
+    if (b >= (int)a.counters[2]) return;
+    const int m = a.act_models[b];
+    const int base = a.act_prefix[b];
+    const int t0 = a.tile_base[m], nt = a.tile_base[m + 1] - t0;
+    for (int i = threadIdx.x; i < nt; i += 64) a.act_tiles[base + i] = t0 + i;
+}
+
 void compact(hipStream_t s, const ConvergeArgs& a) {
     hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(1024), 0, s, a);
+    MORAP_HIP(hipGetLastError());
+    if (a.M > 0) hipLaunchKernelGGL(expand_kernel, dim3(a.M), dim3(64), 0, s, a);
     MORAP_HIP(hipGetLastError());
 }
 
@@ -485,8 +498,7 @@ void init_solve(hipStream_t s, const ConvergeArgs& a) {
     fill_u8(s, a.model_active, 0, a.M);
     hipLaunchKernelGGL(init_solve_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
     MORAP_HIP(hipGetLastError());
-    hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(1024), 0, s, a);
-    MORAP_HIP(hipGetLastError());
+    compact(s, a);
 }
 
 // ---------------------------------------------------------------------------

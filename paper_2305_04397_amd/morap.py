@@ -75,7 +75,7 @@ class Stats(C.Structure):
                 ("ms_eval", C.c_double), ("ms_total", C.c_double), ("ms_sweep_kernel", C.c_double),
                 ("sweep_launches", C.c_int64), ("bytes_refine", C.c_double),
                 ("ms_sweep_kernel_refine", C.c_double), ("sweep_launches_refine", C.c_int64),
-                ("variant", C.c_int32), ("reserved", C.c_int32)]
+                ("variant", C.c_int32), ("variant_refine", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
