@@ -59,6 +59,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic_50x100.txt")
 
 def kernel_name(variant: int, prec: str) -> str:
     """Device symbol (as rocprofv3 prints it) of a sweep variant."""
+    if variant < 0:
+        return "morap::k::inst_vi_kernel"
     t = "float" if prec == "f32" else "double"
     cpl, lps = SHAPES[(variant - 1) % 18]
     if variant > 18 and (cpl, lps) == (1, 64):

@@ -166,7 +166,7 @@ typedef struct {
     int64_t max_pair_sweeps;/* largest sweep count of one (model, column) pair     */
     int64_t eval_sweeps;    /* sweeps of the policy evaluation                      */
     int64_t polish_sweeps;  /* FP64 sweeps after an FP32 solve (evaluate)          */
-    int64_t rank_rounds;    /* attractor ranking rounds (policy extraction)         */
+    int64_t rank_rounds;    /* attractor-rank relaxation sweeps (policy extraction)  */
     int64_t excluded;       /* reserved                                             */
     double  bytes;          /* algorithmic bytes moved by the sweep kernel          */
     double  ms_vi, ms_eval, ms_total;   /* device / host wall time of the phases   */

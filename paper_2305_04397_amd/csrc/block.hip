@@ -377,6 +377,75 @@ bellman_block_wave(const Tile* __restrict__ tiles,
     if (cur_m >= 0) flush(cur_m);
 }
 
+// Value iteration of (column, model) instances over the neighbourhood
+// blocks, FP64, one thread per instance state (instance-major values, one
+// column each), with the summation order of the batched block sweep.  Used to
+// re-solve only the assigned pairs: each instance's weights, its own
+// residual (max over its states, one atomic per tile).
+__global__ void __launch_bounds__(256) inst_vi_kernel(InstArgs a, const int32_t* __restrict__ rec,
+                                                      const double* __restrict__ ablk, const double* wc,
+                                                      const double* wp, const uint8_t* active,
+                                                      const double* __restrict__ x_in, double* __restrict__ x_out,
+                                                      unsigned long long* res, int32_t zero_row) {
+    const int t = blockIdx.x;
+    if (t >= a.n_tiles) return;
+    const int inst = a.inst_tiles[2 * t];
+    double r = 0.0;
+    if (active[inst]) {
+        const int ls = a.inst_tiles[2 * t + 1] + threadIdx.x;
+        const int m = a.inst_model[inst];
+        const int sb = a.state_base[m];
+        if (ls < a.state_base[m + 1] - sb) {
+            const int64_t ib = a.inst_base[inst];
+            const int gs = sb + ls;
+            const int4 r0 = *reinterpret_cast<const int4*>(rec + (int64_t)gs * 8);
+            const int4 r1 = *reinterpret_cast<const int4*>(rec + (int64_t)gs * 8 + 4);
+            const int sc[NSLOT] = {r0.x, r0.y, r0.z, r0.w, r1.x};
+            double xv[NSLOT];
+#pragma unroll
+            for (int d = 0; d < NSLOT; ++d) xv[d] = sc[d] == zero_row ? 0.0 : x_in[ib + (sc[d] - sb)];
+            const double* B = ablk + (int64_t)r1.y * BLK;
+            const int accm = r1.z & 31;
+            const double w0 = wc[inst], w1 = wp[inst];
+            double best = -INFINITY;
+#pragma unroll
+            for (int act = 0; act < 5; ++act) {
+                double rp = 0;
+                if (accm) {
+#pragma unroll
+                    for (int d = 0; d < NSLOT; ++d)
+                        if ((accm >> d) & 1) rp += B[act * NSLOT + d];
+                }
+                double acc = w0 * B[25 + act];
+                if (accm) acc = fma(w1, rp, acc);
+#pragma unroll
+                for (int d = 0; d < NSLOT; ++d) acc = fma(B[act * NSLOT + d], xv[d], acc);
+                best = fmax(best, acc);
+            }
+            const double old = x_in[ib + ls];
+            x_out[ib + ls] = best;
+            r = fabs(best - old);
+        }
+    }
+    r = wave_max(r);
+    __shared__ double l_r[4];
+    if ((threadIdx.x & 63) == 0) l_r[threadIdx.x >> 6] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double m4 = fmax(fmax(l_r[0], l_r[1]), fmax(l_r[2], l_r[3]));
+        if (m4 > 0.0) atomicMax(&res[inst], (unsigned long long)__double_as_longlong(m4));
+    }
+}
+
+void inst_vi_sweep(hipStream_t s, const InstArgs& a, const int32_t* rec, const double* ablk, const double* wc,
+                   const double* wp, const uint8_t* active, const double* x_in, double* x_out,
+                   unsigned long long* res, int32_t zero_row) {
+    if (a.n_tiles <= 0) return;
+    hipLaunchKernelGGL(inst_vi_kernel, dim3(a.n_tiles), dim3(256), 0, s, a, rec, ablk, wc, wp, active, x_in, x_out,
+                       res, zero_row);
+    MORAP_HIP(hipGetLastError());
+}
+
 template <class T, int U>
 static void launch_block_wave(hipStream_t s, int grid, int ktiles, const SweepArgs& a) {
     constexpr int WG = 256;

@@ -215,6 +215,9 @@ struct morap_ctx {
     morap::DevBuf d_xe[2];                          // evaluation values [inst states][2]
     morap::DevBuf d_iwc, d_iwp;                     // per instance FP64 weights
     morap::DevBuf d_init_idx, d_init_val;           // instance initial states, their values
+    morap::DevBuf d_xr;                             // second buffer of the instance value iteration
+    std::vector<int32_t> h_live_tiles;              // instance tiles still active
+    morap::DevBuf d_live_tiles;
     std::vector<int8_t> h_mu;                       // policies of the last evaluate
 
     // autotuner cache: key (prec, Kp) -> variant id
@@ -379,11 +382,15 @@ void inst_converge(hipStream_t s, int n, unsigned long long* res, uint8_t* activ
                    double eps, int64_t* counter);
 void opt_mask(hipStream_t s, const InstArgs& a, const double* wc, const double* wp, const double* x,
               double tau, uint32_t* mask, int32_t* rank, int8_t* mu, bool only_unranked);
-void rank_round(hipStream_t s, const InstArgs& a, const uint32_t* mask, int32_t* rank, int8_t* mu,
-                int level, int64_t* counter);
 void eval_sweep(hipStream_t s, const InstArgs& a, const int8_t* mu, const uint8_t* active,
                 const double* x_in, double* x_out, unsigned long long* res);
 void count_unranked(hipStream_t s, const InstArgs& a, const int32_t* rank, int64_t* counter);
+// attractor ranks as BFS distances (in-place relaxation sweep) and the action
+// choice once they are final
+void relax_ranks(hipStream_t s, const InstArgs& a, const uint32_t* mask, int32_t* rank, int base, bool reverse,
+                 int local, int64_t* changed);
+void choose_actions(hipStream_t s, const InstArgs& a, const uint32_t* mask, const int32_t* rank, int8_t* mu,
+                    int base, int64_t* max_rank);
 // per-instance flags: `width` entries per instance, active when the instance
 // has a live initial state
 void set_active(hipStream_t s, int n, const InstArgs& a, uint8_t* active, unsigned long long* res,
@@ -393,6 +400,11 @@ void select_final(hipStream_t s, const InstArgs& a, double* x0, const double* x1
                   int width);
 // pair mask of a restricted solve: mask[m][k] = 1 for the instances' pairs
 void mark_pairs(hipStream_t s, const InstArgs& a, int Kp, uint8_t* mask);
+// one FP64 value-iteration sweep of instances over the neighbourhood blocks
+// (block.hip); residuals per instance
+void inst_vi_sweep(hipStream_t s, const InstArgs& a, const int32_t* rec, const double* ablk, const double* wc,
+                   const double* wp, const uint8_t* active, const double* x_in, double* x_out,
+                   unsigned long long* res, int32_t zero_row);
 // out[2q + o] = x[2 idx[q] + o] (0 when idx[q] < 0)
 void gather_init(hipStream_t s, int n, const int64_t* idx, const double* x, double* out);
 }  // namespace k

@@ -606,13 +606,102 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
     uint8_t* ipar = c->d_ipar.as<uint8_t>();
     const int chunk = std::max(2, (o.check_every + 1) / 2 * 2);
 
+    // Tiles of the instances that still have an active entry (width entries
+    // per instance): the sweeps between two host checks launch only these.
+    auto live_tiles = [&](const uint8_t* dflags, int width, k::InstArgs& out) {
+        std::vector<uint8_t> f((size_t)width * n);
+        MORAP_HIP(hipMemcpy(f.data(), dflags, f.size(), hipMemcpyDeviceToHost));
+        c->h_live_tiles.clear();
+        int64_t states = 0;
+        for (size_t t = 0; t < tiles.size() / 2; ++t) {
+            const int inst = tiles[2 * t];
+            bool on = false;
+            for (int w = 0; w < width; ++w) on |= f[(size_t)inst * width + w] != 0;
+            if (!on) continue;
+            c->h_live_tiles.push_back(tiles[2 * t]);
+            c->h_live_tiles.push_back(tiles[2 * t + 1]);
+            const int m = c->inst_m[inst];
+            states += std::min<int64_t>(256, c->hm.state_base[m + 1] - c->hm.state_base[m] - tiles[2 * t + 1]);
+        }
+        c->d_live_tiles.ensure(c->h_live_tiles.size() * 4 + 8);
+        if (!c->h_live_tiles.empty())
+            MORAP_HIP(hipMemcpy(c->d_live_tiles.p, c->h_live_tiles.data(), c->h_live_tiles.size() * 4,
+                                hipMemcpyHostToDevice));
+        out = a;
+        out.inst_tiles = c->d_live_tiles.as<int32_t>();
+        out.n_tiles = (int)(c->h_live_tiles.size() / 2);
+        return states;
+    };
+
     // Values for the policies: FP64 value iteration from 0 on exactly the
     // assigned pairs, with each model's two weights scaled to sum 1.  Scaling
     // leaves the optimal policies unchanged; it keeps the absolute stop test
     // and the tie tolerance meaningful when both weights are tiny (the
     // unscaled iteration then stops after a sweep or two and its greedy
-    // policy can take ~1e6 steps to finish).
-    {
+    // policy can take ~1e6 steps to finish).  With the neighbourhood-block
+    // form the instances iterate in their own (instance-major) values;
+    // otherwise the batched sweep re-solves the marked pairs.
+    double* xi = c->d_xi.as<double>();
+    if (c->has_blocks) {
+        c->d_xr.ensure((size_t)NS * 8 + 8);
+        double* x0 = xi;
+        double* x1 = c->d_xr.as<double>();
+        k::fill_f64(s, x0, 0.0, NS);
+        k::fill_f64(s, x1, 0.0, NS);
+        k::set_active(s, n, a, iact, ires, ipar, 1);
+        hipEvent_t v0, v1;
+        MORAP_HIP(hipEventCreate(&v0));
+        MORAP_HIP(hipEventCreate(&v1));
+        MORAP_HIP(hipEventRecord(v0, s));
+        k::InstArgs av = a;
+        int64_t live_states = NS;
+        int64_t vsweeps = 0;
+        EventPairs ev;
+        while (true) {
+            for (int i = 0; i < chunk; ++i) {
+                const bool even = (i & 1) == 0;
+                if (o.time_kernels) {
+                    ev.emplace_back();
+                    MORAP_HIP(hipEventCreate(&ev.back().first));
+                    MORAP_HIP(hipEventCreate(&ev.back().second));
+                    MORAP_HIP(hipEventRecord(ev.back().first, s));
+                }
+                k::inst_vi_sweep(s, av, c->d_blk_rec.as<int32_t>(), c->d_blk64.as<double>(), c->d_iwc.as<double>(),
+                                 c->d_iwp.as<double>(), iact, even ? x0 : x1, even ? x1 : x0, ires, (int32_t)c->S);
+                if (o.time_kernels) MORAP_HIP(hipEventRecord(ev.back().second, s));
+                k::fill_i64(s, dctr, 0, 1);
+                k::inst_converge(s, n, ires, iact, ipar, even ? 1 : 0, o.eps_vi, dctr);
+            }
+            vsweeps += chunk;
+            // record + own value read + write per live instance state
+            st.bytes_refine += (double)chunk * (double)live_states * 48.0;
+            read_counters(c);
+            for (auto& e : ev) {
+                float t = 0;
+                MORAP_HIP(hipEventElapsedTime(&t, e.first, e.second));
+                st.ms_sweep_kernel_refine += t;
+                st.sweep_launches_refine += 1;
+                (void)hipEventDestroy(e.first);
+                (void)hipEventDestroy(e.second);
+            }
+            ev.clear();
+            if (h[0] == 0) break;
+            MORAP_CHECK(vsweeps < o.max_sweeps, MORAP_E_NOT_CONVERGED,
+                        "value iteration of the assigned pairs: " + std::to_string(h[0]) +
+                            " instances still active after " + std::to_string(vsweeps) + " sweeps");
+            live_states = live_tiles(iact, 1, av);
+        }
+        k::select_final(s, a, x0, x1, ipar, 1);
+        MORAP_HIP(hipEventRecord(v1, s));
+        MORAP_HIP(hipEventSynchronize(v1));
+        float vms = 0;
+        MORAP_HIP(hipEventElapsedTime(&vms, v0, v1));
+        (void)hipEventDestroy(v0);
+        (void)hipEventDestroy(v1);
+        st.ms_vi += vms;
+        st.polish_sweeps += vsweeps;
+        st.variant_refine = -1;   // instance-major block iteration
+    } else {
         const int M = c->hm.M, Kp = c->Kp;
         std::vector<double> wc((size_t)M * Kp, 0.0), wp((size_t)M * Kp, 0.0);
         for (int kk = 0; kk < K; ++kk)
@@ -630,15 +719,14 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
         MORAP_HIP(hipMemcpyAsync(c->d_wc64.p, wc.data(), wc.size() * 8, hipMemcpyHostToDevice, s));
         MORAP_HIP(hipMemcpyAsync(c->d_wp64.p, wp.data(), wp.size() * 8, hipMemcpyHostToDevice, s));
         MORAP_HIP(hipStreamSynchronize(s));   // the host vectors go out of scope
-    }
-    ensure_values(c, c->vref, K, c->Kp, MORAP_F64);
-    {
+        ensure_values(c, c->vref, K, c->Kp, MORAP_F64);
         uint8_t* pm = c->d_pair_mask.as<uint8_t>();
         k::fill_u8(s, pm, 0, (int64_t)c->hm.M * c->Kp);
         k::mark_pairs(s, a, c->Kp, pm);
         run_vi(c, 1, c->vref, pm, o, st);
+        k::gather_columns(s, a, MORAP_F64, c->vref.x[0].p, c->vref.x[1].p, c->vref.final_par.as<uint8_t>(),
+                          c->vref.Kp, xi);
     }
-    ValueSet* src = &c->vref;
 
     hipEvent_t e0, e1;
     MORAP_HIP(hipEventCreate(&e0));
@@ -648,8 +736,6 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
         (void)hipEventDestroy(e1);
     };
     MORAP_HIP(hipEventRecord(e0, s));
-    double* xi = c->d_xi.as<double>();
-    k::gather_columns(s, a, MORAP_F64, src->x[0].p, src->x[1].p, src->final_par.as<uint8_t>(), src->Kp, xi);
 
     // Attractor rounds with the tolerance tau; states left unranked get the
     // tolerance widened tenfold (up to tau * 1e6) while ranked states keep
@@ -658,15 +744,23 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
     int32_t* rank = c->d_rank.as<int32_t>();
     int8_t* mu = c->d_mu.as<int8_t>();
     k::opt_mask(s, a, c->d_iwc.as<double>(), c->d_iwp.as<double>(), xi, o.tau, mask, rank, mu, false);
-    int level = 0;
+    int base = 0, relax_sweeps = 0;
     double tau = o.tau;
     for (int widen = 0;; ++widen) {
-        while (true) {
-            k::fill_i64(s, dctr, 0, 1);
-            for (int i = 0; i < chunk; ++i) k::rank_round(s, a, mask, rank, mu, ++level, dctr);
+        // ranks of this phase: relax to the fixed point (8 sweeps per check,
+        // alternating direction; converged when the last sweep changed nothing)
+        for (int round = 0;; ++round) {
+            k::fill_i64(s, dctr, 0, 8);
+            for (int i = 0; i < 8; ++i) k::relax_ranks(s, a, mask, rank, base, (i & 1) != 0, 16, dctr + i);
+            relax_sweeps += 8;
             read_counters(c);
-            if (h[0] == 0) break;
+            if (h[7] == 0) break;
+            MORAP_CHECK(round < 1000000, MORAP_E_IMPROPER, "attractor ranks did not settle");
         }
+        k::fill_i64(s, dctr, 0, 1);
+        k::choose_actions(s, a, mask, rank, mu, base, dctr);
+        read_counters(c);
+        base = std::max<int64_t>(base, h[0]);
         k::fill_i64(s, dctr, 0, 1);
         k::count_unranked(s, a, rank, dctr);
         read_counters(c);
@@ -674,7 +768,7 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
         tau *= 10.0;
         k::opt_mask(s, a, c->d_iwc.as<double>(), c->d_iwp.as<double>(), xi, tau, mask, rank, mu, true);
     }
-    st.rank_rounds += level;
+    st.rank_rounds += relax_sweeps;
     if (h[0] != 0) {
         cleanup();
         fail(MORAP_E_IMPROPER, std::to_string(h[0]) + " states cannot reach done through tau-optimal actions");
@@ -687,17 +781,22 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
     k::fill_f64(s, xe1, 0.0, 2 * NS);
     k::set_active(s, n, a, iact, ires, ipar, 2);
     int64_t esweeps = 0;
+    k::InstArgs ae = a;
     while (true) {
         for (int i = 0; i < chunk; ++i) {
             const bool even = (i & 1) == 0;
-            k::eval_sweep(s, a, mu, iact, even ? xe0 : xe1, even ? xe1 : xe0, ires);
+            k::eval_sweep(s, ae, mu, iact, even ? xe0 : xe1, even ? xe1 : xe0, ires);
             k::fill_i64(s, dctr, 0, 1);
             k::inst_converge(s, 2 * n, ires, iact, ipar, even ? 1 : 0, o.eps_eval, dctr);
         }
         esweeps += chunk;
         read_counters(c);
         if (h[0] == 0) break;
-        if (esweeps >= o.max_sweeps) {
+        if (esweeps < o.max_sweeps) {
+            live_tiles(iact, 2, ae);
+            continue;
+        }
+        {
             // name the (column, task, objective) entries still running; the
             // policies stay readable through morap_get_policy
             std::vector<uint8_t> still((size_t)2 * n);

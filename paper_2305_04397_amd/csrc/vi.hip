@@ -16,7 +16,8 @@
 //  * converge / compact: freeze pairs whose residual is within tolerance
 //    (the stop test of Alg. 3), record their value at the initial state and
 //    rebuild the active tile list.
-//  * instance kernels: eps-optimal action masks, attractor ranking rounds and
+//  * instance kernels: eps-optimal action masks, attractor ranks (BFS
+//    distances by in-place relaxation) with the action choice, and
 //    fixed-policy evaluation sweeps (Alg. 4) on (column, model) instances, one
 //    thread per state.
 #include "common.h"
@@ -617,15 +618,90 @@ void opt_mask(hipStream_t s, const InstArgs& a, const double* wc, const double* 
     MORAP_HIP(hipGetLastError());
 }
 
-// Attractor round `level`: an unranked state is ranked when one of its
-// eps-optimal rows moves mass into done or into a state ranked in an earlier
-// round; its action is the row moving the most probability there (masses
-// within 1e-12 are equal; then the lowest row wins).
-__global__ void __launch_bounds__(256) rank_kernel(InstArgs a, const uint32_t* mask, int32_t* rank,
-                                                   int8_t* mu, int level, int64_t* counter) {
+// Instance state of thread threadIdx.x in tile t (as inst_locate).
+__device__ __forceinline__ bool inst_locate_tile(const InstArgs& a, int t, InstLoc& L) {
+    L.inst = a.inst_tiles[2 * t];
+    L.ls = a.inst_tiles[2 * t + 1] + threadIdx.x;
+    L.m = a.inst_model[L.inst];
+    L.sb = a.state_base[L.m];
+    L.S = a.state_base[L.m + 1] - L.sb;
+    if (L.ls >= L.S) return false;
+    L.is = a.inst_base[L.inst] + L.ls;
+    L.gs = L.sb + L.ls;
+    return true;
+}
+
+// Attractor ranks as BFS distances.  The rank of a state is its distance to
+// done in the graph whose edges are the successors of its tau-optimal rows
+// (done at 0), which is the round in which the level-synchronous attractor
+// ranks it.  States ranked in an earlier phase (rank <= base) are sources
+// at distance base.  The relaxation runs in place: a tile's states are
+// relaxed up to `local` times per launch (neighbours inside the tile
+// propagate within one launch) and read other tiles' current ranks; ranks
+// only decrease, so the fixed point is the exact distance in any order.
+// rank < 0 means not (yet) ranked.
+__global__ void __launch_bounds__(256) relax_kernel(InstArgs a, const uint32_t* mask, int32_t* rank, int base,
+                                                    int reverse, int local, int64_t* changed) {
+    const int t = reverse ? a.n_tiles - 1 - (int)blockIdx.x : (int)blockIdx.x;
     InstLoc L;
-    unsigned long long got = 0;
-    if (inst_locate(a, L) && rank[L.is] < 0) {
+    const bool ok = inst_locate_tile(a, t, L);
+    const bool mine = ok && (rank[L.is] < 0 || rank[L.is] > base);
+    int64_t ib = 0;
+    int rb = 0;
+    uint32_t bits0 = 0;
+    if (mine) {
+        ib = a.inst_base[L.inst];
+        rb = a.state_row[L.gs];
+        bits0 = mask[L.is];
+    }
+    unsigned long long n_upd = 0;
+    for (int it = 0; it < local; ++it) {
+        int upd = 0;
+        if (mine) {
+            const int cur = rank[L.is];
+            int cand = 0x7FFFFFFF;
+            uint32_t bits = bits0;
+            while (bits) {
+                const int row = rb + __builtin_ctz(bits);
+                bits &= bits - 1;
+                if (a.to_done[row]) cand = min(cand, base + 1);
+                for (int e = a.row_ptr[row]; e < a.row_ptr[row + 1]; ++e) {
+                    const int32_t d = rank[ib + (a.col[e] - L.sb)];
+                    if (d >= 0) cand = min(cand, max(d, base) + 1);
+                }
+            }
+            if (cand != 0x7FFFFFFF && (cur < 0 || cand < cur)) {
+                rank[L.is] = cand;
+                upd = 1;
+            }
+        }
+        n_upd += upd;
+        if (!__syncthreads_or(upd)) break;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) n_upd += __shfl_xor(n_upd, o, 64);
+    if ((threadIdx.x & 63) == 0 && n_upd) atomicAdd((unsigned long long*)changed, n_upd);
+}
+
+void relax_ranks(hipStream_t s, const InstArgs& a, const uint32_t* mask, int32_t* rank, int base, bool reverse,
+                 int local, int64_t* changed) {
+    if (a.n_tiles <= 0) return;
+    hipLaunchKernelGGL(relax_kernel, dim3(a.n_tiles), dim3(256), 0, s, a, mask, rank, base, reverse ? 1 : 0,
+                       local, changed);
+    MORAP_HIP(hipGetLastError());
+}
+
+// The action of every state ranked above `base`: among its tau-optimal rows
+// that move mass into done or into states of lower rank, the one moving the
+// most mass there (masses within 1e-12 are equal; then the lowest row).
+// Also records the largest rank in counter[0].
+__global__ void __launch_bounds__(256) choose_kernel(InstArgs a, const uint32_t* mask, const int32_t* rank,
+                                                     int8_t* mu, int base, int64_t* max_rank) {
+    InstLoc L;
+    int top = 0;
+    if (inst_locate(a, L) && rank[L.is] > base) {
+        const int level = rank[L.is];
+        top = level;
         const int64_t ib = a.inst_base[L.inst];
         const int rb = a.state_row[L.gs];
         uint32_t bits = mask[L.is];
@@ -655,21 +731,17 @@ __global__ void __launch_bounds__(256) rank_kernel(InstArgs a, const uint32_t* m
                 best_lr = lr;
             }
         }
-        if (best_lr >= 0) {
-            rank[L.is] = level;
-            mu[L.is] = (int8_t)best_lr;
-            got = 1;
-        }
+        mu[L.is] = (int8_t)best_lr;
     }
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) got += __shfl_xor(got, o, 64);
-    if ((threadIdx.x & 63) == 0 && got) atomicAdd((unsigned long long*)counter, got);
+    for (int o = 32; o >= 1; o >>= 1) top = max(top, __shfl_xor(top, o, 64));
+    if ((threadIdx.x & 63) == 0 && top) atomicMax((unsigned long long*)max_rank, (unsigned long long)top);
 }
 
-void rank_round(hipStream_t s, const InstArgs& a, const uint32_t* mask, int32_t* rank, int8_t* mu,
-                int level, int64_t* counter) {
+void choose_actions(hipStream_t s, const InstArgs& a, const uint32_t* mask, const int32_t* rank, int8_t* mu,
+                    int base, int64_t* max_rank) {
     if (a.n_tiles <= 0) return;
-    hipLaunchKernelGGL(rank_kernel, dim3(a.n_tiles), dim3(256), 0, s, a, mask, rank, mu, level, counter);
+    hipLaunchKernelGGL(choose_kernel, dim3(a.n_tiles), dim3(256), 0, s, a, mask, rank, mu, base, max_rank);
     MORAP_HIP(hipGetLastError());
 }
 
