@@ -58,15 +58,18 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic_50x100.txt")
 
 
 def kernel_name(variant: int, prec: str) -> str:
-    """Device symbol (as rocprofv3 prints it) of a sweep variant."""
+    """Device symbol of a sweep variant as rocprofv3 prints it, up to the
+    block kernels' sparsity-pattern argument."""
     if variant < 0:
         return "morap::k::inst_vi_kernel"
     t = "float" if prec == "f32" else "double"
     cpl, lps = SHAPES[(variant - 1) % 18]
+    if variant > 36:
+        return f"void morap::k::bellman_block_wave<{t}, {2 if variant == 37 else 8}, 256"
     if variant > 18 and (cpl, lps) == (1, 64):
-        return f"void morap::k::bellman_block_wave<{t}, 4, 256>"
+        return f"void morap::k::bellman_block_wave<{t}, 4, 256"
     if variant > 18:
-        return f"void morap::k::bellman_block<{t}, {cpl}, {lps}, 2, 256>"
+        return f"void morap::k::bellman_block<{t}, {cpl}, {lps}, 2, 256"
     v2 = "HIP_vector_type<float, 2u>" if prec == "f32" else "HIP_vector_type<double, 2u>"
     return f"void morap::k::bellman_sweep<{t}, {v2}, {cpl}, {lps}, {min(256, 64 * lps)}>"
 
@@ -83,7 +86,7 @@ def measured_traffic(kernel: str):
         return None
     for l in lines:
         parts = l.split(",", 4)
-        if len(parts) == 5 and parts[4] == kernel:
+        if len(parts) == 5 and parts[4].startswith(kernel):
             return float(parts[3])
     return None
 

@@ -36,7 +36,23 @@ namespace k {
 constexpr int NSLOT = 5;
 constexpr int BLK = 32;   // values per agent block
 
-template <class T, int CPL, int LPS, int U, int WG>
+// Sparsity patterns of the blocks (bit 5a + d = entry P[a][d] may be nonzero):
+// every entry, or the grid pattern of the host's slot order (slot 0 = stay,
+// 1 + a = the cell move a aims at; the N/S moves slip E/W and vice versa).
+constexpr uint32_t PAT_DENSE = (1u << 25) - 1;
+constexpr uint32_t PAT_GRID = (1u << 0) | (1u << 1) | (1u << 3) | (1u << 4) |        // N: stay, N, E, W
+                              (1u << 5) | (1u << 7) | (1u << 8) | (1u << 9) |        // S: stay, S, E, W
+                              (1u << 10) | (1u << 11) | (1u << 12) | (1u << 13) |    // E: stay, N, S, E
+                              (1u << 15) | (1u << 16) | (1u << 17) | (1u << 19) |    // W: stay, N, S, W
+                              (1u << 20);                                            // stay
+template <uint32_t PAT>
+__device__ __forceinline__ constexpr bool nz(int a, int d) { return (PAT >> (a * NSLOT + d)) & 1u; }
+
+static uint32_t pattern_for(uint32_t union_pattern) {
+    return (union_pattern & ~PAT_GRID) == 0 ? PAT_GRID : PAT_DENSE;
+}
+
+template <class T, int CPL, int LPS, int U, int WG, uint32_t PAT>
 __global__ void __launch_bounds__(WG)
 bellman_block(const Tile* __restrict__ tiles,
               const int32_t* __restrict__ act_tiles, const int64_t* __restrict__ counters,
@@ -187,14 +203,15 @@ bellman_block(const Tile* __restrict__ tiles,
                     if (accm) {
 #pragma unroll
                         for (int d = 0; d < NSLOT; ++d)
-                            if ((accm >> d) & 1) rp += B[a * NSLOT + d];
+                            if (nz<PAT>(a, d) && ((accm >> d) & 1)) rp += B[a * NSLOT + d];
                     }
 #pragma unroll
                     for (int c = 0; c < CPL; ++c) {
                         T acc = wc[c] * B[25 + a];
                         if (accm) acc = fma(wp[c], rp, acc);
 #pragma unroll
-                        for (int d = 0; d < NSLOT; ++d) acc = fma(B[a * NSLOT + d], xv[q][d].v[c], acc);
+                        for (int d = 0; d < NSLOT; ++d)
+                            if (nz<PAT>(a, d)) acc = fma(B[a * NSLOT + d], xv[q][d].v[c], acc);
                         best[c] = fmax(best[c], acc);
                     }
                 }
@@ -224,7 +241,7 @@ struct UnitDesc {
     int m, sb, se;
 };
 
-template <class T, int U, int WG>
+template <class T, int U, int WG, uint32_t PAT>
 __global__ void __launch_bounds__(WG)
 bellman_block_wave(const Tile* __restrict__ tiles,
                    const int32_t* __restrict__ act_tiles, const int64_t* __restrict__ counters,
@@ -359,11 +376,12 @@ bellman_block_wave(const Tile* __restrict__ tiles,
                         T rp = 0;
 #pragma unroll
                         for (int dd = 0; dd < NSLOT; ++dd)
-                            if ((accm >> dd) & 1) rp += B[a * NSLOT + dd];
+                            if (nz<PAT>(a, dd) && ((accm >> dd) & 1)) rp += B[a * NSLOT + dd];
                         acc = fma(wp, rp, acc);
                     }
 #pragma unroll
-                    for (int dd = 0; dd < NSLOT; ++dd) acc = fma(B[a * NSLOT + dd], xv[q][dd], acc);
+                    for (int dd = 0; dd < NSLOT; ++dd)
+                        if (nz<PAT>(a, dd)) acc = fma(B[a * NSLOT + dd], xv[q][dd], acc);
                     best = fmax(best, acc);
                 }
                 if (act) {
@@ -382,6 +400,7 @@ bellman_block_wave(const Tile* __restrict__ tiles,
 // column each), with the summation order of the batched block sweep.  Used to
 // re-solve only the assigned pairs: each instance's weights, its own
 // residual (max over its states, one atomic per tile).
+template <uint32_t PAT>
 __global__ void __launch_bounds__(256) inst_vi_kernel(InstArgs a, const int32_t* __restrict__ rec,
                                                       const double* __restrict__ ablk, const double* wc,
                                                       const double* wp, const uint8_t* active,
@@ -414,12 +433,13 @@ __global__ void __launch_bounds__(256) inst_vi_kernel(InstArgs a, const int32_t*
                 if (accm) {
 #pragma unroll
                     for (int d = 0; d < NSLOT; ++d)
-                        if ((accm >> d) & 1) rp += B[act * NSLOT + d];
+                        if (nz<PAT>(act, d) && ((accm >> d) & 1)) rp += B[act * NSLOT + d];
                 }
                 double acc = w0 * B[25 + act];
                 if (accm) acc = fma(w1, rp, acc);
 #pragma unroll
-                for (int d = 0; d < NSLOT; ++d) acc = fma(B[act * NSLOT + d], xv[d], acc);
+                for (int d = 0; d < NSLOT; ++d)
+                    if (nz<PAT>(act, d)) acc = fma(B[act * NSLOT + d], xv[d], acc);
                 best = fmax(best, acc);
             }
             const double old = x_in[ib + ls];
@@ -439,17 +459,36 @@ __global__ void __launch_bounds__(256) inst_vi_kernel(InstArgs a, const int32_t*
 
 void inst_vi_sweep(hipStream_t s, const InstArgs& a, const int32_t* rec, const double* ablk, const double* wc,
                    const double* wp, const uint8_t* active, const double* x_in, double* x_out,
-                   unsigned long long* res, int32_t zero_row) {
+                   unsigned long long* res, int32_t zero_row, uint32_t pattern) {
     if (a.n_tiles <= 0) return;
-    hipLaunchKernelGGL(inst_vi_kernel, dim3(a.n_tiles), dim3(256), 0, s, a, rec, ablk, wc, wp, active, x_in, x_out,
-                       res, zero_row);
+    if (pattern_for(pattern) == PAT_GRID)
+        hipLaunchKernelGGL(inst_vi_kernel<PAT_GRID>, dim3(a.n_tiles), dim3(256), 0, s, a, rec, ablk, wc, wp, active,
+                           x_in, x_out, res, zero_row);
+    else
+        hipLaunchKernelGGL(inst_vi_kernel<PAT_DENSE>, dim3(a.n_tiles), dim3(256), 0, s, a, rec, ablk, wc, wp,
+                           active, x_in, x_out, res, zero_row);
     MORAP_HIP(hipGetLastError());
+}
+
+template <class T, int U, uint32_t PAT>
+static void launch_block_wave_p(hipStream_t s, int grid, int ktiles, const SweepArgs& a) {
+    constexpr int WG = 256;
+    hipLaunchKernelGGL((bellman_block_wave<T, U, WG, PAT>), dim3(grid, ktiles), dim3(WG), 0, s, a.tiles,
+                       a.act_tiles, a.counters, a.rec, (const T*)a.ablk,
+                       (const T*)a.wc, (const T*)a.wp, a.active, (const T*)a.x_in, (T*)a.x_out, a.res, a.ymax,
+                       a.Kp, a.zero_row);
 }
 
 template <class T, int U>
 static void launch_block_wave(hipStream_t s, int grid, int ktiles, const SweepArgs& a) {
+    if (pattern_for(a.pattern) == PAT_GRID) launch_block_wave_p<T, U, PAT_GRID>(s, grid, ktiles, a);
+    else launch_block_wave_p<T, U, PAT_DENSE>(s, grid, ktiles, a);
+}
+
+template <class T, int CPL, int LPS, int U, uint32_t PAT>
+static void launch_block_p(hipStream_t s, int grid, int ktiles, const SweepArgs& a) {
     constexpr int WG = 256;
-    hipLaunchKernelGGL((bellman_block_wave<T, U, WG>), dim3(grid, ktiles), dim3(WG), 0, s, a.tiles,
+    hipLaunchKernelGGL((bellman_block<T, CPL, LPS, U, WG, PAT>), dim3(grid, ktiles), dim3(WG), 0, s, a.tiles,
                        a.act_tiles, a.counters, a.rec, (const T*)a.ablk,
                        (const T*)a.wc, (const T*)a.wp, a.active, (const T*)a.x_in, (T*)a.x_out, a.res, a.ymax,
                        a.Kp, a.zero_row);
@@ -457,11 +496,8 @@ static void launch_block_wave(hipStream_t s, int grid, int ktiles, const SweepAr
 
 template <class T, int CPL, int LPS, int U>
 static void launch_block(hipStream_t s, int grid, int ktiles, const SweepArgs& a) {
-    constexpr int WG = 256;
-    hipLaunchKernelGGL((bellman_block<T, CPL, LPS, U, WG>), dim3(grid, ktiles), dim3(WG), 0, s, a.tiles,
-                       a.act_tiles, a.counters, a.rec, (const T*)a.ablk,
-                       (const T*)a.wc, (const T*)a.wp, a.active, (const T*)a.x_in, (T*)a.x_out, a.res, a.ymax,
-                       a.Kp, a.zero_row);
+    if (pattern_for(a.pattern) == PAT_GRID) launch_block_p<T, CPL, LPS, U, PAT_GRID>(s, grid, ktiles, a);
+    else launch_block_p<T, CPL, LPS, U, PAT_DENSE>(s, grid, ktiles, a);
 }
 
 template <class T>
@@ -471,7 +507,12 @@ static void block_t(hipStream_t s, const Variant& v, int grid, int ktiles, const
     MORAP_B(1, 1) MORAP_B(1, 2) MORAP_B(2, 1) MORAP_B(1, 4) MORAP_B(2, 2) MORAP_B(4, 1)
     MORAP_B(1, 8) MORAP_B(2, 4) MORAP_B(4, 2) MORAP_B(1, 16) MORAP_B(2, 8) MORAP_B(4, 4)
     MORAP_B(1, 32) MORAP_B(2, 16) MORAP_B(4, 8) MORAP_B(2, 32) MORAP_B(4, 16)
-    if (v.cpl == 1 && v.lps == 64) { launch_block_wave<T, 4>(s, grid, ktiles, a); return; }
+    if (v.cpl == 1 && v.lps == 64) {
+        if (v.unroll == 2) launch_block_wave<T, 2>(s, grid, ktiles, a);
+        else if (v.unroll == 8) launch_block_wave<T, 8>(s, grid, ktiles, a);
+        else launch_block_wave<T, 4>(s, grid, ktiles, a);
+        return;
+    }
 #undef MORAP_B
     fail(MORAP_E_UNSUPPORTED, "no block sweep kernel for this variant");
 }
@@ -479,12 +520,16 @@ static void block_t(hipStream_t s, const Variant& v, int grid, int ktiles, const
 template <class T>
 static const void* block_fn(const Variant& v) {
 #define MORAP_F(C, L) \
-    if (v.cpl == C && v.lps == L) return reinterpret_cast<const void*>(&bellman_block<T, C, L, 2, 256>);
+    if (v.cpl == C && v.lps == L) return reinterpret_cast<const void*>(&bellman_block<T, C, L, 2, 256, PAT_GRID>);
     MORAP_F(1, 1) MORAP_F(1, 2) MORAP_F(2, 1) MORAP_F(1, 4) MORAP_F(2, 2) MORAP_F(4, 1)
     MORAP_F(1, 8) MORAP_F(2, 4) MORAP_F(4, 2) MORAP_F(1, 16) MORAP_F(2, 8) MORAP_F(4, 4)
     MORAP_F(1, 32) MORAP_F(2, 16) MORAP_F(4, 8) MORAP_F(2, 32) MORAP_F(4, 16)
 #undef MORAP_F
-    if (v.cpl == 1 && v.lps == 64) return reinterpret_cast<const void*>(&bellman_block_wave<T, 4, 256>);
+    if (v.cpl == 1 && v.lps == 64) {
+        if (v.unroll == 2) return reinterpret_cast<const void*>(&bellman_block_wave<T, 2, 256, PAT_GRID>);
+        if (v.unroll == 8) return reinterpret_cast<const void*>(&bellman_block_wave<T, 8, 256, PAT_GRID>);
+        return reinterpret_cast<const void*>(&bellman_block_wave<T, 4, 256, PAT_GRID>);
+    }
     fail(MORAP_E_UNSUPPORTED, "no block sweep kernel for this variant");
 }
 

@@ -107,6 +107,7 @@ struct HostModels {
     // where a disabled action repeats the first enabled one.
     std::vector<int32_t> blk_rec;      // [8S]
     std::vector<double>  blk_agent;    // [32 * distinct blocks]
+    uint32_t blk_pattern = 0;          // bit 5a + d: some block has P[a][d] != 0
     int64_t S() const { return (int64_t)state_row.size() - 1; }
     int64_t R() const { return (int64_t)row_ptr.size() - 1; }
     int64_t N() const { return (int64_t)col.size(); }
@@ -126,6 +127,7 @@ struct Variant {
     int lps;       // lanes per state
     int wg;        // threads per workgroup
     int kind;      // SWEEP_CSR (LDS-staged CSR tiles) or SWEEP_BLOCK (neighbourhood blocks)
+    int unroll;    // states in flight per lane group (block sweeps)
 };
 
 struct Stats {
@@ -321,6 +323,7 @@ struct SweepArgs {
     const int32_t* rec;     // neighbourhood-block records [8S]
     const void* ablk;       // agent blocks [32 * agent states] (precision of the sweep)
     int32_t zero_row;       // S: the value row that always holds 0
+    uint32_t pattern;       // union of the blocks' nonzero (action, slot) entries
     const int32_t* act_tiles;  // global index of every active tile, in order
 };
 // batched Bellman sweep: variant v, precision prec (MORAP_F32/F64)
@@ -404,7 +407,7 @@ void mark_pairs(hipStream_t s, const InstArgs& a, int Kp, uint8_t* mask);
 // (block.hip); residuals per instance
 void inst_vi_sweep(hipStream_t s, const InstArgs& a, const int32_t* rec, const double* ablk, const double* wc,
                    const double* wp, const uint8_t* active, const double* x_in, double* x_out,
-                   unsigned long long* res, int32_t zero_row);
+                   unsigned long long* res, int32_t zero_row, uint32_t pattern);
 // out[2q + o] = x[2 idx[q] + o] (0 when idx[q] < 0)
 void gather_init(hipStream_t s, int n, const int64_t* idx, const double* x, double* out);
 }  // namespace k

@@ -230,9 +230,28 @@ static void build_blocks(morap_ctx* c, const morap_agent* agents, int nI, const 
         const morap_agent& a = agents[i];
         for (int s = 0; s < a.n_states; ++s) {
             const int64_t ab = abase[i] + s;
+            // slots: 0 = the state itself, 1 + a = the most likely successor
+            // of action a < 4 (on a grid: the cell the move aims at, so a
+            // move's slips land in the slots of the perpendicular moves and
+            // all blocks share one sparsity pattern), then any other successor
             int32_t* sl = &slot[(size_t)ab * NS];
-            int n = 1;
             sl[0] = s;
+            auto find = [&](int32_t v) {
+                for (int d = 0; d < NS; ++d)
+                    if (sl[d] == v) return d;
+                return -1;
+            };
+            for (int act = 0; act + 1 < NS && act < a.n_actions; ++act) {
+                const int64_t r = (int64_t)s * a.n_actions + act;
+                int32_t best = -1;
+                double bp = -1.0;
+                for (int32_t e = a.sa_ptr[r]; e < a.sa_ptr[r + 1]; ++e)
+                    if (a.prob[e] > bp) {
+                        bp = a.prob[e];
+                        best = a.succ[e];
+                    }
+                if (best >= 0 && find(best) < 0) sl[1 + act] = best;
+            }
             double* B = &blk[(size_t)ab * 32];
             for (int act = 0; act < a.n_actions; ++act) {
                 const int64_t r = (int64_t)s * a.n_actions + act;
@@ -240,11 +259,11 @@ static void build_blocks(morap_ctx* c, const morap_agent* agents, int nI, const 
                 amask[ab] |= (uint8_t)(1u << act);
                 B[25 + act] = -a.cost[r];
                 for (int32_t e = a.sa_ptr[r]; e < a.sa_ptr[r + 1]; ++e) {
-                    int d = 0;
-                    while (d < n && sl[d] != a.succ[e]) ++d;
-                    if (d == n) {
-                        if (n == NS) return;   // too many successors: no block form
-                        sl[n++] = a.succ[e];
+                    int d = find(a.succ[e]);
+                    if (d < 0) {
+                        d = find(-1);
+                        if (d < 0) return;   // too many successors: no block form
+                        sl[d] = a.succ[e];
                     }
                     B[act * NS + d] += a.prob[e];
                 }
@@ -324,6 +343,12 @@ static void build_blocks(morap_ctx* c, const morap_agent* agents, int nI, const 
         for (int d = 0; d < NS; ++d)
             MORAP_CHECK(recs[g * 8 + d] >= 0 && recs[g * 8 + d] <= S, MORAP_E_INVALID,
                         "neighbourhood block: a successor that is not a live state of the model");
+    // union of the nonzero (action, slot) entries over all blocks
+    uint32_t pat = 0;
+    for (size_t b = 0; b < ublk.size() / 32; ++b)
+        for (int e = 0; e < NS * NS; ++e)
+            if (ublk[b * 32 + e] != 0.0) pat |= 1u << e;
+    hm.blk_pattern = pat;
     hm.blk_rec = std::move(recs);
     hm.blk_agent = std::move(ublk);
 }

@@ -20,7 +20,8 @@ namespace morap {
 // ---------------------------------------------------------------------------
 // sweep-kernel variants: kernel family x columns per lane x lanes per state.
 // Ids 1-18 are the CSR-tile sweep, 19-36 the same shapes of the
-// neighbourhood-block sweep.
+// neighbourhood-block sweep, 37-38 the wave-per-state block sweep with other
+// numbers of states in flight.
 // ---------------------------------------------------------------------------
 const std::vector<Variant>& variants() {
     static const std::vector<Variant> v = [] {
@@ -29,8 +30,11 @@ const std::vector<Variant>& variants() {
                                 {1, 8},  {2, 4},  {4, 2},  {1, 16}, {2, 8},  {4, 4},
                                 {1, 32}, {2, 16}, {4, 8},  {1, 64}, {2, 32}, {4, 16}};
         int id = 1;
-        for (auto& p : pairs) out.push_back({id++, p[0], p[1], std::min(256, 64 * p[1]), SWEEP_CSR});
-        for (auto& p : pairs) out.push_back({id++, p[0], p[1], 256, SWEEP_BLOCK});
+        for (auto& p : pairs) out.push_back({id++, p[0], p[1], std::min(256, 64 * p[1]), SWEEP_CSR, 0});
+        for (auto& p : pairs) out.push_back({id++, p[0], p[1], 256, SWEEP_BLOCK, p[1] == 64 ? 4 : 2});
+        // the wave-per-state block sweep with 2 and 8 states in flight
+        out.push_back({id++, 1, 64, 256, SWEEP_BLOCK, 2});
+        out.push_back({id++, 1, 64, 256, SWEEP_BLOCK, 8});
         return out;
     }();
     return v;
@@ -161,6 +165,7 @@ static k::SweepArgs sweep_args(morap_ctx* c, ValueSet& vs, int in_par) {
     a.rec = c->has_blocks ? c->d_blk_rec.as<int32_t>() : nullptr;
     a.ablk = c->has_blocks ? (f32 ? c->d_blk32.p : c->d_blk64.p) : nullptr;
     a.zero_row = (int32_t)c->S;
+    a.pattern = c->hm.blk_pattern;
     a.act_tiles = c->d_act_tiles.as<int32_t>();
     return a;
 }
@@ -667,7 +672,8 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
                     MORAP_HIP(hipEventRecord(ev.back().first, s));
                 }
                 k::inst_vi_sweep(s, av, c->d_blk_rec.as<int32_t>(), c->d_blk64.as<double>(), c->d_iwc.as<double>(),
-                                 c->d_iwp.as<double>(), iact, even ? x0 : x1, even ? x1 : x0, ires, (int32_t)c->S);
+                                 c->d_iwp.as<double>(), iact, even ? x0 : x1, even ? x1 : x0, ires, (int32_t)c->S,
+                                 c->hm.blk_pattern);
                 if (o.time_kernels) MORAP_HIP(hipEventRecord(ev.back().second, s));
                 k::fill_i64(s, dctr, 0, 1);
                 k::inst_converge(s, n, ires, iact, ipar, even ? 1 : 0, o.eps_vi, dctr);

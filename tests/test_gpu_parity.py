@@ -108,15 +108,15 @@ SHAPES = [(1, 1), (1, 2), (2, 1), (1, 4), (2, 2), (4, 1), (1, 8), (2, 4), (4, 2)
 
 def test_every_variant_gives_identical_f64_values(ctx, morap):
     """Variants 1-18 (CSR tiles) share one summation order, so their values are
-    bit-identical, eager or graph-replayed; so are variants 19-36 (neighbourhood
+    bit-identical, eager or graph-replayed; so are variants 19-38 (neighbourhood
     blocks) among themselves.  The two families add the same products in a
     different order: they agree to rounding."""
     wl = make_workload(2, n_agents=2, n_tasks=3)
     _load(ctx, wl)
     W = dirichlet_weights(np.random.default_rng(0), 16, 5)
     ref = {}
-    for v in range(1, 37):
-        cpl, lps = SHAPES[(v - 1) % 18]
+    for v in range(1, 39):
+        cpl, lps = SHAPES[(v - 1) % 18] if v <= 36 else (1, 64)
         if 16 % (cpl * lps):
             continue
         fam = v > 18
