@@ -11,7 +11,8 @@
 //   * a 32-byte record: the global product state of each of the 5 agent
 //     successor slots (the zero row when the slot is unused or its successor
 //     is done), the index of its agent state's block, the slots that enter an
-//     accepting location and the enabled actions;
+//     accepting location, the enabled actions and the state itself (records
+//     are stored in the order a tile is walked: column by column on grids);
 //   * its agent state's block: P[a][d] over (action, slot) and -cost[a] (a
 //     disabled action repeats the first enabled one),
 //     shared by every location and every task of that agent.
@@ -145,14 +146,16 @@ bellman_block(const Tile* __restrict__ tiles,
             int32_t sc[U][NSLOT], bi[U], fl[U];
 #pragma unroll
             for (int q = 0; q < U; ++q) {
-                gs[q] = s + q * SPW + g;
-                ok[q] = gs[q] < se;
+                const int pos = s + q * SPW + g;   // record position; the record names its state
+                ok[q] = pos < se;
+                gs[q] = 0;
                 if (ok[q]) {
-                    const int32_t* r = rec + (int64_t)gs[q] * 8;
+                    const int32_t* r = rec + (int64_t)pos * 8;
                     const int4 r0 = *reinterpret_cast<const int4*>(r);
                     const int4 r1 = *reinterpret_cast<const int4*>(r + 4);
                     sc[q][0] = r0.x; sc[q][1] = r0.y; sc[q][2] = r0.z; sc[q][3] = r0.w;
                     sc[q][4] = r1.x; bi[q] = r1.y; fl[q] = r1.z;
+                    gs[q] = r1.w;
                 } else {
 #pragma unroll
                     for (int d = 0; d < NSLOT; ++d) sc[q][d] = zero_row;
@@ -278,11 +281,15 @@ bellman_block_wave(const Tile* __restrict__ tiles,
         const int len = tl.s_end - tl.s_begin;
         return UnitDesc{tl.model, tl.s_begin + (len * part) / sub, tl.s_begin + (len * (part + 1)) / sub};
     };
+    // records are read once per sweep: streaming loads keep them from
+    // displacing value rows in the caches
     auto stage = [&](const UnitDesc& d, int4& r0, int4& r1) {
         if (lane < d.se - d.sb) {
-            const int32_t* r = rec + (int64_t)(d.sb + lane) * 8;
-            r0 = *reinterpret_cast<const int4*>(r);
-            r1 = *reinterpret_cast<const int4*>(r + 4);
+            typedef int i32x4 __attribute__((ext_vector_type(4)));
+            const i32x4* r = reinterpret_cast<const i32x4*>(rec + (int64_t)(d.sb + lane) * 8);
+            const i32x4 v0 = __builtin_nontemporal_load(r), v1 = __builtin_nontemporal_load(r + 1);
+            r0 = make_int4(v0.x, v0.y, v0.z, v0.w);
+            r1 = make_int4(v1.x, v1.y, v1.z, v1.w);
         }
     };
 
@@ -322,7 +329,7 @@ bellman_block_wave(const Tile* __restrict__ tiles,
         if (!on) continue;
         const int n = d.se - d.sb;
         for (int i = 0; i < n; i += U) {
-            int32_t sc[U][NSLOT], bi[U], fl[U];
+            int32_t sc[U][NSLOT], bi[U], fl[U], gs[U];
 #pragma unroll
             for (int q = 0; q < U; ++q) {
                 const int j = min(i + q, n - 1);   // past the end: repeat the last state, not stored
@@ -334,6 +341,7 @@ bellman_block_wave(const Tile* __restrict__ tiles,
                 sc[q][4] = __builtin_amdgcn_readfirstlane(a1.x);
                 bi[q] = __builtin_amdgcn_readfirstlane(a1.y);
                 fl[q] = __builtin_amdgcn_readfirstlane(a1.z);
+                gs[q] = __builtin_amdgcn_readfirstlane(a1.w);   // the record's state
             }
             // successor rows and the state's own row (usually slot 0 again:
             // an L1 hit), all loads unconditional so they retire in order
@@ -345,12 +353,11 @@ bellman_block_wave(const Tile* __restrict__ tiles,
                     const T* row = x_in + (int64_t)sc[q][dd] * Kp;
                     xv[q][dd] = row[kc];
                 }
-                xo[q] = (x_in + (int64_t)(d.sb + min(i + q, n - 1)) * Kp)[kc];
+                xo[q] = (x_in + (int64_t)gs[q] * Kp)[kc];
             }
 #pragma unroll
             for (int q = 0; q < U; ++q) {
                 if (i + q >= n) break;
-                const int gs = d.sb + i + q;
                 T B[BLK];
                 {
                     using V4 = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
@@ -385,7 +392,8 @@ bellman_block_wave(const Tile* __restrict__ tiles,
                     best = fmax(best, acc);
                 }
                 if (act) {
-                    (x_out + (int64_t)gs * Kp)[kc] = best;
+                    // the new values are read only by the next sweep: stream them out
+                    __builtin_nontemporal_store(best, (x_out + (int64_t)gs[q] * Kp) + kc);
                     res = fmax(res, fabs((double)best - (double)old));
                     if (want_ymax) ym = fmax(ym, fabs((double)best));
                 }
@@ -416,9 +424,10 @@ __global__ void __launch_bounds__(256) inst_vi_kernel(InstArgs a, const int32_t*
         const int sb = a.state_base[m];
         if (ls < a.state_base[m + 1] - sb) {
             const int64_t ib = a.inst_base[inst];
-            const int gs = sb + ls;
-            const int4 r0 = *reinterpret_cast<const int4*>(rec + (int64_t)gs * 8);
-            const int4 r1 = *reinterpret_cast<const int4*>(rec + (int64_t)gs * 8 + 4);
+            // the record at position sb + ls names its state
+            const int4 r0 = *reinterpret_cast<const int4*>(rec + (int64_t)(sb + ls) * 8);
+            const int4 r1 = *reinterpret_cast<const int4*>(rec + (int64_t)(sb + ls) * 8 + 4);
+            const int own = r1.w - sb;
             const int sc[NSLOT] = {r0.x, r0.y, r0.z, r0.w, r1.x};
             double xv[NSLOT];
 #pragma unroll
@@ -442,8 +451,8 @@ __global__ void __launch_bounds__(256) inst_vi_kernel(InstArgs a, const int32_t*
                     if (nz<PAT>(act, d)) acc = fma(B[act * NSLOT + d], xv[d], acc);
                 best = fmax(best, acc);
             }
-            const double old = x_in[ib + ls];
-            x_out[ib + ls] = best;
+            const double old = x_in[ib + own];
+            x_out[ib + own] = best;
             r = fabs(best - old);
         }
     }

@@ -103,6 +103,8 @@ struct HostModels {
     //          slot unused, or its successor is done), slot 0 = the agent
     //          state itself; [5] index of its agent state's block; [6] bits 0-4: slot
     //          d enters an accepting location, bits 8-12: action a enabled;
+    //          [7] the record's own state (records are stored tile by tile,
+    //          each tile's in the order the sweep walks it);
     // and per distinct agent-state block 32 values: P[a][d] (a-major, 25), -cost[a] (5), 0, 0,
     // where a disabled action repeats the first enabled one.
     std::vector<int32_t> blk_rec;      // [8S]

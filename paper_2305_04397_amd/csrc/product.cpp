@@ -332,6 +332,7 @@ static void build_blocks(morap_ctx* c, const morap_agent* agents, int nI, const 
                 }
                 r[5] = uniq[(size_t)ab];
                 r[6] = acc | ((int32_t)amask[ab] << 8);
+                r[7] = g;
             }
         }
     };
@@ -439,6 +440,60 @@ static void upload(morap::DevBuf& d, const std::vector<T>& h, hipStream_t s) {
     if (!h.empty()) MORAP_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
+// Order of the neighbourhood-block records inside every tile (a record
+// carries its state in [7]).  With the grid slot order (slot 1 / 2 = the
+// state a north / south move aims at) a tile is walked column by column:
+// vertical neighbours follow each other and the tiles processed side by side
+// reach the same columns at about the same time, so every successor row is
+// reused from cache soon after it is first fetched.  Otherwise state order.
+static void order_records(morap_ctx* c) {
+    HostModels& hm = c->hm;
+    const int64_t S = hm.S();
+    // back to state order (idempotent)
+    {
+        std::vector<int32_t> nat(hm.blk_rec.size());
+        for (int64_t p = 0; p < S; ++p) {
+            const int32_t g = hm.blk_rec[(size_t)p * 8 + 7];
+            std::copy(&hm.blk_rec[(size_t)p * 8], &hm.blk_rec[(size_t)p * 8 + 8], &nat[(size_t)g * 8]);
+        }
+        hm.blk_rec.swap(nat);
+    }
+    constexpr uint32_t kGridPattern = (1u << 0) | (1u << 1) | (1u << 3) | (1u << 4) | (1u << 5) | (1u << 7) |
+                                      (1u << 8) | (1u << 9) | (1u << 10) | (1u << 11) | (1u << 12) |
+                                      (1u << 13) | (1u << 15) | (1u << 16) | (1u << 17) | (1u << 19) | (1u << 20);
+    if ((hm.blk_pattern & ~kGridPattern) != 0) return;
+    std::vector<int32_t> out(hm.blk_rec.size());
+    std::vector<int> order, up, down;
+    std::vector<uint8_t> seen;
+    for (const Tile& t : c->tiles) {
+        const int b = t.s_begin, n = t.s_end - t.s_begin;
+        auto local = [&](int32_t g) { return (g >= b && g < b + n) ? g - b : -1; };
+        up.assign(n, -1);
+        down.assign(n, -1);
+        seen.assign(n, 0);
+        order.clear();
+        for (int i = 0; i < n; ++i) {
+            up[i] = local(hm.blk_rec[(size_t)(b + i) * 8 + 1]);
+            down[i] = local(hm.blk_rec[(size_t)(b + i) * 8 + 2]);
+        }
+        for (int i = 0; i < n; ++i) {
+            if (seen[i]) continue;
+            int j = i;
+            for (int steps = 0; steps < n && up[j] >= 0 && !seen[up[j]] && up[j] != i; ++steps) j = up[j];
+            for (int from : {j, i})   // from i too when the column above does not lead back to it
+                for (int k = from; k >= 0 && !seen[k]; k = down[k]) {
+                    seen[k] = 1;
+                    order.push_back(k);
+                }
+        }
+        MORAP_CHECK((int)order.size() == n, MORAP_E_INVALID, "record order is not a permutation");
+        for (int p = 0; p < n; ++p)
+            std::copy(&hm.blk_rec[(size_t)(b + order[p]) * 8], &hm.blk_rec[(size_t)(b + order[p]) * 8 + 8],
+                      &out[(size_t)(b + p) * 8]);
+    }
+    hm.blk_rec.swap(out);
+}
+
 void upload_models(morap_ctx* c) {
     const HostModels& hm = c->hm;
     hipStream_t s = c->stream;
@@ -457,13 +512,6 @@ void upload_models(morap_ctx* c) {
     upload(c->d_to_done, hm.to_done, s);
     upload(c->d_state_base, hm.state_base, s);
     upload(c->d_init, hm.init, s);
-    c->has_blocks = !hm.blk_rec.empty();
-    if (c->has_blocks) {
-        upload(c->d_blk_rec, hm.blk_rec, s);
-        upload(c->d_blk64, hm.blk_agent, s);
-        c->d_blk32.ensure(hm.blk_agent.size() * 4 + 16);
-        k::to_f32(s, c->d_blk64.as<double>(), c->d_blk32.as<float>(), (int64_t)hm.blk_agent.size());
-    }
     // FP32 copies for FP32 sweeps
     c->d_prob32.ensure((size_t)c->N * 4 + 16);
     c->d_rew32.ensure((size_t)c->R * 8 + 16);
@@ -509,6 +557,14 @@ void upload_models(morap_ctx* c) {
     c->tile_base[hm.M] = (int32_t)c->tiles.size();
     upload(c->d_tiles, c->tiles, s);
     upload(c->d_tile_base, c->tile_base, s);
+    c->has_blocks = !hm.blk_rec.empty();
+    if (c->has_blocks) {
+        order_records(c);
+        upload(c->d_blk_rec, hm.blk_rec, s);
+        upload(c->d_blk64, hm.blk_agent, s);
+        c->d_blk32.ensure(hm.blk_agent.size() * 4 + 16);
+        k::to_f32(s, c->d_blk64.as<double>(), c->d_blk32.as<float>(), (int64_t)hm.blk_agent.size());
+    }
     MORAP_HIP(hipStreamSynchronize(s));
     c->loaded = true;
 }
