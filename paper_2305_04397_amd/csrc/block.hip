@@ -108,9 +108,8 @@ bellman_block(const Tile* __restrict__ tiles,
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
                 const int64_t idx = (int64_t)m * Kp + kc + c;
-                if (res[c] > 0.0) atomicMax(&res_all[idx], (unsigned long long)__double_as_longlong(res[c]));
-                if (want_ymax && ym[c] > 0.0)
-                    atomicMax(&ymax_all[idx], (unsigned long long)__double_as_longlong(ym[c]));
+                max_flush(&res_all[idx], res[c]);
+                if (want_ymax) max_flush(&ymax_all[idx], ym[c]);
             }
         }
 #pragma unroll
@@ -299,8 +298,8 @@ bellman_block_wave(const Tile* __restrict__ tiles,
     double res = 0.0, ym = 0.0;
     auto flush = [&](int m) {
         const int64_t idx = (int64_t)m * Kp + kc;
-        if (res > 0.0) atomicMax(&res_all[idx], (unsigned long long)__double_as_longlong(res));
-        if (want_ymax && ym > 0.0) atomicMax(&ymax_all[idx], (unsigned long long)__double_as_longlong(ym));
+        max_flush(&res_all[idx], res);
+        if (want_ymax) max_flush(&ymax_all[idx], ym);
         res = ym = 0.0;
     };
 

@@ -46,6 +46,18 @@ __device__ __forceinline__ double group_max(double v) {
     return v;
 }
 
+// Raise the FP64 maximum stored (as its bit pattern) at p to v >= 0.  The
+// current value is read first and the atomic skipped when it is already at
+// least v: many workers flush maxima of the same (model, column) pairs, and
+// most of them do not raise it, so this keeps atomics on a hot address few.
+__device__ __forceinline__ void max_flush(unsigned long long* p, double v) {
+    if (!(v > 0.0)) return;
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    // non-negative doubles order like their bit patterns
+    if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= b) return;
+    atomicMax(p, b);
+}
+
 // Share [b, e) of n ordered work items for worker idx of count workers on XCD
 // xcd.  Workgroups are dealt to the 8 XCDs round-robin by blockIdx.x, so each
 // XCD takes one contiguous eighth of the items (neighbouring items share its

@@ -107,8 +107,8 @@ __device__ __forceinline__ void flush_residuals(double (&res)[CPL], double (&ym)
             y = fmax(y, l_red[1][w][tid]);
         }
         const int64_t idx = (int64_t)m * Kp + blockIdx.y * KT + tid;
-        if (r > 0.0) atomicMax(&res_all[idx], (unsigned long long)__double_as_longlong(r));
-        if (want_ymax && y > 0.0) atomicMax(&ymax_all[idx], (unsigned long long)__double_as_longlong(y));
+        max_flush(&res_all[idx], r);
+        if (want_ymax) max_flush(&ymax_all[idx], y);
     }
     __syncthreads();
 #pragma unroll
