@@ -1,0 +1,95 @@
+"""Parity at the full 50 x 100 size (5,000 product MDPs, 1.3e7 states), in
+the launch configuration bench.py times: K = 64 Dirichlet columns, FP32
+batched solve with the autotuned persistent sweep replayed from hipGraphs,
+then the support step (assignment, FP64 re-solve of the assigned pairs,
+policies, evaluation).  The oracle cannot solve the whole workload, so it
+recomputes sampled outputs one by one (models of 32 x 32 agents, where its
+FP64 value iteration takes about a second), and properties that hold at any
+size are checked on everything."""
+import numpy as np
+import pytest
+
+from workloads import make_workload, dirichlet_weights
+from oracle import product, vi, alg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def full():
+    from paper_2305_04397_amd import morap
+    wl = make_workload(3)
+    ctx = morap.Context(0)
+    ctx.build_products(wl)
+    yield morap, ctx, wl
+    ctx.close()
+
+
+def _small_models(wl, rng, n):
+    nI, nJ = wl.n_agents, wl.n_tasks
+    cand = [(i, j) for i in range(nI) for j in range(nJ)
+            if wl.agents[i].width == 32 and wl.tasks[j].n_locs <= 4]
+    pick = rng.choice(len(cand), size=n, replace=False)
+    return [cand[p] for p in pick]
+
+
+def test_full_size_solve_sampled(full):
+    morap, ctx, wl = full
+    nI, nJ = wl.n_agents, wl.n_tasks
+    rng = np.random.default_rng(0)
+    W = dirichlet_weights(rng, 64, nI + nJ)
+    eps = 1e-6
+    c, st = ctx.solve(W, morap.Options(eps_vi=eps, precision="f32"))
+    assert st["variant"] > 18                       # the neighbourhood-block sweep served the solve
+    # costs are negative and a task's probability is at most 1: c[k, i, j] <= w_j
+    assert np.isfinite(c).all()
+    assert (c <= W[:, None, nI:] + 1e-6).all()
+    for i, j in _small_models(wl, rng, 6):
+        p = product.build_product(wl.agents[i], wl.tasks[j], wl.letters[i][j])
+        ks = rng.choice(64, size=3, replace=False)
+        y, _ = vi.value_iteration(p, W[ks, i], W[ks, nI + j], eps)
+        for col, k in enumerate(ks):
+            ref = y[p.init, col] if p.init >= 0 else 0.0
+            # FP32 sweeps stop at max(eps, 8 u32 |y|): 2e-4 relative covers it
+            assert abs(c[k, i, j] - ref) <= 2e-4 * max(1.0, abs(ref)), (i, j, k, c[k, i, j], ref)
+
+
+def test_full_size_support_sampled(full):
+    morap, ctx, wl = full
+    nI, nJ = wl.n_agents, wl.n_tasks
+    rng = np.random.default_rng(1)
+    W = dirichlet_weights(rng, 4, nI + nJ)
+    eps = 1e-6
+    r, A, c, st = ctx.support(W, morap.Options(eps_vi=eps, precision="f32"))
+    for k in range(W.shape[0]):
+        # lem:face: w.r equals the assignment optimum, here up to the FP32
+        # stopping error of c and the FP64 evaluation of r
+        opt = sum(c[k][A[k][j], j] for j in range(nJ))
+        assert W[k] @ r[k] == pytest.approx(opt, rel=1e-3, abs=1e-3)
+        loads = np.bincount(A[k], minlength=nI)
+        assert loads.max() <= 2 and (r[k][nI:] >= -1e-12).all() and (r[k][nI:] <= 1 + 1e-9).all()
+    # the policy and the probability of sampled tasks whose assigned agent
+    # lives on a 32 x 32 grid
+    checked = 0
+    for j in rng.permutation(nJ):
+        if checked == 5:
+            break
+        k = int(rng.integers(W.shape[0]))
+        i = int(A[k][j])
+        if wl.agents[i].width != 32 or wl.tasks[j].n_locs > 4:
+            continue
+        p = product.build_product(wl.agents[i], wl.tasks[j], wl.letters[i][j])
+        mu = ctx.get_policy(k, int(j), p.n_states)
+        mo = alg.policy_for(p, W[k, i], W[k, nI + j], eps)
+        diff = np.flatnonzero(mu != mo)
+        if diff.size:
+            # only where the two actions tie to the accuracy of the values
+            sc = W[k, i] + W[k, nI + j]
+            x, _ = vi.value_iteration(p, np.array([W[k, i] / sc]), np.array([W[k, nI + j] / sc]), eps)
+            Q = vi.q_values(p, x[:, 0], W[k, i] / sc, W[k, nI + j] / sc)[:, 0]
+            rows0 = p.state_row[diff]
+            assert np.abs(Q[rows0 + mu[diff]] - Q[rows0 + mo[diff]]).max() <= 1e-6
+        (_, vp), _, _ = vi.evaluate(p, mu.astype(np.int64), eps)
+        assert r[k][nI + j] == pytest.approx(vp, rel=1e-9, abs=4 * eps)
+        checked += 1
+    assert checked >= 3
