@@ -478,6 +478,77 @@ void inst_vi_sweep(hipStream_t s, const InstArgs& a, const int32_t* rec, const d
     MORAP_HIP(hipGetLastError());
 }
 
+// Alg. 4 over the neighbourhood blocks: one fixed-policy Jacobi sweep of both
+// objectives (cost, probability) of (column, model) instances, FP64, one
+// thread per instance state; x is [instance state][2], the policy mu the
+// chosen row among the state's enabled actions.
+template <uint32_t PAT>
+__global__ void __launch_bounds__(256) eval_block_kernel(InstArgs a, const int32_t* __restrict__ rec,
+                                                         const double* __restrict__ ablk, const int8_t* mu,
+                                                         const uint8_t* active, const double* __restrict__ x_in,
+                                                         double* __restrict__ x_out, unsigned long long* res,
+                                                         int32_t zero_row) {
+    const int t = blockIdx.x;
+    if (t >= a.n_tiles) return;
+    const int inst = a.inst_tiles[2 * t];
+    const bool a0 = active[2 * inst] != 0, a1 = active[2 * inst + 1] != 0;
+    double r0 = 0.0, r1 = 0.0;
+    if (a0 || a1) {
+        const int ls = a.inst_tiles[2 * t + 1] + threadIdx.x;
+        const int m = a.inst_model[inst];
+        const int sb = a.state_base[m];
+        if (ls < a.state_base[m + 1] - sb) {
+            const int64_t ib = a.inst_base[inst];
+            const int4 q0 = *reinterpret_cast<const int4*>(rec + (int64_t)(sb + ls) * 8);
+            const int4 q1 = *reinterpret_cast<const int4*>(rec + (int64_t)(sb + ls) * 8 + 4);
+            const int own = q1.w - sb;
+            // the chosen row is the mu-th enabled action
+            uint32_t am = (uint32_t)(q1.z >> 8) & 31u;
+            for (int k = mu[ib + own]; k > 0; --k) am &= am - 1;
+            const int act = __builtin_ctz(am);
+            const double* B = ablk + (int64_t)q1.y * BLK;
+            const int accm = q1.z & 31;
+            const int sc[NSLOT] = {q0.x, q0.y, q0.z, q0.w, q1.x};
+            double c0 = B[25 + act], c1 = 0.0;
+#pragma unroll
+            for (int d = 0; d < NSLOT; ++d)
+                if (nz<PAT>(0, d) || nz<PAT>(1, d) || nz<PAT>(2, d) || nz<PAT>(3, d) || nz<PAT>(4, d))
+                    if ((accm >> d) & 1) c1 += B[act * NSLOT + d];
+#pragma unroll
+            for (int d = 0; d < NSLOT; ++d) {
+                const double p = B[act * NSLOT + d];
+                if (sc[d] != zero_row) {
+                    const double2 v = reinterpret_cast<const double2*>(x_in)[ib + (sc[d] - sb)];
+                    c0 = fma(p, v.x, c0);
+                    c1 = fma(p, v.y, c1);
+                }
+            }
+            const double2 old = reinterpret_cast<const double2*>(x_in)[ib + own];
+            if (a0) { x_out[2 * (ib + own)] = c0; r0 = fabs(c0 - old.x); }
+            if (a1) { x_out[2 * (ib + own) + 1] = c1; r1 = fabs(c1 - old.y); }
+        }
+    }
+    r0 = wave_max(r0);
+    r1 = wave_max(r1);
+    if ((threadIdx.x & 63) == 0) {
+        max_flush(&res[2 * inst], r0);
+        max_flush(&res[2 * inst + 1], r1);
+    }
+}
+
+void eval_block_sweep(hipStream_t s, const InstArgs& a, const int32_t* rec, const double* ablk, const int8_t* mu,
+                      const uint8_t* active, const double* x_in, double* x_out, unsigned long long* res,
+                      int32_t zero_row, uint32_t pattern) {
+    if (a.n_tiles <= 0) return;
+    if (pattern_for(pattern) == PAT_GRID)
+        hipLaunchKernelGGL(eval_block_kernel<PAT_GRID>, dim3(a.n_tiles), dim3(256), 0, s, a, rec, ablk, mu, active,
+                           x_in, x_out, res, zero_row);
+    else
+        hipLaunchKernelGGL(eval_block_kernel<PAT_DENSE>, dim3(a.n_tiles), dim3(256), 0, s, a, rec, ablk, mu,
+                           active, x_in, x_out, res, zero_row);
+    MORAP_HIP(hipGetLastError());
+}
+
 template <class T, int U, uint32_t PAT>
 static void launch_block_wave_p(hipStream_t s, int grid, int ktiles, const SweepArgs& a) {
     constexpr int WG = 256;

@@ -410,6 +410,11 @@ void mark_pairs(hipStream_t s, const InstArgs& a, int Kp, uint8_t* mask);
 void inst_vi_sweep(hipStream_t s, const InstArgs& a, const int32_t* rec, const double* ablk, const double* wc,
                    const double* wp, const uint8_t* active, const double* x_in, double* x_out,
                    unsigned long long* res, int32_t zero_row, uint32_t pattern);
+// one Alg. 4 sweep (both objectives) of instances over the neighbourhood
+// blocks (block.hip)
+void eval_block_sweep(hipStream_t s, const InstArgs& a, const int32_t* rec, const double* ablk, const int8_t* mu,
+                      const uint8_t* active, const double* x_in, double* x_out, unsigned long long* res,
+                      int32_t zero_row, uint32_t pattern);
 // out[2q + o] = x[2 idx[q] + o] (0 when idx[q] < 0)
 void gather_init(hipStream_t s, int n, const int64_t* idx, const double* x, double* out);
 }  // namespace k

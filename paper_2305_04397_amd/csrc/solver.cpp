@@ -791,7 +791,11 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
     while (true) {
         for (int i = 0; i < chunk; ++i) {
             const bool even = (i & 1) == 0;
-            k::eval_sweep(s, ae, mu, iact, even ? xe0 : xe1, even ? xe1 : xe0, ires);
+            if (c->has_blocks)
+                k::eval_block_sweep(s, ae, c->d_blk_rec.as<int32_t>(), c->d_blk64.as<double>(), mu, iact,
+                                    even ? xe0 : xe1, even ? xe1 : xe0, ires, (int32_t)c->S, c->hm.blk_pattern);
+            else
+                k::eval_sweep(s, ae, mu, iact, even ? xe0 : xe1, even ? xe1 : xe0, ires);
             k::fill_i64(s, dctr, 0, 1);
             k::inst_converge(s, 2 * n, ires, iact, ipar, even ? 1 : 0, o.eps_eval, dctr);
         }

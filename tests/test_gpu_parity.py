@@ -298,3 +298,57 @@ def test_edge_cases(ctx, morap):
     assert e.value.code == morap.E_UNSUPPORTED
     c, st = ctx.solve(np.eye(4)[:1], morap.Options(eps_vi=1e-8, precision="f64"))
     assert st["variant"] <= 18
+
+
+def _cfg1_thresholds(prods):
+    rng = np.random.default_rng(21)
+    base = alg.support(prods, 2, 2, np.full(4, 0.25), 1e-8).r
+    T = [np.array([-40.0, -40.0, 0.8, 0.8]), base - np.array([3.0, 3.0, 0.0, 0.0])]
+    for _ in range(3):
+        T.append(base + np.array([5.0, 5.0, 0.0, 0.0]) * rng.uniform(-1, 1, 4))
+    return np.array(T)
+
+
+def test_query_batch_equals_single_queries(ctx, morap):
+    """Lockstep queries (one weight column each per pass) give what the
+    same queries give one at a time."""
+    wl = make_workload(1)
+    prods = _load(ctx, wl)
+    o = morap.Options(eps_vi=1e-8, precision="f64")
+    T = _cfg1_thresholds(prods)
+    batch = ctx.query_batch(T, eps=1e-6, opts=o)
+    for t, b in zip(T, batch):
+        s = ctx.query(t, eps=1e-6, opts=o)
+        assert b["verdict"] == s["verdict"] and b["iterations"] == s["iterations"]
+        assert np.abs(b["t_down"] - s["t_down"]).max() <= 1e-9
+        assert np.abs(b["t_up"] - s["t_up"]).max() <= 1e-9
+
+
+def test_query_with_norm_matrix_matches_oracle(ctx, morap):
+    """Alg. 1 with a diagonal SPD norm matrix M (the M-norm projections)."""
+    wl = make_workload(1)
+    prods = _load(ctx, wl)
+    o = morap.Options(eps_vi=1e-8, precision="f64")
+    M = np.diag([1.0, 2.0, 30.0, 40.0])
+    for t in _cfg1_thresholds(prods)[:3]:
+        g = ctx.query(t, M=M, eps=1e-6, opts=o, trace=True)
+        q = alg.query(prods, 2, 2, t, 1e-6, 1e-8, M=M)
+        assert g["verdict"] == q.verdict
+        assert np.abs(g["t_down"] - q.t_down).max() <= 1e-6
+        assert np.abs(g["t_up"] - q.t_up).max() <= 1e-6
+
+
+def test_verification_only_stops_at_the_first_separation(ctx, morap):
+    """Verification mode (Sec. 5, second experiment): stop once a hyperplane
+    separates t from the achievable set."""
+    wl = make_workload(1)
+    prods = _load(ctx, wl)
+    o = morap.Options(eps_vi=1e-8, precision="f64")
+    t = _cfg1_thresholds(prods)[1] + np.array([0.0, 0.0, 0.5, 0.5])   # beyond every probability
+    g = ctx.query(t, eps=1e-6, opts=o, verification_only=True, trace=True)
+    q = alg.query(prods, 2, 2, t, 1e-6, 1e-8, verification_only=True)
+    full = ctx.query(t, eps=1e-6, opts=o)
+    assert g["verdict"] == q.verdict == morap.INFEASIBLE
+    assert g["iterations"] == q.iterations <= full["iterations"]
+    w, r = g["W"][-1], g["R"][-1]
+    assert w @ r < w @ t
