@@ -5,6 +5,9 @@
 // dummies, which keeps the problem a square assignment.
 #include "common.h"
 
+#include <atomic>
+#include <thread>
+
 #include <algorithm>
 #include <cmath>
 #include <limits>
@@ -63,26 +66,34 @@ static std::vector<int> min_cost_matching(const std::vector<double>& cost, int n
 
 void assign_columns(int nI, int nJ, const double* c, int K, int32_t* out) {
     MORAP_CHECK(nI > 0 && nJ > 0 && c && out && K > 0, MORAP_E_INVALID, "bad assignment arguments");
+    for (int64_t q = 0; q < (int64_t)K * nI * nJ; ++q)
+        MORAP_CHECK(std::isfinite(c[q]), MORAP_E_INVALID, "non-finite assignment value");
     const int cap = std::max(1, (nJ + nI - 1) / nI);
     const int n = nI * cap;   // >= nJ
-    std::vector<double> cost((size_t)n * n);
-    for (int k = 0; k < K; ++k) {
-        const double* ck = c + (size_t)k * nI * nJ;
-        for (int r = 0; r < n; ++r) {
-            const int i = r / cap;
-            for (int j = 0; j < n; ++j) {
-                double val = 0.0;
-                if (j < nJ) {
-                    val = ck[(size_t)i * nJ + j];
-                    MORAP_CHECK(std::isfinite(val), MORAP_E_INVALID, "non-finite assignment value");
-                }
-                cost[(size_t)r * n + j] = -val;
+    // the K columns are independent: one Hungarian solve per column, spread
+    // over host threads
+    std::atomic<int> next{0};
+    auto worker = [&] {
+        std::vector<double> cost((size_t)n * n);
+        for (int k; (k = next++) < K;) {
+            const double* ck = c + (size_t)k * nI * nJ;
+            for (int r = 0; r < n; ++r) {
+                const int i = r / cap;
+                for (int j = 0; j < n; ++j) cost[(size_t)r * n + j] = j < nJ ? -ck[(size_t)i * nJ + j] : 0.0;
             }
+            const auto match = min_cost_matching(cost, n);
+            for (int r = 0; r < n; ++r)
+                if (match[r] >= 0 && match[r] < nJ) out[(size_t)k * nJ + match[r]] = r / cap;
         }
-        const auto match = min_cost_matching(cost, n);
-        for (int r = 0; r < n; ++r)
-            if (match[r] >= 0 && match[r] < nJ) out[(size_t)k * nJ + match[r]] = r / cap;
+    };
+    const int nt = std::max(1, std::min<int>(K, std::min(16u, std::thread::hardware_concurrency())));
+    if (nt == 1 || (int64_t)K * n * n < (int64_t)1 << 16) {
+        worker();
+        return;
     }
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) th.emplace_back(worker);
+    for (auto& t : th) t.join();
 }
 
 }  // namespace morap
