@@ -24,7 +24,8 @@ Extra objects on the JSON line:
                 counter summary (profiles/sweep_traffic_50x100.txt), null when
                 the sweep sources changed since it was taken;
   cpu_baseline  the FP64 oracle's value iteration timed on a bounded sample of
-                models of the same workload on the host (single process);
+                models of the same workload on the host, one process per
+                core used (8 by default);
   ms_per_query  Alg. 1 queries (eps 0.01, at most --query-max-iter passes) on
                 the timed workload from the plain first weight (1, 0, ..., 0);
   proposer      learned vs plain first weight on the 10 x 20 family: the
@@ -101,17 +102,24 @@ def thresholds(rng, front: np.ndarray, n: int, nI: int) -> np.ndarray:
     return t
 
 
-def cpu_baseline(wl, K: int, eps: float, budget_s: float, seed: int) -> dict:
-    """FP64 oracle value iteration on a sample of the workload's models."""
+_CPU_WL = None   # the workload, inherited by the forked baseline workers
+
+
+def _cpu_worker(task):
+    """One worker of the CPU baseline: FP64 oracle value iteration on models
+    drawn at random (its own stream) until `budget_s` of VI time."""
+    from threadpoolctl import threadpool_limits
     from oracle import product, vi
-    rng = np.random.default_rng(seed)
+    threadpool_limits(1)                      # one core per process
+    K, eps, budget_s, seed, worker = task
+    wl = _CPU_WL
+    rng = np.random.default_rng([seed, worker])
     nI, nJ = wl.n_agents, wl.n_tasks
-    W = rng.dirichlet(np.ones(nI + nJ), size=K)
-    order = rng.permutation(nI * nJ)
+    W = np.random.default_rng(seed).dirichlet(np.ones(nI + nJ), size=K)
     backups, elapsed, done = 0, 0.0, 0
-    for m in order:
+    for m in rng.permutation(nI * nJ):
         i, j = divmod(int(m), nJ)
-        if wl.agents[i].n_states > 2000:      # keep the sample bounded
+        if wl.agents[i].n_states > 2000:      # keep the sample bounded: 32 x 32 agents
             continue
         p = product.build_product(wl.agents[i], wl.tasks[j], wl.letters[i][j])
         t0 = time.perf_counter()
@@ -121,10 +129,29 @@ def cpu_baseline(wl, K: int, eps: float, budget_s: float, seed: int) -> dict:
         done += 1
         if elapsed >= budget_s:
             break
-    return {"value": backups / elapsed, "unit": "backups/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} models drawn at random from the workload (agents on 32x32 grids), "
-                      f"K={K} Dirichlet weight columns, eps {eps:g}, FP64 Jacobi value iteration, "
-                      f"{elapsed:.1f} s of single-process CPU work"}
+    return backups, elapsed, done
+
+
+def cpu_baseline(wl, K: int, eps: float, budget_s: float, seed: int, workers: int) -> dict:
+    """The FP64 oracle's value iteration on a bounded sample of the workload's
+    models, one process per host core used (forked before the GPU is
+    touched).  value = sum over workers of backups / VI seconds."""
+    import multiprocessing as mp
+    global _CPU_WL
+    _CPU_WL = wl
+    tasks = [(K, eps, budget_s, seed, w) for w in range(workers)]
+    if workers == 1:
+        res = [_cpu_worker(tasks[0])]
+    else:
+        with mp.get_context("fork").Pool(workers) as pool:
+            res = pool.map(_cpu_worker, tasks)
+    rate = sum(b / e for b, e, _ in res if e > 0)
+    done = sum(d for _, _, d in res)
+    return {"value": rate, "unit": "backups/s", "cores": workers, "kind": "oracle",
+            "per_core": rate / workers,
+            "sample": f"{done} models drawn at random from the workload (agents on 32x32 grids) by {workers} "
+                      f"processes, K={K} Dirichlet weight columns, eps {eps:g}, FP64 Jacobi value iteration "
+                      f"(numpy/scipy), about {budget_s:.0f} s of VI per process"}
 
 
 def proposer_eval(args) -> dict:
@@ -198,7 +225,8 @@ def main():
     ap.add_argument("--workload", default="50x100", choices=["50x100", "10x20"])
     ap.add_argument("--queries", type=int, default=64, help="queries for the ms-per-query measurement (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="VI seconds per baseline process")
+    ap.add_argument("--cpu-workers", type=int, default=8, help="baseline processes (at most the host's cores)")
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--query-max-iter", type=int, default=16,
@@ -224,6 +252,12 @@ def main():
     nI, nJ = wl.n_agents, wl.n_tasks
     d = nI + nJ
     log(f"workload {wl.name}: generated in {time.time() - t0:.1f} s")
+    # the CPU baseline first: its worker processes fork before the GPU is used
+    cpu = None
+    if not args.no_cpu_baseline:
+        workers = max(1, min(args.cpu_workers, os.cpu_count() or 1))
+        cpu = cpu_baseline(wl, K, eps, args.cpu_seconds, args.seed, workers)
+        log(f"cpu baseline: {cpu['value']:.3e} backups/s on {workers} processes")
     ctx = morap.Context(0)
     t0 = time.time()
     ctx.build_products(wl)
@@ -309,10 +343,6 @@ def main():
     if args.proposer_queries > 0:
         learned = proposer_eval(args)
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl, K, eps, args.cpu_seconds, args.seed)
-        log(f"cpu baseline: {cpu['value']:.3e} backups/s")
 
     line = {"metric": METRIC, "value": value, "unit": "backups/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": round(float(np.mean(step_ms)), 2), "higher_is_better": True,
