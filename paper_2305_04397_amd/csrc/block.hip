@@ -254,8 +254,10 @@ bellman_block_wave(const Tile* __restrict__ tiles,
                    int32_t zero_row) {
     constexpr int NW = WG / 64;
     constexpr bool want_ymax = sizeof(T) == 4;
-    // each wave's records of its current unit (lane i wrote state i's)
-    __shared__ int4 l_rec[NW][64][2];
+    // each wave's records of its current unit (lane i wrote records i and
+    // 64 + i); a unit is at most one tile of 128 states
+    constexpr int RPL = 2;
+    __shared__ int4 l_rec[NW][64 * RPL][2];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const unsigned kc = blockIdx.y * 64u + (unsigned)lane;
@@ -282,13 +284,16 @@ bellman_block_wave(const Tile* __restrict__ tiles,
     };
     // records are read once per sweep: streaming loads keep them from
     // displacing value rows in the caches
-    auto stage = [&](const UnitDesc& d, int4& r0, int4& r1) {
-        if (lane < d.se - d.sb) {
-            typedef int i32x4 __attribute__((ext_vector_type(4)));
-            const i32x4* r = reinterpret_cast<const i32x4*>(rec + (int64_t)(d.sb + lane) * 8);
-            const i32x4 v0 = __builtin_nontemporal_load(r), v1 = __builtin_nontemporal_load(r + 1);
-            r0 = make_int4(v0.x, v0.y, v0.z, v0.w);
-            r1 = make_int4(v1.x, v1.y, v1.z, v1.w);
+    auto stage = [&](const UnitDesc& d, int4 (&rr)[RPL][2]) {
+#pragma unroll
+        for (int h = 0; h < RPL; ++h) {
+            if (64 * h + lane < d.se - d.sb) {
+                typedef int i32x4 __attribute__((ext_vector_type(4)));
+                const i32x4* r = reinterpret_cast<const i32x4*>(rec + (int64_t)(d.sb + 64 * h + lane) * 8);
+                const i32x4 v0 = __builtin_nontemporal_load(r), v1 = __builtin_nontemporal_load(r + 1);
+                rr[h][0] = make_int4(v0.x, v0.y, v0.z, v0.w);
+                rr[h][1] = make_int4(v1.x, v1.y, v1.z, v1.w);
+            }
         }
     };
 
@@ -304,17 +309,22 @@ bellman_block_wave(const Tile* __restrict__ tiles,
     };
 
     UnitDesc nd = describe(u_begin);
-    int4 n0 = make_int4(0, 0, 0, 0), n1 = make_int4(0, 0, 0, 0);
-    stage(nd, n0, n1);
+    int4 nr[RPL][2];
+#pragma unroll
+    for (int h = 0; h < RPL; ++h) nr[h][0] = nr[h][1] = make_int4(0, 0, 0, 0);
+    stage(nd, nr);
     for (int u = u_begin; u < xe; u += count) {
         const UnitDesc d = nd;
         // publish this unit's records to the wave's LDS slots (same-wave
         // LDS accesses are ordered: no barrier), then fetch the next unit's
-        l_rec[wave][lane][0] = n0;
-        l_rec[wave][lane][1] = n1;
+#pragma unroll
+        for (int h = 0; h < RPL; ++h) {
+            l_rec[wave][64 * h + lane][0] = nr[h][0];
+            l_rec[wave][64 * h + lane][1] = nr[h][1];
+        }
         if (u + count < xe) {
             nd = describe(u + count);
-            stage(nd, n0, n1);
+            stage(nd, nr);
         }
         if (d.m != cur_m) {
             if (cur_m >= 0) flush(cur_m);

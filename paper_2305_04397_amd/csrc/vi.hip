@@ -29,9 +29,9 @@ namespace morap {
 namespace k {
 
 // LDS staging limits of one tile (host tiles respect them)
-constexpr int TILE_STATES = 64;
-constexpr int TILE_ROWS = 384;
-constexpr int TILE_NNZ = 1024;
+constexpr int TILE_STATES = 128;
+constexpr int TILE_ROWS = 768;
+constexpr int TILE_NNZ = 2048;
 
 int sweep_lds_rows() { return TILE_ROWS; }
 int sweep_lds_nnz() { return TILE_NNZ; }
