@@ -351,13 +351,16 @@ void sweep(hipStream_t s, int prec, const Variant& v, int grid, int ktiles, cons
 // updated (each one value read and one written).
 template <class T>
 __global__ void converge_kernel(ConvergeArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t n = (int64_t)a.M * a.Kp;
+    // threads walk the pairs of the models active in the sweep just done
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = a.counters[2] * a.Kp;
     bool still = false;
     int m = 0;
-    if (i < n) {
-        m = (int)(i / a.Kp);
-        const int k = (int)(i % a.Kp);
+    int64_t i = 0;
+    if (t < n) {
+        m = a.act_models[t / a.Kp];
+        const int k = (int)(t % a.Kp);
+        i = (int64_t)m * a.Kp + k;
         if (a.active[i]) {
             const double r = __longlong_as_double((long long)a.res[i]);
             const double y = __longlong_as_double((long long)a.ymax[i]);
@@ -378,7 +381,7 @@ __global__ void converge_kernel(ConvergeArgs a) {
         }
     }
     // backups of this sweep: rows of the model for every pair that was active
-    const bool was = (i < n) && (still || a.pair_sweeps[i] == (int32_t)(a.counters[5] + 1));
+    const bool was = (t < n) && (still || a.pair_sweeps[i] == (int32_t)(a.counters[5] + 1));
     unsigned long long bk = was ? (unsigned long long)a.rows_per_model[m] : 0ull;
     unsigned long long sc = was ? (unsigned long long)a.states_per_model[m] : 0ull;
     unsigned long long cnt = still ? 1ull : 0ull;
