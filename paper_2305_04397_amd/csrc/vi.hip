@@ -345,22 +345,24 @@ void sweep(hipStream_t s, int prec, const Variant& v, int grid, int ktiles, cons
 // ---------------------------------------------------------------------------
 // convergence of (model, column) pairs and compaction of the active tiles
 // ---------------------------------------------------------------------------
-// One thread per (model, column).  counters: [0] active pairs (accumulating),
-// [1] active tiles, [2] active models, [3] active pairs after the last sweep,
-// [4] backups done, [5] sweeps done, [6] CSR bytes streamed, [7] state-columns
-// updated (each one value read and one written).
+// Threads stride over the (model, column) pairs of the models active in the
+// sweep just done.  counters: [0] active pairs (accumulating), [1] active
+// tiles, [2] active models, [3] active pairs after the last sweep, [4]
+// backups done, [5] sweeps done, [6] CSR bytes streamed, [7] state-columns
+// updated (each one value read and one written).  The three sums are reduced
+// in the workgroup and added with one atomic each: thousands of atomics on
+// the same counters would serialise in L2.
+constexpr int kConvergeBlocks = 256;
 template <class T>
-__global__ void converge_kernel(ConvergeArgs a) {
-    // threads walk the pairs of the models active in the sweep just done
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) converge_kernel(ConvergeArgs a) {
     const int64_t n = a.counters[2] * a.Kp;
-    bool still = false;
-    int m = 0;
-    int64_t i = 0;
-    if (t < n) {
-        m = a.act_models[t / a.Kp];
+    const int32_t next_sweep = (int32_t)(a.counters[5] + 1);
+    unsigned long long bk = 0, sc = 0, cnt = 0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const int m = a.act_models[t / a.Kp];
         const int k = (int)(t % a.Kp);
-        i = (int64_t)m * a.Kp + k;
+        const int64_t i = (int64_t)m * a.Kp + k;
+        bool still = false;
         if (a.active[i]) {
             const double r = __longlong_as_double((long long)a.res[i]);
             const double y = __longlong_as_double((long long)a.ymax[i]);
@@ -368,7 +370,7 @@ __global__ void converge_kernel(ConvergeArgs a) {
             if (r <= tol) {
                 a.active[i] = 0;
                 a.final_par[i] = (uint8_t)a.out_par;
-                a.pair_sweeps[i] = (int32_t)(a.counters[5] + 1);
+                a.pair_sweeps[i] = next_sweep;
                 const int32_t s0 = a.init[m];
                 a.c[(int64_t)k * a.M + m] =
                     s0 >= 0 ? (double)((const T*)a.x_out)[(int64_t)s0 * a.Kp + k] : 0.0;
@@ -379,28 +381,38 @@ __global__ void converge_kernel(ConvergeArgs a) {
             a.res[i] = 0ull;
             a.ymax[i] = 0ull;
         }
+        // backups of this sweep: rows of the model for every pair that was active
+        if (still || a.pair_sweeps[i] == next_sweep) {
+            bk += (unsigned long long)a.rows_per_model[m];
+            sc += (unsigned long long)a.states_per_model[m];
+        }
+        cnt += still ? 1ull : 0ull;
     }
-    // backups of this sweep: rows of the model for every pair that was active
-    const bool was = (t < n) && (still || a.pair_sweeps[i] == (int32_t)(a.counters[5] + 1));
-    unsigned long long bk = was ? (unsigned long long)a.rows_per_model[m] : 0ull;
-    unsigned long long sc = was ? (unsigned long long)a.states_per_model[m] : 0ull;
-    unsigned long long cnt = still ? 1ull : 0ull;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
         bk += __shfl_xor(bk, o, 64);
         sc += __shfl_xor(sc, o, 64);
         cnt += __shfl_xor(cnt, o, 64);
     }
+    __shared__ unsigned long long part[3][4];
+    const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        if (cnt) atomicAdd((unsigned long long*)&a.counters[0], cnt);
-        if (bk) atomicAdd((unsigned long long*)&a.counters[4], bk);
-        if (sc) atomicAdd((unsigned long long*)&a.counters[7], sc);
+        part[0][w] = cnt;
+        part[1][w] = bk;
+        part[2][w] = sc;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const unsigned long long v = part[threadIdx.x][0] + part[threadIdx.x][1] + part[threadIdx.x][2] +
+                                     part[threadIdx.x][3];
+        const int slot = threadIdx.x == 0 ? 0 : (threadIdx.x == 1 ? 4 : 7);
+        if (v) atomicAdd((unsigned long long*)&a.counters[slot], v);
     }
 }
 
 void converge(hipStream_t s, const ConvergeArgs& a) {
     const int64_t n = (int64_t)a.M * a.Kp;
-    const unsigned blocks = (unsigned)((n + 255) / 256);
+    const unsigned blocks = (unsigned)std::min<int64_t>(kConvergeBlocks, std::max<int64_t>(1, (n + 255) / 256));
     if (a.prec == MORAP_F32)
         hipLaunchKernelGGL(converge_kernel<float>, dim3(blocks), dim3(256), 0, s, a);
     else
