@@ -246,7 +246,9 @@ typedef struct {
  *   t_up[d], t_down[d]              final inner / outer closest points;
  *   lam[max_iter]                   convex weights of the points of Phi whose
  *                                   combination dominates t_up;
- *   trace_w / trace_r [max_iter][d] weight vector and point of every pass. */
+ *   trace_w / trace_r [max_iter][d] weight vector and point of every pass;
+ *   trace_f [max_iter][|J|]         assignment of every pass (the agent of
+ *                                   each task), for morap_synthesize. */
 typedef struct {
     int32_t verdict;         /* MORAP_FEASIBLE, MORAP_INFEASIBLE, MORAP_UNDECIDED */
     int32_t iterations;      /* Alg. 2 calls                                      */
@@ -260,6 +262,7 @@ typedef struct {
     double* lam;
     double* trace_w;
     double* trace_r;
+    int32_t* trace_f;
 } morap_query_result;
 
 /* Alg. 1 for threshold t[d] with norm matrix M[d][d] (symmetric positive
@@ -281,6 +284,27 @@ int morap_query(morap_ctx* ctx, const double* t, const double* M,
  * results[Q].  Errors: as morap_query. */
 int morap_query_batch(morap_ctx* ctx, const double* T, const double* W0, int Q, const double* M,
                       const morap_query_opts* opts, morap_query_result* results);
+
+/* Synthesis after Alg. 1 (Sec. 3.3, the random assignment and schedulers
+ * extracted from the loop): with v a convex weighting of the passes' points
+ * that dominates t_up (the query's lam), the random assignment picks the
+ * assignment f of pass i with probability v[i] and then runs, for every task
+ * j, the scheduler that pass computed for model (f(j), j).
+ * Inputs (host, caller-owned): the n passes' weight vectors W[n][d], their
+ * assignments F[n][|J|] (a query's trace_w, trace_f) and v[n] >= 0.  The
+ * passes with v > 0 are re-solved and their recorded assignments evaluated
+ * (morap_solve and morap_evaluate on exactly those columns), which reproduces
+ * their points and schedulers.  Outputs: n_picked, picked_out[n] (indices of
+ * the passes with v > 0, in order), r_out[n][d] (their points, first n_picked
+ * rows), matrix_out[|I|][|J|] (nullable): the probability that agent i
+ * serves task j, sum of v[i] over the picked passes with f(j) = i, divided by
+ * the sum of their v.  Afterwards morap_get_policy(q, j) returns the
+ * scheduler of task j in the q-th picked pass.  Errors: INVALID (no v > 0,
+ * an agent index out of range, negative v), and those of morap_solve and
+ * morap_evaluate. */
+int morap_synthesize(morap_ctx* ctx, const double* W, const int32_t* F, const double* v, int n,
+                     const morap_vi_opts* opts, int32_t* n_picked, int32_t* picked_out, double* r_out,
+                     double* matrix_out);
 
 /* Projections of Alg. 1 on their own (host, FP64).  Inner: x_out[d] in
  * down(conv Phi[m][d]) closest to t in the M-norm, lam_out[m] (nullable) its

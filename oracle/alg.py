@@ -154,6 +154,40 @@ def query(products, nI: int, nJ: int, t: np.ndarray, eps: float, eps_vi: float,
                        Phi=Phi, W=Ws, lam=lam, trace=trace)
 
 
+@dataclass
+class Synthesis:
+    picked: np.ndarray       # passes with v > 0
+    v: np.ndarray            # their weights, scaled to sum 1
+    F: np.ndarray            # [m, |J|] assignment of each picked pass
+    R: np.ndarray            # [m, d] its point
+    matrix: np.ndarray       # [|I|, |J|] probability that agent i serves task j
+    policies: list           # [m][|J|] scheduler of task j in pass m (model (F[m, j], j))
+
+
+def synthesis(products, nI: int, nJ: int, Ws, v, eps_vi: float, eps_eval: Optional[float] = None,
+              tau: float = 1e-9) -> Synthesis:
+    """The answer extracted after Alg. 1 (Sec. 3.3, end): v is a convex
+    weighting of the passes' points whose combination dominates t_up (the
+    inner projection's weights); pass i's assignment f_i is drawn with
+    probability v_i, and task j then runs the scheduler that pass computed for
+    model (f_i(j), j).  The passes with v_i > 0 are replayed with Alg. 2 on
+    their weight vectors; the convex combination of their assignments is the
+    random assignment (each task served with probability 1)."""
+    v = np.asarray(v, dtype=np.float64)
+    picked = np.nonzero(v > 0)[0]
+    vs = v[picked] / v[picked].sum()
+    F, R, pol = [], [], []
+    matrix = np.zeros((nI, nJ))
+    for q, i in enumerate(picked):
+        res = support(products, nI, nJ, np.asarray(Ws[i], dtype=np.float64), eps_vi, eps_eval, tau)
+        F.append(res.f)
+        R.append(res.r)
+        pol.append(res.policies)
+        for j in range(nJ):
+            matrix[res.f[j], j] += vs[q]
+    return Synthesis(picked=picked, v=vs, F=np.array(F), R=np.array(R), matrix=matrix, policies=pol)
+
+
 def verdict_of(t, t_up, Ws, Rs, M=None, tol_in=1e-9, tol_sep=1e-12) -> int:
     if geometry.mnorm(t - t_up, M) <= tol_in:
         return FEASIBLE

@@ -191,6 +191,51 @@ int morap_support(morap_ctx* ctx, const double* W, int K, const morap_vi_opts* o
     });
 }
 
+// Synthesis after Alg. 1 (Sec. 3.3): re-solve the weight vectors of the
+// passes with v > 0 and evaluate exactly their recorded assignments.
+int morap_synthesize(morap_ctx* ctx, const double* W, const int32_t* F, const double* v, int n,
+                     const morap_vi_opts* opts, int32_t* n_picked, int32_t* picked_out, double* r_out,
+                     double* matrix_out) {
+    return guarded(ctx, [&] {
+        MORAP_CHECK(W && F && v && opts && n_picked && picked_out && r_out && n >= 1, MORAP_E_INVALID,
+                    "bad synthesis arguments");
+        MORAP_CHECK(ctx->loaded, MORAP_E_STATE, "no models loaded");
+        const int nI = ctx->hm.nI, nJ = ctx->hm.nJ, d = nI + nJ;
+        std::vector<int32_t> pick;
+        double vsum = 0;
+        for (int i = 0; i < n; ++i) {
+            MORAP_CHECK(std::isfinite(v[i]) && v[i] >= 0, MORAP_E_INVALID, "v must be finite and >= 0");
+            if (v[i] > 0) {
+                pick.push_back(i);
+                vsum += v[i];
+            }
+        }
+        MORAP_CHECK(!pick.empty(), MORAP_E_INVALID, "no pass has v > 0");
+        const int m = (int)pick.size();
+        std::vector<double> Wp((size_t)m * d), C((size_t)m * nI * nJ);
+        std::vector<int32_t> Fp((size_t)m * nJ);
+        for (int q = 0; q < m; ++q) {
+            std::copy(W + (size_t)pick[q] * d, W + (size_t)(pick[q] + 1) * d, &Wp[(size_t)q * d]);
+            for (int j = 0; j < nJ; ++j) {
+                const int32_t a = F[(size_t)pick[q] * nJ + j];
+                MORAP_CHECK(a >= 0 && a < nI, MORAP_E_INVALID, "assignment entry out of range");
+                Fp[(size_t)q * nJ + j] = a;
+            }
+        }
+        Stats st;
+        solve(ctx, Wp.data(), m, *opts, C.data(), st);
+        evaluate(ctx, Fp.data(), m, *opts, r_out, st);
+        if (matrix_out) {
+            std::fill(matrix_out, matrix_out + (size_t)nI * nJ, 0.0);
+            for (int q = 0; q < m; ++q)
+                for (int j = 0; j < nJ; ++j)
+                    matrix_out[(size_t)Fp[(size_t)q * nJ + j] * nJ + j] += v[pick[q]] / vsum;
+        }
+        std::copy(pick.begin(), pick.end(), picked_out);
+        *n_picked = m;
+    });
+}
+
 int morap_get_stats(const morap_ctx* cctx, morap_stats* out) {
     morap_ctx* ctx = const_cast<morap_ctx*>(cctx);
     return guarded(ctx, [&] {

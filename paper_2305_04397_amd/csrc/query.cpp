@@ -36,6 +36,7 @@ double mnorm(const std::vector<double>& v, const double* M) {
 struct QState {
     std::vector<double> t, t_up, t_down, w, lam;
     std::vector<std::vector<double>> Phi, Ws;
+    std::vector<std::vector<int32_t>> Fs;   // assignment of every pass
     bool done = false, separated = false;
     int fallback = 0;
     double gap = 0;
@@ -133,6 +134,7 @@ void query_batch(morap_ctx* c, const double* T, const double* W0, int Q, const d
                 std::vector<double> w(W.begin() + (size_t)kk * d, W.begin() + (size_t)(kk + 1) * d);
                 s.Phi.push_back(r);
                 s.Ws.push_back(w);
+                s.Fs.emplace_back(A.begin() + (size_t)kk * nJ, A.begin() + (size_t)(kk + 1) * nJ);
                 double wr = 0, wt = 0;
                 for (int k = 0; k < d; ++k) {
                     wr += w[k] * r[k];
@@ -223,6 +225,7 @@ void query_batch(morap_ctx* c, const double* T, const double* W0, int Q, const d
             for (size_t i = 0; i < s.Phi.size(); ++i) {
                 if (r.trace_w) std::copy(s.Ws[i].begin(), s.Ws[i].end(), r.trace_w + i * d);
                 if (r.trace_r) std::copy(s.Phi[i].begin(), s.Phi[i].end(), r.trace_r + i * d);
+                if (r.trace_f) std::copy(s.Fs[i].begin(), s.Fs[i].end(), r.trace_f + i * nJ);
             }
         }
     }

@@ -89,7 +89,7 @@ class QueryOpts(C.Structure):
 class QueryResult(C.Structure):
     _fields_ = [("verdict", C.c_int32), ("iterations", C.c_int32), ("fallback", C.c_int32),
                 ("reserved", C.c_int32), ("gap", C.c_double), ("ms", C.c_double), ("backups", C.c_int64),
-                ("t_up", _p), ("t_down", _p), ("lam", _p), ("trace_w", _p), ("trace_r", _p)]
+                ("t_up", _p), ("t_down", _p), ("lam", _p), ("trace_w", _p), ("trace_r", _p), ("trace_f", _p)]
 
 
 class TrainOpts(C.Structure):
@@ -123,6 +123,7 @@ _sig("morap_reset_stats", C.c_int, _ctxp)
 _sig("morap_get_values", C.c_int, _ctxp, C.c_int, C.c_int, _p)
 _sig("morap_query", C.c_int, _ctxp, _p, _p, C.POINTER(QueryOpts), C.POINTER(QueryResult))
 _sig("morap_query_batch", C.c_int, _ctxp, _p, _p, C.c_int, _p, C.POINTER(QueryOpts), C.POINTER(QueryResult))
+_sig("morap_synthesize", C.c_int, _ctxp, _p, _p, _p, C.c_int, C.POINTER(ViOpts), _p, _p, _p, _p)
 _sig("morap_project_inner", C.c_int, _p, C.c_int, C.c_int, _p, _p, _p, _p)
 _sig("morap_project_outer", C.c_int, _p, _p, C.c_int, C.c_int, _p, _p, _p)
 _sig("morap_set_features", C.c_int, _ctxp, _p, C.c_int)
@@ -370,7 +371,8 @@ class Context:
         bufs = []
         for q in range(Q):
             b = {"t_up": np.zeros(d), "t_down": np.zeros(d), "lam": np.zeros(max_iter),
-                 "trace_w": np.zeros((max_iter, d)), "trace_r": np.zeros((max_iter, d))}
+                 "trace_w": np.zeros((max_iter, d)), "trace_r": np.zeros((max_iter, d)),
+                 "trace_f": np.zeros((max_iter, self.nJ), np.int32)}
             bufs.append(b)
             for k, v in b.items():
                 setattr(res[q], k, _ptr(v))
@@ -383,11 +385,34 @@ class Context:
             out.append({"verdict": res[q].verdict, "iterations": n, "fallback": res[q].fallback,
                         "gap": res[q].gap, "ms": res[q].ms, "backups": res[q].backups,
                         "t_up": bufs[q]["t_up"], "t_down": bufs[q]["t_down"], "lam": bufs[q]["lam"][:n],
-                        "W": bufs[q]["trace_w"][:n], "R": bufs[q]["trace_r"][:n]})
+                        "W": bufs[q]["trace_w"][:n], "R": bufs[q]["trace_r"][:n], "F": bufs[q]["trace_f"][:n]})
         return out
 
     def query(self, t, M=None, **kw) -> dict:
         return self.query_batch(np.atleast_2d(t), M, **kw)[0]
+
+    def synthesize(self, q: dict, opts: Options = Options()) -> dict:
+        """morap_synthesize on a traced query result (its W, F and lam): the
+        picked passes, their points, the random assignment matrix [|I|][|J|]
+        and the scheduler of every task in every picked pass (model
+        (F[pass][j], j))."""
+        W = _c(q["W"], np.float64)
+        F = _c(q["F"], np.int32)
+        v = _c(q["lam"], np.float64)
+        n = W.shape[0]
+        npk = C.c_int32(0)
+        picked = np.zeros(n, np.int32)
+        R = np.zeros((n, self.d))
+        mat = np.zeros((self.nI, self.nJ))
+        o = opts.to_c()
+        self._check(lib.morap_synthesize(self._h, _ptr(W), _ptr(F), _ptr(v), n, C.byref(o), C.byref(npk),
+                                         _ptr(picked), _ptr(R), _ptr(mat)), "morap_synthesize")
+        m = npk.value
+        picked = picked[:m]
+        sched = [[self.get_policy(k, j, self.model_info(int(F[p, j]) * self.nJ + j)["n_states"])
+                  for j in range(self.nJ)] for k, p in enumerate(picked)]
+        return {"picked": picked, "v": v[picked], "F": F[picked], "R": R[:m], "matrix": mat,
+                "schedulers": sched}
 
     # -- proposer ----------------------------------------------------------
     def set_features(self, phi):

@@ -352,3 +352,55 @@ def test_verification_only_stops_at_the_first_separation(ctx, morap):
     assert g["iterations"] == q.iterations <= full["iterations"]
     w, r = g["W"][-1], g["R"][-1]
     assert w @ r < w @ t
+
+
+@pytest.mark.parametrize("cfg", ["cfg1", "rep"])
+def test_synthesis_matches_oracle(ctx, morap, cfg):
+    """morap_synthesize on traced queries: the picked passes reproduce the
+    query's points and assignments, every returned scheduler attains its
+    point under an exact linear solve of the oracle, the assignment matrix is
+    the v-weighted sum of the picked assignments with unit columns, and on a
+    feasible threshold the random assignment meets t in expectation."""
+    if cfg == "cfg1":
+        wl = make_workload(1)
+    else:
+        wl = tiny_workload(5, 2, 3, width=3, height=3, kinds=("reach", "avoid"), k=1, p_slip=0.2)
+    prods = _load(ctx, wl)
+    nI, nJ = wl.n_agents, wl.n_tasks
+    d = nI + nJ
+    o = morap.Options(eps_vi=1e-10, precision="f64")
+    rng = np.random.default_rng(4)
+    pts = [alg.support(prods, nI, nJ, rng.dirichlet(np.ones(d)), 1e-10).r for _ in range(4)]
+    mix = sum(l * p for l, p in zip(rng.dirichlet(np.ones(4)), pts))
+    feasible_t = mix - 0.02 * np.abs(mix)
+    infeasible_t = mix + 0.05 * np.abs(mix)
+    infeasible_t[nI:] = np.minimum(infeasible_t[nI:], 1.0)
+    for t, feasible in ((feasible_t, True), (infeasible_t, False)):
+        g = ctx.query(t, eps=1e-6, max_iter=200, opts=o, trace=True)
+        syn = ctx.synthesize(g, o)
+        picked = syn["picked"]
+        assert len(picked) >= 1 and (g["lam"][picked] > 0).all()
+        assert (g["lam"][np.setdiff1d(np.arange(g["iterations"]), picked)] == 0).all()
+        assert np.array_equal(syn["F"], g["F"][picked])
+        assert np.abs(syn["R"] - g["R"][picked]).max() <= 1e-12 * max(1.0, np.abs(g["R"]).max())
+        mat = np.zeros((nI, nJ))
+        v = syn["v"] / syn["v"].sum()
+        for vq, f in zip(v, syn["F"]):
+            mat[f, np.arange(nJ)] += vq
+        assert np.abs(syn["matrix"] - mat).max() <= 1e-12
+        assert np.allclose(syn["matrix"].sum(axis=0), 1.0)
+        expect = np.zeros(d)
+        for vq, f, r, sch in zip(v, syn["F"], syn["R"], syn["schedulers"]):
+            rx = np.zeros(d)
+            for j in range(nJ):
+                p = prods[f[j] * nJ + j]
+                ex = vi.evaluate_exact(p, sch[j])
+                if p.init >= 0:
+                    rx[f[j]] += ex[p.init, 0]
+                    rx[nI + j] = ex[p.init, 1]
+            assert np.abs(rx - r).max() <= 1e-6 * max(1.0, np.abs(r).max())
+            expect += vq * rx
+        assert (expect >= g["t_up"] - 1e-6 * np.maximum(1.0, np.abs(g["t_up"]))).all()
+        if feasible:
+            assert g["verdict"] == morap.FEASIBLE
+            assert (expect >= t - 1e-6 * np.maximum(1.0, np.abs(t))).all()

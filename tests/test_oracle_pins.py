@@ -664,3 +664,51 @@ def test_policy_from_tiny_weights_is_the_scaled_one():
     y, _ = vi.value_iteration(prod, 1.0, 0.0, 1e-12)
     cost = vi.evaluate_exact(prod, mu_tiny)[prod.init, 0]
     assert cost == pytest.approx(y[prod.init, 0], abs=1e-9)
+
+
+# --------------------------------------------------------------------------
+# synthesis after Alg. 1 (Sec. 3.3, end)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("cfg", ["cfg1", "rep"])
+def test_synthesis_meets_feasible_thresholds(cfg):
+    """On feasible thresholds the random assignment and its schedulers meet t
+    in expectation (Def. MORAP), with every scheduler's values taken from an
+    exact linear solve, not from the loop; the assignment matrix is doubly
+    stochastic for |I| = |J| and has unit columns and rows of at most
+    ceil(|J|/|I|) tasks with agent re-use."""
+    if cfg == "cfg1":
+        wl = make_workload(1)
+    else:
+        wl = tiny_workload(5, 2, 3, width=3, height=3, kinds=("reach", "avoid"), k=1, p_slip=0.2)
+    prods = product.build_all(wl)
+    nI, nJ = wl.n_agents, wl.n_tasks
+    d = nI + nJ
+    rng = np.random.default_rng(4)
+    # thresholds below convex combinations of supporting points: feasible
+    pts = [alg.support(prods, nI, nJ, rng.dirichlet(np.ones(d)), 1e-10).r for _ in range(4)]
+    checked = 0
+    for _ in range(3):
+        lam = rng.dirichlet(np.ones(len(pts)))
+        t = sum(l * p for l, p in zip(lam, pts)) - 0.02 * np.abs(sum(l * p for l, p in zip(lam, pts)))
+        q = alg.query(prods, nI, nJ, t, 1e-9, 1e-10, max_iter=200)
+        assert q.verdict == alg.FEASIBLE
+        syn = alg.synthesis(prods, nI, nJ, q.W, q.lam, 1e-10)
+        expect = np.zeros(d)
+        for vq, f, pol in zip(syn.v, syn.F, syn.policies):
+            r = np.zeros(d)
+            for j in range(nJ):
+                ex = vi.evaluate_exact(prods[f[j] * nJ + j], pol[j])
+                init = prods[f[j] * nJ + j].init
+                if init >= 0:
+                    r[f[j]] += ex[init, 0]
+                    r[nI + j] = ex[init, 1]
+            expect += vq * r
+        assert (expect >= t - 1e-7).all()
+        assert np.allclose(syn.matrix.sum(axis=0), 1.0)
+        cap = -(-nJ // nI)
+        assert (syn.matrix.sum(axis=1) <= cap + 1e-12).all()
+        if nI == nJ:
+            assert np.allclose(syn.matrix.sum(axis=1), 1.0)
+        checked += 1
+    assert checked == 3
