@@ -85,11 +85,15 @@ def measured_traffic(kernel: str):
     src = [l.split(":", 1)[1].strip() for l in lines if l.startswith("kernel_source_sha256:")]
     if not src or src[0] != sources_hash():
         return None
+    # the kernel the solves ran (most dispatches), not an autotuner candidate
+    # of the same name prefix
+    best = None
     for l in lines:
         parts = l.split(",", 4)
-        if len(parts) == 5 and parts[4].startswith(kernel):
-            return float(parts[3])
-    return None
+        if len(parts) == 5 and parts[4].startswith(kernel) and parts[0].isdigit():
+            if best is None or int(parts[0]) > best[0]:
+                best = (int(parts[0]), float(parts[3]))
+    return None if best is None else best[1]
 
 
 def thresholds(rng, front: np.ndarray, n: int, nI: int) -> np.ndarray:
