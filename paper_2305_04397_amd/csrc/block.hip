@@ -498,52 +498,87 @@ __global__ void __launch_bounds__(256) eval_block_kernel(InstArgs a, const int32
                                                          const uint8_t* active, const double* __restrict__ x_in,
                                                          double* __restrict__ x_out, unsigned long long* res,
                                                          int32_t zero_row) {
-    const int t = blockIdx.x;
-    if (t >= a.n_tiles) return;
-    const int inst = a.inst_tiles[2 * t];
-    const bool a0 = active[2 * inst] != 0, a1 = active[2 * inst + 1] != 0;
-    double r0 = 0.0, r1 = 0.0;
-    if (a0 || a1) {
-        const int ls = a.inst_tiles[2 * t + 1] + threadIdx.x;
-        const int m = a.inst_model[inst];
-        const int sb = a.state_base[m];
-        if (ls < a.state_base[m + 1] - sb) {
-            const int64_t ib = a.inst_base[inst];
-            const int4 q0 = *reinterpret_cast<const int4*>(rec + (int64_t)(sb + ls) * 8);
-            const int4 q1 = *reinterpret_cast<const int4*>(rec + (int64_t)(sb + ls) * 8 + 4);
-            const int own = q1.w - sb;
-            // the chosen row is the mu-th enabled action
-            uint32_t am = (uint32_t)(q1.z >> 8) & 31u;
-            for (int k = mu[ib + own]; k > 0; --k) am &= am - 1;
-            const int act = __builtin_ctz(am);
-            const double* B = ablk + (int64_t)q1.y * BLK;
-            const int accm = q1.z & 31;
-            const int sc[NSLOT] = {q0.x, q0.y, q0.z, q0.w, q1.x};
-            double c0 = B[25 + act], c1 = 0.0;
-#pragma unroll
-            for (int d = 0; d < NSLOT; ++d)
-                if (nz<PAT>(0, d) || nz<PAT>(1, d) || nz<PAT>(2, d) || nz<PAT>(3, d) || nz<PAT>(4, d))
-                    if ((accm >> d) & 1) c1 += B[act * NSLOT + d];
-#pragma unroll
-            for (int d = 0; d < NSLOT; ++d) {
-                const double p = B[act * NSLOT + d];
-                if (sc[d] != zero_row) {
-                    const double2 v = reinterpret_cast<const double2*>(x_in)[ib + (sc[d] - sb)];
-                    c0 = fma(p, v.x, c0);
-                    c1 = fma(p, v.y, c1);
-                }
+    // each wave walks a contiguous run of quarter tiles (64 states of one
+    // instance) in a grid of resident size: one short-lived workgroup per
+    // tile would leave most of each CU idle behind the workgroup dispatcher.
+    // Residuals are kept per instance and flushed when the instance changes.
+    const int n_units = a.n_tiles * 4;
+    const int n_waves = gridDim.x * 4;
+    const int per = (n_units + n_waves - 1) / n_waves;
+    const int u0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * per;
+    const int u1 = min(n_units, u0 + per);
+    int cur = -1;
+    double m0 = 0.0, m1 = 0.0;
+    for (int u = u0; u < u1; ++u) {
+        const int t = u >> 2;
+        const int inst = a.inst_tiles[2 * t];
+        if (inst != cur) {
+            if (cur >= 0 && (threadIdx.x & 63) == 0) {
+                max_flush(&res[2 * cur], m0);
+                max_flush(&res[2 * cur + 1], m1);
             }
-            const double2 old = reinterpret_cast<const double2*>(x_in)[ib + own];
-            if (a0) { x_out[2 * (ib + own)] = c0; r0 = fabs(c0 - old.x); }
-            if (a1) { x_out[2 * (ib + own) + 1] = c1; r1 = fabs(c1 - old.y); }
+            cur = inst;
+            m0 = m1 = 0.0;
         }
+        const bool a0 = active[2 * inst] != 0, a1 = active[2 * inst + 1] != 0;
+        double r0 = 0.0, r1 = 0.0;
+        if (a0 || a1) {
+            const int ls = a.inst_tiles[2 * t + 1] + (u & 3) * 64 + (threadIdx.x & 63);
+            const int m = a.inst_model[inst];
+            const int sb = a.state_base[m];
+            if (ls < a.state_base[m + 1] - sb) {
+                const int64_t ib = a.inst_base[inst];
+                const int4 q0 = *reinterpret_cast<const int4*>(rec + (int64_t)(sb + ls) * 8);
+                const int4 q1 = *reinterpret_cast<const int4*>(rec + (int64_t)(sb + ls) * 8 + 4);
+                const int own = q1.w - sb;
+                // the chosen row is the mu-th enabled action
+                uint32_t am = (uint32_t)(q1.z >> 8) & 31u;
+                for (int k = mu[ib + own]; k > 0; --k) am &= am - 1;
+                const int act = __builtin_ctz(am);
+                const double* B = ablk + (int64_t)q1.y * BLK;
+                const int accm = q1.z & 31;
+                const int sc[NSLOT] = {q0.x, q0.y, q0.z, q0.w, q1.x};
+                double c0 = B[25 + act], c1 = 0.0;
+#pragma unroll
+                for (int d = 0; d < NSLOT; ++d)
+                    if (nz<PAT>(0, d) || nz<PAT>(1, d) || nz<PAT>(2, d) || nz<PAT>(3, d) || nz<PAT>(4, d))
+                        if ((accm >> d) & 1) c1 += B[act * NSLOT + d];
+#pragma unroll
+                for (int d = 0; d < NSLOT; ++d) {
+                    const double p = B[act * NSLOT + d];
+                    if (sc[d] != zero_row) {
+                        const double2 v = reinterpret_cast<const double2*>(x_in)[ib + (sc[d] - sb)];
+                        c0 = fma(p, v.x, c0);
+                        c1 = fma(p, v.y, c1);
+                    }
+                }
+                const double2 old = reinterpret_cast<const double2*>(x_in)[ib + own];
+                if (a0) { x_out[2 * (ib + own)] = c0; r0 = fabs(c0 - old.x); }
+                if (a1) { x_out[2 * (ib + own) + 1] = c1; r1 = fabs(c1 - old.y); }
+            }
+        }
+        m0 = fmax(m0, wave_max(r0));
+        m1 = fmax(m1, wave_max(r1));
     }
-    r0 = wave_max(r0);
-    r1 = wave_max(r1);
-    if ((threadIdx.x & 63) == 0) {
-        max_flush(&res[2 * inst], r0);
-        max_flush(&res[2 * inst + 1], r1);
+    if (cur >= 0 && (threadIdx.x & 63) == 0) {
+        max_flush(&res[2 * cur], m0);
+        max_flush(&res[2 * cur + 1], m1);
     }
+}
+
+// Workgroups of 256 threads that stay resident per CU (occupancy API, once
+// per kernel): the striding evaluation kernel is launched with exactly as
+// many as fit, so no workgroup waits for a second round.
+template <class F>
+static int resident_per_cu(F* kern) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, 256, 0) != hipSuccess) n = 1;
+    return std::max(1, n);
+}
+template <uint32_t PAT>
+static int eval_groups(const InstArgs& a) {
+    static const int per_cu = resident_per_cu(eval_block_kernel<PAT>);
+    return std::min(a.n_tiles, std::max(1, a.cus) * per_cu);
 }
 
 void eval_block_sweep(hipStream_t s, const InstArgs& a, const int32_t* rec, const double* ablk, const int8_t* mu,
@@ -551,11 +586,11 @@ void eval_block_sweep(hipStream_t s, const InstArgs& a, const int32_t* rec, cons
                       int32_t zero_row, uint32_t pattern) {
     if (a.n_tiles <= 0) return;
     if (pattern_for(pattern) == PAT_GRID)
-        hipLaunchKernelGGL(eval_block_kernel<PAT_GRID>, dim3(a.n_tiles), dim3(256), 0, s, a, rec, ablk, mu, active,
-                           x_in, x_out, res, zero_row);
+        hipLaunchKernelGGL(eval_block_kernel<PAT_GRID>, dim3(eval_groups<PAT_GRID>(a)), dim3(256), 0, s, a, rec,
+                           ablk, mu, active, x_in, x_out, res, zero_row);
     else
-        hipLaunchKernelGGL(eval_block_kernel<PAT_DENSE>, dim3(a.n_tiles), dim3(256), 0, s, a, rec, ablk, mu,
-                           active, x_in, x_out, res, zero_row);
+        hipLaunchKernelGGL(eval_block_kernel<PAT_DENSE>, dim3(eval_groups<PAT_DENSE>(a)), dim3(256), 0, s, a, rec,
+                           ablk, mu, active, x_in, x_out, res, zero_row);
     MORAP_HIP(hipGetLastError());
 }
 

@@ -380,6 +380,7 @@ struct InstArgs {
     const double* rew;
     const uint8_t* to_done;
     const int32_t* init;
+    int cus;                       // compute units (resident-sized grids of the striding kernels)
 };
 void gather_columns(hipStream_t s, const InstArgs& a, int prec, const void* x0, const void* x1,
                     const uint8_t* final_par, int Kp, double* xi);

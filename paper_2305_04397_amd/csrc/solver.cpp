@@ -520,6 +520,7 @@ static k::InstArgs inst_args(morap_ctx* c, int n_tiles, int n_inst) {
     a.rew = c->d_rew64.as<double>();
     a.to_done = c->d_to_done.as<uint8_t>();
     a.init = c->d_init.as<int32_t>();
+    a.cus = c->prop.multiProcessorCount;
     return a;
 }
 
