@@ -11,8 +11,12 @@
 #include "common.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <exception>
+#include <mutex>
+#include <thread>
 
 namespace morap {
 
@@ -43,6 +47,33 @@ struct QState {
     int64_t backups = 0;
     double ms = 0;
 };
+
+// f(i) for i < n on up to 16 host threads; the first exception is rethrown.
+template <class F>
+void parallel_for(int n, F f) {
+    const int nt = std::max(1, std::min<int>(n, (int)std::min(16u, std::thread::hardware_concurrency())));
+    if (nt == 1) {
+        for (int i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::atomic<int> next{0};
+    std::exception_ptr err;
+    std::mutex mu;
+    auto worker = [&] {
+        for (int i; (i = next++) < n;) {
+            try {
+                f(i);
+            } catch (...) {
+                std::lock_guard<std::mutex> g(mu);
+                if (!err) err = std::current_exception();
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) th.emplace_back(worker);
+    for (auto& t : th) t.join();
+    if (err) std::rethrow_exception(err);
+}
 
 }  // namespace
 
@@ -126,7 +157,9 @@ void query_batch(morap_ctx* c, const double* T, const double* W0, int Q, const d
             assign_columns(nI, nJ, C.data(), K, A.data());
             evaluate(c, A.data(), K, vo, R.data(), st);
             const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-            for (int kk = 0; kk < K; ++kk) {
+            // the geometry of each query (both projections, the stop test and
+            // the next weight vector) on host threads: queries share nothing
+            parallel_for(K, [&](int kk) {
                 QState& s = qs[act[b + kk]];
                 s.backups += st.backups / K;
                 s.ms += ms / K;
@@ -158,7 +191,7 @@ void query_batch(morap_ctx* c, const double* T, const double* W0, int Q, const d
                 s.gap = mnorm(diff, M);
                 if (s.separated || s.gap <= o.eps) {
                     s.done = true;
-                    continue;
+                    return;
                 }
                 // w = M (t - t_up) / ||M (t - t_up)||_1.  Components at or
                 // below 1e-12 max(1, ||t||_inf) are rounding noise of the
@@ -184,10 +217,10 @@ void query_batch(morap_ctx* c, const double* T, const double* W0, int Q, const d
                 }
                 if (!(sum > 0)) {
                     s.done = true;   // t_up == t up to rounding
-                    continue;
+                    return;
                 }
                 for (int k = 0; k < d; ++k) s.w[k] = mv[k] / sum;
-            }
+            });
         }
     }
     const double total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
