@@ -676,7 +676,6 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
                                  c->d_iwp.as<double>(), iact, even ? x0 : x1, even ? x1 : x0, ires, (int32_t)c->S,
                                  c->hm.blk_pattern);
                 if (o.time_kernels) MORAP_HIP(hipEventRecord(ev.back().second, s));
-                k::fill_i64(s, dctr, 0, 1);
                 k::inst_converge(s, n, ires, iact, ipar, even ? 1 : 0, o.eps_vi, dctr);
             }
             vsweeps += chunk;
@@ -797,7 +796,6 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
                                     even ? xe0 : xe1, even ? xe1 : xe0, ires, (int32_t)c->S, c->hm.blk_pattern);
             else
                 k::eval_sweep(s, ae, mu, iact, even ? xe0 : xe1, even ? xe1 : xe0, ires);
-            k::fill_i64(s, dctr, 0, 1);
             k::inst_converge(s, 2 * n, ires, iact, ipar, even ? 1 : 0, o.eps_eval, dctr);
         }
         esweeps += chunk;

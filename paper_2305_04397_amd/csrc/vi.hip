@@ -563,30 +563,44 @@ void gather_columns(hipStream_t s, const InstArgs& a, int prec, const void* x0, 
     MORAP_HIP(hipGetLastError());
 }
 
-__global__ void inst_converge_kernel(int n, unsigned long long* res, uint8_t* active, uint8_t* par,
-                                     int out_par, double eps, int64_t* counter) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// One workgroup: the stop test of every entry (entry i stops when res[i] <=
+// eps; its final buffer parity is recorded), residuals cleared, and the
+// number still running written to *counter (no separate clearing launch).
+__global__ void __launch_bounds__(1024) inst_converge_kernel(int n, unsigned long long* res, uint8_t* active,
+                                                             uint8_t* par, int out_par, double eps,
+                                                             int64_t* counter) {
     unsigned long long still = 0;
-    if (i < n && active[i]) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        if (!active[i]) continue;
         const double r = __longlong_as_double((long long)res[i]);
         if (r <= eps) {
             active[i] = 0;
             par[i] = (uint8_t)out_par;
         } else {
-            still = 1;
+            ++still;
         }
         res[i] = 0ull;
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) still += __shfl_xor(still, o, 64);
-    if ((threadIdx.x & 63) == 0 && still) atomicAdd((unsigned long long*)counter, still);
+    __shared__ unsigned long long part[16];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = still;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long total = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) total += part[w];
+        *counter = (int64_t)total;
+    }
 }
 
 void inst_converge(hipStream_t s, int n, unsigned long long* res, uint8_t* active, uint8_t* par,
                    int out_par, double eps, int64_t* counter) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(inst_converge_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, res, active, par,
-                       out_par, eps, counter);
+    if (n <= 0) {
+        fill_i64(s, counter, 0, 1);
+        return;
+    }
+    hipLaunchKernelGGL(inst_converge_kernel, dim3(1), dim3(1024), 0, s, n, res, active, par, out_par, eps,
+                       counter);
     MORAP_HIP(hipGetLastError());
 }
 
