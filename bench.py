@@ -339,7 +339,10 @@ def main():
                                "feasible": verdicts.count(morap.FEASIBLE),
                                "infeasible": verdicts.count(morap.INFEASIBLE),
                                "undecided": verdicts.count(morap.UNDECIDED)},
-                     "learned": None}
+                     "learned": None,
+                     "learned_note": "no proposer is trained for this workload (d = 150): its training "
+                                     "tuples need plain-loop queries of many passes each; the learned-vs-"
+                                     "plain comparison is the 'proposer' object (10x20, d = 30)"}
         log(f"queries: {len(res)} in {wq:.0f} ms, passes mean {its.mean():.1f}")
 
     ctx.close()

@@ -404,3 +404,20 @@ def test_synthesis_matches_oracle(ctx, morap, cfg):
         if feasible:
             assert g["verdict"] == morap.FEASIBLE
             assert (expect >= t - 1e-6 * np.maximum(1.0, np.abs(t))).all()
+
+
+def test_synthesis_rejects_bad_inputs(ctx, morap):
+    """morap_synthesize: no pass with v > 0, a negative v and an agent index out
+    of range are INVALID; a valid call after them still works."""
+    wl = make_workload(1)
+    _load(ctx, wl)
+    o = morap.Options(eps_vi=1e-8, precision="f64")
+    g = ctx.query(np.array([-40.0, -40.0, 0.8, 0.8]), eps=1e-6, max_iter=64, opts=o, trace=True)
+    for bad in ({**g, "lam": np.zeros_like(g["lam"])},
+                {**g, "lam": np.where(np.arange(len(g["lam"])) == 0, -1.0, g["lam"])},
+                {**g, "F": np.full_like(g["F"], 7)}):
+        with pytest.raises(morap.MorapError) as e:
+            ctx.synthesize(bad, o)
+        assert e.value.code == morap.E_INVALID
+    syn = ctx.synthesize(g, o)
+    assert np.allclose(syn["matrix"].sum(axis=0), 1.0)
