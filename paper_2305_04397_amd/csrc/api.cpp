@@ -13,6 +13,7 @@ morap_ctx::~morap_ctx() {
         if (chunk_exec[g]) (void)hipGraphExecDestroy(chunk_exec[g]);
         if (chunk_graph[g]) (void)hipGraphDestroy(chunk_graph[g]);
     }
+    for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
     if (prop_mlp) proposer_destroy(prop_mlp);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
 }

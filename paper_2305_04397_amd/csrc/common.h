@@ -202,6 +202,7 @@ struct morap_ctx {
     morap::PinnedBuf h_log;                         // per-launch tile counts (sweep log)
     std::vector<double> W;                          // [K][d] of the last solve
     int last_variant = 0;
+    std::vector<hipEvent_t> event_pool;             // reusable per-launch timing events
     hipGraph_t chunk_graph[2] = {nullptr, nullptr}; // captured chunks of sweeps (main, FP64 refine)
     hipGraphExec_t chunk_exec[2] = {nullptr, nullptr};
     std::string graph_key[2];

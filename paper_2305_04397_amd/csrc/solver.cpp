@@ -192,6 +192,23 @@ static int persistent_grid(morap_ctx* c, int prec, const Variant& v) {
 
 using EventPairs = std::vector<std::pair<hipEvent_t, hipEvent_t>>;
 
+// per-launch timing events come from a pool: creating and destroying two
+// events per sweep costs host time on every launch
+static hipEvent_t take_event(morap_ctx* c) {
+    if (!c->event_pool.empty()) {
+        const hipEvent_t e = c->event_pool.back();
+        c->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    MORAP_HIP(hipEventCreate(&e));
+    return e;
+}
+static void give_events(morap_ctx* c, const std::pair<hipEvent_t, hipEvent_t>& e) {
+    c->event_pool.push_back(e.first);
+    c->event_pool.push_back(e.second);
+}
+
 // Optional per-launch log (environment variable MORAP_SWEEP_LOG = file path):
 // the autotuner's timings and, for solves run with time_kernels, one line per
 // sweep launch with its active tile count and duration.
@@ -217,9 +234,7 @@ static void enqueue_chunk(morap_ctx* c, ValueSet& vs, const uint8_t* mask, const
                 MORAP_HIP(hipMemcpyAsync(c->h_log.as<int64_t>() + ev->size(), c->d_counters.as<int64_t>() + 1, 8,
                                          hipMemcpyDeviceToHost, c->stream));
             }
-            ev->emplace_back();
-            MORAP_HIP(hipEventCreate(&ev->back().first));
-            MORAP_HIP(hipEventCreate(&ev->back().second));
+            ev->emplace_back(take_event(c), take_event(c));
             MORAP_HIP(hipEventRecord(ev->back().first, c->stream));
         }
         if (v.kind == SWEEP_BLOCK)
@@ -367,8 +382,7 @@ static void run_vi(morap_ctx* c, int g, ValueSet& vs, const uint8_t* mask, const
                 st.ms_sweep_kernel += t;
                 st.sweep_launches += 1;
             }
-            (void)hipEventDestroy(e.first);
-            (void)hipEventDestroy(e.second);
+            give_events(c, e);
         }
         ev.clear();
     };
@@ -667,9 +681,7 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
             for (int i = 0; i < chunk; ++i) {
                 const bool even = (i & 1) == 0;
                 if (o.time_kernels) {
-                    ev.emplace_back();
-                    MORAP_HIP(hipEventCreate(&ev.back().first));
-                    MORAP_HIP(hipEventCreate(&ev.back().second));
+                    ev.emplace_back(take_event(c), take_event(c));
                     MORAP_HIP(hipEventRecord(ev.back().first, s));
                 }
                 k::inst_vi_sweep(s, av, c->d_blk_rec.as<int32_t>(), c->d_blk64.as<double>(), c->d_iwc.as<double>(),
@@ -687,8 +699,7 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
                 MORAP_HIP(hipEventElapsedTime(&t, e.first, e.second));
                 st.ms_sweep_kernel_refine += t;
                 st.sweep_launches_refine += 1;
-                (void)hipEventDestroy(e.first);
-                (void)hipEventDestroy(e.second);
+                give_events(c, e);
             }
             ev.clear();
             if (h[0] == 0) break;
