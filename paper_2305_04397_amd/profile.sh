@@ -4,9 +4,9 @@
 # pass each for FETCH_SIZE and WRITE_SIZE, then the HBM bytes per sweep launch
 # (traffic.txt).  The model upload's FP64->FP32 conversion kernels (a plain
 # stream of known size: 8 bytes read, 4 written per element) calibrate the
-# byte counters.  Output under $1 (default gpurun_out/prof).
+# byte counters.  Output under $1 (default ./profile_out).
 set -o pipefail
-OUT=${1:-gpurun_out/prof}
+OUT=${1:-profile_out}
 REPO=$(cd "$(dirname "$0")/.." && pwd)
 mkdir -p "$OUT"
 OUT=$(cd "$OUT" && pwd)

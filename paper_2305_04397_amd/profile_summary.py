@@ -110,10 +110,11 @@ def traffic(fetch_dir: str, write_dir: str, bench_json: str, out_path: str) -> s
     values = N + 2 * R
     f_scale = 8.0 * values / (fetch[cal][1] * 1024.0)
     w_scale = 4.0 * values / (write[cal][1] * 1024.0)
+    rel = lambda q: os.path.relpath(q)   # paths as seen from the repository root
     rows = [f"# HBM traffic of the sweep kernels: {cfg['workload']}",
-            "# command: bash paper_2305_04397_amd/profile.sh gpurun_out/prof, then",
-            "#   python3 -m paper_2305_04397_amd.profile_summary traffic gpurun_out/prof/fetch gpurun_out/prof/write "
-            "gpurun_out/prof/trace.json <this file>",
+            f"# command: bash paper_2305_04397_amd/profile.sh {rel(os.path.dirname(os.path.abspath(fetch_dir)))}, then",
+            f"#   python3 -m paper_2305_04397_amd.profile_summary traffic {rel(fetch_dir)} {rel(write_dir)} "
+            f"{rel(bench_json)} <this file>",
             f"calibration_kernel: {cal} (values converted: N + 2R = {values})",
             f"fetch_scale: {f_scale:.4f}",
             f"write_scale: {w_scale:.4f}",
