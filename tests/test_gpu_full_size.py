@@ -93,3 +93,46 @@ def test_full_size_support_sampled(full):
         assert r[k][nI + j] == pytest.approx(vp, rel=1e-9, abs=4 * eps)
         checked += 1
     assert checked >= 3
+
+
+def test_full_size_query_geometry_replay(full):
+    """Alg. 1 at full size (d = 150, lockstep queries inside and outside the
+    achievable set): the oracle's projections, run on the device's own trace
+    of weight vectors and points, reproduce every pass's next weight vector,
+    the final t_up and t_down and the verdict.  The points themselves are
+    the support step's, whose sampled parity is checked above."""
+    from oracle import geometry
+    morap, ctx, wl = full
+    nI, nJ = wl.n_agents, wl.n_tasks
+    d = nI + nJ
+    rng = np.random.default_rng(2)
+    opts = morap.Options(eps_vi=1e-6, precision="f32")
+    front, _, _, _ = ctx.support(dirichlet_weights(rng, 4, d), opts)
+    T = []
+    for k in range(8):
+        # above the front in every objective (separated, outer projections)
+        # or below it (inside, inner projections only)
+        u = front[k % 4]
+        t = u + rng.uniform(0.0, 0.3, d) * np.abs(u) * (1 if k % 2 else -1)
+        t[nI:] = np.clip(t[nI:], 0.0, 1.0)
+        T.append(t)
+    res = ctx.query_batch(np.array(T), eps=0.01, max_iter=6, opts=opts, trace=True)
+    separated = 0
+    for t, q in zip(T, res):
+        n = q["iterations"]
+        W, R = q["W"], q["R"]
+        scale = max(1.0, np.abs(t).max())
+        t_down = t.copy()
+        for i in range(n):
+            if W[i] @ R[i] < W[i] @ t_down:
+                t_down = geometry.project_outer(W[:i + 1], R[:i + 1], t)
+            t_up, _ = geometry.project_inner(R[:i + 1], t)
+            if i + 1 < n:
+                w = geometry.weight_from(t, t_up)
+                assert w is not None
+                assert np.abs(w - W[i + 1]).max() <= 1e-6, (i, np.abs(w - W[i + 1]).max())
+        assert np.abs(t_up - q["t_up"]).max() <= 1e-6 * scale
+        assert np.abs(t_down - q["t_down"]).max() <= 1e-6 * scale
+        assert q["verdict"] == alg.verdict_of(t, t_up, W, R)
+        separated += int(np.any(np.einsum("ij,ij->i", W, R) < W @ t))
+    assert separated >= 2
