@@ -235,7 +235,7 @@ def main():
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--query-max-iter", type=int, default=16,
                     help="Alg. 2 passes allowed per query in the ms-per-query measurement")
-    ap.add_argument("--proposer-queries", type=int, default=256,
+    ap.add_argument("--proposer-queries", type=int, default=1000,
                     help="unseen 10x20 queries for the learned-vs-plain comparison (0 = skip)")
     ap.add_argument("--proposer-train", type=int, default=512, help="training queries per 10x20 variant")
     ap.add_argument("--proposer-variants", type=int, default=4)
