@@ -214,8 +214,13 @@ def proposer_eval(args) -> dict:
         out[name] = {"queries": len(r), "wall_ms": round(ms, 1), "ms_per_query": round(ms / len(r), 3),
                      "passes_mean": round(float(its.mean()), 3), "passes_max": int(its.max())}
         log(f"proposer eval {name}: {ms / len(r):.2f} ms/query, passes mean {its.mean():.2f}")
-    agree = sum(p["verdict"] == q["verdict"] for p, q in zip(res["plain"], res["learned"]))
-    out["verdict_agreement"] = f"{agree}/{len(eval_T)}"
+    # verdicts are compared where both loops decided; a threshold within eps
+    # of the front may end UNDECIDED in one loop and decided in the other
+    decided = [(p, q) for p, q in zip(res["plain"], res["learned"])
+               if p["verdict"] != morap.UNDECIDED and q["verdict"] != morap.UNDECIDED]
+    agree = sum(p["verdict"] == q["verdict"] for p, q in decided)
+    out["verdict_agreement"] = f"{agree}/{len(decided)}"
+    out["undecided_in_either"] = len(eval_T) - len(decided)
     out["fallbacks"] = int(sum(q["fallback"] for q in res["learned"]))
     ctx.close()
     return out
