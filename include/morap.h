@@ -171,7 +171,7 @@ typedef struct {
     double  bytes;          /* algorithmic bytes moved by the sweep kernel          */
     double  ms_vi, ms_eval, ms_total;   /* device / host wall time of the phases   */
     double  ms_sweep_kernel;/* summed sweep-kernel time (time_kernels = 1)          */
-    int64_t sweep_launches; /* sweep kernels timed                                  */
+    int64_t sweep_launches; /* sweep kernels timed (every 4th launch)               */
     double  bytes_refine;   /* the three fields above for the FP64 re-solve of the   */
     double  ms_sweep_kernel_refine; /* assigned pairs after an FP32 solve           */
     int64_t sweep_launches_refine;

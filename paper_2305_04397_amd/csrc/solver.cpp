@@ -192,6 +192,11 @@ static int persistent_grid(morap_ctx* c, int prec, const Variant& v) {
 
 using EventPairs = std::vector<std::pair<hipEvent_t, hipEvent_t>>;
 
+// With time_kernels, every kTimedEvery-th sweep launch of a chunk is timed
+// (a uniform sample: its average duration is the launches' average, with a
+// quarter of the events in the stream)
+constexpr int kTimedEvery = 4;
+
 // per-launch timing events come from a pool: creating and destroying two
 // events per sweep costs host time on every launch
 static hipEvent_t take_event(morap_ctx* c) {
@@ -228,7 +233,8 @@ static void enqueue_chunk(morap_ctx* c, ValueSet& vs, const uint8_t* mask, const
     const int ktiles = vs.Kp / kt_of(v);
     for (int i = 0; i < n; ++i) {
         const int in_par = i & 1;
-        if (ev) {
+        const bool timed = ev && i % kTimedEvery == 0;
+        if (timed) {
             if (sweep_log() && ev->size() < 4096) {
                 c->h_log.ensure(4096 * 8);
                 MORAP_HIP(hipMemcpyAsync(c->h_log.as<int64_t>() + ev->size(), c->d_counters.as<int64_t>() + 1, 8,
@@ -241,7 +247,7 @@ static void enqueue_chunk(morap_ctx* c, ValueSet& vs, const uint8_t* mask, const
             k::sweep_block(c->stream, vs.prec, v, grid, ktiles, sweep_args(c, vs, in_par));
         else
             k::sweep(c->stream, vs.prec, v, grid, ktiles, sweep_args(c, vs, in_par));
-        if (ev) MORAP_HIP(hipEventRecord(ev->back().second, c->stream));
+        if (timed) MORAP_HIP(hipEventRecord(ev->back().second, c->stream));
         const auto ca = converge_args(c, vs, mask, eps, 1 - in_par);
         k::converge(c->stream, ca);
         k::compact(c->stream, ca);
@@ -680,14 +686,15 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
         while (true) {
             for (int i = 0; i < chunk; ++i) {
                 const bool even = (i & 1) == 0;
-                if (o.time_kernels) {
+                const bool timed = o.time_kernels && i % kTimedEvery == 0;
+                if (timed) {
                     ev.emplace_back(take_event(c), take_event(c));
                     MORAP_HIP(hipEventRecord(ev.back().first, s));
                 }
                 k::inst_vi_sweep(s, av, c->d_blk_rec.as<int32_t>(), c->d_blk64.as<double>(), c->d_iwc.as<double>(),
                                  c->d_iwp.as<double>(), iact, even ? x0 : x1, even ? x1 : x0, ires, (int32_t)c->S,
                                  c->hm.blk_pattern);
-                if (o.time_kernels) MORAP_HIP(hipEventRecord(ev.back().second, s));
+                if (timed) MORAP_HIP(hipEventRecord(ev.back().second, s));
                 k::inst_converge(s, n, ires, iact, ipar, even ? 1 : 0, o.eps_vi, dctr);
             }
             vsweeps += chunk;
