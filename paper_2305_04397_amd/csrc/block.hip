@@ -507,7 +507,12 @@ __global__ void __launch_bounds__(256) eval_block_kernel(InstArgs a, const int32
     const int per = (n_units + n_waves - 1) / n_waves;
     const int u0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * per;
     const int u1 = min(n_units, u0 + per);
-    int cur = -1;
+    // the instance's descriptor (model, state range, value base, active
+    // entries) is loaded when the instance changes, not per unit: consecutive
+    // units mostly share it, and its loads form a dependent chain
+    int cur = -1, sb = 0, n_st = 0;
+    int64_t ib = 0;
+    bool a0 = false, a1 = false;
     double m0 = 0.0, m1 = 0.0;
     for (int u = u0; u < u1; ++u) {
         const int t = u >> 2;
@@ -519,15 +524,17 @@ __global__ void __launch_bounds__(256) eval_block_kernel(InstArgs a, const int32
             }
             cur = inst;
             m0 = m1 = 0.0;
+            const int m = a.inst_model[inst];
+            sb = a.state_base[m];
+            n_st = a.state_base[m + 1] - sb;
+            ib = a.inst_base[inst];
+            a0 = active[2 * inst] != 0;
+            a1 = active[2 * inst + 1] != 0;
         }
-        const bool a0 = active[2 * inst] != 0, a1 = active[2 * inst + 1] != 0;
         double r0 = 0.0, r1 = 0.0;
         if (a0 || a1) {
             const int ls = a.inst_tiles[2 * t + 1] + (u & 3) * 64 + (threadIdx.x & 63);
-            const int m = a.inst_model[inst];
-            const int sb = a.state_base[m];
-            if (ls < a.state_base[m + 1] - sb) {
-                const int64_t ib = a.inst_base[inst];
+            if (ls < n_st) {
                 const int4 q0 = *reinterpret_cast<const int4*>(rec + (int64_t)(sb + ls) * 8);
                 const int4 q1 = *reinterpret_cast<const int4*>(rec + (int64_t)(sb + ls) * 8 + 4);
                 const int own = q1.w - sb;
