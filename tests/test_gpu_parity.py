@@ -421,3 +421,20 @@ def test_synthesis_rejects_bad_inputs(ctx, morap):
         assert e.value.code == morap.E_INVALID
     syn = ctx.synthesize(g, o)
     assert np.allclose(syn["matrix"].sum(axis=0), 1.0)
+
+
+def test_readme_example(ctx, morap):
+    """The usage example of the README runs as written and returns a
+    consistent answer: the threshold lies below an achievable point, so it is
+    never INFEASIBLE (with eps = 0.01 the loop may stop UNDECIDED within eps of
+    it), and the synthesised random assignment serves every task."""
+    wl = make_workload(2)
+    ctx.build_products(wl)
+    opts = morap.Options(eps_vi=1e-6, precision="f32")
+    r, assign, c, stats = ctx.support(np.full((1, 30), 1 / 30), opts)
+    q = ctx.query(r[0] - 0.05 * np.abs(r[0]), eps=0.01, opts=opts, trace=True)
+    syn = ctx.synthesize(q, opts)
+    assert q["verdict"] in (morap.FEASIBLE, morap.UNDECIDED)
+    t = r[0] - 0.05 * np.abs(r[0])
+    assert q["verdict"] == morap.FEASIBLE or np.linalg.norm(t - q["t_up"]) <= 0.01 + 1e-9
+    assert np.allclose(syn["matrix"].sum(axis=0), 1.0)
