@@ -438,3 +438,41 @@ def test_readme_example(ctx, morap):
     t = r[0] - 0.05 * np.abs(r[0])
     assert q["verdict"] == morap.FEASIBLE or np.linalg.norm(t - q["t_up"]) <= 0.01 + 1e-9
     assert np.allclose(syn["matrix"].sum(axis=0), 1.0)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_support_on_caller_loaded_csr_products(ctx, morap, prec):
+    """Products handed over as CSR (morap_load_models, no neighbourhood-block
+    form): the CSR sweep, the masked batched FP64 re-solve of the assigned
+    pairs and the CSR evaluation kernel.  Same bar as the block path: c within
+    the FP32 stopping error (or 4 eps in FP64), identical policies and r to
+    rounding wherever the assignment is the oracle's."""
+    wl = make_workload(2, n_agents=3, n_tasks=6)
+    prods = product.build_all(wl)
+    nI, nJ = wl.n_agents, wl.n_tasks
+    ctx.load_models([{"state_row": p.state_row, "row_ptr": p.row_ptr, "col": p.col, "prob": p.prob,
+                      "rew": np.stack([p.rew_cost, p.rew_prob], 1), "to_done": p.to_done, "init": p.init}
+                     for p in prods], nI, nJ)
+    W = dirichlet_weights(np.random.default_rng(8), 16, nI + nJ)
+    W[1] = np.eye(nI + nJ)[nI]
+    eps = 1e-6 if prec == "f32" else 1e-8
+    r, A, c, st = ctx.support(W, morap.Options(eps_vi=eps, precision=prec))
+    assert st["variant"] <= 18                      # the CSR sweep served the solve
+    co, _, _ = _oracle_c(prods, nI, nJ, W, eps)
+    tol = 2e-4 * np.maximum(1.0, np.abs(co)) if prec == "f32" else 4 * eps + 1e-10 * np.abs(co).max()
+    assert (np.abs(c - co) <= tol).all()
+    matched = 0
+    for k in range(W.shape[0]):
+        if not np.array_equal(alg.assign(co[k]), A[k]):
+            continue
+        matched += 1
+        ro = np.zeros(nI + nJ)
+        for j in range(nJ):
+            p = prods[A[k][j] * nJ + j]
+            mu = _oracle_policy(p, W[k, A[k][j]], W[k, nI + j], eps)
+            assert ctx.get_policy(k, j, p.n_states).tolist() == mu.tolist()
+            (vc, vp), _, _ = vi.evaluate(p, mu, eps)
+            ro[nI + j] = vp
+            ro[A[k][j]] += vc
+        assert np.abs(r[k] - ro).max() <= 1e-9 * max(1.0, np.abs(ro).max())
+    assert matched >= W.shape[0] // 2
