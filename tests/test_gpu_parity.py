@@ -476,3 +476,18 @@ def test_support_on_caller_loaded_csr_products(ctx, morap, prec):
             ro[A[k][j]] += vc
         assert np.abs(r[k] - ro).max() <= 1e-9 * max(1.0, np.abs(ro).max())
     assert matched >= W.shape[0] // 2
+
+
+@pytest.mark.parametrize("K", [65, 128, 130])
+def test_f32_solve_more_than_64_columns(ctx, morap, K):
+    """K > 64 pads to multiples of 64 and sweeps two or three column tiles per
+    launch (FP32, neighbourhood blocks): every column against the oracle."""
+    wl = make_workload(2, n_agents=2, n_tasks=4)
+    prods = _load(ctx, wl)
+    nI, nJ = wl.n_agents, wl.n_tasks
+    W = dirichlet_weights(np.random.default_rng(K), K, nI + nJ)
+    eps = 1e-6
+    c, st = ctx.solve(W, morap.Options(eps_vi=eps, precision="f32"))
+    assert st["variant"] > 18
+    co, _, _ = _oracle_c(prods, nI, nJ, W, eps)
+    assert (np.abs(c - co) <= 2e-4 * np.maximum(1.0, np.abs(co))).all()
