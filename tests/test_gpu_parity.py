@@ -354,6 +354,43 @@ def test_verification_only_stops_at_the_first_separation(ctx, morap):
     assert w @ r < w @ t
 
 
+def test_single_agent_single_task_query(ctx, morap):
+    """One agent and one task, a plain MOMDP with d = 2 (the setting of the
+    paper's verification experiment), on a product of several tiles with a
+    ragged last one: the device loop gives the oracle's verdicts and points,
+    in the full and in the verification-only mode."""
+    wl = make_workload(2, n_agents=1, n_tasks=1)
+    prods = _load(ctx, wl)
+    assert prods[0].n_states > 512 and prods[0].n_states % 128
+    o = morap.Options(eps_vi=1e-8, precision="f64")
+    r1 = alg.support(prods, 1, 1, np.array([1.0, 0.0]), 1e-8).r     # cost only
+    r2 = alg.support(prods, 1, 1, np.array([0.0, 1.0]), 1e-8).r     # probability only
+    T = [r2 + np.array([0.0, 0.05]),                                # beyond probability 1
+         0.75 * r1 + 0.25 * r2 + np.array([60.0, 0.2])]             # projects to the cost corner
+    for a in (0.25, 0.5):
+        base = a * r1 + (1 - a) * r2
+        T += [base - np.array([0.5, 0.02]), base + np.array([20.0, 0.1])]
+    verdicts = set()
+    for t in T:
+        tol = 1e-6 * max(1.0, np.abs(t).max())
+        g = ctx.query(t, eps=1e-6, opts=o, trace=True)
+        q = alg.query(prods, 1, 1, t, 1e-6, 1e-8)
+        verdicts.add(q.verdict)
+        assert g["verdict"] == q.verdict, t
+        assert np.abs(g["t_down"] - q.t_down).max() <= tol
+        assert np.abs(g["t_up"] - q.t_up).max() <= tol
+        for w, r in zip(g["W"], g["R"]):
+            ro = alg.support(prods, 1, 1, w, 1e-8).r
+            assert np.abs(r - ro).max() <= 1e-9 * max(1.0, np.abs(ro).max())
+        if all(np.abs(x - y).max() <= 1e-9 for x, y in zip(g["W"], q.W)):
+            assert g["iterations"] == q.iterations
+        gv = ctx.query(t, eps=1e-6, opts=o, verification_only=True)
+        qv = alg.query(prods, 1, 1, t, 1e-6, 1e-8, verification_only=True)
+        assert gv["verdict"] == qv.verdict
+        assert gv["iterations"] <= g["iterations"]
+    assert verdicts == {alg.FEASIBLE, alg.INFEASIBLE}
+
+
 @pytest.mark.parametrize("cfg", ["cfg1", "rep"])
 def test_synthesis_matches_oracle(ctx, morap, cfg):
     """morap_synthesize on traced queries: the picked passes reproduce the

@@ -712,3 +712,66 @@ def test_synthesis_meets_feasible_thresholds(cfg):
             assert np.allclose(syn.matrix.sum(axis=1), 1.0)
         checked += 1
     assert checked == 3
+
+
+# --------------------------------------------------------------------------
+# one agent, one task: the MOMDP special case (Sec. 5, verification
+# experiment)
+# --------------------------------------------------------------------------
+def _projection_by_support(obj, Aeq, beq, t):
+    """Euclidean projection of t (outside the set) onto the down-closure of
+    the product's achievable (cost, probability) pairs, d = 2.  The distance
+    is the maximum over unit weights w >= 0 of w.t - h(w), with h the
+    occupation-measure LP's optimum; along the quarter circle that function is
+    unimodal (its superlevel sets are convex and closed under scaling up), so
+    a bounded scalar search finds it.  Returns (distance, projection)."""
+    from scipy.optimize import minimize_scalar
+    bounds = [(0, None)] * Aeq.shape[1]
+
+    def gap(th):
+        w = np.array([np.cos(th), np.sin(th)])
+        lp = linprog(-(w @ obj), A_eq=Aeq, b_eq=beq, bounds=bounds, method="highs")
+        assert lp.status == 0
+        return w @ t + lp.fun
+
+    best = minimize_scalar(lambda th: -gap(th), bounds=(0.0, np.pi / 2), method="bounded",
+                           options={"xatol": 1e-12})
+    # the search never evaluates the ends: a pure-cost or pure-probability
+    # normal is taken from there
+    dist, th = max((gap(x), x) for x in (best.x, 0.0, np.pi / 2))
+    return dist, t - dist * np.array([np.cos(th), np.sin(th)])
+
+
+@pytest.mark.parametrize("seed,kind", [(61, "reach"), (62, "avoid")])
+def test_single_agent_single_task_is_the_momdp(seed, kind):
+    """With one agent and one task the achievable set is the product MOMDP's
+    own set of (cost, probability) pairs.  Verdicts equal the feasibility of
+    its occupation-measure LP; outside the set, t_up lies within the bound the
+    stop rule of Alg. 1 gives, sqrt(2 dist eps), of the exact projection."""
+    wl = tiny_workload(seed, 1, 1, width=3, height=3, kinds=(kind,), k=2, p_slip=0.2)
+    prods = product.build_all(wl)
+    Aeq, beq, obj = _mo_lp(prods, 1, 1)
+    mid = alg.support(prods, 1, 1, np.array([0.5, 0.5]), 1e-13).r
+    rng = np.random.default_rng(seed)
+    T = [mid - np.array([0.5, 0.05]), mid + np.array([0.5, 0.05])]
+    for _ in range(4):
+        T.append(mid + np.array([1.0, 0.2]) * rng.uniform(-1, 1, 2))
+    eps = 1e-9
+    seen = set()
+    for t in T:
+        lp = linprog(np.zeros(Aeq.shape[1]), A_ub=-obj, b_ub=-t, A_eq=Aeq, b_eq=beq,
+                     bounds=[(0, None)] * Aeq.shape[1], method="highs")
+        res = alg.query(prods, 1, 1, t, eps, 1e-13, max_iter=200)
+        seen.add(res.verdict)
+        if lp.status == 0:
+            assert res.verdict == alg.FEASIBLE or geometry.mnorm(res.t_down - t) < 1e-6
+            continue
+        assert res.verdict != alg.FEASIBLE
+        dist, p = _projection_by_support(obj, Aeq, beq, t)
+        assert dist > 0
+        assert np.linalg.norm(res.t_up - p) <= np.sqrt(2 * dist * eps) + 1e-7
+        # inner and outer approximations bracket the distance (up to the LP
+        # solver's own tolerance, ~1e-7)
+        assert geometry.mnorm(t - res.t_down) <= dist + 1e-7
+        assert dist <= geometry.mnorm(t - res.t_up) + 1e-7
+    assert alg.FEASIBLE in seen and len(seen) > 1
