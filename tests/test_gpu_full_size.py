@@ -54,14 +54,17 @@ def test_full_size_solve_sampled(full):
             assert abs(c[k, i, j] - ref) <= 2e-4 * max(1.0, abs(ref)), (i, j, k, c[k, i, j], ref)
 
 
-def test_full_size_largest_product_sampled(full):
-    """The product of maximum size class: the 128 x 128 agent with a
-    12-location task (1.3e5 live states, about a thousand tiles), the oracle's
-    FP64 value iteration on two columns against the batched FP32 solve."""
+@pytest.mark.parametrize("kind", ["avoid", "reach"])
+def test_full_size_largest_product_sampled(full, kind):
+    """The products of maximum size class: the 128 x 128 agent with a
+    12-location task (1.3-1.4e5 live states, about a thousand tiles each), the
+    oracle's FP64 value iteration on two columns against the batched FP32
+    solve.  The reach-seq(11) product is the one that converges last (over
+    2,200 sweeps), where the FP32 stop rule's error is largest."""
     morap, ctx, wl = full
     nI, nJ = wl.n_agents, wl.n_tasks
     i = max(range(nI), key=lambda a: wl.agents[a].width)
-    j = max((b for b in range(nJ) if wl.tasks[b].kind == "avoid"), key=lambda b: wl.tasks[b].n_locs)
+    j = max((b for b in range(nJ) if wl.tasks[b].kind == kind), key=lambda b: wl.tasks[b].n_locs)
     assert wl.agents[i].width == 128 and wl.tasks[j].n_locs == 12
     W = dirichlet_weights(np.random.default_rng(0), 64, nI + nJ)
     eps = 1e-6
@@ -73,7 +76,8 @@ def test_full_size_largest_product_sampled(full):
     for col, k in enumerate(ks):
         ref = y[p.init, col]
         # the FP32 stop rule max(eps, 8 u32 |y|) leaves an error of that
-        # residual times 1/(1 - rho) (rho ~ 0.96 here): ~1e-5 relative
+        # residual times 1/(1 - rho): rho ~ 0.96 (avoid) and ~0.992 (reach)
+        # give ~1e-5 and ~6e-5 relative
         assert abs(c[k, i, j] - ref) <= 2e-4 * max(1.0, abs(ref)), (k, c[k, i, j], ref)
 
 
