@@ -11,8 +11,9 @@ Modules (each function cites the passage of Robinson & Su, "Multi-Objective
 Task Assignment and Multiagent Planning with Hybrid GPU-CPU Acceleration",
 that it follows):
   product   agent x DFA product MDPs with done_j and the two reward columns
-  vi        scalarised value iteration (Alg. 3), policy extraction, policy
-            evaluation (Alg. 4), exact evaluation by a sparse solve
+  vi        scalarised value iteration (Alg. 3) and its stage-ordered form,
+            policy extraction, policy evaluation (Alg. 4), exact evaluation
+            by a sparse solve
   geometry  M-norm projections of Alg. 1 (inner and outer approximation)
   alg       Alg. 2 (supporting hyperplane: VI, assignment, evaluation) and
             Alg. 1 (point-oriented Pareto computation)

@@ -81,6 +81,85 @@ def value_iteration(prod: Product, wc, wp, eps: float, max_sweeps: int = 1_000_0
     return x, sweeps
 
 
+def location_stages(prod: Product) -> np.ndarray:
+    """Stage of every live state for the stage-ordered iteration.
+
+    The location graph has an edge q -> q' when a live transition leads from a
+    state at location q to a state at q'.  Its strongly connected groups form
+    a DAG; a group's stage is its height there (0 for a group with no other
+    successor group, else one more than the highest successor group).  Every
+    transition therefore leads to the same or a lower stage, and groups of one
+    stage have no transitions between them.  Returns int64 [S]."""
+    from scipy.sparse.csgraph import connected_components
+    S = prod.n_states
+    if S == 0:
+        return np.zeros(0, dtype=np.int64)
+    locs, loc_of = np.unique(prod.states[:, 1], return_inverse=True)
+    L = len(locs)
+    src = loc_of[np.repeat(prod.row_state(), np.diff(prod.row_ptr))]
+    dst = loc_of[prod.col]
+    g = sp.csr_matrix((np.ones(len(src)), (src, dst)), shape=(L, L))
+    n_groups, group = connected_components(g, directed=True, connection="strong")
+    succ = [set() for _ in range(n_groups)]
+    for a, b in zip(group[src], group[dst]):
+        if a != b:
+            succ[a].add(b)
+    height = [-1] * n_groups
+
+    def h(u):
+        if height[u] < 0:
+            height[u] = 1 + max((h(v) for v in succ[u]), default=-1)
+        return height[u]
+
+    for u in range(n_groups):
+        h(u)
+    return np.asarray(height, dtype=np.int64)[group[loc_of]]
+
+
+def stage_ordered_value_iteration(prod: Product, wc, wp, eps: float, max_sweeps: int = 1_000_000):
+    """Value iteration stage by stage (the staged form of Alg. 3 that the
+    acyclic stages of a reach-sequence automaton allow).
+
+    Stages (``location_stages``) are solved in increasing order.  Stage g
+    runs the Jacobi sweeps of ``value_iteration`` over its own states only,
+    from 0, reading the values of lower stages as final, until its residual
+    over its own states is <= eps (each column on its own).  The fixed point
+    is the one of Alg. 3; the stopping points differ.
+
+    Returns (y [S, K], sweeps [n_stages, K])."""
+    r = scalarised_rewards(prod, wc, wp)
+    K = r.shape[1]
+    S = prod.n_states
+    x = np.zeros((S, K))
+    if S == 0:
+        return x, np.zeros((0, K), dtype=np.int64)
+    stage = location_stages(prod)
+    n_stages = int(stage.max()) + 1
+    sweeps = np.zeros((n_stages, K), dtype=np.int64)
+    P = prod.P()
+    for g in range(n_stages):
+        sel = np.flatnonzero(stage == g)
+        counts = np.diff(prod.state_row)[sel]
+        assert (counts > 0).all()
+        offsets = np.concatenate([[0], np.cumsum(counts)[:-1]])
+        rows = np.repeat(prod.state_row[sel], counts) + (np.arange(counts.sum()) - np.repeat(offsets, counts))
+        Pg, rg = P[rows], r[rows]
+        active = np.ones(K, dtype=bool)
+        n = 0
+        while active.any():
+            n += 1
+            if n > max_sweeps:
+                raise RuntimeError("value iteration did not converge")
+            cols = np.flatnonzero(active)
+            y = np.maximum.reduceat(rg[:, cols] + Pg @ x[:, cols], offsets, axis=0)
+            res = np.abs(y - x[np.ix_(sel, cols)]).max(axis=0)
+            x[np.ix_(sel, cols)] = y
+            done = res <= eps
+            sweeps[g, cols[done]] = n
+            active[cols[done]] = False
+    return x, sweeps
+
+
 def q_values(prod: Product, x: np.ndarray, wc, wp) -> np.ndarray:
     """Q(s,a) = (w . rho)(s,a) + sum_s' P(s,a,s') x(s') for every row, [R, K]."""
     x2 = x.reshape(prod.n_states, -1)

@@ -775,3 +775,74 @@ def test_single_agent_single_task_is_the_momdp(seed, kind):
         assert geometry.mnorm(t - res.t_down) <= dist + 1e-7
         assert dist <= geometry.mnorm(t - res.t_up) + 1e-7
     assert alg.FEASIBLE in seen and len(seen) > 1
+
+
+# --------------------------------------------------------------------------
+# stage-ordered value iteration (the staged form of Alg. 3)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("kind,k", [("reach", 4), ("avoid", 3)])
+def test_location_stages_follow_the_sequence(kind, k):
+    """reach-seq(k) / avoid-seq(k) automata are chains of waypoint locations
+    (the trap and acceptance are done), so location q is stage k - 1 - q, and
+    no transition climbs to a higher stage."""
+    wl = tiny_workload(71, 1, 1, width=4, height=4, kinds=(kind,), k=k, p_slip=0.2)
+    p = product.build_all(wl)[0]
+    st = vi.location_stages(p)
+    q = p.states[:, 1]
+    assert set(q.tolist()) == set(range(k))
+    assert np.array_equal(st, k - 1 - q)
+    src = np.repeat(p.row_state(), np.diff(p.row_ptr))
+    assert (st[p.col] <= st[src]).all()
+
+
+def test_stage_ordered_vi_on_one_location_is_plain_vi():
+    """With one live location there is one stage: the staged iteration is
+    Alg. 3's iteration, bit for bit and sweep for sweep."""
+    wl = tiny_workload(72, 1, 1, width=4, height=4, kinds=("avoid",), k=1, p_slip=0.2)
+    p = product.build_all(wl)[0]
+    assert len(np.unique(p.states[:, 1])) == 1
+    W = np.random.default_rng(72).dirichlet(np.ones(2), size=4)
+    xs, ss = vi.stage_ordered_value_iteration(p, W[:, 0], W[:, 1], 1e-9)
+    xp, sp_ = vi.value_iteration(p, W[:, 0], W[:, 1], 1e-9)
+    assert np.array_equal(xs, xp) and np.array_equal(ss[0], sp_)
+
+
+@pytest.mark.parametrize("seed", [73, 74])
+def test_stage_ordered_vi_reaches_the_lp_optimum(seed):
+    """Four stages solved lowest first reach the scalarised optimum that the
+    occupation-measure LP gives at the initial state, and plain VI's values
+    everywhere (a stage solved in the wrong order, or against the wrong rows,
+    misses both)."""
+    wl = tiny_workload(seed, 1, 1, width=3, height=3, kinds=("reach",), k=4, p_slip=0.2)
+    prods = product.build_all(wl)
+    p = prods[0]
+    Aeq, beq, obj = _mo_lp(prods, 1, 1)
+    W = np.random.default_rng(seed).dirichlet(np.ones(2), size=3)
+    xs, ss = vi.stage_ordered_value_iteration(p, W[:, 0], W[:, 1], 1e-12)
+    assert ss.shape[0] == 4 and (ss > 0).all()
+    xp, _ = vi.value_iteration(p, W[:, 0], W[:, 1], 1e-12)
+    assert np.abs(xs - xp).max() <= 1e-9 * max(1.0, np.abs(xp).max())
+    for col, w in enumerate(W):
+        lp = linprog(-(w @ obj), A_eq=Aeq, b_eq=beq, bounds=[(0, None)] * Aeq.shape[1], method="highs")
+        assert lp.status == 0
+        assert xs[p.init, col] == pytest.approx(-lp.fun, abs=1e-7)
+
+
+def test_stage_ordered_vi_trades_updates_for_sweeps():
+    """On a reach-seq(7) product (seven stages of equal size) the staged
+    iteration updates fewer states than plain VI, but the stages run one after
+    another while plain VI's converge together: more sweeps in sequence.  Both
+    stop within eps of each other's fixed point."""
+    wl = make_workload(2, n_agents=1, n_tasks=20)
+    j = next(b for b, t in enumerate(wl.tasks) if t.kind == "reach" and t.n_locs == 8)
+    p = product.build_product(wl.agents[0], wl.tasks[j], wl.letters[0][j])
+    W = np.array([[0.3, 0.7], [0.05, 0.95]])
+    xs, ss = vi.stage_ordered_value_iteration(p, W[:, 0], W[:, 1], 1e-6)
+    xp, sp_ = vi.value_iteration(p, W[:, 0], W[:, 1], 1e-6)
+    sizes = np.bincount(vi.location_stages(p))
+    assert len(sizes) == 7
+    updates = (sizes[:, None] * ss).sum(axis=0)
+    assert (updates < p.n_states * sp_).all()
+    assert (ss.sum(axis=0) > sp_).all()
+    assert (ss.max(axis=0) <= sp_ + 1).all()
+    assert np.abs(xs - xp).max() <= 1e-4
