@@ -18,9 +18,11 @@ that it follows):
   alg       Alg. 2 (supporting hyperplane: VI, assignment, evaluation) and
             Alg. 1 (point-oriented Pareto computation)
   mlp       FP64 reference of the learned weight proposer (not in the paper)
+  centralised  the team MDP of the decentralised model (Def. teamMDP), small
+            instances only, as an independent check of Alg. 2
 
 Parity unpinned: the literal pre-sink probability reward (``presink_literal``)
 and the trajectory-dependent policy rule (``policy_rule="paper"``) are kept as
 options for the record only; nothing pins them.
 """
-from . import product, vi, geometry, alg, mlp  # noqa: F401
+from . import product, vi, geometry, alg, mlp, centralised  # noqa: F401

@@ -14,7 +14,7 @@ from scipy.sparse.csgraph import dijkstra
 
 from workloads import worked_example, tiny_workload, make_workload
 from workloads.gridworld import Agent, Task, Workload, make_task_dfa, make_grid, make_agent
-from oracle import product, vi, alg, geometry
+from oracle import product, vi, alg, geometry, centralised
 
 HERE = os.path.dirname(__file__)
 GOLD = json.load(open(os.path.join(HERE, "golden", "worked_example.json")))
@@ -371,77 +371,19 @@ def test_verdict_equals_lp_feasibility(seed):
         assert (res.verdict == alg.FEASIBLE) == (lp.status == 0) or (slack is not None and slack < 1e-6)
 
 
-def _centralised_value(wl, w):
-    """Scalarised optimum of the centralised MDP of Def. teamMDP, built as a
-    flat MDP and solved by value iteration (agents / tasks 0-based)."""
-    nI, nJ = wl.n_agents, wl.n_tasks
-    agents, tasks = wl.agents, wl.tasks
-    done = [tasks[j].accepting.astype(bool) | product.traps(tasks[j].n_locs, tasks[j].delta,
-                                                            tasks[j].accepting) for j in range(nJ)]
-    index = {}
-    states = []
-    for i in range(nI):
-        for j in range(nJ):
-            for s in range(agents[i].n_states):
-                for q in range(tasks[j].n_locs):
-                    for sharp in range(1 << nI):
-                        index[(i, j, s, q, sharp)] = len(states)
-                        states.append((i, j, s, q, sharp))
-    rows = []          # (state, reward, [(succ, p)])
-    for n, (i, j, s, q, sharp) in enumerate(states):
-        ag, tk = agents[i], tasks[j]
-        at_start = s == ag.init and q == tk.q0
-        if (sharp >> i) & 1 and not done[j][q]:
-            for a in range(ag.n_actions):
-                r = s * ag.n_actions + a
-                lo, hi = ag.sa_ptr[r], ag.sa_ptr[r + 1]
-                if hi == lo:
-                    continue
-                succ, rew_p = [], 0.0
-                for e in range(lo, hi):
-                    s2 = int(ag.succ[e])
-                    q2 = int(tk.delta[q, wl.letters[i][j][s2]])
-                    if tk.accepting[q2] and not tk.accepting[q]:
-                        rew_p += ag.prob[e]
-                    succ.append((index[(i, j, s2, q2, sharp)], ag.prob[e]))
-                rows.append((n, -w[i] * ag.cost[r] + w[nI + j] * rew_p, succ))
-        if at_start and not (sharp >> i) & 1:
-            rows.append((n, 0.0, [(index[(i, j, s, q, sharp | (1 << i))], 1.0)]))       # b1
-            nxt = [k for k in range(i + 1, nI) if not (sharp >> k) & 1]
-            if nxt:
-                k = nxt[0]
-                rows.append((n, 0.0, [(index[(k, j, agents[k].init, q, sharp)], 1.0)]))  # b2
-        if done[j][q] and (sharp >> i) & 1 and j < nJ - 1:
-            free = [k for k in range(nI) if not (sharp >> k) & 1]
-            if free:
-                k = free[0]
-                rows.append((n, 0.0, [(index[(k, j + 1, agents[k].init, tasks[j + 1].q0, sharp)], 1.0)]))  # b3
-    N = len(states)
-    has = np.zeros(N, bool)
-    for n, _, _ in rows:
-        has[n] = True
-    x = np.zeros(N)
-    for _ in range(100000):
-        y = np.where(has, -np.inf, 0.0)
-        for n, rew, succ in rows:
-            v = rew + sum(p * x[k] for k, p in succ)
-            if v > y[n]:
-                y[n] = v
-        if np.abs(y - x).max() <= 1e-12:
-            x = y
-            break
-        x = y
-    return x[index[(0, 0, agents[0].init, tasks[0].q0, 0)]]
-
-
-def test_centralised_optimum_equals_decentralised_assignment():
-    wl = tiny_workload(41, 2, 2, width=3, height=2, kinds=("reach",), k=1, p_slip=0.25)
+@pytest.mark.parametrize("n,seed", [(2, 41), (3, 42)])
+def test_centralised_optimum_equals_decentralised_assignment(n, seed):
+    """The team MDP of Def. teamMDP (n agents, n tasks) reaches, from its joint
+    initial state, the value of the best assignment that Alg. 2 finds
+    (Lemma lem:ct-mdp-prop)."""
+    wl = tiny_workload(seed, n, n, width=3, height=2, kinds=("reach",), k=1, p_slip=0.25)
     prods = product.build_all(wl)
-    rng = np.random.default_rng(41)
+    team = centralised.build_team_mdp(wl)
+    rng = np.random.default_rng(seed)
     for _ in range(2):
-        w = rng.dirichlet(np.ones(4))
-        s = alg.support(prods, 2, 2, w, 1e-13)
-        assert _centralised_value(wl, w) == pytest.approx(w @ s.r, abs=1e-8)
+        w = rng.dirichlet(np.ones(2 * n))
+        s = alg.support(prods, n, n, w, 1e-13)
+        assert centralised.team_value(team, w) == pytest.approx(w @ s.r, abs=1e-8)
 
 
 # --------------------------------------------------------------------------
