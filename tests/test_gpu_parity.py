@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 from workloads import make_workload, worked_example, tiny_workload, dirichlet_weights
-from oracle import product, vi, alg
+from oracle import product, vi, alg, centralised
 
 pytestmark = pytest.mark.gpu
 
@@ -389,6 +389,53 @@ def test_single_agent_single_task_query(ctx, morap):
         assert gv["verdict"] == qv.verdict
         assert gv["iterations"] <= g["iterations"]
     assert verdicts == {alg.FEASIBLE, alg.INFEASIBLE}
+
+
+def _team_model(team, w):
+    """The team MDP scalarised for one weight vector, as a caller-built model
+    with a single objective (the reward in the cost column).  States without
+    rows get an empty one: all mass to done, reward 0, so their value is 0."""
+    state_row, row_ptr, col, prob, rew = [0], [0], [], [], []
+    r = team.rew @ w
+    for s in range(team.n_states):
+        rows = range(team.state_row[s], team.state_row[s + 1])
+        for q in rows:
+            lo, hi = team.row_ptr[q], team.row_ptr[q + 1]
+            col += team.col[lo:hi].tolist()
+            prob += team.prob[lo:hi].tolist()
+            row_ptr.append(len(col))
+            rew.append((r[q], 0.0))
+        if len(rows) == 0:
+            row_ptr.append(len(col))
+            rew.append((0.0, 0.0))
+        state_row.append(len(row_ptr) - 1)
+    row_ptr = np.asarray(row_ptr)
+    prob = np.asarray(prob)
+    sums = np.array([prob[row_ptr[q]:row_ptr[q + 1]].sum() for q in range(len(row_ptr) - 1)])
+    return {"state_row": np.asarray(state_row), "row_ptr": row_ptr, "col": np.asarray(col), "prob": prob,
+            "rew": np.asarray(rew), "to_done": (sums < 1 - 1e-12).astype(np.uint8), "init": team.init}
+
+
+@pytest.mark.parametrize("n,seed", [(2, 41), (3, 42)])
+def test_team_mdp_on_the_device(ctx, morap, n, seed):
+    """The team MDP of Def. teamMDP (the centralised model), scalarised for
+    one weight vector and loaded as a caller-built model, solved by the
+    device's CSR sweep: its value at the joint initial state is the oracle's,
+    and the best assignment's that the device's own Alg. 2 finds on the
+    decentralised products (Lemma lem:ct-mdp-prop)."""
+    wl = tiny_workload(seed, n, n, width=3, height=2, kinds=("reach",), k=1, p_slip=0.25)
+    team = centralised.build_team_mdp(wl)
+    o = morap.Options(eps_vi=1e-12, precision="f64")
+    rng = np.random.default_rng(seed)
+    for _ in range(2):
+        w = rng.dirichlet(np.ones(2 * n))
+        ctx.build_products(wl)
+        r, _, _, _ = ctx.support(w[None, :], o)
+        ctx.load_models([_team_model(team, w)], 1, 1)
+        cv, st = ctx.solve(np.array([[1.0, 0.0]]), o)
+        assert st["variant"] <= 18
+        assert cv[0, 0, 0] == pytest.approx(centralised.team_value(team, w), abs=1e-9)
+        assert cv[0, 0, 0] == pytest.approx(w @ r[0], abs=1e-8)
 
 
 @pytest.mark.parametrize("cfg", ["cfg1", "rep"])
