@@ -210,9 +210,48 @@ static hipEvent_t take_event(morap_ctx* c) {
     return e;
 }
 static void give_events(morap_ctx* c, const std::pair<hipEvent_t, hipEvent_t>& e) {
-    c->event_pool.push_back(e.first);
-    c->event_pool.push_back(e.second);
+    if (e.first) c->event_pool.push_back(e.first);
+    if (e.second) c->event_pool.push_back(e.second);
 }
+
+// Sampled launch events held by a loop; whatever is still held when the
+// scope ends (an error thrown mid-chunk included) goes back to the pool.
+struct PooledEvents {
+    morap_ctx* c;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> v;
+    explicit PooledEvents(morap_ctx* ctx) : c(ctx) {}
+    PooledEvents(const PooledEvents&) = delete;
+    PooledEvents& operator=(const PooledEvents&) = delete;
+    ~PooledEvents() {
+        for (auto& e : v) give_events(c, e);
+    }
+};
+
+// Two HIP events bracketing a timed region, destroyed on every way out of
+// the scope that owns them.
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    EventPair() {
+        MORAP_HIP(hipEventCreate(&a));
+        const hipError_t e = hipEventCreate(&b);
+        if (e != hipSuccess) {
+            (void)hipEventDestroy(a);
+            a = nullptr;
+            fail(MORAP_E_HIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
+        }
+    }
+    EventPair(const EventPair&) = delete;
+    EventPair& operator=(const EventPair&) = delete;
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+    float elapsed_ms() const {
+        float ms = 0;
+        MORAP_HIP(hipEventElapsedTime(&ms, a, b));
+        return ms;
+    }
+};
 
 // Optional per-launch log (environment variable MORAP_SWEEP_LOG = file path):
 // the autotuner's timings and, for solves run with time_kernels, one line per
@@ -240,7 +279,8 @@ static void enqueue_chunk(morap_ctx* c, ValueSet& vs, const uint8_t* mask, const
                 MORAP_HIP(hipMemcpyAsync(c->h_log.as<int64_t>() + ev->size(), c->d_counters.as<int64_t>() + 1, 8,
                                          hipMemcpyDeviceToHost, c->stream));
             }
-            ev->emplace_back(take_event(c), take_event(c));
+            ev->emplace_back(take_event(c), nullptr);
+            ev->back().second = take_event(c);
             MORAP_HIP(hipEventRecord(ev->back().first, c->stream));
         }
         if (v.kind == SWEEP_BLOCK)
@@ -309,20 +349,14 @@ static void read_counters(morap_ctx* c) {
 
 // time 6 sweeps of variant v from a fresh start (autotuner)
 static double time_variant(morap_ctx* c, ValueSet& vs, const uint8_t* mask, const Variant& v, double eps) {
-    hipEvent_t e0, e1;
-    MORAP_HIP(hipEventCreate(&e0));
-    MORAP_HIP(hipEventCreate(&e1));
+    EventPair t;
     reset_solve(c, vs, mask, eps);
     enqueue_chunk(c, vs, mask, v, eps, 2);
-    MORAP_HIP(hipEventRecord(e0, c->stream));
+    MORAP_HIP(hipEventRecord(t.a, c->stream));
     enqueue_chunk(c, vs, mask, v, eps, 6);
-    MORAP_HIP(hipEventRecord(e1, c->stream));
-    MORAP_HIP(hipEventSynchronize(e1));
-    float ms = 0;
-    MORAP_HIP(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    return ms;
+    MORAP_HIP(hipEventRecord(t.b, c->stream));
+    MORAP_HIP(hipEventSynchronize(t.b));
+    return t.elapsed_ms();
 }
 
 // autotuner: the fastest candidate variant for (precision, padded width,
@@ -365,14 +399,13 @@ static void run_vi(morap_ctx* c, int g, ValueSet& vs, const uint8_t* mask, const
     const Variant& v = choose_variant(c, vs, mask, o.eps_vi, o.schedule);
     c->last_variant = v.id;
     const int chunk = std::max(2, (o.check_every + 1) / 2 * 2);
-    hipEvent_t e0, e1;
-    MORAP_HIP(hipEventCreate(&e0));
-    MORAP_HIP(hipEventCreate(&e1));
+    EventPair wall;
     reset_solve(c, vs, mask, o.eps_vi);
-    MORAP_HIP(hipEventRecord(e0, c->stream));
+    MORAP_HIP(hipEventRecord(wall.a, c->stream));
     int64_t launched = 0;
     int64_t* h = c->h_counters.as<int64_t>();
-    EventPairs ev;
+    PooledEvents held(c);
+    EventPairs& ev = held.v;
     auto harvest = [&] {
         for (size_t i = 0; i < ev.size(); ++i) {
             auto& e = ev[i];
@@ -389,6 +422,7 @@ static void run_vi(morap_ctx* c, int g, ValueSet& vs, const uint8_t* mask, const
                 st.sweep_launches += 1;
             }
             give_events(c, e);
+            e = {nullptr, nullptr};
         }
         ev.clear();
     };
@@ -398,20 +432,14 @@ static void run_vi(morap_ctx* c, int g, ValueSet& vs, const uint8_t* mask, const
         read_counters(c);
         harvest();
         if (h[3] == 0) break;
-        if (launched >= o.max_sweeps) {
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
+        if (launched >= o.max_sweeps)
             fail(MORAP_E_NOT_CONVERGED, "value iteration: " + std::to_string(h[3]) +
                                             " (model, column) pairs still active after " +
                                             std::to_string(launched) + " sweeps");
-        }
     }
-    MORAP_HIP(hipEventRecord(e1, c->stream));
-    MORAP_HIP(hipEventSynchronize(e1));
-    float ms = 0;
-    MORAP_HIP(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    MORAP_HIP(hipEventRecord(wall.b, c->stream));
+    MORAP_HIP(hipEventSynchronize(wall.b));
+    const float ms = wall.elapsed_ms();
     std::vector<int32_t> ps((size_t)c->hm.M * vs.Kp);
     MORAP_HIP(hipMemcpy(ps.data(), c->d_pair_sweeps.p, ps.size() * 4, hipMemcpyDeviceToHost));
     const size_t el = vs.prec == MORAP_F32 ? 4 : 8;
@@ -675,20 +703,20 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
         k::fill_f64(s, x0, 0.0, NS);
         k::fill_f64(s, x1, 0.0, NS);
         k::set_active(s, n, a, iact, ires, ipar, 1);
-        hipEvent_t v0, v1;
-        MORAP_HIP(hipEventCreate(&v0));
-        MORAP_HIP(hipEventCreate(&v1));
-        MORAP_HIP(hipEventRecord(v0, s));
+        EventPair wall;
+        MORAP_HIP(hipEventRecord(wall.a, s));
         k::InstArgs av = a;
         int64_t live_states = NS;
         int64_t vsweeps = 0;
-        EventPairs ev;
+        PooledEvents held(c);
+        EventPairs& ev = held.v;
         while (true) {
             for (int i = 0; i < chunk; ++i) {
                 const bool even = (i & 1) == 0;
                 const bool timed = o.time_kernels && i % kTimedEvery == 0;
                 if (timed) {
-                    ev.emplace_back(take_event(c), take_event(c));
+                    ev.emplace_back(take_event(c), nullptr);
+                    ev.back().second = take_event(c);
                     MORAP_HIP(hipEventRecord(ev.back().first, s));
                 }
                 k::inst_vi_sweep(s, av, c->d_blk_rec.as<int32_t>(), c->d_blk64.as<double>(), c->d_iwc.as<double>(),
@@ -707,6 +735,7 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
                 st.ms_sweep_kernel_refine += t;
                 st.sweep_launches_refine += 1;
                 give_events(c, e);
+                e = {nullptr, nullptr};
             }
             ev.clear();
             if (h[0] == 0) break;
@@ -716,13 +745,9 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
             live_states = live_tiles(iact, 1, av);
         }
         k::select_final(s, a, x0, x1, ipar, 1);
-        MORAP_HIP(hipEventRecord(v1, s));
-        MORAP_HIP(hipEventSynchronize(v1));
-        float vms = 0;
-        MORAP_HIP(hipEventElapsedTime(&vms, v0, v1));
-        (void)hipEventDestroy(v0);
-        (void)hipEventDestroy(v1);
-        st.ms_vi += vms;
+        MORAP_HIP(hipEventRecord(wall.b, s));
+        MORAP_HIP(hipEventSynchronize(wall.b));
+        st.ms_vi += wall.elapsed_ms();
         st.polish_sweeps += vsweeps;
         st.variant_refine = -1;   // instance-major block iteration
     } else {
@@ -752,14 +777,8 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
                           c->vref.Kp, xi);
     }
 
-    hipEvent_t e0, e1;
-    MORAP_HIP(hipEventCreate(&e0));
-    MORAP_HIP(hipEventCreate(&e1));
-    auto cleanup = [&] {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-    };
-    MORAP_HIP(hipEventRecord(e0, s));
+    EventPair wall;
+    MORAP_HIP(hipEventRecord(wall.a, s));
 
     // Attractor rounds with the tolerance tau; states left unranked get the
     // tolerance widened tenfold (up to tau * 1e6) while ranked states keep
@@ -794,7 +813,6 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
     }
     st.rank_rounds += relax_sweeps;
     if (h[0] != 0) {
-        cleanup();
         fail(MORAP_E_IMPROPER, std::to_string(h[0]) + " states cannot reach done through tau-optimal actions");
     }
 
@@ -850,7 +868,6 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
                 }
             c->eK = K;
             c->evaluated = true;
-            cleanup();
             fail(MORAP_E_NOT_CONVERGED, "policy evaluation did not converge after " + std::to_string(esweeps) +
                                             " sweeps:" + who);
         }
@@ -861,11 +878,9 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
     k::gather_init(s, n, c->d_init_idx.as<int64_t>(), xe0, ival);
     std::vector<double> vals((size_t)2 * n);
     MORAP_HIP(hipMemcpyAsync(vals.data(), ival, vals.size() * 8, hipMemcpyDeviceToHost, s));
-    MORAP_HIP(hipEventRecord(e1, s));
-    MORAP_HIP(hipEventSynchronize(e1));
-    float ms = 0;
-    MORAP_HIP(hipEventElapsedTime(&ms, e0, e1));
-    cleanup();
+    MORAP_HIP(hipEventRecord(wall.b, s));
+    MORAP_HIP(hipEventSynchronize(wall.b));
+    const float ms = wall.elapsed_ms();
 
     if (r_out) {
         std::fill(r_out, r_out + (size_t)K * d, 0.0);

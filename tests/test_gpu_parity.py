@@ -391,6 +391,28 @@ def test_single_agent_single_task_query(ctx, morap):
     assert verdicts == {alg.FEASIBLE, alg.INFEASIBLE}
 
 
+def test_timed_solves_match_untimed(ctx, morap):
+    """Sampled launch timing (``time_kernels``, which the benchmark uses)
+    changes no value: a timed solve enqueues the same launches directly
+    instead of replaying graphs.  Its events go back to the context's pool
+    also when a solve fails part-way, and a timed solve after a failed one
+    still works."""
+    wl = make_workload(2, n_agents=3, n_tasks=6)
+    _load(ctx, wl)
+    W = dirichlet_weights(np.random.default_rng(9), 64, 9)
+    c0, _ = ctx.solve(W, morap.Options(eps_vi=1e-6, precision="f32"))
+    with pytest.raises(morap.MorapError) as e:
+        ctx.solve(W, morap.Options(eps_vi=1e-6, precision="f32", time_kernels=True, max_sweeps=4, check_every=2))
+    assert e.value.code == morap.E_NOT_CONVERGED
+    c1, s1 = ctx.solve(W, morap.Options(eps_vi=1e-6, precision="f32", time_kernels=True))
+    assert np.array_equal(c0, c1)
+    assert s1["sweep_launches"] > 0 and s1["ms_sweep_kernel"] > 0
+    r0, a0, _, _ = ctx.support(W[:4], morap.Options(eps_vi=1e-6, precision="f32"))
+    r1, a1, _, s2 = ctx.support(W[:4], morap.Options(eps_vi=1e-6, precision="f32", time_kernels=True))
+    assert np.array_equal(a0, a1) and np.array_equal(r0, r1)
+    assert s2["sweep_launches_refine"] > 0 and s2["ms_sweep_kernel_refine"] > 0
+
+
 def _team_model(team, w):
     """The team MDP scalarised for one weight vector, as a caller-built model
     with a single objective (the reward in the cost column).  States without
