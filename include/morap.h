@@ -208,6 +208,12 @@ int morap_evaluate(morap_ctx* ctx, const int32_t* assign, int K, const morap_vi_
  * Errors: INVALID. */
 int morap_assign(morap_ctx* ctx, const double* c, int K, int32_t* assign_out);
 
+/* The same assignment without a context (host only, no device touched), for
+ * c[K][n_agents][n_tasks] given by the caller: assign_out[K][n_tasks] holds
+ * the agent of each task.  Caller-owned buffers.  Errors: INVALID (sizes,
+ * NULL pointers, a non-finite value). */
+int morap_assign_host(const double* c, int n_agents, int n_tasks, int K, int32_t* assign_out);
+
 /* Alg. 2 whole, for K weight vectors: solve -> assignment -> evaluate.
  * r_out[K][d], assign_out[K][|J|] (nullable), c_out[K][|I|][|J|] (nullable).
  * Errors: as morap_solve and morap_evaluate. */

@@ -174,6 +174,17 @@ int morap_assign(morap_ctx* ctx, const double* c, int K, int32_t* assign_out) {
     });
 }
 
+int morap_assign_host(const double* c, int n_agents, int n_tasks, int K, int32_t* assign_out) {
+    try {
+        assign_columns(n_agents, n_tasks, c, K, assign_out);
+        return MORAP_OK;
+    } catch (const MorapError& e) {
+        return e.code;
+    } catch (...) {
+        return MORAP_E_INVALID;
+    }
+}
+
 int morap_support(morap_ctx* ctx, const double* W, int K, const morap_vi_opts* opts, double* r_out,
                   int32_t* assign_out, double* c_out, morap_stats* stats) {
     return guarded(ctx, [&] {

@@ -116,6 +116,7 @@ _sig("morap_default_opts", None, C.POINTER(ViOpts))
 _sig("morap_solve", C.c_int, _ctxp, _p, C.c_int, C.POINTER(ViOpts), _p, C.POINTER(Stats))
 _sig("morap_evaluate", C.c_int, _ctxp, _p, C.c_int, C.POINTER(ViOpts), _p, C.POINTER(Stats))
 _sig("morap_assign", C.c_int, _ctxp, _p, C.c_int, _p)
+_sig("morap_assign_host", C.c_int, _p, C.c_int, C.c_int, C.c_int, _p)
 _sig("morap_support", C.c_int, _ctxp, _p, C.c_int, C.POINTER(ViOpts), _p, _p, _p, C.POINTER(Stats))
 _sig("morap_get_policy", C.c_int, _ctxp, C.c_int, C.c_int, _p)
 _sig("morap_get_stats", C.c_int, _ctxp, C.POINTER(Stats))
@@ -172,6 +173,19 @@ class Options:
         o.use_graph = 1 if self.use_graph else 0
         o.time_kernels = 1 if self.time_kernels else 0
         return o
+
+
+def assign_host(c):
+    """Alg. 2's assignment on the host, no context: c [K, nI, nJ] -> the
+    agent of each task, [K, nJ]."""
+    c = np.asarray(c, dtype=np.float64)
+    c = _c(c[None] if c.ndim == 2 else c, np.float64)
+    K, nI, nJ = c.shape
+    out = np.zeros((K, nJ), np.int32)
+    rc = lib.morap_assign_host(_ptr(c), nI, nJ, K, _ptr(out))
+    if rc:
+        raise MorapError(rc, "assignment failed")
+    return out
 
 
 def project_inner(Phi, t, M=None):

@@ -98,3 +98,61 @@ def test_projections_stress_against_oracle(mode):
         t2 = R.max(0) + rng.uniform(-1, 2, d)
         assert np.abs(morap.project_outer(W, R, t2) - geometry.project_outer(W, R, t2)).max() <= 1e-9 * max(
             1.0, np.abs(t2).max())
+
+
+# --------------------------------------------------------------------------
+# Alg. 2's assignment step on the host (the library's Hungarian method)
+# --------------------------------------------------------------------------
+def _value(c, f):
+    return sum(c[f[j], j] for j in range(c.shape[1]))
+
+
+def _valid(f, nI, nJ):
+    cap = max(1, -(-nJ // nI))
+    return f.shape == (nJ,) and (f >= 0).all() and (f < nI).all() and np.bincount(f, minlength=nI).max() <= cap
+
+
+@pytest.mark.parametrize("nI,nJ", [(1, 1), (3, 3), (2, 5), (3, 7), (4, 2), (4, 7)])
+def test_assignment_equals_brute_force(nI, nJ):
+    """Every assignment with at most ceil(|J|/|I|) tasks per agent is
+    enumerated; the library's optimum reaches the best value."""
+    import itertools
+    from paper_2305_04397_amd import morap
+    rng = np.random.default_rng(nI * 10 + nJ)
+    cap = max(1, -(-nJ // nI))
+    C = rng.normal(size=(5, nI, nJ)) * rng.uniform(0.1, 10)
+    F = morap.assign_host(C)
+    for k in range(C.shape[0]):
+        best = max(_value(C[k], f) for f in itertools.product(range(nI), repeat=nJ)
+                   if np.bincount(f, minlength=nI).max() <= cap)
+        assert _valid(F[k], nI, nJ)
+        assert _value(C[k], F[k]) == pytest.approx(best, abs=1e-9)
+
+
+@pytest.mark.parametrize("nI,nJ,K", [(50, 100, 64), (10, 20, 200), (30, 30, 3)])
+def test_assignment_matches_oracle_at_workload_sizes(nI, nJ, K):
+    """At the workloads' sizes (and with enough columns for the threaded
+    path), the optimum equals the oracle's (scipy's Hungarian on the
+    replicated matrix)."""
+    from paper_2305_04397_amd import morap
+    from oracle import alg
+    rng = np.random.default_rng(nI + nJ + K)
+    C = -rng.uniform(0, 200, size=(K, nI, nJ)) + rng.uniform(0, 1, size=(K, 1, nJ))
+    F = morap.assign_host(C)
+    for k in range(K):
+        assert _valid(F[k], nI, nJ)
+        fo = alg.assign(C[k])
+        assert _value(C[k], F[k]) == pytest.approx(_value(C[k], fo), rel=1e-12, abs=1e-9)
+
+
+def test_assignment_rejects_bad_input():
+    from paper_2305_04397_amd import morap
+    C = np.zeros((2, 3, 3))
+    C[1, 2, 0] = np.nan
+    with pytest.raises(morap.MorapError) as e:
+        morap.assign_host(C)
+    assert e.value.code == morap.E_INVALID
+    out = np.zeros(3, np.int32)
+    assert morap.lib.morap_assign_host(None, 3, 3, 1, out.ctypes.data) == morap.E_INVALID
+    assert morap.lib.morap_assign_host(np.zeros(9).ctypes.data, 0, 3, 1, out.ctypes.data) == morap.E_INVALID
+    assert morap.lib.morap_assign_host(np.zeros(9).ctypes.data, 3, 3, 0, out.ctypes.data) == morap.E_INVALID
