@@ -123,6 +123,17 @@ int morap_build_products(morap_ctx* ctx, const morap_agent* agents, int n_agents
                          const morap_dfa* tasks, int n_tasks,
                          const int32_t* const* letters);
 
+/* One product M_i (x) A_j on the host only (no context, no device touched):
+ * the model morap_build_products makes for (agent, task, letters), with the
+ * layout of morap_get_model.  sizes_out[4] = {S, R, N, init}.  Call once with
+ * NULL arrays to get the sizes, then with caller-owned arrays of
+ * state_row[S+1], row_ptr[R+1], col[N], prob[N], rew[R][2], to_done[R],
+ * states[S][2] (agent state, location); each array may be NULL.
+ * Errors: INVALID (malformed agent / DFA / letters), OOM. */
+int morap_product_host(const morap_agent* agent, const morap_dfa* task, const int32_t* letters,
+                       int32_t* sizes_out, int32_t* state_row, int32_t* row_ptr, int32_t* col,
+                       double* prob, double* rew, uint8_t* to_done, int32_t* states);
+
 /* Load caller-built product models (same semantics as above).  models[m] must
  * have agent = m / n_tasks and task = m % n_tasks, m < n_agents * n_tasks.
  * Errors: INVALID (structure, ranges, row sums outside [0, 1+1e-6],

@@ -174,6 +174,19 @@ int morap_assign(morap_ctx* ctx, const double* c, int K, int32_t* assign_out) {
     });
 }
 
+int morap_product_host(const morap_agent* agent, const morap_dfa* task, const int32_t* letters,
+                       int32_t* sizes_out, int32_t* state_row, int32_t* row_ptr, int32_t* col, double* prob,
+                       double* rew, uint8_t* to_done, int32_t* states) {
+    try {
+        product_host(agent, task, letters, sizes_out, state_row, row_ptr, col, prob, rew, to_done, states);
+        return MORAP_OK;
+    } catch (const MorapError& e) {
+        return e.code;
+    } catch (...) {
+        return MORAP_E_OOM;
+    }
+}
+
 int morap_assign_host(const double* c, int n_agents, int n_tasks, int K, int32_t* assign_out) {
     try {
         assign_columns(n_agents, n_tasks, c, K, assign_out);

@@ -271,6 +271,11 @@ int guarded(morap_ctx* c, F&& f) {
 void build_products(morap_ctx* ctx, const morap_agent* agents, int nI, const morap_dfa* tasks, int nJ,
                     const int32_t* const* letters);
 void load_models(morap_ctx* ctx, const morap_model* models, int n, int nI, int nJ);
+// one product on the host (no context, no device): sizes = {S, R, N, init},
+// arrays filled where non-NULL
+void product_host(const morap_agent* a, const morap_dfa* t, const int32_t* letters, int32_t* sizes,
+                  int32_t* state_row, int32_t* row_ptr, int32_t* col, double* prob, double* rew, uint8_t* to_done,
+                  int32_t* states);
 void upload_models(morap_ctx* ctx);
 
 // solver.cpp

@@ -354,6 +354,29 @@ static void build_blocks(morap_ctx* c, const morap_agent* agents, int nI, const 
     hm.blk_agent = std::move(ublk);
 }
 
+void product_host(const morap_agent* a, const morap_dfa* t, const int32_t* letters, int32_t* sizes,
+                  int32_t* state_row, int32_t* row_ptr, int32_t* col, double* prob, double* rew, uint8_t* to_done,
+                  int32_t* states) {
+    MORAP_CHECK(a && t && letters && sizes, MORAP_E_INVALID, "bad arguments");
+    validate_agent(*a, 0);
+    validate_dfa(*t, 0);
+    for (int s = 0; s < a->n_states; ++s)
+        MORAP_CHECK(letters[s] >= 0 && letters[s] < t->n_letters, MORAP_E_INVALID, "letter out of range");
+    const Built b = build_one(*a, *t, letters);
+    const int32_t S = (int32_t)b.state_row.size() - 1, R = (int32_t)b.row_ptr.size() - 1, N = (int32_t)b.col.size();
+    sizes[0] = S;
+    sizes[1] = R;
+    sizes[2] = N;
+    sizes[3] = b.init;
+    if (state_row) std::copy(b.state_row.begin(), b.state_row.end(), state_row);
+    if (row_ptr) std::copy(b.row_ptr.begin(), b.row_ptr.end(), row_ptr);
+    if (col) std::copy(b.col.begin(), b.col.end(), col);
+    if (prob) std::copy(b.prob.begin(), b.prob.end(), prob);
+    if (rew) std::copy(b.rew.begin(), b.rew.end(), rew);
+    if (to_done) std::copy(b.to_done.begin(), b.to_done.end(), to_done);
+    if (states) std::copy(b.states_sq.begin(), b.states_sq.end(), states);
+}
+
 void build_products(morap_ctx* c, const morap_agent* agents, int nI, const morap_dfa* tasks, int nJ,
                     const int32_t* const* letters) {
     MORAP_CHECK(agents && tasks && letters && nI > 0 && nJ > 0, MORAP_E_INVALID, "bad arguments");

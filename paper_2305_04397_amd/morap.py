@@ -117,6 +117,7 @@ _sig("morap_solve", C.c_int, _ctxp, _p, C.c_int, C.POINTER(ViOpts), _p, C.POINTE
 _sig("morap_evaluate", C.c_int, _ctxp, _p, C.c_int, C.POINTER(ViOpts), _p, C.POINTER(Stats))
 _sig("morap_assign", C.c_int, _ctxp, _p, C.c_int, _p)
 _sig("morap_assign_host", C.c_int, _p, C.c_int, C.c_int, C.c_int, _p)
+_sig("morap_product_host", C.c_int, C.POINTER(Agent), C.POINTER(Dfa), _p, _p, _p, _p, _p, _p, _p, _p, _p)
 _sig("morap_support", C.c_int, _ctxp, _p, C.c_int, C.POINTER(ViOpts), _p, _p, _p, C.POINTER(Stats))
 _sig("morap_get_policy", C.c_int, _ctxp, C.c_int, C.c_int, _p)
 _sig("morap_get_stats", C.c_int, _ctxp, C.POINTER(Stats))
@@ -173,6 +174,31 @@ class Options:
         o.use_graph = 1 if self.use_graph else 0
         o.time_kernels = 1 if self.time_kernels else 0
         return o
+
+
+def product_host(agent, task, letters) -> dict:
+    """One agent x task product built on the host, no context (the layout of
+    ``Context.get_model``)."""
+    arrs = [_c(agent.sa_ptr, np.int32), _c(agent.succ, np.int32), _c(agent.prob, np.float64),
+            _c(agent.cost, np.float64)]
+    a = Agent(agent.n_states, agent.n_actions, agent.init, *[_ptr(x) for x in arrs])
+    tarrs = [_c(task.delta, np.int32), _c(task.accepting, np.uint8)]
+    t = Dfa(task.n_locs, task.n_letters, task.q0, *[_ptr(x) for x in tarrs])
+    lets = _c(letters, np.int32)
+    sizes = np.zeros(4, np.int32)
+    rc = lib.morap_product_host(C.byref(a), C.byref(t), _ptr(lets), _ptr(sizes), *([None] * 7))
+    if rc:
+        raise MorapError(rc, "product construction failed")
+    S, R, N, init = (int(v) for v in sizes)
+    out = {"state_row": np.zeros(S + 1, np.int32), "row_ptr": np.zeros(R + 1, np.int32),
+           "col": np.zeros(N, np.int32), "prob": np.zeros(N), "rew": np.zeros((R, 2)),
+           "to_done": np.zeros(R, np.uint8), "states": np.zeros((S, 2), np.int32), "init": init}
+    rc = lib.morap_product_host(C.byref(a), C.byref(t), _ptr(lets), _ptr(sizes),
+                                *[_ptr(out[k]) for k in ("state_row", "row_ptr", "col", "prob", "rew", "to_done",
+                                                         "states")])
+    if rc:
+        raise MorapError(rc, "product construction failed")
+    return out
 
 
 def assign_host(c):

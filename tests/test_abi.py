@@ -156,3 +156,49 @@ def test_assignment_rejects_bad_input():
     assert morap.lib.morap_assign_host(None, 3, 3, 1, out.ctypes.data) == morap.E_INVALID
     assert morap.lib.morap_assign_host(np.zeros(9).ctypes.data, 0, 3, 1, out.ctypes.data) == morap.E_INVALID
     assert morap.lib.morap_assign_host(np.zeros(9).ctypes.data, 3, 3, 0, out.ctypes.data) == morap.E_INVALID
+
+
+# --------------------------------------------------------------------------
+# product construction on the host (Sec. 2 "Product MDP", Sec. 3.1)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["example", "cfg1", "cfg2_sub", "tiny", "q0_accepting"])
+def test_host_products_bit_exact(name):
+    """The library's product builder, called without a context, gives the
+    oracle's product bit for bit: states in (q, s) order, rows, successors,
+    probabilities, both reward columns, the to-done flags and the initial
+    state (-1 and no states when q0 is already accepting)."""
+    from paper_2305_04397_amd import morap
+    from workloads import worked_example, make_workload, tiny_workload
+    from oracle import product
+    if name == "q0_accepting":
+        wl = worked_example()
+        wl.tasks[0].q0 = 1
+    else:
+        wl = {"example": worked_example, "cfg1": lambda: make_workload(1),
+              "cfg2_sub": lambda: make_workload(2, n_agents=3, n_tasks=5),
+              "tiny": lambda: tiny_workload(5, 2, 3, width=3, height=3, kinds=("avoid", "reach"))}[name]()
+    for i, ag in enumerate(wl.agents):
+        for j, tk in enumerate(wl.tasks):
+            g = morap.product_host(ag, tk, wl.letters[i][j])
+            o = product.build_product(ag, tk, wl.letters[i][j])
+            assert g["init"] == o.init
+            assert g["state_row"].tolist() == o.state_row.tolist()
+            assert g["row_ptr"].tolist() == o.row_ptr.tolist()
+            assert g["col"].tolist() == o.col.tolist()
+            assert np.array_equal(g["prob"], o.prob)
+            assert np.array_equal(g["rew"][:, 0], o.rew_cost) and np.array_equal(g["rew"][:, 1], o.rew_prob)
+            assert g["to_done"].astype(bool).tolist() == o.to_done.tolist()
+            assert g["states"].tolist() == o.states.tolist()
+    if name == "q0_accepting":
+        assert g["init"] == -1 and len(g["state_row"]) == 1
+
+
+def test_host_product_rejects_bad_letters():
+    from paper_2305_04397_amd import morap
+    from workloads import worked_example
+    wl = worked_example()
+    bad = np.array(wl.letters[0][0]).copy()
+    bad[0] = wl.tasks[0].n_letters
+    with pytest.raises(morap.MorapError) as e:
+        morap.product_host(wl.agents[0], wl.tasks[0], bad)
+    assert e.value.code == morap.E_INVALID
