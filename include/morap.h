@@ -20,6 +20,9 @@
  *     costs (as negative rewards) and |I|..d-1 the tasks' completion
  *     probabilities (Alg. 1 input t = (c, p), Def. MORAP).
  *   - Model index m = i * |J| + j for agent i and task j.
+ *   - Calls without a context (morap_product_host, morap_assign_host,
+ *     morap_project_inner, morap_project_outer) run on the host only, touch
+ *     no device, and report errors by their return code alone.
  */
 #ifndef MORAP_H
 #define MORAP_H
