@@ -202,3 +202,37 @@ def test_host_product_rejects_bad_letters():
     with pytest.raises(morap.MorapError) as e:
         morap.product_host(wl.agents[0], wl.tasks[0], bad)
     assert e.value.code == morap.E_INVALID
+
+
+@pytest.mark.parametrize("case", ["duplicates", "collinear", "one_dim", "repeated_halfspaces"])
+def test_projections_on_degenerate_sets(case):
+    """Inputs Alg. 1 really produces: the same support point twice (two passes
+    that return one point), points on a line, a single objective, and the same
+    hyperplane recorded twice.  The library's projections agree with the
+    oracle's and satisfy the optimality conditions."""
+    from paper_2305_04397_amd import morap
+    rng = np.random.default_rng(len(case))
+    d = 1 if case == "one_dim" else 5
+    base = rng.normal(size=(3, d)) * 10
+    if case == "duplicates":
+        Phi = np.vstack([base, base[:2]])
+    elif case == "collinear":
+        a, b = base[0], base[1]
+        Phi = np.array([a + s * (b - a) for s in (0.0, 0.25, 0.5, 1.0)])
+    else:
+        Phi = base
+    for t in (Phi.max(0) + 1.0, Phi.mean(0), Phi.min(0) - 1.0, Phi.max(0) + rng.uniform(-2, 2, d)):
+        x, lam = morap.project_inner(Phi, t)
+        xo, _ = geometry.project_inner(Phi, t)
+        sc = max(1.0, np.abs(t).max())
+        assert np.abs(x - xo).max() <= 1e-9 * sc
+        assert geometry.kkt_inner(Phi, t, x, lam) <= 1e-9 * sc
+        W = rng.dirichlet(np.ones(d), size=len(Phi))
+        if case == "repeated_halfspaces":
+            W = np.vstack([W, W[:2]])
+            R = np.vstack([Phi, Phi[:2]])
+        else:
+            R = Phi
+        z = morap.project_outer(W, R, t)
+        assert np.abs(z - geometry.project_outer(W, R, t)).max() <= 1e-9 * sc
+        assert (W @ z <= np.einsum("ij,ij->i", W, R) + 1e-9 * sc).all()
