@@ -236,3 +236,15 @@ def test_projections_on_degenerate_sets(case):
         z = morap.project_outer(W, R, t)
         assert np.abs(z - geometry.project_outer(W, R, t)).max() <= 1e-9 * sc
         assert (W @ z <= np.einsum("ij,ij->i", W, R) + 1e-9 * sc).all()
+
+
+@pytest.mark.parametrize("nI,nJ", [(3, 3), (2, 5), (4, 2)])
+def test_assignment_under_ties_is_valid(nI, nJ):
+    """All-equal values and values equal per task (every assignment optimal):
+    the result is still a valid assignment within each agent's capacity."""
+    from paper_2305_04397_amd import morap
+    C = np.stack([np.zeros((nI, nJ)), np.tile(np.arange(nJ, dtype=float), (nI, 1))])
+    F = morap.assign_host(C)
+    for k in range(2):
+        assert _valid(F[k], nI, nJ)
+        assert _value(C[k], F[k]) == pytest.approx(C[k].max(axis=0).sum(), abs=1e-12)
