@@ -132,7 +132,8 @@ int morap_build_products(morap_ctx* ctx, const morap_agent* agents, int n_agents
  * NULL arrays to get the sizes, then with caller-owned arrays of
  * state_row[S+1], row_ptr[R+1], col[N], prob[N], rew[R][2], to_done[R],
  * states[S][2] (agent state, location); each array may be NULL.
- * Errors: INVALID (malformed agent / DFA / letters), OOM. */
+ * Errors: INVALID (malformed agent / DFA / letters), OOM, UNSUPPORTED (more
+ * than 2^31-1 states, rows or entries). */
 int morap_product_host(const morap_agent* agent, const morap_dfa* task, const int32_t* letters,
                        int32_t* sizes_out, int32_t* state_row, int32_t* row_ptr, int32_t* col,
                        double* prob, double* rew, uint8_t* to_done, int32_t* states);

@@ -363,6 +363,9 @@ void product_host(const morap_agent* a, const morap_dfa* t, const int32_t* lette
     for (int s = 0; s < a->n_states; ++s)
         MORAP_CHECK(letters[s] >= 0 && letters[s] < t->n_letters, MORAP_E_INVALID, "letter out of range");
     const Built b = build_one(*a, *t, letters);
+    const size_t lim = 0x7fffffff;
+    MORAP_CHECK(b.state_row.size() <= lim && b.row_ptr.size() <= lim && b.col.size() < lim, MORAP_E_UNSUPPORTED,
+                "more than 2^31-1 states, rows or entries");
     const int32_t S = (int32_t)b.state_row.size() - 1, R = (int32_t)b.row_ptr.size() - 1, N = (int32_t)b.col.size();
     sizes[0] = S;
     sizes[1] = R;
