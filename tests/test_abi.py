@@ -248,3 +248,17 @@ def test_assignment_under_ties_is_valid(nI, nJ):
     for k in range(2):
         assert _valid(F[k], nI, nJ)
         assert _value(C[k], F[k]) == pytest.approx(C[k].max(axis=0).sum(), abs=1e-12)
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """The binding has no fallback: a copy of it beside no built library
+    refuses to import, naming the missing file."""
+    import importlib.util
+    import shutil
+    src = os.path.join(ROOT, "paper_2305_04397_amd", "morap.py")
+    dst = tmp_path / "morap_copy.py"
+    shutil.copy(src, dst)
+    spec = importlib.util.spec_from_file_location("morap_copy", dst)
+    mod = importlib.util.module_from_spec(spec)
+    with pytest.raises(ImportError, match="libmorap.so is missing"):
+        spec.loader.exec_module(mod)
