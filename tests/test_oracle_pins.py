@@ -788,3 +788,69 @@ def test_stage_ordered_vi_trades_updates_for_sweeps():
     assert (ss.sum(axis=0) > sp_).all()
     assert (ss.max(axis=0) <= sp_ + 1).all()
     assert np.abs(xs - xp).max() <= 1e-4
+
+
+# --------------------------------------------------------------------------
+# the pins have teeth: a plausible mistake planted in the oracle (on the CPU,
+# through monkeypatch) makes the independent check disagree far beyond its
+# tolerance
+# --------------------------------------------------------------------------
+def _lp_gap(prods, w):
+    Aeq, beq, obj = _mo_lp(prods, 2, 2)
+    lp = linprog(-(w @ obj), A_eq=Aeq, b_eq=beq, bounds=[(0, None)] * Aeq.shape[1], method="highs")
+    assert lp.status == 0
+    return abs(w @ alg.support(prods, 2, 2, w, 1e-13).r - (-lp.fun))
+
+
+def test_mutation_dropped_probability_term_fails_the_lp_pin(monkeypatch):
+    wl = tiny_workload(31, 2, 2, width=3, height=3, kinds=("avoid", "reach"), k=1, p_slip=0.2)
+    prods = product.build_all(wl)
+    w = np.array([0.1, 0.1, 0.4, 0.4])
+    assert _lp_gap(prods, w) <= 1e-8
+    real = vi.scalarised_rewards
+    monkeypatch.setattr(vi, "scalarised_rewards", lambda p, wc, wp: real(p, wc, 0.0 * np.atleast_1d(wp)))
+    assert _lp_gap(prods, w) > 1e-3
+
+
+def test_mutation_cost_sign_fails_the_lp_pin(monkeypatch):
+    wl = tiny_workload(32, 2, 2, width=3, height=3, kinds=("avoid", "reach"), k=1, p_slip=0.2)
+    prods = product.build_all(wl)
+    w = np.array([0.3, 0.3, 0.2, 0.2])
+    assert _lp_gap(prods, w) <= 1e-8
+    real = vi.scalarised_rewards
+    monkeypatch.setattr(vi, "scalarised_rewards", lambda p, wc, wp: real(p, -np.atleast_1d(wc), wp))
+    real_vi = vi.value_iteration      # a diverging iteration is reported after 20k sweeps, not 1M
+    monkeypatch.setattr(vi, "value_iteration",
+                        lambda p, wc, wp, eps, max_sweeps=20_000: real_vi(p, wc, wp, eps, min(max_sweeps, 20_000)))
+    try:
+        failed = _lp_gap(prods, w) > 1e-3
+    except (RuntimeError, vi.ImproperPolicy):
+        failed = True          # rewarding cost makes the iteration diverge
+    assert failed
+
+
+def test_mutation_minimising_assignment_fails_brute_force(monkeypatch):
+    rng = np.random.default_rng(33)
+    c = rng.normal(size=(3, 5))
+    cap = 2
+    best = max(sum(c[f[j], j] for j in range(5)) for f in itertools.product(range(3), repeat=5)
+               if np.bincount(f, minlength=3).max() <= cap)
+    f = alg.assign(c)
+    assert sum(c[f[j], j] for j in range(5)) == pytest.approx(best, abs=1e-12)
+    real = alg.assign
+    monkeypatch.setattr(alg, "assign", lambda m: real(-m))
+    f = alg.assign(c)
+    assert sum(c[f[j], j] for j in range(5)) < best - 1e-3
+
+
+def test_mutation_reversed_stage_order_fails_the_plain_vi_pin(monkeypatch):
+    wl = tiny_workload(73, 1, 1, width=3, height=3, kinds=("reach",), k=4, p_slip=0.2)
+    p = product.build_all(wl)[0]
+    W = np.array([[0.4, 0.6]])
+    xp, _ = vi.value_iteration(p, W[:, 0], W[:, 1], 1e-12)
+    xs, _ = vi.stage_ordered_value_iteration(p, W[:, 0], W[:, 1], 1e-12)
+    assert np.abs(xs - xp).max() <= 1e-9 * max(1.0, np.abs(xp).max())
+    real = vi.location_stages
+    monkeypatch.setattr(vi, "location_stages", lambda q: real(q).max() - real(q))
+    xs, _ = vi.stage_ordered_value_iteration(p, W[:, 0], W[:, 1], 1e-12)
+    assert np.abs(xs - xp).max() > 1e-3
