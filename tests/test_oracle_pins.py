@@ -854,3 +854,17 @@ def test_mutation_reversed_stage_order_fails_the_plain_vi_pin(monkeypatch):
     monkeypatch.setattr(vi, "location_stages", lambda q: real(q).max() - real(q))
     xs, _ = vi.stage_ordered_value_iteration(p, W[:, 0], W[:, 1], 1e-12)
     assert np.abs(xs - xp).max() > 1e-3
+
+
+def test_mutation_frozen_weight_update_fails_the_projection_pin(monkeypatch):
+    wl = tiny_workload(62, 1, 1, width=3, height=3, kinds=("avoid",), k=2, p_slip=0.2)
+    prods = product.build_all(wl)
+    Aeq, beq, obj = _mo_lp(prods, 1, 1)
+    r1 = alg.support(prods, 1, 1, np.array([1.0, 0.0]), 1e-13).r
+    r2 = alg.support(prods, 1, 1, np.array([0.0, 1.0]), 1e-13).r
+    t = 0.2 * r1 + 0.8 * r2 + np.array([0.5, 0.1])
+    dist, p = _projection_by_support(obj, Aeq, beq, t)
+    bound = np.sqrt(2 * dist * 1e-9) + 1e-7
+    assert np.linalg.norm(alg.query(prods, 1, 1, t, 1e-9, 1e-13, max_iter=200).t_up - p) <= bound
+    monkeypatch.setattr(geometry, "weight_from", lambda t, t_up, M=None: np.full(len(t), 1.0 / len(t)))
+    assert np.linalg.norm(alg.query(prods, 1, 1, t, 1e-9, 1e-13, max_iter=40).t_up - p) > 1e-3
