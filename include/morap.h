@@ -20,9 +20,10 @@
  *     costs (as negative rewards) and |I|..d-1 the tasks' completion
  *     probabilities (Alg. 1 input t = (c, p), Def. MORAP).
  *   - Model index m = i * |J| + j for agent i and task j.
- *   - Calls without a context (morap_product_host, morap_assign_host,
- *     morap_project_inner, morap_project_outer) run on the host only, touch
- *     no device, and report errors by their return code alone.
+ *   - Calls without a context (morap_product_host, morap_team_model_host,
+ *     morap_assign_host, morap_project_inner, morap_project_outer) run on
+ *     the host only, touch no device, and report errors by their return code
+ *     alone.
  */
 #ifndef MORAP_H
 #define MORAP_H
@@ -222,6 +223,25 @@ int morap_evaluate(morap_ctx* ctx, const int32_t* assign, int K, const morap_vi_
  * most ceil(|J|/|I|) tasks per agent (Hungarian method, O(n^3)).
  * Errors: INVALID. */
 int morap_assign(morap_ctx* ctx, const double* c, int K, int32_t* assign_out);
+
+/* The team MDP of the decentralised model (Sec. 3.1, Def. teamMDP) for n
+ * agents and n tasks (n_agents = n_tasks = n <= 16, else INVALID),
+ * scalarised for one weight vector w[2n] and
+ * laid out as one caller-built model for morap_load_models with one agent and
+ * one task, to be solved with the weight row (1, 0): rew[r][0] = w . (the
+ * objective vector of row r), rew[r][1] = 0.  A state is (agent, task, agent
+ * state, task location, committed agents); its rows are the committed agent's
+ * actions, the zero-reward switches that commit an agent or hand a task on at
+ * its start and start the next task once one is done, or else one empty row
+ * (value 0).  letters[i * n + j] as in morap_build_products.  Host only, no
+ * context; two calls as morap_product_host (sizes_out = {S, R, N, init}).
+ * Its optimum from the initial state is the best assignment's (Lemma
+ * lem:ct-mdp-prop).  Errors: INVALID, UNSUPPORTED (the state count is
+ * exponential in n), OOM. */
+int morap_team_model_host(const morap_agent* agents, int n_agents, const morap_dfa* tasks,
+                          int n_tasks, const int32_t* const* letters, const double* w,
+                          int32_t* sizes_out, int32_t* state_row, int32_t* row_ptr, int32_t* col,
+                          double* prob, double* rew, uint8_t* to_done);
 
 /* The same assignment without a context (host only, no device touched), for
  * c[K][n_agents][n_tasks] given by the caller: assign_out[K][n_tasks] holds

@@ -187,6 +187,20 @@ int morap_product_host(const morap_agent* agent, const morap_dfa* task, const in
     }
 }
 
+int morap_team_model_host(const morap_agent* agents, int n_agents, const morap_dfa* tasks, int n_tasks,
+                          const int32_t* const* letters, const double* w, int32_t* sizes_out, int32_t* state_row,
+                          int32_t* row_ptr, int32_t* col, double* prob, double* rew, uint8_t* to_done) {
+    try {
+        team_model_host(agents, n_agents, tasks, n_tasks, letters, w, sizes_out, state_row, row_ptr, col, prob, rew,
+                        to_done);
+        return MORAP_OK;
+    } catch (const MorapError& e) {
+        return e.code;
+    } catch (...) {
+        return MORAP_E_OOM;
+    }
+}
+
 int morap_assign_host(const double* c, int n_agents, int n_tasks, int K, int32_t* assign_out) {
     try {
         assign_columns(n_agents, n_tasks, c, K, assign_out);

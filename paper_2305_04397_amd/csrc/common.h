@@ -271,6 +271,16 @@ int guarded(morap_ctx* c, F&& f) {
 void build_products(morap_ctx* ctx, const morap_agent* agents, int nI, const morap_dfa* tasks, int nJ,
                     const int32_t* const* letters);
 void load_models(morap_ctx* ctx, const morap_model* models, int n, int nI, int nJ);
+// agent / automaton validation (INVALID on malformed input) and the done
+// locations of an automaton (accepting, or no run reaches acceptance)
+void check_agent(const morap_agent& a, int i);
+void check_dfa(const morap_dfa& t, int j);
+std::vector<uint8_t> dfa_done(const morap_dfa& t);
+// the team MDP of Def. teamMDP scalarised for one weight vector, as a
+// single-objective model (host only): sizes = {S, R, N, init}
+void team_model_host(const morap_agent* agents, int n_agents, const morap_dfa* tasks, int n_tasks,
+                     const int32_t* const* letters, const double* w, int32_t* sizes, int32_t* state_row,
+                     int32_t* row_ptr, int32_t* col, double* prob, double* rew, uint8_t* to_done);
 // one product on the host (no context, no device): sizes = {S, R, N, init},
 // arrays filled where non-NULL
 void product_host(const morap_agent* a, const morap_dfa* t, const int32_t* letters, int32_t* sizes,

@@ -156,6 +156,10 @@ Built build_one(const morap_agent& a, const morap_dfa& t, const int32_t* letters
 
 }  // namespace
 
+void check_agent(const morap_agent& a, int i) { validate_agent(a, i); }
+void check_dfa(const morap_dfa& t, int j) { validate_dfa(t, j); }
+std::vector<uint8_t> dfa_done(const morap_dfa& t) { return done_locations(t); }
+
 static void concat(morap_ctx* c, std::vector<Built>& parts, int nI, int nJ) {
     HostModels hm;
     hm.nI = nI;

@@ -118,6 +118,8 @@ _sig("morap_evaluate", C.c_int, _ctxp, _p, C.c_int, C.POINTER(ViOpts), _p, C.POI
 _sig("morap_assign", C.c_int, _ctxp, _p, C.c_int, _p)
 _sig("morap_assign_host", C.c_int, _p, C.c_int, C.c_int, C.c_int, _p)
 _sig("morap_product_host", C.c_int, C.POINTER(Agent), C.POINTER(Dfa), _p, _p, _p, _p, _p, _p, _p, _p, _p)
+_sig("morap_team_model_host", C.c_int, C.POINTER(Agent), C.c_int, C.POINTER(Dfa), C.c_int, C.POINTER(_p), _p, _p,
+     _p, _p, _p, _p, _p, _p)
 _sig("morap_support", C.c_int, _ctxp, _p, C.c_int, C.POINTER(ViOpts), _p, _p, _p, C.POINTER(Stats))
 _sig("morap_get_policy", C.c_int, _ctxp, C.c_int, C.c_int, _p)
 _sig("morap_get_stats", C.c_int, _ctxp, C.POINTER(Stats))
@@ -198,6 +200,45 @@ def product_host(agent, task, letters) -> dict:
                                                          "states")])
     if rc:
         raise MorapError(rc, "product construction failed")
+    return out
+
+
+def team_model_host(workload, w) -> dict:
+    """The team MDP of ``workload`` (|I| = |J|) scalarised for the weight
+    vector w, as one single-objective model for ``Context.load_models`` (a
+    1 x 1 problem solved with the weight row (1, 0))."""
+    n = workload.n_agents
+    keep = []
+    agents = (Agent * n)()
+    for i, a in enumerate(workload.agents):
+        arrs = [_c(a.sa_ptr, np.int32), _c(a.succ, np.int32), _c(a.prob, np.float64), _c(a.cost, np.float64)]
+        keep += arrs
+        agents[i] = Agent(a.n_states, a.n_actions, a.init, *[_ptr(x) for x in arrs])
+    tasks = (Dfa * workload.n_tasks)()
+    for j, t in enumerate(workload.tasks):
+        arrs = [_c(t.delta, np.int32), _c(t.accepting, np.uint8)]
+        keep += arrs
+        tasks[j] = Dfa(t.n_locs, t.n_letters, t.q0, *[_ptr(x) for x in arrs])
+    lets = (_p * (n * workload.n_tasks))()
+    for i in range(n):
+        for j in range(workload.n_tasks):
+            arr = _c(workload.letters[i][j], np.int32)
+            keep.append(arr)
+            lets[i * workload.n_tasks + j] = arr.ctypes.data
+    wv = _c(w, np.float64)
+    sizes = np.zeros(4, np.int32)
+    nJ = workload.n_tasks
+    rc = lib.morap_team_model_host(agents, n, tasks, nJ, lets, _ptr(wv), _ptr(sizes), *([None] * 6))
+    if rc:
+        raise MorapError(rc, "team MDP construction failed")
+    S, R, N, init = (int(v) for v in sizes)
+    out = {"state_row": np.zeros(S + 1, np.int32), "row_ptr": np.zeros(R + 1, np.int32),
+           "col": np.zeros(N, np.int32), "prob": np.zeros(N), "rew": np.zeros((R, 2)),
+           "to_done": np.zeros(R, np.uint8), "init": init}
+    rc = lib.morap_team_model_host(agents, n, tasks, nJ, lets, _ptr(wv), _ptr(sizes),
+                                   *[_ptr(out[k]) for k in ("state_row", "row_ptr", "col", "prob", "rew", "to_done")])
+    if rc:
+        raise MorapError(rc, "team MDP construction failed")
     return out
 
 

@@ -5,6 +5,7 @@ import os
 import re
 
 import numpy as np
+import scipy.sparse as sp
 import pytest
 
 from oracle import geometry
@@ -262,3 +263,49 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
     mod = importlib.util.module_from_spec(spec)
     with pytest.raises(ImportError, match="libmorap.so is missing"):
         spec.loader.exec_module(mod)
+
+
+# --------------------------------------------------------------------------
+# the team MDP (Def. teamMDP) built by the library on the host
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n,seed", [(2, 41), (3, 42), (2, 43)])
+def test_host_team_model_equals_the_oracle(n, seed):
+    """The library's team-MDP builder (written separately from the oracle's)
+    gives the oracle's single-objective layout: states, rows, successors,
+    probabilities, to-done flags and the initial state exactly, rewards to
+    one rounding (the oracle's dot product may fuse its multiply-adds).  Its
+    value from the initial state is the oracle's team value."""
+    from paper_2305_04397_amd import morap
+    from workloads import tiny_workload
+    from oracle import centralised
+    kinds = ("reach",) if seed != 43 else ("avoid", "reach")
+    wl = tiny_workload(seed, n, n, width=3, height=2, kinds=kinds, k=1, p_slip=0.25)
+    team = centralised.build_team_mdp(wl)
+    rng = np.random.default_rng(seed)
+    for _ in range(2):
+        w = rng.dirichlet(np.ones(2 * n))
+        g = morap.team_model_host(wl, w)
+        o = centralised.single_objective_model(team, w)
+        for k in ("state_row", "row_ptr", "col", "to_done"):
+            assert g[k].tolist() == o[k].tolist(), k
+        assert np.array_equal(g["prob"], o["prob"]) and g["init"] == o["init"]
+        assert np.abs(g["rew"] - o["rew"]).max() <= 4e-16 * max(1.0, np.abs(o["rew"]).max())
+        # plain VI on the library's model
+        S, R = len(g["state_row"]) - 1, len(g["row_ptr"]) - 1
+        P = sp.csr_matrix((g["prob"], g["col"], g["row_ptr"]), shape=(R, S))
+        x = np.zeros(S)
+        for _ in range(100_000):
+            y = np.maximum.reduceat(g["rew"][:, 0] + P @ x, g["state_row"][:-1])
+            if np.abs(y - x).max() <= 1e-13:
+                break
+            x = y
+        assert y[g["init"]] == pytest.approx(centralised.team_value(team, w), abs=1e-10)
+
+
+def test_host_team_model_rejects_unequal_counts():
+    from paper_2305_04397_amd import morap
+    from workloads import tiny_workload
+    wl = tiny_workload(44, 2, 3, width=3, height=2, kinds=("reach",), k=1)
+    with pytest.raises(morap.MorapError) as e:
+        morap.team_model_host(wl, np.full(5, 0.2))
+    assert e.value.code == morap.E_INVALID

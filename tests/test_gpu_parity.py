@@ -414,28 +414,7 @@ def test_timed_solves_match_untimed(ctx, morap):
 
 
 def _team_model(team, w):
-    """The team MDP scalarised for one weight vector, as a caller-built model
-    with a single objective (the reward in the cost column).  States without
-    rows get an empty one: all mass to done, reward 0, so their value is 0."""
-    state_row, row_ptr, col, prob, rew = [0], [0], [], [], []
-    r = team.rew @ w
-    for s in range(team.n_states):
-        rows = range(team.state_row[s], team.state_row[s + 1])
-        for q in rows:
-            lo, hi = team.row_ptr[q], team.row_ptr[q + 1]
-            col += team.col[lo:hi].tolist()
-            prob += team.prob[lo:hi].tolist()
-            row_ptr.append(len(col))
-            rew.append((r[q], 0.0))
-        if len(rows) == 0:
-            row_ptr.append(len(col))
-            rew.append((0.0, 0.0))
-        state_row.append(len(row_ptr) - 1)
-    row_ptr = np.asarray(row_ptr)
-    prob = np.asarray(prob)
-    sums = np.array([prob[row_ptr[q]:row_ptr[q + 1]].sum() for q in range(len(row_ptr) - 1)])
-    return {"state_row": np.asarray(state_row), "row_ptr": row_ptr, "col": np.asarray(col), "prob": prob,
-            "rew": np.asarray(rew), "to_done": (sums < 1 - 1e-12).astype(np.uint8), "init": team.init}
+    return centralised.single_objective_model(team, w)
 
 
 @pytest.mark.parametrize("n,seed", [(2, 41), (3, 42)])
