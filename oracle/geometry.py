@@ -64,6 +64,11 @@ def nnls(A: np.ndarray, b: np.ndarray, maxiter: int | None = None):
 
 
 
+# Every projection is certified by its optimality conditions: the largest
+# violation (kkt_inner / kkt_outer) must be at most KKT_TOL * max(1, ||t||_inf).
+KKT_TOL = 1e-10
+
+
 def mnorm(v: np.ndarray, M: np.ndarray | None = None) -> float:
     v = np.asarray(v, dtype=np.float64)
     if M is None:
@@ -118,7 +123,7 @@ def project_inner(Phi: np.ndarray, t: np.ndarray, M: np.ndarray | None = None):
     if M is None:
         x, lam = _polish_inner(Phi, t, x, lam)
     viol = kkt_inner(Phi, t, x, lam, M)
-    if viol > 1e-7 * max(1.0, float(np.abs(t).max())):
+    if viol > KKT_TOL * max(1.0, float(np.abs(t).max())):
         raise RuntimeError(f"inner projection failed its optimality check ({viol:.3g})")
     return x, lam
 
@@ -197,7 +202,7 @@ def project_outer(Ws: np.ndarray, Rs: np.ndarray, t: np.ndarray,
         raise RuntimeError("outer approximation is empty")
     out = t + np.linalg.solve(L.T, z)
     viol = kkt_outer(Ws, Rs, t, out, M)
-    if viol > 1e-7 * max(1.0, float(np.abs(t).max())):
+    if viol > KKT_TOL * max(1.0, float(np.abs(t).max())):
         raise RuntimeError(f"outer projection failed its optimality check ({viol:.3g})")
     return out
 

@@ -170,14 +170,17 @@ TAU_STEPS = 6   # widenings of the tie tolerance: tau * 10**k, k <= 6
 
 
 def extract_policy(prod: Product, x: np.ndarray, wc: float, wp: float,
-                   tau: float = 1e-9) -> np.ndarray:
+                   tau: float = 1e-9, return_tau: bool = False):
     """Attractor tie rule on the eps-optimal action sets (module doc).
 
     ``x`` is one column of values.  Returns mu[S], the chosen row of each
-    state counted from the state's first row (int64)."""
+    state counted from the state's first row (int64); with ``return_tau``
+    also the tolerance each state's choice was made with (tau, or tau * 10^k
+    after k widenings), as (mu, tau_used)."""
     S = prod.n_states
     if S == 0:
-        return np.zeros(0, dtype=np.int64)
+        z = np.zeros(0, dtype=np.int64)
+        return (z, np.zeros(0)) if return_tau else z
     Q = q_values(prod, x, wc, wp)[:, 0]
     row_state = prod.row_state()
     qmax = _state_max(prod, Q[:, None])[:, 0]
@@ -187,6 +190,7 @@ def extract_policy(prod: Product, x: np.ndarray, wc: float, wp: float,
                       shape=(prod.n_rows, S))
     rank = np.full(S, -1, dtype=np.int64)
     mu = np.full(S, -1, dtype=np.int64)
+    tau_used = np.zeros(S)
     first_row = prod.state_row[:-1]
     level = 0
     widen = 0
@@ -223,17 +227,21 @@ def extract_policy(prod: Product, x: np.ndarray, wc: float, wp: float,
                     best_r, best_m = r, m
             rank[s] = level
             mu[s] = best_r - first_row[s]
+            tau_used[s] = tau * 10.0 ** widen
     if (rank < 0).any():
         raise ImproperPolicy(f"{int((rank < 0).sum())} states cannot reach done "
                              "through eps-optimal actions")
-    return mu
+    return (mu, tau_used) if return_tau else mu
 
 
 def extract_policy_paper(prod: Product, wc: float, wp: float, eps: float,
                          max_sweeps: int = 1_000_000) -> np.ndarray:
-    """Alg. 3 literally (Gauss-Seidel, mu updated only where |y - x| > eps,
-    mu initialised to the first action).  Parity unpinned; kept for the
-    record."""
+    """Alg. 3 as printed: Gauss-Seidel sweeps in state order, the maximising
+    action (first one on ties) recorded only where |y - x| > eps, mu
+    initialised to the first action.  The policy depends on the trajectory
+    (where each state's value last moved by more than eps), so the device
+    does not use it; it is pinned where the optimal action is unique (the
+    corridor, the worked example, brute force on tiny products)."""
     S = prod.n_states
     r = scalarised_rewards(prod, wc, wp)[:, 0]
     x = np.zeros(S)

@@ -146,6 +146,99 @@ def test_corridor_closed_form(p, c):
     assert vc == pytest.approx(-2 * c / p, rel=1e-10) and vp == pytest.approx(1.0, abs=1e-12)
 
 
+@pytest.mark.parametrize("p,c", [(0.5, 1.0), (0.8, 2.5), (0.3, 1.7)])
+def test_paper_policy_rule_on_the_corridor(p, c):
+    # Alg. 3's own policy rule (trajectory form): "right" is the unique
+    # optimal action of both live cells for the cost objective
+    prod = _corridor(p, c)
+    mu = vi.extract_policy_paper(prod, 1.0, 0.0, 1e-12)
+    assert mu.tolist() == [0, 0]
+
+
+def test_paper_policy_rule_on_the_worked_example(example):
+    """Probability only: policy a (row 0 of (s0, q0), 5/7 against 0.1) in
+    both rules.  Cost only, the optimum is policy b (row 1, one step) and the
+    final-value rule finds it; the printed rule records row 0 at the first
+    sweep (both rows give -1 from x = 0, the first wins the tie) and never
+    again, because the value of (s0, q0) stays at -1 while the best row
+    changes: the trajectory dependence that makes the build extract policies
+    from the final values instead."""
+    p = example[0]
+    assert vi.extract_policy_paper(p, 0.0, 1.0, 1e-12).tolist() == [0, 0]
+    assert vi.extract_policy_paper(p, 1.0, 0.0, 1e-12).tolist() == [0, 0]
+    y, _ = vi.value_iteration(p, 1.0, 0.0, 1e-12)
+    assert vi.extract_policy(p, y[:, 0], 1.0, 0.0).tolist() == [1, 0]
+    # the printed rule's policy a costs 15/7 against b's 1
+    assert vi.evaluate_exact(p, np.array([0, 0]))[p.init, 0] == pytest.approx(-15 / 7, abs=1e-12)
+
+
+@pytest.mark.parametrize("seed,w,h,kind", [(11, 3, 2, "reach"), (12, 3, 3, "avoid"), (14, 3, 2, "avoid")])
+def test_paper_policy_rule_is_optimal_on_tiny_products(seed, w, h, kind):
+    # with both weights positive the optimum is unique by a margin here; the
+    # trajectory rule's policy then attains the brute-force optimum exactly
+    wl = tiny_workload(seed, 1, 1, width=w, height=h, kinds=(kind,), k=1)
+    prod = product.build_all(wl)[0]
+    pts, _ = _policy_points(prod)
+    rng = np.random.default_rng(seed + 100)
+    for _ in range(4):
+        wv = rng.dirichlet([1.0, 1.0])
+        vals = np.sort(pts @ wv)
+        mu = vi.extract_policy_paper(prod, wv[0], wv[1], 1e-12)
+        ex = vi.evaluate_exact(prod, mu)[prod.init] @ wv
+        assert ex == pytest.approx(vals[-1], abs=1e-9)
+
+
+def _widened_policy_loss(prod, wc, wp, noise, seed):
+    """Optimal values V*, a policy extracted from values perturbed by
+    `noise` (so the tie tolerance has to widen), and the bound on its loss."""
+    vstar, _ = vi.value_iteration(prod, wc, wp, 1e-14)
+    vstar = vstar[:, 0]
+    x = vstar + np.random.default_rng(seed).uniform(-noise, noise, size=vstar.shape)
+    mu, tau_used = vi.extract_policy(prod, x, wc, wp, tau=1e-9, return_tau=True)
+    rows = vi.policy_rows(prod, mu)
+    A = sp.identity(prod.n_states, format="csc") - prod.P()[rows].tocsc()
+    vmu = vi.evaluate_exact(prod, mu) @ np.array([wc, wp])
+    e = float(np.abs(x - vstar).max())
+    # V* - V^mu <= (I - P_mu)^-1 (tau_used + 2 e): mu is tau_used-greedy for x,
+    # and x is within e of V*
+    bound = sp.linalg.spsolve(A, tau_used + 2 * e)
+    return vstar, vmu, bound, tau_used
+
+
+@pytest.mark.parametrize("noise", [1e-6, 1e-5, 3e-4])
+def test_widened_tie_tolerance_loss_is_bounded(noise):
+    """The tie rule's widening (tau up to 1e-3) picks actions up to tau below
+    the best; the loss of the resulting policy is bounded by tau_used + 2 e
+    per expected step.  Values perturbed by `noise` force widenings."""
+    widened = 0
+    for seed, (w, h, kind) in enumerate([(4, 4, "reach"), (5, 4, "avoid"), (6, 5, "reach")]):
+        wl = tiny_workload(40 + seed, 1, 1, width=w, height=h, kinds=(kind,), k=2, p_slip=0.1)
+        prod = product.build_all(wl)[0]
+        for wc, wp in ((1.0, 0.0), (0.3, 0.7), (0.0, 1.0)):
+            vstar, vmu, bound, tau_used = _widened_policy_loss(prod, wc, wp, noise, seed)
+            widened += int((tau_used > 1e-9).sum())
+            assert (vstar - vmu <= bound + 1e-9).all()
+            # and the bound is what the values allow: at most 1e-3 + 2 noise per step
+            assert (tau_used <= 1e-3 * (1 + 1e-12)).all()
+    assert widened > 0   # the widening did happen
+
+
+def test_widening_loss_pin_catches_a_non_greedy_choice(monkeypatch):
+    # plant a mistake on the CPU: a tie rule that ignores the tolerance
+    # (every action counts as optimal) breaks the loss bound
+    wl = tiny_workload(40, 1, 1, width=4, height=4, kinds=("reach",), k=2, p_slip=0.1)
+    prod = product.build_all(wl)[0]
+    real_q = vi.q_values
+
+    def flat_q(prod_, x, wc, wp):
+        q = real_q(prod_, x, wc, wp)
+        return np.zeros_like(q)
+
+    monkeypatch.setattr(vi, "q_values", flat_q)
+    vstar, vmu, bound, _ = _widened_policy_loss(prod, 1.0, 0.0, 1e-6, 0)
+    assert (vstar - vmu > bound + 1e-3).any()
+
+
 def test_corridor_probability_iterates_monotone():
     prod = _corridor(0.4, 1.0)
     P = prod.P()
