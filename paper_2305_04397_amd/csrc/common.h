@@ -53,9 +53,10 @@ struct DevBuf {
         p = nullptr;
         bytes = 0;
     }
-    // (re)allocate when the requested size exceeds the current one
-    void ensure(size_t n) {
-        if (n <= bytes && p) return;
+    // (re)allocate when the requested size exceeds the current one; true
+    // when the buffer moved
+    bool ensure(size_t n) {
+        if (n <= bytes && p) return false;
         release();
         if (n == 0) n = 16;
         hipError_t e = hipMalloc(&p, n);
@@ -64,6 +65,7 @@ struct DevBuf {
             fail(MORAP_E_OOM, "hipMalloc of " + std::to_string(n) + " bytes failed: " + hipGetErrorString(e));
         }
         bytes = n;
+        return true;
     }
     template <class T> T* as() const { return static_cast<T*>(p); }
 };
@@ -206,6 +208,8 @@ struct morap_ctx {
     hipGraph_t chunk_graph[2] = {nullptr, nullptr}; // captured chunks of sweeps (main, FP64 refine)
     hipGraphExec_t chunk_exec[2] = {nullptr, nullptr};
     std::string graph_key[2];
+    uint64_t load_gen = 0;                          // bumped by every model upload (graph keys)
+    uint64_t buf_gen = 0;                           // bumped when a solve buffer moves (graph keys)
 
     // evaluation state
     int eK = 0;

@@ -531,6 +531,9 @@ void upload_models(morap_ctx* c) {
     c->solved = false;
     c->evaluated = false;
     c->tuned.clear();
+    // captured sweep graphs bake in the model buffers, the zero row and the
+    // block pattern: none of them may replay after a new upload
+    ++c->load_gen;
     c->S = hm.S();
     c->R = hm.R();
     c->N = hm.N();

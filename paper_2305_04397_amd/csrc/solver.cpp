@@ -79,30 +79,36 @@ static const Variant& variant_by_id(int id) {
 static void ensure_scratch(morap_ctx* c, int Kp) {
     const int M = c->hm.M;
     const size_t pairs = (size_t)M * Kp;
-    c->d_wc32.ensure(pairs * 4);
-    c->d_wp32.ensure(pairs * 4);
-    c->d_wc64.ensure(pairs * 8);
-    c->d_wp64.ensure(pairs * 8);
-    c->d_res.ensure(pairs * 8);
-    c->d_ymax.ensure(pairs * 8);
-    c->d_active.ensure(pairs);
-    c->d_pair_mask.ensure(pairs);
-    c->d_pair_sweeps.ensure(pairs * 4);
-    c->d_model_active.ensure(M);
-    c->d_act_models.ensure((size_t)M * 4 + 4);
-    c->d_act_prefix.ensure((size_t)(M + 1) * 4 + 4);
-    c->d_act_tiles.ensure(c->tiles.size() * 4 + 4);
-    c->d_counters.ensure(8 * 8);
+    bool moved = false;
+    moved |= c->d_wc32.ensure(pairs * 4);
+    moved |= c->d_wp32.ensure(pairs * 4);
+    moved |= c->d_wc64.ensure(pairs * 8);
+    moved |= c->d_wp64.ensure(pairs * 8);
+    moved |= c->d_res.ensure(pairs * 8);
+    moved |= c->d_ymax.ensure(pairs * 8);
+    moved |= c->d_active.ensure(pairs);
+    moved |= c->d_pair_mask.ensure(pairs);
+    moved |= c->d_pair_sweeps.ensure(pairs * 4);
+    moved |= c->d_model_active.ensure(M);
+    moved |= c->d_act_models.ensure((size_t)M * 4 + 4);
+    moved |= c->d_act_prefix.ensure((size_t)(M + 1) * 4 + 4);
+    moved |= c->d_act_tiles.ensure(c->tiles.size() * 4 + 4);
+    moved |= c->d_counters.ensure(8 * 8);
     c->h_counters.ensure(8 * 8);
+    // a captured sweep graph holds these addresses: it must not replay
+    // after any of them moved
+    if (moved) ++c->buf_gen;
 }
 
 static void ensure_values(morap_ctx* c, ValueSet& vs, int K, int Kp, int prec) {
     const size_t el = prec == MORAP_F32 ? 4 : 8;
+    bool moved = false;
     // one row past the last state: the zero row of the block sweep
-    vs.x[0].ensure((size_t)(c->S + 1) * Kp * el);
-    vs.x[1].ensure((size_t)(c->S + 1) * Kp * el);
-    vs.final_par.ensure((size_t)c->hm.M * Kp);
-    vs.c.ensure((size_t)K * c->hm.M * 8);
+    moved |= vs.x[0].ensure((size_t)(c->S + 1) * Kp * el);
+    moved |= vs.x[1].ensure((size_t)(c->S + 1) * Kp * el);
+    moved |= vs.final_par.ensure((size_t)c->hm.M * Kp);
+    moved |= vs.c.ensure((size_t)K * c->hm.M * 8);
+    if (moved) ++c->buf_gen;
     vs.prec = prec;
     vs.K = K;
     vs.Kp = Kp;
@@ -322,8 +328,12 @@ static void run_chunk(morap_ctx* c, int g, ValueSet& vs, const uint8_t* mask, co
         return;
     }
     char key[320];
-    snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%.17g/%p/%p/%p/%p/%zu", v.id, vs.K, vs.Kp, vs.prec, n, eps,
-             vs.x[0].p, vs.x[1].p, (const void*)mask, vs.c.p, c->tiles.size());
+    // the key names everything the captured launches hold: the model upload
+    // and the solve buffers (by generation, so a buffer reallocated at an
+    // old address still counts as new), the variant and the sizes
+    snprintf(key, sizeof key, "%llu/%llu/%d/%d/%d/%d/%d/%.17g/%p/%p/%p/%p/%zu", (unsigned long long)c->load_gen,
+             (unsigned long long)c->buf_gen, v.id, vs.K, vs.Kp, vs.prec, n, eps, vs.x[0].p, vs.x[1].p,
+             (const void*)mask, vs.c.p, c->tiles.size());
     if (c->graph_key[g] != key) {
         release_graph(c, g);
         MORAP_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));

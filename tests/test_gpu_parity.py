@@ -129,6 +129,35 @@ def test_every_variant_gives_identical_f64_values(ctx, morap):
     assert np.abs(ref[True] - ref[False]).max() <= 1e-12 * np.abs(ref[False]).max()
 
 
+def test_graph_is_not_replayed_after_a_new_upload(ctx, morap):
+    """A captured chunk of sweeps holds the model buffers, the zero row and
+    the block pattern.  After a larger load has sized every buffer, model set
+    A is solved with graph replay; model set B has A's tile count (one tile
+    per product) but more states, so its zero row moves while no buffer is
+    reallocated.  B's replayed solve must equal its eager solve bit for bit."""
+    W = dirichlet_weights(np.random.default_rng(3), 64, 4)
+    big = make_workload(2, n_agents=2, n_tasks=2)
+    a = tiny_workload(21, 2, 2, width=3, height=2)
+    b = tiny_workload(22, 2, 2, width=5, height=4)
+    pa, pb = product.build_all(a), product.build_all(b)
+    n_tiles = lambda ps: sum((p.n_states + 127) // 128 for p in ps)
+    assert n_tiles(pa) == n_tiles(pb) == 4
+    assert sum(p.n_states for p in pb) > sum(p.n_states for p in pa)
+    for prec in ("f64", "f32"):
+        opts = dict(eps_vi=1e-7, precision=prec, schedule=37)
+        ctx.build_products(big)
+        ctx.solve(W, morap.Options(**opts, use_graph=True))
+        ctx.build_products(a)
+        ctx.solve(W, morap.Options(**opts, use_graph=True))
+        ctx.build_products(b)
+        cg, _ = ctx.solve(W, morap.Options(**opts, use_graph=True))
+        ce, _ = ctx.solve(W, morap.Options(**opts, use_graph=False))
+        assert np.array_equal(cg, ce), prec
+        co, _, _ = _oracle_c(pb, 2, 2, W, 1e-7)
+        assert np.abs(ce - co).max() <= (4e-7 + 1e-10 * np.abs(co).max() if prec == "f64"
+                                         else 1e-4 * max(1.0, np.abs(co).max())), prec
+
+
 @pytest.mark.parametrize("v", [28, 31, 34, 36])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_block_sweep_matches_oracle_cfg2(ctx, morap, v, prec):
