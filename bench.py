@@ -64,6 +64,8 @@ def kernel_name(variant: int, prec: str) -> str:
     if variant < 0:
         return "morap::k::inst_vi_kernel"
     t = "float" if prec == "f32" else "double"
+    if variant in (39, 40):
+        return f"void morap::k::bellman_halo<{2 if variant == 39 else 4}"
     cpl, lps = SHAPES[(variant - 1) % 18]
     if variant > 36:
         return f"void morap::k::bellman_block_wave<{t}, {2 if variant == 37 else 8}, 256"

@@ -109,6 +109,13 @@ struct HostModels {
     //          each tile's in the order the sweep walks it);
     // and per distinct agent-state block 32 values: P[a][d] (a-major, 25), -cost[a] (5), 0, 0,
     // where a disabled action repeats the first enabled one.
+    // halo tiles (built with the block form): [4 * tiles] HTile fields, the
+    // first tile of each model, per record position (tile by tile) two words
+    //   w0 = halo place of slots 0..3 (8 bits each), w1 = slot 4 | accepting
+    //   slots << 8 | block << 13   (HALO_MAX = the zero row),
+    // and the halo lists (global states)
+    std::vector<int32_t> hal_tile, hal_tile_base, hal_list;
+    std::vector<uint32_t> hal_rec;
     std::vector<int32_t> blk_rec;      // [8S]
     std::vector<double>  blk_agent;    // [32 * distinct blocks]
     uint32_t blk_pattern = 0;          // bit 5a + d: some block has P[a][d] != 0
@@ -123,14 +130,32 @@ struct Tile {
     int32_t model, s_begin, s_end, pad;
 };
 
+// A halo tile of the LDS-staged sweep: at most HALO_TILE states of one model
+// whose value rows (own states and successors) number at most HALO_MAX.
+// Its records are hal_rec[rec_begin .. rec_begin + n), its halo list
+// hal_list[halo_begin .. halo_begin + H) (own states first, in record order).
+#ifndef MORAP_HALO_TILE
+#define MORAP_HALO_TILE 64
+#endif
+#ifndef MORAP_HALO_MAX
+#define MORAP_HALO_MAX 96
+#endif
+constexpr int HALO_TILE = MORAP_HALO_TILE;
+constexpr int HALO_MAX = MORAP_HALO_MAX;   // < 256: halo places are bytes
+static_assert(HALO_MAX < 256 && HALO_TILE <= HALO_MAX && HALO_TILE <= 128, "halo tile limits");
+struct HTile {
+    int32_t model, rec_begin, n, halo_begin;   // n = states | H << 16
+};
+
 // sweep-kernel variants: kernel family x columns per lane x lanes per state
-enum { SWEEP_CSR = 0, SWEEP_BLOCK = 1 };
+enum { SWEEP_CSR = 0, SWEEP_BLOCK = 1, SWEEP_HALO = 2 };
 struct Variant {
     int id;        // > 0
     int cpl;       // columns per lane
     int lps;       // lanes per state
     int wg;        // threads per workgroup
-    int kind;      // SWEEP_CSR (LDS-staged CSR tiles) or SWEEP_BLOCK (neighbourhood blocks)
+    int kind;      // SWEEP_CSR (LDS-staged CSR tiles), SWEEP_BLOCK (neighbourhood blocks) or
+                   // SWEEP_HALO (neighbourhood blocks, halo rows staged in LDS)
     int unroll;    // states in flight per lane group (block sweeps)
 };
 
@@ -176,6 +201,9 @@ struct morap_ctx {
     int max_rows_per_state = 0;
     bool has_blocks = false;                        // the neighbourhood-block form exists
     morap::DevBuf d_blk_rec, d_blk32, d_blk64;
+    bool has_halo = false;                          // halo tiles exist
+    morap::DevBuf d_htiles, d_htile_base, d_hrec, d_hlist;
+    int64_t n_htiles = 0;
     morap::DevBuf d_state_row, d_row_ptr, d_col, d_prob32, d_prob64, d_rew32, d_rew64, d_to_done;
     morap::DevBuf d_state_base, d_init;
     morap::DevBuf d_rows_per_model, d_states_per_model;  // [M] int32
@@ -347,6 +375,9 @@ struct SweepArgs {
     int32_t zero_row;       // S: the value row that always holds 0
     uint32_t pattern;       // union of the blocks' nonzero (action, slot) entries
     const int32_t* act_tiles;  // global index of every active tile, in order
+    const HTile* htiles;       // halo tiles (LDS-staged sweep)
+    const uint2* hrec;         // their records
+    const int32_t* hlist;      // their halo lists
 };
 // batched Bellman sweep: variant v, precision prec (MORAP_F32/F64)
 void sweep(hipStream_t s, int prec, const Variant& v, int grid, int ktiles, const SweepArgs& a);
@@ -354,6 +385,9 @@ void sweep_block(hipStream_t s, int prec, const Variant& v, int grid, int ktiles
 // workgroups of the variant's kernel that fit one compute unit at once
 int sweep_resident(int prec, const Variant& v);
 int sweep_block_resident(int prec, const Variant& v);
+// LDS-staged sweep over halo tiles (halo.hip): FP32, k-tiles of 64 columns
+void sweep_halo(hipStream_t s, int prec, const Variant& v, int grid, int ktiles, const SweepArgs& a);
+int sweep_halo_resident(const Variant& v, uint32_t pattern);
 int sweep_lds_rows();
 int sweep_lds_nnz();
 int sweep_tile_states(const Variant& v);

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <functional>
 #include <cmath>
 #include <thread>
 #include <unordered_map>
@@ -210,6 +211,270 @@ static void concat(morap_ctx* c, std::vector<Built>& parts, int nI, int nJ) {
     c->max_rows_per_state = max_rows;
 }
 
+// Connected regions of at most HALO_TILE states of every agent's transition
+// graph (edges from each state to its successor slots, both directions):
+// seeds are taken in breadth-first order of the whole graph and each region
+// grows breadth-first over unassigned states, so regions are compact and
+// consecutive regions are neighbours.  reg[s] = region of s, pos[s] = its
+// place in the region's growth order.
+static void agent_regions(int64_t n, const int32_t* slot, std::vector<int32_t>& reg, std::vector<int32_t>& pos) {
+    constexpr int NS = 5;
+    std::vector<int64_t> deg(n + 1, 0);
+    for (int64_t s = 0; s < n; ++s)
+        for (int d = 1; d < NS; ++d) {
+            const int32_t t = slot[s * NS + d];
+            if (t >= 0 && t != s) {
+                ++deg[s + 1];
+                ++deg[t + 1];
+            }
+        }
+    for (int64_t s = 0; s < n; ++s) deg[s + 1] += deg[s];
+    std::vector<int32_t> adj(deg[n]);
+    std::vector<int64_t> fill(deg.begin(), deg.end() - 1);
+    for (int64_t s = 0; s < n; ++s)
+        for (int d = 1; d < NS; ++d) {
+            const int32_t t = slot[s * NS + d];
+            if (t >= 0 && t != s) {
+                adj[fill[s]++] = t;
+                adj[fill[t]++] = (int32_t)s;
+            }
+        }
+    // breadth-first order of the whole graph (every component)
+    std::vector<int32_t> order;
+    order.reserve(n);
+    std::vector<uint8_t> seen(n, 0);
+    for (int64_t r0 = 0; r0 < n; ++r0) {
+        if (seen[r0]) continue;
+        seen[r0] = 1;
+        size_t head = order.size();
+        order.push_back((int32_t)r0);
+        while (head < order.size()) {
+            const int32_t s = order[head++];
+            for (int64_t e = deg[s]; e < deg[s + 1]; ++e)
+                if (!seen[adj[e]]) {
+                    seen[adj[e]] = 1;
+                    order.push_back(adj[e]);
+                }
+        }
+    }
+    reg.assign(n, -1);
+    pos.assign(n, 0);
+    std::vector<int32_t> cur;
+    int32_t nreg = 0;
+    for (const int32_t seed : order) {
+        if (reg[seed] >= 0) continue;
+        cur.clear();
+        cur.push_back(seed);
+        reg[seed] = nreg;
+        for (size_t head = 0; head < cur.size() && (int)cur.size() < HALO_TILE; ++head) {
+            const int32_t s = cur[head];
+            for (int64_t e = deg[s]; e < deg[s + 1] && (int)cur.size() < HALO_TILE; ++e)
+                if (reg[adj[e]] < 0) {
+                    reg[adj[e]] = nreg;
+                    cur.push_back(adj[e]);
+                }
+        }
+        for (size_t k = 0; k < cur.size(); ++k) pos[cur[k]] = (int32_t)k;
+        ++nreg;
+    }
+}
+
+// Halo tiles of the LDS-staged sweep (see its kernel), from the product
+// states' block records (recs[8 g ..], in state order).  Per model, states are
+// grouped by (location, agent region) in region order; groups are packed into
+// tiles of at most HALO_TILE states and HALO_MAX halo rows, a group that
+// alone exceeds the halo limit being halved.  Not built when a block index
+// does not fit the record's 19 bits.
+static void build_halo(HostModels& hm, const std::vector<int64_t>& abase, const std::vector<int32_t>& slot, int nI,
+                       int nJ, const std::vector<int32_t>& recs, int64_t n_blocks) {
+    hm.hal_tile.clear();
+    hm.hal_tile_base.clear();
+    hm.hal_list.clear();
+    hm.hal_rec.clear();
+    if (n_blocks >= (int64_t)1 << 19) return;
+    constexpr int NS = 5;
+    const int M = hm.M;
+    const int32_t S = (int32_t)hm.S();
+    std::vector<std::vector<int32_t>> reg(nI), pos(nI);
+    {
+        std::atomic<int> next{0};
+        auto worker = [&] {
+            for (int i; (i = next++) < nI;)
+                agent_regions(abase[i + 1] - abase[i], &slot[(size_t)abase[i] * NS], reg[i], pos[i]);
+        };
+        const int nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        std::vector<std::thread> th;
+        for (int k = 0; k < nt; ++k) th.emplace_back(worker);
+        for (auto& k : th) k.join();
+    }
+    struct Part {
+        std::vector<int32_t> tiles;   // model, rec_begin, n | H << 16, local halo begin
+        std::vector<uint32_t> rec;
+        std::vector<int32_t> list;
+    };
+    std::vector<Part> parts(M);
+    std::atomic<int> next{0};
+    auto worker = [&] {
+        std::vector<int64_t> key;
+        std::vector<int32_t> ord, stamp, place, own, halo, added;
+        for (int m; (m = next++) < M;) {
+            const int i = m / nJ;
+            const int32_t s0 = hm.state_base[m], s1 = hm.state_base[m + 1], n = s1 - s0;
+            if (n == 0) continue;
+            Part& P = parts[m];
+            // states sorted by (location, region, place in region)
+            const int64_t nreg = (int64_t)abase[i + 1] - abase[i];
+            key.resize(n);
+            ord.resize(n);
+            for (int32_t g = s0; g < s1; ++g) {
+                const int32_t s = hm.states_sq[2 * (size_t)g], q = hm.states_sq[2 * (size_t)g + 1];
+                key[g - s0] = ((int64_t)q * nreg + reg[i][s]) * HALO_TILE + pos[i][s];
+                ord[g - s0] = g - s0;
+            }
+            std::sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+            stamp.assign(n, -1);
+            place.assign(n, -1);
+            int32_t tile_id = 0;
+            own.clear();
+            halo.clear();
+            // rows a state brings: itself and its live successors (local)
+            auto rows_of = [&](int32_t l, int32_t* out) {
+                int k = 0;
+                out[k++] = l;
+                for (int d = 0; d < NS; ++d) {
+                    const int32_t r = recs[(size_t)(s0 + l) * 8 + d];
+                    if (r != S) out[k++] = r - s0;
+                }
+                return k;
+            };
+            // try to add states ord[b..e) to the open tile; false (and nothing
+            // changed) when a limit would be exceeded
+            auto try_add = [&](size_t b, size_t e) {
+                if (own.size() + (e - b) > (size_t)HALO_TILE) return false;
+                added.clear();
+                int32_t rr[NS + 1];
+                for (size_t p = b; p < e; ++p) {
+                    const int k = rows_of(ord[p], rr);
+                    for (int z = 0; z < k; ++z)
+                        if (stamp[rr[z]] != tile_id) {
+                            stamp[rr[z]] = tile_id;
+                            added.push_back(rr[z]);
+                        }
+                }
+                if (halo.size() + added.size() > (size_t)HALO_MAX) {
+                    for (int32_t l : added) stamp[l] = -1;
+                    return false;
+                }
+                for (size_t p = b; p < e; ++p) own.push_back(ord[p]);
+                halo.insert(halo.end(), added.begin(), added.end());
+                return true;
+            };
+            auto close = [&] {
+                if (own.empty()) return;
+                const int32_t hb = (int32_t)P.list.size();
+                const int32_t rb = s0 + (int32_t)(P.rec.size() / 2);
+                // halo list: own states first (record order), then the rest
+                int32_t h = 0;
+                for (int32_t l : own) {
+                    place[l] = h++;
+                    P.list.push_back(s0 + l);
+                }
+                for (int32_t l : halo)
+                    if (place[l] < 0) {   // not one of the own states
+                        place[l] = h++;
+                        P.list.push_back(s0 + l);
+                    }
+                for (int32_t l : own) {
+                    const int32_t* r = &recs[(size_t)(s0 + l) * 8];
+                    uint32_t loc[NS];
+                    for (int d = 0; d < NS; ++d) loc[d] = r[d] == S ? (uint32_t)HALO_MAX : (uint32_t)place[r[d] - s0];
+                    P.rec.push_back(loc[0] | loc[1] << 8 | loc[2] << 16 | loc[3] << 24);
+                    P.rec.push_back(loc[4] | ((uint32_t)r[6] & 31u) << 8 | (uint32_t)r[5] << 13);
+                }
+                P.tiles.insert(P.tiles.end(), {m, rb, (int32_t)own.size() | h << 16, hb});
+                for (int32_t l : halo) place[l] = -1;
+                for (int32_t l : own) place[l] = -1;
+                own.clear();
+                halo.clear();
+                ++tile_id;
+            };
+            // add [b, e) to the open tile, else to a fresh one, else halve it
+            std::function<void(size_t, size_t)> put = [&](size_t b, size_t e) {
+                if (try_add(b, e)) return;
+                close();
+                if (try_add(b, e)) return;
+                const size_t mid = b + (e - b) / 2;
+                put(b, mid);
+                put(mid, e);
+            };
+            for (size_t b = 0; b < (size_t)n;) {
+                size_t e = b + 1;
+                while (e < (size_t)n && key[ord[e]] / HALO_TILE == key[ord[b]] / HALO_TILE) ++e;
+                put(b, e);
+                b = e;
+            }
+            close();
+        }
+    };
+    const int nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (int k = 0; k < nt; ++k) th.emplace_back(worker);
+    for (auto& k : th) k.join();
+    hm.hal_tile_base.assign(M + 1, 0);
+    size_t nl = 0;
+    for (int m = 0; m < M; ++m) nl += parts[m].list.size();
+    MORAP_CHECK(nl < (size_t)0x7fffffff, MORAP_E_UNSUPPORTED, "halo lists exceed 2^31 entries");
+    hm.hal_rec.resize((size_t)2 * S);
+    hm.hal_list.reserve(nl);
+    for (int m = 0; m < M; ++m) {
+        Part& P = parts[m];
+        hm.hal_tile_base[m] = (int32_t)(hm.hal_tile.size() / 4);
+        const int32_t lb = (int32_t)hm.hal_list.size();
+        for (size_t t = 0; t < P.tiles.size(); t += 4) {
+            hm.hal_tile.insert(hm.hal_tile.end(), {P.tiles[t], P.tiles[t + 1], P.tiles[t + 2], P.tiles[t + 3] + lb});
+        }
+        std::copy(P.rec.begin(), P.rec.end(), hm.hal_rec.begin() + (size_t)2 * hm.state_base[m]);
+        hm.hal_list.insert(hm.hal_list.end(), P.list.begin(), P.list.end());
+        P = Part();
+    }
+    hm.hal_tile_base[M] = (int32_t)(hm.hal_tile.size() / 4);
+    // the sweep trusts this layout for its LDS and HBM addresses: check it
+    // (every state in exactly one tile of its model, halo places in range and
+    // naming the record's successors, own states first)
+    std::vector<uint8_t> seen((size_t)S, 0);
+    for (int m = 0; m < M; ++m)
+        for (int32_t t = hm.hal_tile_base[m]; t < hm.hal_tile_base[m + 1]; ++t) {
+            const int32_t* T = &hm.hal_tile[(size_t)t * 4];
+            const int32_t n = T[2] & 0xffff, H = T[2] >> 16, rb = T[1], hb = T[3];
+            MORAP_CHECK(T[0] == m && n >= 1 && n <= HALO_TILE && H >= n && H <= HALO_MAX &&
+                            rb >= hm.state_base[m] && rb + n <= hm.state_base[m + 1] && hb >= 0 &&
+                            (size_t)hb + H <= hm.hal_list.size(),
+                        MORAP_E_INVALID, "halo tiles: a tile out of its bounds");
+            for (int32_t h = 0; h < H; ++h) {
+                const int32_t g = hm.hal_list[(size_t)hb + h];
+                MORAP_CHECK(g >= hm.state_base[m] && g < hm.state_base[m + 1], MORAP_E_INVALID,
+                            "halo tiles: a row outside its model");
+            }
+            for (int32_t p = 0; p < n; ++p) {
+                const int32_t g = hm.hal_list[(size_t)hb + p];
+                MORAP_CHECK(!seen[g], MORAP_E_INVALID, "halo tiles: a state in two tiles");
+                seen[g] = 1;
+                const uint32_t w0 = hm.hal_rec[2 * (size_t)(rb + p)], w1 = hm.hal_rec[2 * (size_t)(rb + p) + 1];
+                const uint32_t loc[NS] = {w0 & 255u, (w0 >> 8) & 255u, (w0 >> 16) & 255u, w0 >> 24, w1 & 255u};
+                for (int d = 0; d < NS; ++d) {
+                    const int32_t r = recs[(size_t)g * 8 + d];
+                    const bool ok = r == S ? loc[d] == (uint32_t)HALO_MAX
+                                           : (loc[d] < (uint32_t)H && hm.hal_list[(size_t)hb + loc[d]] == r);
+                    MORAP_CHECK(ok, MORAP_E_INVALID, "halo tiles: a record slot names the wrong row");
+                }
+                MORAP_CHECK((w1 >> 13) == (uint32_t)recs[(size_t)g * 8 + 5] &&
+                                ((w1 >> 8) & 31u) == ((uint32_t)recs[(size_t)g * 8 + 6] & 31u),
+                            MORAP_E_INVALID, "halo tiles: a record's block or accepting slots differ");
+            }
+        }
+    for (int32_t g = 0; g < S; ++g) MORAP_CHECK(seen[g], MORAP_E_INVALID, "halo tiles: a state in no tile");
+}
+
 // Neighbourhood-block form of built products (see the sweep over it): needs
 // at most 5 actions per agent and at most 5 distinct successors per agent
 // state, the state itself included; otherwise the form is not built and the
@@ -354,6 +619,7 @@ static void build_blocks(morap_ctx* c, const morap_agent* agents, int nI, const 
         for (int e = 0; e < NS * NS; ++e)
             if (ublk[b * 32 + e] != 0.0) pat |= 1u << e;
     hm.blk_pattern = pat;
+    build_halo(hm, abase, slot, nI, nJ, recs, (int64_t)(ublk.size() / 32));
     hm.blk_rec = std::move(recs);
     hm.blk_agent = std::move(ublk);
 }
@@ -531,6 +797,7 @@ void upload_models(morap_ctx* c) {
     c->solved = false;
     c->evaluated = false;
     c->tuned.clear();
+    c->resident.clear();
     // captured sweep graphs bake in the model buffers, the zero row and the
     // block pattern: none of them may replay after a new upload
     ++c->load_gen;
@@ -591,6 +858,14 @@ void upload_models(morap_ctx* c) {
     upload(c->d_tiles, c->tiles, s);
     upload(c->d_tile_base, c->tile_base, s);
     c->has_blocks = !hm.blk_rec.empty();
+    c->has_halo = c->has_blocks && !hm.hal_tile.empty();
+    c->n_htiles = (int64_t)hm.hal_tile.size() / 4;
+    if (c->has_halo) {
+        upload(c->d_htiles, hm.hal_tile, s);
+        upload(c->d_htile_base, hm.hal_tile_base, s);
+        upload(c->d_hrec, hm.hal_rec, s);
+        upload(c->d_hlist, hm.hal_list, s);
+    }
     if (c->has_blocks) {
         order_records(c);
         upload(c->d_blk_rec, hm.blk_rec, s);

@@ -21,7 +21,7 @@ namespace morap {
 // sweep-kernel variants: kernel family x columns per lane x lanes per state.
 // Ids 1-18 are the CSR-tile sweep, 19-36 the same shapes of the
 // neighbourhood-block sweep, 37-38 the wave-per-state block sweep with other
-// numbers of states in flight.
+// numbers of states in flight, 39-40 the LDS-staged sweep over halo tiles.
 // ---------------------------------------------------------------------------
 const std::vector<Variant>& variants() {
     static const std::vector<Variant> v = [] {
@@ -35,12 +35,16 @@ const std::vector<Variant>& variants() {
         // the wave-per-state block sweep with 2 and 8 states in flight
         out.push_back({id++, 1, 64, 256, SWEEP_BLOCK, 2});
         out.push_back({id++, 1, 64, 256, SWEEP_BLOCK, 8});
+        // the LDS-staged sweep over halo tiles (FP32), 2 and 4 states in flight
+        out.push_back({id++, 1, 64, 256, SWEEP_HALO, 2});
+        out.push_back({id++, 1, 64, 256, SWEEP_HALO, 4});
         return out;
     }();
     return v;
 }
 
 static int kt_of(const Variant& v) { return v.cpl * v.lps; }
+static bool uses_halo_tiles(const Variant& v) { return v.kind == SWEEP_HALO; }
 
 static int padded_k(int K) {
     if (K <= 64) {
@@ -54,11 +58,12 @@ static int padded_k(int K) {
 // candidate variants for a padded width: k-tiles of min(Kp, 64) columns and
 // of half that; a restricted solve (few active columns per model) also tries
 // narrower k-tiles, which skip the k-tiles without active columns
-static std::vector<Variant> candidates(int Kp, bool restricted, bool blocks) {
+static std::vector<Variant> candidates(int Kp, bool restricted, bool blocks, bool halo) {
     std::vector<Variant> out;
     const int kt_full = std::min(Kp, 64);
     for (const auto& v : variants()) {
         if (v.kind == SWEEP_BLOCK && !blocks) continue;
+        if (v.kind == SWEEP_HALO && !halo) continue;
         const int kt = kt_of(v);
         if (Kp % kt) continue;
         if (kt == kt_full || (kt * 2 == kt_full && kt >= 8) || (restricted && kt >= 8 && kt <= kt_full))
@@ -92,7 +97,7 @@ static void ensure_scratch(morap_ctx* c, int Kp) {
     moved |= c->d_model_active.ensure(M);
     moved |= c->d_act_models.ensure((size_t)M * 4 + 4);
     moved |= c->d_act_prefix.ensure((size_t)(M + 1) * 4 + 4);
-    moved |= c->d_act_tiles.ensure(c->tiles.size() * 4 + 4);
+    moved |= c->d_act_tiles.ensure(std::max<size_t>(c->tiles.size(), (size_t)c->n_htiles) * 4 + 4);
     moved |= c->d_counters.ensure(8 * 8);
     c->h_counters.ensure(8 * 8);
     // a captured sweep graph holds these addresses: it must not replay
@@ -115,7 +120,10 @@ static void ensure_values(morap_ctx* c, ValueSet& vs, int K, int Kp, int prec) {
     vs.valid = false;
 }
 
-static k::ConvergeArgs converge_args(morap_ctx* c, ValueSet& vs, const uint8_t* mask, double eps, int out_par) {
+// `halo`: the active tile list is built over the halo tiles (LDS-staged
+// sweep) instead of the CSR / block tiles
+static k::ConvergeArgs converge_args(morap_ctx* c, ValueSet& vs, const uint8_t* mask, double eps, int out_par,
+                                     bool halo) {
     k::ConvergeArgs a{};
     a.res = c->d_res.as<unsigned long long>();
     a.ymax = c->d_ymax.as<unsigned long long>();
@@ -137,7 +145,7 @@ static k::ConvergeArgs converge_args(morap_ctx* c, ValueSet& vs, const uint8_t* 
     // FP32 backups cannot resolve changes below a few units in the last
     // place of the values: stop there too (FP64: the bound is below eps)
     a.unit = vs.prec == MORAP_F32 ? 8.0 * std::ldexp(1.0, -24) : 8.0 * std::ldexp(1.0, -53);
-    a.tile_base = c->d_tile_base.as<int32_t>();
+    a.tile_base = halo ? c->d_htile_base.as<int32_t>() : c->d_tile_base.as<int32_t>();
     a.act_models = c->d_act_models.as<int32_t>();
     a.act_prefix = c->d_act_prefix.as<int32_t>();
     a.rows_per_model = c->d_rows_per_model.as<int32_t>();
@@ -173,6 +181,9 @@ static k::SweepArgs sweep_args(morap_ctx* c, ValueSet& vs, int in_par) {
     a.zero_row = (int32_t)c->S;
     a.pattern = c->hm.blk_pattern;
     a.act_tiles = c->d_act_tiles.as<int32_t>();
+    a.htiles = c->has_halo ? c->d_htiles.as<HTile>() : nullptr;
+    a.hrec = c->has_halo ? c->d_hrec.as<uint2>() : nullptr;
+    a.hlist = c->has_halo ? c->d_hlist.as<int32_t>() : nullptr;
     return a;
 }
 
@@ -186,12 +197,14 @@ static int persistent_grid(morap_ctx* c, int prec, const Variant& v) {
     for (auto& r : c->resident)
         if (r.first == key) per_cu = r.second;
     if (per_cu == 0) {
-        per_cu = v.kind == SWEEP_BLOCK ? k::sweep_block_resident(prec, v) : k::sweep_resident(prec, v);
+        per_cu = v.kind == SWEEP_HALO                                   ? k::sweep_halo_resident(v, c->hm.blk_pattern)
+                 : v.kind == SWEEP_BLOCK                              ? k::sweep_block_resident(prec, v)
+                                                                        : k::sweep_resident(prec, v);
         per_cu = std::max(1, per_cu);
         c->resident.push_back({key, per_cu});
     }
     int g = c->prop.multiProcessorCount * per_cu;
-    const int tiles = (int)c->tiles.size();
+    const int tiles = uses_halo_tiles(v) ? (int)c->n_htiles : (int)c->tiles.size();
     g = std::min(g, (tiles + 7) / 8 * 8);
     return std::max(8, g / 8 * 8);
 }
@@ -289,18 +302,20 @@ static void enqueue_chunk(morap_ctx* c, ValueSet& vs, const uint8_t* mask, const
             ev->back().second = take_event(c);
             MORAP_HIP(hipEventRecord(ev->back().first, c->stream));
         }
-        if (v.kind == SWEEP_BLOCK)
+        if (v.kind == SWEEP_HALO)
+            k::sweep_halo(c->stream, vs.prec, v, grid, ktiles, sweep_args(c, vs, in_par));
+        else if (v.kind == SWEEP_BLOCK)
             k::sweep_block(c->stream, vs.prec, v, grid, ktiles, sweep_args(c, vs, in_par));
         else
             k::sweep(c->stream, vs.prec, v, grid, ktiles, sweep_args(c, vs, in_par));
         if (timed) MORAP_HIP(hipEventRecord(ev->back().second, c->stream));
-        const auto ca = converge_args(c, vs, mask, eps, 1 - in_par);
+        const auto ca = converge_args(c, vs, mask, eps, 1 - in_par, uses_halo_tiles(v));
         k::converge(c->stream, ca);
         k::compact(c->stream, ca);
     }
 }
 
-static void reset_solve(morap_ctx* c, ValueSet& vs, const uint8_t* mask, double eps) {
+static void reset_solve(morap_ctx* c, ValueSet& vs, const uint8_t* mask, double eps, const Variant& v) {
     const int64_t n = (c->S + 1) * vs.Kp;
     if (vs.prec == MORAP_F32) {
         k::fill_f32(c->stream, vs.x[0].as<float>(), 0.f, n);
@@ -309,7 +324,7 @@ static void reset_solve(morap_ctx* c, ValueSet& vs, const uint8_t* mask, double 
         k::fill_f64(c->stream, vs.x[0].as<double>(), 0.0, n);
         k::fill_f64(c->stream, vs.x[1].as<double>(), 0.0, n);
     }
-    k::init_solve(c->stream, converge_args(c, vs, mask, eps, 1));
+    k::init_solve(c->stream, converge_args(c, vs, mask, eps, 1, uses_halo_tiles(v)));
 }
 
 static void release_graph(morap_ctx* c, int g) {
@@ -360,7 +375,7 @@ static void read_counters(morap_ctx* c) {
 // time 6 sweeps of variant v from a fresh start (autotuner)
 static double time_variant(morap_ctx* c, ValueSet& vs, const uint8_t* mask, const Variant& v, double eps) {
     EventPair t;
-    reset_solve(c, vs, mask, eps);
+    reset_solve(c, vs, mask, eps, v);
     enqueue_chunk(c, vs, mask, v, eps, 2);
     MORAP_HIP(hipEventRecord(t.a, c->stream));
     enqueue_chunk(c, vs, mask, v, eps, 6);
@@ -378,12 +393,14 @@ static const Variant& choose_variant(morap_ctx* c, ValueSet& vs, const uint8_t* 
         MORAP_CHECK(v.kind != SWEEP_BLOCK || c->has_blocks, MORAP_E_UNSUPPORTED,
                     "the neighbourhood-block sweep needs products built from agents with at most 5 actions "
                     "and 5 successors per state");
+        MORAP_CHECK(v.kind != SWEEP_HALO || (c->has_halo && vs.prec == MORAP_F32), MORAP_E_UNSUPPORTED,
+                    "the LDS-staged sweep needs halo tiles (built with the block form) and FP32 values");
         return v;
     }
     const int64_t key = ((int64_t)vs.prec << 40) | ((int64_t)(mask != nullptr) << 32) | vs.Kp;
     for (auto& t : c->tuned)
         if (t.first == key) return variant_by_id(t.second);
-    auto cand = candidates(vs.Kp, mask != nullptr, c->has_blocks);
+    auto cand = candidates(vs.Kp, mask != nullptr, c->has_blocks, c->has_halo && vs.prec == MORAP_F32);
     MORAP_CHECK(!cand.empty(), MORAP_E_UNSUPPORTED, "no sweep variant for this column count");
     int best = cand[0].id;
     if (cand.size() > 1) {
@@ -410,7 +427,7 @@ static void run_vi(morap_ctx* c, int g, ValueSet& vs, const uint8_t* mask, const
     c->last_variant = v.id;
     const int chunk = std::max(2, (o.check_every + 1) / 2 * 2);
     EventPair wall;
-    reset_solve(c, vs, mask, o.eps_vi);
+    reset_solve(c, vs, mask, o.eps_vi, v);
     MORAP_HIP(hipEventRecord(wall.a, c->stream));
     int64_t launched = 0;
     int64_t* h = c->h_counters.as<int64_t>();
