@@ -392,6 +392,23 @@ int morap_proposer_set_input_norm(morap_ctx* ctx, const float* mu, const float* 
  * STATE (no proposer), HIP. */
 int morap_proposer_infer(morap_ctx* ctx, const float* X, int n, float* W_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * forward pass of morap_proposer_infer on DEVICE buffers, with no allocation
+ * of any kind.  X_dev[n][n_in] (FP32, device pointer, caller-owned) ->
+ * W_out_dev[n][d] (FP32 softmax rows, device pointer, caller-owned).  The
+ * work is enqueued on the context's stream and not waited for (synchronise
+ * the device or the stream before reading W_out_dev).  The activations use a
+ * fixed scratch of 8 MiB per device (held until the process ends, its address
+ * taken when the first context on the device is created): n must satisfy
+ * n * (2 n_in + 1536 + 4 d) bytes (each part rounded up to 256) <= 8 MiB,
+ * e.g. at most 4,712 rows for n_in = 62, d = 30; larger n returns
+ * UNSUPPORTED with the limit in the message and enqueues nothing.  Every call
+ * on a device shares that scratch: calls that overlap on one device (from
+ * several contexts or streams) race.  Errors: INVALID (NULL pointers,
+ * n < 1), STATE (no proposer), UNSUPPORTED (too many rows), HIP. */
+int morap_proposer_infer_noalloc(morap_ctx* ctx, const float* X_dev, int n, float* W_out_dev);
+
 /* One forward + backward pass on X[n][n_in] with targets T[n][d] (rows on the
  * simplex), mean cross-entropy loss.  loss_out (nullable) gets the loss;
  * grads_out (nullable) gets the FP32 gradients in parameter order.  When

@@ -60,6 +60,7 @@ int morap_create(morap_ctx** out, int device, void* hip_stream) {
     c->device = device;
     const int rc = guarded(c, [&] {
         MORAP_HIP(hipGetDeviceProperties(&c->prop, device));
+        proposer_scratch_init(device);   // the allocation-free inference's scratch address
         if (hip_stream) {
             c->stream = static_cast<hipStream_t>(hip_stream);
         } else {

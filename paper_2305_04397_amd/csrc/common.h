@@ -340,6 +340,8 @@ void query_batch(morap_ctx* ctx, const double* T, const double* W0, int Q, const
 
 // mlp.hip
 void proposer_destroy(Proposer* p);
+// device address of the fixed inference scratch, taken once per device
+void proposer_scratch_init(int device);
 
 // kernels (vi.hip): launch wrappers
 namespace k {

@@ -24,6 +24,8 @@
 //   * adam: the update of every parameter and its BF16 copy.
 #include "common.h"
 
+#include <mutex>
+
 #include <cmath>
 #include <cstdio>
 #include <numeric>
@@ -281,14 +283,32 @@ struct Proposer {
         return l == 0 ? xb.as<uint16_t>() : h[l - 1].as<uint16_t>();
     }
 
+    // activation buffers of one forward pass
+    struct Acts {
+        const float* xf;       // [n][n_in] FP32 input
+        uint16_t* xb;          // [n][n_in] BF16 standardised input
+        uint16_t* h[NLAYER - 1];
+        float* logits;         // [n][d]
+        float* prob;           // [n][d]
+    };
+    Acts own_acts() {
+        Acts a{xf.as<float>(), xb.as<uint16_t>(), {}, logits.as<float>(), prob.as<float>()};
+        for (int l = 0; l < NLAYER - 1; ++l) a.h[l] = h[l].as<uint16_t>();
+        return a;
+    }
+
     // forward of n rows already in xf (FP32); logits then softmax into prob
-    void forward(hipStream_t s, int n, const float* T_dev) {
-        hipLaunchKernelGGL(input_kernel, dim3(blocks_for((int64_t)n * n_in)), dim3(256), 0, s, xf.as<float>(),
-                           mu.as<float>(), sd.as<float>(), xb.as<uint16_t>(), (int64_t)n * n_in, n_in);
+    void forward(hipStream_t s, int n, const float* T_dev) { forward_into(s, n, own_acts(), T_dev); }
+
+    // the same into the buffers of `b` (T_dev, when given, also fills the
+    // loss and the output gradient of the context's own buffers)
+    void forward_into(hipStream_t s, int n, const Acts& b, const float* T_dev) {
+        hipLaunchKernelGGL(input_kernel, dim3(blocks_for((int64_t)n * n_in)), dim3(256), 0, s, b.xf, mu.as<float>(),
+                           sd.as<float>(), b.xb, (int64_t)n * n_in, n_in);
         MORAP_HIP(hipGetLastError());
         for (int l = 0; l < NLAYER; ++l) {
             GemmArgs a{};
-            a.A = act(l);
+            a.A = l == 0 ? b.xb : b.h[l - 1];
             a.sam = fan_in[l];
             a.sak = 1;
             a.B = pb16.as<uint16_t>() + w_off[l];
@@ -301,15 +321,15 @@ struct Proposer {
             a.bias = p32.as<float>() + b_off[l];
             if (l < NLAYER - 1) {
                 a.mode = EP_HIDDEN;
-                a.Cb = h[l].as<uint16_t>();
+                a.Cb = b.h[l];
             } else {
                 a.mode = EP_LOGITS;
-                a.Cf = logits.as<float>();
+                a.Cf = b.logits;
             }
             gemm(s, a);
         }
-        hipLaunchKernelGGL(softmax_xent, dim3(blocks_for(n, 64)), dim3(64), 0, s, logits.as<float>(), T_dev,
-                           prob.as<float>(), gout.as<uint16_t>(), T_dev ? loss.as<float>() : nullptr, n, d,
+        hipLaunchKernelGGL(softmax_xent, dim3(blocks_for(n, 64)), dim3(64), 0, s, b.logits, T_dev, b.prob,
+                           T_dev ? gout.as<uint16_t>() : nullptr, T_dev ? loss.as<float>() : nullptr, n, d,
                            1.f / (float)n);
         MORAP_HIP(hipGetLastError());
     }
@@ -396,6 +416,42 @@ struct Proposer {
 };
 
 void proposer_destroy(Proposer* p) { delete p; }
+
+// ---------------------------------------------------------------------------
+// allocation-free inference: the activations of morap_proposer_infer_noalloc
+// live in this fixed array (one copy per device, held until the process
+// ends).  Its device address is taken once per device when a context is
+// created there; host code uses that address, never the array's name.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)8 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static std::vector<unsigned char*> g_scratch;   // per device
+
+void proposer_scratch_init(int device) {   // with `device` current
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch.size() <= device) g_scratch.resize((size_t)device + 1, nullptr);
+    if (g_scratch[(size_t)device]) return;
+    void* p = nullptr;
+    MORAP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    MORAP_CHECK(p != nullptr, MORAP_E_HIP, "no device address for the inference scratch");
+    g_scratch[(size_t)device] = static_cast<unsigned char*>(p);
+}
+
+static unsigned char* scratch_of(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    MORAP_CHECK(device >= 0 && device < (int)g_scratch.size() && g_scratch[(size_t)device], MORAP_E_STATE,
+                "the inference scratch of this device was not set up (no context created on it)");
+    return g_scratch[(size_t)device];
+}
+
+static size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+// scratch bytes of an n-row forward pass: BF16 input, three BF16 hidden
+// layers, FP32 logits
+static size_t scratch_need(int64_t n, int n_in, int d) {
+    return round256((size_t)n * n_in * 2) + 3 * round256((size_t)n * HID * 2) + round256((size_t)n * d * 4);
+}
 
 bool proposer_ready(const morap_ctx* c, int n_in, int d) {
     return c->prop_mlp && c->prop_mlp->n_in == n_in && c->prop_mlp->d == d;
@@ -499,6 +555,35 @@ int morap_proposer_infer(morap_ctx* ctx, const float* X, int n, float* W_out) {
         check_rows(X, nullptr, n, p.n_in, p.d);
         MORAP_CHECK(W_out, MORAP_E_INVALID, "NULL output");
         p.infer(ctx->stream, X, n, W_out);
+    });
+}
+
+int morap_proposer_infer_noalloc(morap_ctx* ctx, const float* X_dev, int n, float* W_out_dev) {
+    return guarded(ctx, [&] {
+        Proposer& p = need(ctx);
+        MORAP_CHECK(X_dev && W_out_dev && n >= 1, MORAP_E_INVALID, "need device X, device W_out and n >= 1");
+        const size_t need_b = scratch_need(n, p.n_in, p.d);
+        if (need_b > kScratchBytes) {
+            int64_t max_rows = 0;
+            while (scratch_need(max_rows + 1, p.n_in, p.d) <= kScratchBytes) ++max_rows;
+            fail(MORAP_E_UNSUPPORTED, std::to_string(n) + " rows need " + std::to_string(need_b) +
+                                          " bytes of inference scratch; the fixed scratch holds " +
+                                          std::to_string(kScratchBytes) + " bytes (at most " +
+                                          std::to_string(max_rows) + " rows for this network)");
+        }
+        unsigned char* base = scratch_of(ctx->device);
+        Proposer::Acts a{};
+        a.xf = X_dev;
+        size_t off = 0;
+        a.xb = reinterpret_cast<uint16_t*>(base + off);
+        off += round256((size_t)n * p.n_in * 2);
+        for (int l = 0; l < NLAYER - 1; ++l) {
+            a.h[l] = reinterpret_cast<uint16_t*>(base + off);
+            off += round256((size_t)n * HID * 2);
+        }
+        a.logits = reinterpret_cast<float*>(base + off);
+        a.prob = W_out_dev;
+        p.forward_into(ctx->stream, n, a, nullptr);
     });
 }
 

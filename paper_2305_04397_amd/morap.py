@@ -137,6 +137,7 @@ _sig("morap_proposer_get_params", C.c_int, _ctxp, _p)
 _sig("morap_proposer_set_params", C.c_int, _ctxp, _p)
 _sig("morap_proposer_set_input_norm", C.c_int, _ctxp, _p, _p)
 _sig("morap_proposer_infer", C.c_int, _ctxp, _p, C.c_int, _p)
+_sig("morap_proposer_infer_noalloc", C.c_int, _ctxp, _p, C.c_int, _p)
 _sig("morap_proposer_step", C.c_int, _ctxp, _p, _p, C.c_int, C.POINTER(TrainOpts), C.c_int, _p, _p)
 _sig("morap_proposer_train", C.c_int, _ctxp, _p, _p, C.c_int, C.POINTER(TrainOpts), _p)
 _sig("morap_proposer_save", C.c_int, _ctxp, C.c_char_p)
@@ -523,6 +524,12 @@ class Context:
         out = np.zeros((X.shape[0], d), np.float32)
         self._check(lib.morap_proposer_infer(self._h, _ptr(X), X.shape[0], _ptr(out)), "morap_proposer_infer")
         return out
+
+    def proposer_infer_noalloc(self, x_dev: int, n: int, w_dev: int):
+        """morap_proposer_infer_noalloc on device pointers (integers); enqueued
+        on the context's stream, not waited for."""
+        self._check(lib.morap_proposer_infer_noalloc(self._h, C.c_void_p(x_dev), n, C.c_void_p(w_dev)),
+                    "morap_proposer_infer_noalloc")
 
     @staticmethod
     def _topts(batch=4096, epochs=1, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8, seed=0) -> TrainOpts:
