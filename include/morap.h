@@ -61,6 +61,13 @@ int morap_create(morap_ctx** out, int device, void* hip_stream);
 /* Release all device and host memory of the context.  NULL is accepted. */
 int morap_destroy(morap_ctx* ctx);
 
+/* Device memory budget of the context in bytes (0 = none, the default).  An
+ * allocation that would take the context's device memory beyond it fails
+ * with MORAP_E_OOM, as a failed hipMalloc does; what the context already
+ * holds is kept.  used_out (nullable) receives the bytes the context holds
+ * now.  Errors: INVALID (negative budget). */
+int morap_set_memory_budget(morap_ctx* ctx, int64_t bytes, int64_t* used_out);
+
 /* Text of the last error on this context ("" if none).  Valid until the next
  * call on the context. */
 const char* morap_last_error(const morap_ctx* ctx);

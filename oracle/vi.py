@@ -308,3 +308,46 @@ def evaluate_exact(prod: Product, mu: np.ndarray) -> np.ndarray:
     A = sp.identity(S, format="csc") - prod.P()[rows].tocsc()
     rho = np.stack([prod.rew_cost[rows], prod.rew_prob[rows]], axis=1)
     return np.column_stack([spla.spsolve(A, rho[:, 0]), spla.spsolve(A, rho[:, 1])])
+
+
+def optimal_exact(prod: Product, wc: float, wp: float, tau: float = 1e-9, max_iter: int = 100):
+    """Exact optimal scalarised values by policy iteration, the ground truth
+    for comparing chosen actions: value iteration (Alg. 3) to a tight
+    tolerance gives a first proper policy (attractor tie rule), which is then
+    evaluated exactly (a sparse linear solve) and improved greedily on its own
+    exact values until no action beats the evaluated values by more than
+    1e-12 max(1, |v|).  Returns (v[S], Q[R], err) where Q are the one-step
+    values of every row at v and err = max_s |max_a Q(s, a) - v(s)|, the
+    Bellman residual of the result."""
+    S = prod.n_states
+    if S == 0:
+        return np.zeros(0), np.zeros(0), 0.0
+    x, _ = value_iteration(prod, wc, wp, 1e-11)
+    x = x[:, 0]
+    w = np.array([wc, wp], dtype=np.float64)
+    for _ in range(max_iter):
+        mu = extract_policy(prod, x, wc, wp, tau)
+        v = evaluate_exact(prod, mu) @ w
+        Q = q_values(prod, v, wc, wp)[:, 0]
+        qmax = _state_max(prod, Q[:, None])[:, 0]
+        scale = max(1.0, float(np.abs(v).max()))
+        if (qmax <= v + 1e-12 * scale).all():
+            return v, Q, float(np.abs(qmax - v).max())
+        x = v
+    raise RuntimeError("policy iteration did not settle")
+
+
+def q_gaps(prod: Product, Q: np.ndarray) -> tuple:
+    """Per state: the best row (counted from the state's first row, lowest
+    index among equal values) and the gap to the next best row's value (inf
+    for a state with one row)."""
+    S = prod.n_states
+    best = np.zeros(S, dtype=np.int64)
+    gap = np.full(S, np.inf)
+    for s in range(S):
+        q = Q[prod.state_row[s]:prod.state_row[s + 1]]
+        order = np.argsort(-q, kind="stable")
+        best[s] = order[0]
+        if q.size > 1:
+            gap[s] = q[order[0]] - q[order[1]]
+    return best, gap

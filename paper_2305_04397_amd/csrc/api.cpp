@@ -8,6 +8,10 @@
 
 using namespace morap;
 
+namespace morap {
+thread_local AllocMeter* g_meter = nullptr;
+}
+
 morap_ctx::~morap_ctx() {
     for (int g = 0; g < 2; ++g) {
         if (chunk_exec[g]) (void)hipGraphExecDestroy(chunk_exec[g]);
@@ -76,6 +80,14 @@ int morap_create(morap_ctx** out, int device, void* hip_stream) {
     }
     *out = c;
     return MORAP_OK;
+}
+
+int morap_set_memory_budget(morap_ctx* ctx, int64_t bytes, int64_t* used_out) {
+    return guarded(ctx, [&] {
+        MORAP_CHECK(bytes >= 0, MORAP_E_INVALID, "the budget must be >= 0 (0 = none)");
+        ctx->meter.budget = bytes;
+        if (used_out) *used_out = ctx->meter.used;
+    });
 }
 
 int morap_destroy(morap_ctx* ctx) {

@@ -41,30 +41,47 @@ struct MorapError : std::runtime_error {
 // ---------------------------------------------------------------------------
 // device buffers
 // ---------------------------------------------------------------------------
+// Device bytes held by a context and its optional budget (0 = none).  The
+// context's meter is current on the thread during every call on it, and each
+// buffer remembers the meter that paid for it.
+struct AllocMeter {
+    int64_t budget = 0, used = 0;
+};
+extern thread_local AllocMeter* g_meter;
+
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    AllocMeter* meter = nullptr;
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { release(); }
     void release() {
         if (p) (void)hipFree(p);
+        if (p && meter) meter->used -= (int64_t)bytes;
         p = nullptr;
         bytes = 0;
+        meter = nullptr;
     }
     // (re)allocate when the requested size exceeds the current one; true
-    // when the buffer moved
+    // when the buffer moved.  Over the context's budget: OOM, buffer released.
     bool ensure(size_t n) {
         if (n <= bytes && p) return false;
         release();
         if (n == 0) n = 16;
+        AllocMeter* m = g_meter;
+        if (m && m->budget > 0 && m->used + (int64_t)n > m->budget)
+            fail(MORAP_E_OOM, "device memory budget of " + std::to_string(m->budget) + " bytes exceeded (" +
+                                  std::to_string(m->used) + " held, " + std::to_string(n) + " more requested)");
         hipError_t e = hipMalloc(&p, n);
         if (e != hipSuccess) {
             p = nullptr;
             fail(MORAP_E_OOM, "hipMalloc of " + std::to_string(n) + " bytes failed: " + hipGetErrorString(e));
         }
         bytes = n;
+        meter = m;
+        if (m) m->used += (int64_t)n;
         return true;
     }
     template <class T> T* as() const { return static_cast<T*>(p); }
@@ -188,6 +205,7 @@ struct Proposer;  // mlp.hip
 // the context
 // ---------------------------------------------------------------------------
 struct morap_ctx {
+    morap::AllocMeter meter;                        // first member: outlives every buffer
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -251,6 +269,8 @@ struct morap_ctx {
     morap::DevBuf d_mask, d_rank, d_mu;             // per instance state
     morap::DevBuf d_xe[2];                          // evaluation values [inst states][2]
     morap::DevBuf d_iwc, d_iwp;                     // per instance FP64 weights
+    morap::DevBuf d_iscale;                         // per instance 1 / (w_i + w_j) (warm start)
+    morap::DevBuf d_ichanged;                       // per instance: ranks changed in the last round
     morap::DevBuf d_init_idx, d_init_val;           // instance initial states, their values
     morap::DevBuf d_xr;                             // second buffer of the instance value iteration
     std::vector<int32_t> h_live_tiles;              // instance tiles still active
@@ -279,6 +299,11 @@ namespace morap {
 template <class F>
 int guarded(morap_ctx* c, F&& f) {
     if (!c) return MORAP_E_INVALID;
+    struct MeterScope {   // the context pays for what the call allocates
+        AllocMeter* prev;
+        explicit MeterScope(AllocMeter* m) : prev(g_meter) { g_meter = m; }
+        ~MeterScope() { g_meter = prev; }
+    } scope(&c->meter);
     try {
         c->err.clear();
         MORAP_HIP(hipSetDevice(c->device));
@@ -440,6 +465,10 @@ struct InstArgs {
 };
 void gather_columns(hipStream_t s, const InstArgs& a, int prec, const void* x0, const void* x1,
                     const uint8_t* final_par, int Kp, double* xi);
+// FP64 start of the instances from the FP32 solve's values, scaled by
+// scale[inst] (instances with a zero cost weight start from 0)
+void warm_start(hipStream_t s, const InstArgs& a, const void* x0, const void* x1, const uint8_t* final_par, int Kp,
+                const double* scale, const double* iwc, double* xi);
 void inst_converge(hipStream_t s, int n, unsigned long long* res, uint8_t* active, uint8_t* par, int out_par,
                    double eps, int64_t* counter);
 void opt_mask(hipStream_t s, const InstArgs& a, const double* wc, const double* wp, const double* x,
@@ -450,7 +479,7 @@ void count_unranked(hipStream_t s, const InstArgs& a, const int32_t* rank, int64
 // attractor ranks as BFS distances (in-place relaxation sweep) and the action
 // choice once they are final
 void relax_ranks(hipStream_t s, const InstArgs& a, const uint32_t* mask, int32_t* rank, int base, bool reverse,
-                 int local, int64_t* changed);
+                 int local, int64_t* changed, uint8_t* inst_changed);
 void choose_actions(hipStream_t s, const InstArgs& a, const uint32_t* mask, const int32_t* rank, int8_t* mu,
                     int base, int64_t* max_rank);
 // per-instance flags: `width` entries per instance, active when the instance

@@ -628,7 +628,7 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
     c->inst_m.resize(n);
     c->inst_base.assign(n + 1, 0);
     std::vector<int32_t> tiles;
-    std::vector<double> iwc(n), iwp(n);
+    std::vector<double> iwc(n), iwp(n), iscale(n, 0.0);
     std::vector<int64_t> init_idx(n, -1);
     for (int kk = 0; kk < K; ++kk)
         for (int j = 0; j < nJ; ++j) {
@@ -649,6 +649,7 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
             if (sc > 0) {
                 iwc[q] /= sc;
                 iwp[q] /= sc;
+                iscale[q] = 1.0 / sc;
             }
             if (c->hm.init[m] >= 0) init_idx[q] = c->inst_base[q] + (c->hm.init[m] - c->hm.state_base[m]);
         }
@@ -660,6 +661,7 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
     c->d_inst_tiles.ensure(tiles.size() * 4 + 8);
     c->d_iwc.ensure((size_t)n * 8);
     c->d_iwp.ensure((size_t)n * 8);
+    c->d_iscale.ensure((size_t)n * 8);
     c->d_xi.ensure((size_t)NS * 8 + 8);
     c->d_ires.ensure((size_t)2 * n * 8);
     c->d_iactive.ensure((size_t)2 * n);
@@ -678,6 +680,7 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
         MORAP_HIP(hipMemcpyAsync(c->d_inst_tiles.p, tiles.data(), tiles.size() * 4, hipMemcpyHostToDevice, s));
     MORAP_HIP(hipMemcpyAsync(c->d_iwc.p, iwc.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
     MORAP_HIP(hipMemcpyAsync(c->d_iwp.p, iwp.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+    MORAP_HIP(hipMemcpyAsync(c->d_iscale.p, iscale.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
     MORAP_HIP(hipMemcpyAsync(c->d_init_idx.p, init_idx.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
     const k::InstArgs a = inst_args(c, n_tiles, n);
     int64_t* dctr = c->d_counters.as<int64_t>();
@@ -727,7 +730,13 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
         c->d_xr.ensure((size_t)NS * 8 + 8);
         double* x0 = xi;
         double* x1 = c->d_xr.as<double>();
-        k::fill_f64(s, x0, 0.0, NS);
+        // after an FP32 solve the re-solve starts from its values (scaled to
+        // the instance's weights); after an FP64 solve from 0, as Alg. 3
+        if (c->prec == MORAP_F32 && c->vmain.valid)
+            k::warm_start(s, a, c->vmain.x[0].p, c->vmain.x[1].p, c->vmain.final_par.as<uint8_t>(), c->vmain.Kp,
+                          c->d_iscale.as<double>(), c->d_iwc.as<double>(), x0);
+        else
+            k::fill_f64(s, x0, 0.0, NS);
         k::fill_f64(s, x1, 0.0, NS);
         k::set_active(s, n, a, iact, ires, ipar, 1);
         EventPair wall;
@@ -812,20 +821,27 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
     // their choice.
     uint32_t* mask = c->d_mask.as<uint32_t>();
     int32_t* rank = c->d_rank.as<int32_t>();
+    c->d_ichanged.ensure((size_t)n + 8);
+    uint8_t* ichg = c->d_ichanged.as<uint8_t>();
     int8_t* mu = c->d_mu.as<int8_t>();
     k::opt_mask(s, a, c->d_iwc.as<double>(), c->d_iwp.as<double>(), xi, o.tau, mask, rank, mu, false);
     int base = 0, relax_sweeps = 0;
     double tau = o.tau;
     for (int widen = 0;; ++widen) {
         // ranks of this phase: relax to the fixed point (8 sweeps per check,
-        // alternating direction; converged when the last sweep changed nothing)
+        // alternating direction; converged when the last sweep changed
+        // nothing).  After a round only the tiles of instances that changed
+        // in it are relaxed again: ranks spread only inside an instance.
+        k::InstArgs ar = a;
         for (int round = 0;; ++round) {
             k::fill_i64(s, dctr, 0, 8);
-            for (int i = 0; i < 8; ++i) k::relax_ranks(s, a, mask, rank, base, (i & 1) != 0, 16, dctr + i);
+            k::fill_u8(s, ichg, 0, n);
+            for (int i = 0; i < 8; ++i) k::relax_ranks(s, ar, mask, rank, base, (i & 1) != 0, 16, dctr + i, ichg);
             relax_sweeps += 8;
             read_counters(c);
             if (h[7] == 0) break;
             MORAP_CHECK(round < 1000000, MORAP_E_IMPROPER, "attractor ranks did not settle");
+            live_tiles(ichg, 1, ar);
         }
         k::fill_i64(s, dctr, 0, 1);
         k::choose_actions(s, a, mask, rank, mu, base, dctr);

@@ -551,6 +551,34 @@ __global__ void gather_kernel(InstArgs a, const T* x0, const T* x1, const uint8_
     xi[L.is] = (double)x[(int64_t)L.gs * Kp + k];
 }
 
+// Start of the FP64 re-solve of an instance from the FP32 solve's values of
+// its pair: the optimal values of the model scale with its two weights, so
+// x = x32 / (w_i + w_j) (scale[inst] = 1 / (w_i + w_j)).  Only instances
+// whose scaled cost weight is positive start there: every improper policy
+// then loses without bound and the Bellman operator has one fixed point,
+// reached from any start.  With a zero cost weight zero-reward loops admit
+// larger fixed points, and those instances start from 0 as Alg. 3 does.
+__global__ void warm_kernel(InstArgs a, const float* x0, const float* x1, const uint8_t* par, int Kp,
+                            const double* scale, const double* iwc, double* xi) {
+    InstLoc L;
+    if (!inst_locate(a, L)) return;
+    double v = 0.0;
+    if (iwc[L.inst] > 0.0) {
+        const int k = a.inst_k[L.inst];
+        const float* x = par[(int64_t)L.m * Kp + k] ? x1 : x0;
+        v = (double)x[(int64_t)L.gs * Kp + k] * scale[L.inst];
+    }
+    xi[L.is] = v;
+}
+
+void warm_start(hipStream_t s, const InstArgs& a, const void* x0, const void* x1, const uint8_t* final_par, int Kp,
+                const double* scale, const double* iwc, double* xi) {
+    if (a.n_tiles <= 0) return;
+    hipLaunchKernelGGL(warm_kernel, dim3(a.n_tiles), dim3(256), 0, s, a, (const float*)x0, (const float*)x1,
+                       final_par, Kp, scale, iwc, xi);
+    MORAP_HIP(hipGetLastError());
+}
+
 void gather_columns(hipStream_t s, const InstArgs& a, int prec, const void* x0, const void* x1,
                     const uint8_t* final_par, int Kp, double* xi) {
     if (a.n_tiles <= 0) return;
@@ -670,7 +698,8 @@ __device__ __forceinline__ bool inst_locate_tile(const InstArgs& a, int t, InstL
 // only decrease, so the fixed point is the exact distance in any order.
 // rank < 0 means not (yet) ranked.
 __global__ void __launch_bounds__(256) relax_kernel(InstArgs a, const uint32_t* mask, int32_t* rank, int base,
-                                                    int reverse, int local, int64_t* changed) {
+                                                    int reverse, int local, int64_t* changed,
+                                                    uint8_t* inst_changed) {
     const int t = reverse ? a.n_tiles - 1 - (int)blockIdx.x : (int)blockIdx.x;
     InstLoc L;
     const bool ok = inst_locate_tile(a, t, L);
@@ -709,14 +738,19 @@ __global__ void __launch_bounds__(256) relax_kernel(InstArgs a, const uint32_t* 
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) n_upd += __shfl_xor(n_upd, o, 64);
-    if ((threadIdx.x & 63) == 0 && n_upd) atomicAdd((unsigned long long*)changed, n_upd);
+    if ((threadIdx.x & 63) == 0 && n_upd) {
+        atomicAdd((unsigned long long*)changed, n_upd);
+        // the instance is not at its fixed point yet (ranks spread only
+        // inside an instance, so one without updates for a whole round is)
+        inst_changed[a.inst_tiles[2 * t]] = 1;
+    }
 }
 
 void relax_ranks(hipStream_t s, const InstArgs& a, const uint32_t* mask, int32_t* rank, int base, bool reverse,
-                 int local, int64_t* changed) {
+                 int local, int64_t* changed, uint8_t* inst_changed) {
     if (a.n_tiles <= 0) return;
     hipLaunchKernelGGL(relax_kernel, dim3(a.n_tiles), dim3(256), 0, s, a, mask, rank, base, reverse ? 1 : 0,
-                       local, changed);
+                       local, changed, inst_changed);
     MORAP_HIP(hipGetLastError());
 }
 

@@ -108,6 +108,7 @@ _ctxp = _p
 _sig("morap_create", C.c_int, C.POINTER(_p), C.c_int, _p)
 _sig("morap_destroy", C.c_int, _ctxp)
 _sig("morap_last_error", C.c_char_p, _ctxp)
+_sig("morap_set_memory_budget", C.c_int, _ctxp, C.c_int64, _p)
 _sig("morap_build_products", C.c_int, _ctxp, C.POINTER(Agent), C.c_int, C.POINTER(Dfa), C.c_int, C.POINTER(_p))
 _sig("morap_load_models", C.c_int, _ctxp, C.POINTER(Model), C.c_int, C.c_int, C.c_int)
 _sig("morap_model_info", C.c_int, _ctxp, C.c_int, _p)
@@ -500,6 +501,15 @@ class Context:
     def set_features(self, phi):
         phi = _c(phi, np.float64)
         self._check(lib.morap_set_features(self._h, _ptr(phi), len(phi)), "morap_set_features")
+
+    def proposer_num_params(self) -> int:
+        return int(lib.morap_proposer_num_params(self._h))
+
+    def set_memory_budget(self, nbytes: int) -> int:
+        """Device memory budget in bytes (0 = none); returns the bytes held."""
+        used = C.c_int64()
+        self._check(lib.morap_set_memory_budget(self._h, int(nbytes), C.byref(used)), "morap_set_memory_budget")
+        return int(used.value)
 
     def proposer_init(self, n_in: int, d: int, seed: int = 0):
         self._check(lib.morap_proposer_init(self._h, n_in, d, seed), "morap_proposer_init")

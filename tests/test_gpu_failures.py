@@ -1,0 +1,103 @@
+"""Failure handling through the C ABI, each condition forced from the host so
+that every kernel still exits normally: a model with no path to done
+(IMPROPER), a device memory budget (OOM), malformed caller-loaded models
+(INVALID), and a proposer whose output is not a weight vector (the plain
+rule takes over, fallback = 1)."""
+import numpy as np
+import pytest
+
+from workloads import make_workload, dirichlet_weights
+
+pytestmark = pytest.mark.gpu
+
+E_INVALID, E_OOM, E_IMPROPER = -1, -2, -4
+
+
+@pytest.fixture(scope="module")
+def morap():
+    from paper_2305_04397_amd import morap as m
+    return m
+
+
+@pytest.fixture()
+def ctx(morap):
+    c = morap.Context(0)
+    yield c
+    c.close()
+
+
+def _one_state_model(row_prob=1.0, col=0, rew=(-1.0, 0.0)):
+    """One live state with one row: a loop back to itself (mass row_prob),
+    the rest of the row's mass into done."""
+    return {"state_row": np.array([0, 1]), "row_ptr": np.array([0, 1]), "col": np.array([col]),
+            "prob": np.array([row_prob]), "rew": np.array([rew]), "to_done": np.array([row_prob < 1.0]),
+            "init": 0}
+
+
+def test_improper_model_is_reported(ctx, morap):
+    # the only action loops forever: under a probability-only weight the
+    # values converge (to 0), but no action reaches done -> IMPROPER
+    ctx.load_models([_one_state_model()], 1, 1)
+    with pytest.raises(morap.MorapError) as e:
+        ctx.support(np.array([[0.0, 1.0]]), morap.Options(eps_vi=1e-8, precision="f64"))
+    assert e.value.code == E_IMPROPER
+    # a model that does reach done is fine on the same context afterwards
+    ctx.load_models([_one_state_model(row_prob=0.5, rew=(-1.0, 0.5))], 1, 1)
+    r, A, c, _ = ctx.support(np.array([[0.5, 0.5]]), morap.Options(eps_vi=1e-10, precision="f64"))
+    assert r[0] == pytest.approx([-2.0, 1.0], abs=1e-8)
+
+
+@pytest.mark.parametrize("bad", ["row_sum", "col", "nan_reward", "neg_prob"])
+def test_load_models_rejects_malformed_models(ctx, morap, bad):
+    m = _one_state_model(row_prob=0.5)
+    if bad == "row_sum":
+        m.update(row_ptr=np.array([0, 2]), col=np.array([0, 0]), prob=np.array([0.7, 0.5]))
+    elif bad == "col":
+        m.update(col=np.array([3]))
+    elif bad == "nan_reward":
+        m.update(rew=np.array([[np.nan, 0.0]]))
+    else:
+        m.update(prob=np.array([-0.25]))
+    with pytest.raises(morap.MorapError) as e:
+        ctx.load_models([m], 1, 1)
+    assert e.value.code == E_INVALID
+
+
+def test_memory_budget_gives_oom_and_recovers(ctx, morap):
+    wl = make_workload(2, n_agents=2, n_tasks=3)
+    ctx.build_products(wl)
+    W = dirichlet_weights(np.random.default_rng(0), 64, 5)
+    held = ctx.set_memory_budget(0)
+    assert held > 0
+    # the solve's value buffers do not fit a budget just above what is held
+    ctx.set_memory_budget(held + 4096)
+    with pytest.raises(morap.MorapError) as e:
+        ctx.solve(W, morap.Options(eps_vi=1e-6, precision="f32"))
+    assert e.value.code == E_OOM and "budget" in str(e.value)
+    # lifting the budget lets the same context solve
+    ctx.set_memory_budget(0)
+    c, _ = ctx.solve(W, morap.Options(eps_vi=1e-6, precision="f32"))
+    assert np.isfinite(c).all()
+    with pytest.raises(morap.MorapError) as e:
+        ctx.set_memory_budget(-1)
+    assert e.value.code == E_INVALID
+
+
+def test_proposer_nan_output_falls_back_to_the_plain_rule(ctx, morap):
+    wl = make_workload(1)
+    ctx.build_products(wl)
+    d, nfeat = 4, 2
+    ctx.set_features(np.array([0.1, 0.2]))
+    ctx.proposer_init(d + nfeat, d, seed=5)
+    # finite parameters (the library rejects others) that overflow the
+    # network: its softmax rows come out non-finite
+    ctx.proposer_set_params(np.full(ctx.proposer_num_params(), 3e38, dtype=np.float32))
+    out = ctx.proposer_infer(np.array([[-40.0, -40.0, 0.8, 0.8, 0.1, 0.2]], np.float32), d)
+    assert not np.isfinite(out).all()
+    t = np.array([-40.0, -40.0, 0.8, 0.8])
+    opts = morap.Options(eps_vi=1e-8, precision="f64")
+    learned = ctx.query(t, eps=1e-3, max_iter=32, opts=opts, use_proposer=True)
+    plain = ctx.query(t, eps=1e-3, max_iter=32, opts=opts)
+    assert learned["fallback"] == 1 and plain["fallback"] == 0
+    assert learned["verdict"] == plain["verdict"] and learned["iterations"] == plain["iterations"]
+    assert np.array_equal(learned["t_up"], plain["t_up"])

@@ -15,6 +15,7 @@ import pytest
 
 from workloads import make_workload, worked_example, tiny_workload, dirichlet_weights
 from oracle import product, vi, alg, centralised
+from parity_g12 import check_support
 
 pytestmark = pytest.mark.gpu
 
@@ -264,6 +265,10 @@ def test_query_cfg1_matches_oracle(ctx, morap):
 
 
 def test_f32_solve_and_support_cfg2(ctx, morap):
+    """FP32 solve, FP64 re-solve of the assigned pairs from the FP32 values,
+    policies and evaluation: every column against the oracle under the
+    contract of parity_g12 (assignment within the FP32 errors of the oracle's
+    optimum, actions equal to the exact optimum's off ties, r and w.r)."""
     wl = make_workload(2, n_agents=3, n_tasks=6)
     prods = _load(ctx, wl)
     nI, nJ = wl.n_agents, wl.n_tasks
@@ -277,24 +282,9 @@ def test_f32_solve_and_support_cfg2(ctx, morap):
     # max(eps, 8 u32 |y|); the values stay within 2e-4 relative of the oracle's
     err = np.abs(c - co)
     assert (err <= 2e-4 * np.maximum(1.0, np.abs(co))).all(), err.max()
-    matched = 0
-    for k in range(W.shape[0]):
-        # the assigned pairs are re-solved in FP64 from 0: with the oracle's
-        # assignment, policies are identical and r agrees to rounding
-        if not np.array_equal(alg.assign(co[k]), A[k]):
-            continue
-        matched += 1
-        ro = np.zeros(nI + nJ)
-        for j in range(nJ):
-            m = A[k][j] * nJ + j
-            p = prods[m]
-            mu = _oracle_policy(p, W[k, A[k][j]], W[k, nI + j], eps)
-            assert ctx.get_policy(k, j, p.n_states).tolist() == mu.tolist()
-            (vc, vp), _, _ = vi.evaluate(p, mu, eps)
-            ro[nI + j] = vp
-            ro[A[k][j]] += vc
-        assert np.abs(r[k] - ro).max() <= 1e-9 * max(1.0, np.abs(ro).max())
-    assert matched >= W.shape[0] // 2
+    rep = check_support(ctx, prods, nI, nJ, W, r, A, c, co, eps)
+    print("\nparity f32 cfg2:", dict(rep))
+    assert rep["excluded_states"] <= 0.05 * rep["states"]
 
 
 def test_edge_cases(ctx, morap):
@@ -567,7 +557,7 @@ def test_support_on_caller_loaded_csr_products(ctx, morap, prec):
     ctx.load_models([{"state_row": p.state_row, "row_ptr": p.row_ptr, "col": p.col, "prob": p.prob,
                       "rew": np.stack([p.rew_cost, p.rew_prob], 1), "to_done": p.to_done, "init": p.init}
                      for p in prods], nI, nJ)
-    W = dirichlet_weights(np.random.default_rng(8), 16, nI + nJ)
+    W = dirichlet_weights(np.random.default_rng(8), 8, nI + nJ)
     W[1] = np.eye(nI + nJ)[nI]
     eps = 1e-6 if prec == "f32" else 1e-8
     r, A, c, st = ctx.support(W, morap.Options(eps_vi=eps, precision=prec))
@@ -575,21 +565,8 @@ def test_support_on_caller_loaded_csr_products(ctx, morap, prec):
     co, _, _ = _oracle_c(prods, nI, nJ, W, eps)
     tol = 2e-4 * np.maximum(1.0, np.abs(co)) if prec == "f32" else 4 * eps + 1e-10 * np.abs(co).max()
     assert (np.abs(c - co) <= tol).all()
-    matched = 0
-    for k in range(W.shape[0]):
-        if not np.array_equal(alg.assign(co[k]), A[k]):
-            continue
-        matched += 1
-        ro = np.zeros(nI + nJ)
-        for j in range(nJ):
-            p = prods[A[k][j] * nJ + j]
-            mu = _oracle_policy(p, W[k, A[k][j]], W[k, nI + j], eps)
-            assert ctx.get_policy(k, j, p.n_states).tolist() == mu.tolist()
-            (vc, vp), _, _ = vi.evaluate(p, mu, eps)
-            ro[nI + j] = vp
-            ro[A[k][j]] += vc
-        assert np.abs(r[k] - ro).max() <= 1e-9 * max(1.0, np.abs(ro).max())
-    assert matched >= W.shape[0] // 2
+    rep = check_support(ctx, prods, nI, nJ, W, r, A, c, co, eps)
+    print(f"\nparity {prec} caller-loaded CSR:", dict(rep))
 
 
 @pytest.mark.parametrize("K", [65, 128, 130])

@@ -961,3 +961,56 @@ def test_mutation_frozen_weight_update_fails_the_projection_pin(monkeypatch):
     assert np.linalg.norm(alg.query(prods, 1, 1, t, 1e-9, 1e-13, max_iter=200).t_up - p) <= bound
     monkeypatch.setattr(geometry, "weight_from", lambda t, t_up, M=None: np.full(len(t), 1.0 / len(t)))
     assert np.linalg.norm(alg.query(prods, 1, 1, t, 1e-9, 1e-13, max_iter=40).t_up - p) > 1e-3
+
+
+@pytest.mark.parametrize("seed,w,h,kind", [(11, 3, 2, "reach"), (12, 3, 3, "avoid"), (13, 3, 3, "avoid")])
+def test_exact_policy_iteration_equals_brute_force(seed, w, h, kind):
+    """The oracle's exact optimum (policy iteration) is the best deterministic
+    policy's value at the initial state, and its Q-gaps name that policy's
+    action wherever they are clear."""
+    wl = tiny_workload(seed, 1, 1, width=w, height=h, kinds=(kind,), k=1)
+    prod = product.build_all(wl)[0]
+    pts, pols = _policy_points(prod)
+    rng = np.random.default_rng(seed + 7)
+    for _ in range(4):
+        wv = rng.dirichlet([1.0, 1.0])
+        v, Q, err = vi.optimal_exact(prod, wv[0], wv[1])
+        vals = pts @ wv
+        assert v[prod.init] == pytest.approx(vals.max(), abs=1e-11)
+        assert err <= 1e-11
+        best, gap = vi.q_gaps(prod, Q)
+        # every optimal deterministic policy takes the unique best action
+        # wherever the gap is clear (states reachable or not: all of them are
+        # optimal from their own start in an optimal stationary policy)
+        opt = [pols[i] for i in np.flatnonzero(vals >= vals.max() - 1e-11)]
+        clear = gap > 1e-9
+        assert any((mu[clear] == best[clear]).all() for mu in opt)
+
+
+@pytest.mark.parametrize("seed", [73, 74])
+def test_exact_policy_iteration_equals_the_lp_optimum(seed):
+    wl = tiny_workload(seed, 1, 1, width=3, height=3, kinds=("reach",), k=3, p_slip=0.2)
+    prods = product.build_all(wl)
+    p = prods[0]
+    Aeq, beq, obj = _mo_lp(prods, 1, 1)
+    for w in np.random.default_rng(seed).dirichlet(np.ones(2), size=3):
+        v, _, _ = vi.optimal_exact(p, w[0], w[1])
+        lp = linprog(-(w @ obj), A_eq=Aeq, b_eq=beq, bounds=[(0, None)] * Aeq.shape[1], method="highs")
+        assert lp.status == 0
+        assert v[p.init] == pytest.approx(-lp.fun, abs=1e-7)
+
+
+def test_exact_policy_iteration_pin_catches_a_minimising_improvement(monkeypatch):
+    # plant a mistake on the CPU: an improvement step that keeps the worst
+    # action instead of the best one misses the brute-force optimum
+    wl = tiny_workload(12, 1, 1, width=3, height=3, kinds=("avoid",), k=1)
+    prod = product.build_all(wl)[0]
+    pts, _ = _policy_points(prod)
+    real = vi.q_values
+    monkeypatch.setattr(vi, "q_values", lambda p, x, wc, wp: -real(p, x, wc, wp))
+    wv = np.array([0.4, 0.6])
+    try:
+        v, _, _ = vi.optimal_exact(prod, wv[0], wv[1])
+        assert abs(v[prod.init] - (pts @ wv).max()) > 1e-3
+    except (RuntimeError, vi.ImproperPolicy):
+        pass   # or it fails outright: either way the planted mistake is caught
