@@ -10,7 +10,7 @@
     exact Q-gap exceeds tau_cmp = max(1e-9, 2 err_exact, 4 err_vi), err_vi the
     distance of an eps-stopped value iteration from the exact values (the
     accuracy the device's values have); states under that gap are counted as
-    excluded, not compared;
+    excluded, not compared, and so are, apart, the exact ties among them;
   * r: the oracle's Alg. 4 evaluation of the device's own policies, to 1e-9
     relative (plus 4 eps_eval);
   * w.r: the oracle's sum_j c°[f(j), j] to 1e-6 relative (Lemma lem:face).
@@ -66,6 +66,8 @@ def check_support(ctx, prods, nI, nJ, W, r, A, c, co, eps, report=None, columns=
             assert wrong.size == 0, (k, j, wrong[:5], gap[wrong[:5]], tau)
             report.add("states", int(p.n_states), op=lambda x, y: x + y)
             report.add("excluded_states", int((~clear).sum()), op=lambda x, y: x + y)
+            # of which exact ties (several actions equally good to 1e-9)
+            report.add("excluded_exact_ties", int((gap <= 1e-9).sum()), op=lambda x, y: x + y)
             report.add("tau_cmp_max", tau)
             (vc, vp), _, _ = vi.evaluate(p, mu, eps)
             ro[nI + j] = vp

@@ -124,7 +124,7 @@ def test_full_size_support_sampled(full):
                 best, gap = vi.q_gaps(p, Q)
                 clear = gap > tau
                 assert not (clear & (mu != best)).any(), (k, i, j)
-                excluded += int((~clear).sum())
+                excluded += int((~clear & (gap > 1e-9)).sum())
                 states += p.n_states
                 tau_max = max(tau_max, tau)
                 (vc, vp), _, _ = vi.evaluate(p, mu, eps)
@@ -134,8 +134,8 @@ def test_full_size_support_sampled(full):
             assert r[k][i] == pytest.approx(ri, rel=1e-9, abs=8 * eps), (k, i)
             agents += 1
     print(f"\nparity f32 50x100: w.r vs sum c max rel {worst:.2e}; {agents} agents; "
-          f"{excluded} of {states} states within tau_cmp (max {tau_max:.1e}) excluded")
-    assert agents == 8 and excluded <= 0.05 * states
+          f"{excluded} of {states} states with a Q-gap in (1e-9, tau_cmp] (max {tau_max:.1e}) excluded")
+    assert agents == 8 and excluded <= 0.02 * states
 
 
 def test_full_size_query_geometry_replay(full):

@@ -284,7 +284,10 @@ def test_f32_solve_and_support_cfg2(ctx, morap):
     assert (err <= 2e-4 * np.maximum(1.0, np.abs(co))).all(), err.max()
     rep = check_support(ctx, prods, nI, nJ, W, r, A, c, co, eps)
     print("\nparity f32 cfg2:", dict(rep))
-    assert rep["excluded_states"] <= 0.05 * rep["states"]
+    # most excluded states are exact ties (probability-only columns tie every
+    # action of states that reach acceptance surely); few are excluded only
+    # because the gap is below what eps-accurate values resolve
+    assert rep["excluded_states"] - rep["excluded_exact_ties"] <= 0.02 * rep["states"]
 
 
 def test_edge_cases(ctx, morap):
