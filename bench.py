@@ -26,8 +26,12 @@ Extra objects on the JSON line:
   cpu_baseline  the FP64 oracle's value iteration timed on a bounded sample of
                 models of the same workload on the host, one process per
                 core used (8 by default);
-  ms_per_query  Alg. 1 queries (eps 0.01, at most --query-max-iter passes) on
-                the timed workload from the plain first weight (1, 0, ..., 0);
+  ms_per_query  Alg. 1 queries (eps 0.01, at most --query-max-iter passes,
+                each pass's solve started from the previous pass's values) on
+                the timed workload: latency p50 / p99, passes, verdicts, how
+                many met the stop test; plain first weight (1, 0, ..., 0)
+                against the learned proposer trained on the device from
+                plain-loop queries of other thresholds of the same workload;
   proposer      learned vs plain first weight on the 10 x 20 family: the
                 proposer is trained on the device from plain-loop queries of
                 seeded variants, then both loops answer unseen thresholds.
@@ -98,14 +102,84 @@ def measured_traffic(kernel: str):
     return None if best is None else best[1]
 
 
-def thresholds(rng, front: np.ndarray, n: int, nI: int) -> np.ndarray:
-    """t = u* + delta |u*| around points u* of the front, delta ~ U[-0.3, 0.3];
-    probabilities clipped to [0, 1]."""
+def thresholds(rng, front: np.ndarray, n: int, nI: int, inside_half: bool = False) -> np.ndarray:
+    """t = u* + delta |u*| around points u* of the front, delta ~ U[-0.3, 0.3]
+    per coordinate; probabilities clipped to [0, 1].  With inside_half, every
+    second threshold takes delta ~ U[-0.3, 0] (below a front point, hence
+    achievable): in d = 150 a threshold with mixed signs is almost surely
+    outside."""
     idx = rng.integers(front.shape[0], size=n)
     u = front[idx]
-    t = u + rng.uniform(-0.3, 0.3, size=u.shape) * np.abs(u)
+    hi = np.full((n, 1), 0.3)
+    if inside_half:
+        hi[1::2] = 0.0
+    t = u + (rng.uniform(0.0, 1.0, size=u.shape) * (hi + 0.3) - 0.3) * np.abs(u)
     t[:, nI:] = np.clip(t[:, nI:], 0.0, 1.0)
     return t
+
+
+def query_stats(res, wall_ms: float, eps: float, morap) -> dict:
+    """Summary of one lockstep batch of queries: latency to each query's last
+    pass (p50 / p99), passes, verdicts, how many met the loop's stop test."""
+    its = np.array([q["iterations"] for q in res])
+    lat = np.array([q["latency_ms"] for q in res])
+    gaps = np.array([q["gap"] for q in res])
+    v = [q["verdict"] for q in res]
+    return {"queries": len(res), "wall_ms": round(wall_ms, 1), "ms_per_query": round(wall_ms / len(res), 2),
+            "latency_p50_ms": round(float(np.percentile(lat, 50)), 1),
+            "latency_p99_ms": round(float(np.percentile(lat, 99)), 1),
+            "passes_mean": round(float(its.mean()), 2), "passes_p50": float(np.median(its)),
+            "passes_max": int(its.max()), "stopped_within_eps": int((gaps <= eps).sum()),
+            "gap_p50": round(float(np.median(gaps)), 4),
+            "feasible": v.count(morap.FEASIBLE), "infeasible": v.count(morap.INFEASIBLE),
+            "undecided": v.count(morap.UNDECIDED),
+            "backups": int(sum(q["backups"] for q in res))}
+
+
+def query_eval(ctx, wl, front, rng, args, eps_vi: float) -> dict:
+    """ms per point-oriented Pareto query on the timed workload, plain and
+    learned first weight.  Thresholds: half below front points (achievable),
+    half around them.  The learned proposer for this workload's d is trained
+    on the device from plain-loop queries on other thresholds of the same
+    workload (G15 tuples: threshold, face normal at the loop's outer point or
+    its last weight), then answers the same thresholds as the plain loop."""
+    from paper_2305_04397_amd import morap, proposer_data as pdata
+    nI, d = wl.n_agents, wl.n_agents + wl.n_tasks
+    opts = morap.Options(eps_vi=eps_vi, precision=args.precision)
+    loop_eps = 0.01
+    T = thresholds(rng, front, args.queries, nI, inside_half=True)
+    out = {"workload": wl.name, "eps": loop_eps, "max_iter": args.query_max_iter,
+           "thresholds": "half below front points, half around them (U[-0.3, 0.3] per coordinate)",
+           "warm_started_passes": True}
+    tq = time.perf_counter()
+    plain = ctx.query_batch(T, max_iter=args.query_max_iter, eps=loop_eps, opts=opts)
+    out["plain"] = query_stats(plain, (time.perf_counter() - tq) * 1e3, loop_eps, morap)
+    log(f"queries plain: {out['plain']}")
+    out["learned"] = None
+    if args.query_train > 0:
+        t0 = time.perf_counter()
+        phi = pdata.features(ctx, wl, opts)
+        Ttr = thresholds(rng, front, args.query_train, nI, inside_half=True)
+        X, Wt, _ = pdata.generate(ctx, wl, Ttr, phi, opts, eps=loop_eps, max_iter=args.query_max_iter)
+        gen_s = time.perf_counter() - t0
+        ctx.proposer_init(X.shape[1], d, seed=args.seed)
+        ctx.proposer_set_input_norm(X.mean(0), X.std(0) + 1e-3)
+        tt = time.perf_counter()
+        losses = ctx.proposer_train(X, Wt, batch=64, epochs=200, lr=1e-3, seed=args.seed)
+        train_s = time.perf_counter() - tt
+        ctx.set_features(phi)
+        tq = time.perf_counter()
+        learned = ctx.query_batch(T, max_iter=args.query_max_iter, eps=loop_eps, opts=opts, use_proposer=True)
+        out["learned"] = query_stats(learned, (time.perf_counter() - tq) * 1e3, loop_eps, morap)
+        out["learned"].update({"train_tuples": int(len(X)), "data_s": round(gen_s, 1),
+                               "train_s": round(train_s, 2), "loss_first": round(float(losses[0]), 4),
+                               "loss_last": round(float(losses[-1]), 4),
+                               "fallbacks": int(sum(q["fallback"] for q in learned))})
+        decided = [(p, q) for p, q in zip(plain, learned)
+                   if p["verdict"] != morap.UNDECIDED and q["verdict"] != morap.UNDECIDED]
+        out["learned_vs_plain_verdicts"] = f"{sum(p['verdict'] == q['verdict'] for p, q in decided)}/{len(decided)}"
+        log(f"queries learned: {out['learned']}")
+    return out
 
 
 _CPU_WL = None   # the workload, inherited by the forked baseline workers
@@ -240,8 +314,10 @@ def main():
     ap.add_argument("--cpu-workers", type=int, default=8, help="baseline processes (at most the host's cores)")
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--seed", type=int, default=7)
-    ap.add_argument("--query-max-iter", type=int, default=16,
+    ap.add_argument("--query-max-iter", type=int, default=48,
                     help="Alg. 2 passes allowed per query in the ms-per-query measurement")
+    ap.add_argument("--query-train", type=int, default=128,
+                    help="plain-loop training queries for the learned proposer on the timed workload (0 = skip)")
     ap.add_argument("--proposer-queries", type=int, default=1000,
                     help="unseen 10x20 queries for the learned-vs-plain comparison (0 = skip)")
     ap.add_argument("--proposer-train", type=int, default=512, help="training queries per 10x20 variant")
@@ -335,28 +411,8 @@ def main():
         f"{st['ms_sweep_kernel_refine']:.0f} ms over {st['sweep_launches_refine']} timed launches; "
         f"VI {st['ms_vi']:.0f} ms, evaluation {st['ms_eval']:.0f} ms")
 
-    # full queries: plain first weight
-    per_query = None
-    if args.queries > 0:
-        T = thresholds(rng, front, args.queries, nI)
-        tq = time.perf_counter()
-        res = ctx.query_batch(T, max_iter=args.query_max_iter, eps=0.01,
-                              opts=morap.Options(eps_vi=eps, precision=args.precision))
-        wq = (time.perf_counter() - tq) * 1e3
-        its = np.array([q["iterations"] for q in res])
-        verdicts = [q["verdict"] for q in res]
-        per_query = {"workload": wl.name, "eps": 0.01, "max_iter": args.query_max_iter,
-                     "plain": {"queries": len(res), "wall_ms": round(wq, 1),
-                               "ms_per_query": round(wq / len(res), 2),
-                               "passes_mean": round(float(its.mean()), 2), "passes_max": int(its.max()),
-                               "feasible": verdicts.count(morap.FEASIBLE),
-                               "infeasible": verdicts.count(morap.INFEASIBLE),
-                               "undecided": verdicts.count(morap.UNDECIDED)},
-                     "learned": None,
-                     "learned_note": "the proposer is trained and compared in the 'proposer' object (10x20 "
-                                     "family, d = 30, 1,000 unseen thresholds); none is trained for this "
-                                     f"workload's queries here (d = {nI + wl.n_tasks})"}
-        log(f"queries: {len(res)} in {wq:.0f} ms, passes mean {its.mean():.1f}")
+    # full queries on the timed workload: plain and learned first weight
+    per_query = query_eval(ctx, wl, front, rng, args, eps) if args.queries > 0 else None
 
     ctx.close()
     learned = None

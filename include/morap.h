@@ -286,6 +286,9 @@ typedef struct {
     int32_t verification_only; /* stop once t is separated (Sec. 5, Experiment 2) */
     int32_t use_proposer;    /* 1 = learned proposer gives the first weight vector  */
     int32_t keep_trace;      /* 1 = fill the trace arrays of the result             */
+    int32_t warm_start;      /* 1 = after the first pass, each FP32 solve starts a
+                                query's column from its values of the previous
+                                pass (pairs with a zero cost weight from 0)     */
     morap_vi_opts vi;
 } morap_query_opts;
 
@@ -303,7 +306,8 @@ typedef struct {
     int32_t fallback;        /* 1 = the proposer's weight was rejected            */
     int32_t reserved;
     double  gap;             /* ||t_down - t_up||_M at exit                        */
-    double  ms;              /* wall time                                         */
+    double  ms;              /* wall time (in a batch: its share of every pass it
+                                took part in)                                   */
     int64_t backups;
     double* t_up;
     double* t_down;
@@ -311,6 +315,9 @@ typedef struct {
     double* trace_w;
     double* trace_r;
     int32_t* trace_f;
+    double  latency_ms;      /* wall time from the start of the call to the end
+                                of the Alg. 2 pass in which the query stopped
+                                (batches: queries run in lockstep)             */
 } morap_query_result;
 
 /* Alg. 1 for threshold t[d] with norm matrix M[d][d] (symmetric positive
@@ -326,7 +333,8 @@ int morap_query(morap_ctx* ctx, const double* t, const double* M,
 
 /* Q queries T[Q][d] advanced in lockstep: every Alg. 1 pass solves the weight
  * vectors of all unfinished queries as the columns of one morap_support call
- * (at most 64 columns per call; larger Q runs in groups of 64).
+ * (at most 64 columns per call; larger Q runs in groups of 64, each group to
+ * its end before the next starts).
  * W0[Q][d] (nullable) replaces each query's first weight vector (rows >= 0,
  * summing to 1); NULL means (1, 0, ..., 0) or the learned proposer's output.
  * results[Q].  Errors: as morap_query. */
@@ -435,6 +443,17 @@ int morap_proposer_train(morap_ctx* ctx, const float* X, const float* T, int n,
  * Errors: INVALID (I/O, size mismatch), STATE. */
 int morap_proposer_save(const morap_ctx* ctx, const char* path);
 int morap_proposer_load(morap_ctx* ctx, const char* path);
+
+/* Training target of the proposer for one answered query (host only, no
+ * context): for a threshold t[d] outside the achievable set (t_down != t),
+ * the normal M (t - t_down) of the face of the outer approximation that holds
+ * the closest point t_down[d]; for a threshold inside it, the last weight
+ * vector w_last[d] the plain loop used.  Negative entries become 0 and the
+ * result w_out[d] is normalised to sum 1 (the uniform vector if nothing is
+ * left).  M = NULL means the identity.  Errors: INVALID (NULL arrays, d < 1,
+ * non-finite input). */
+int morap_proposer_target(const double* t, const double* t_down, const double* w_last, int d, const double* M,
+                          double* w_out);
 
 /* Instance feature vector phi[n_feat] used by morap_query when
  * use_proposer = 1: the proposer's input is [t; phi] (n_in = d + n_feat).

@@ -224,6 +224,9 @@ struct morap_ctx {
     int64_t n_htiles = 0;
     morap::DevBuf d_state_row, d_row_ptr, d_col, d_prob32, d_prob64, d_rew32, d_rew64, d_to_done;
     morap::DevBuf d_state_base, d_init;
+    morap::DevBuf d_state_model;                    // [S] model of every state
+    morap::DevBuf d_xwarm, d_warm_map, d_warm_ab;    // warm start of a solve: values [S+1][Kp], column map,
+                                                     // per-pair start a x + b [M][Kp][2]
     morap::DevBuf d_rows_per_model, d_states_per_model;  // [M] int32
     morap::DevBuf d_csr_bytes32, d_csr_bytes64;          // [M] int64: CSR bytes read per sweep
 
@@ -346,7 +349,11 @@ void product_host(const morap_agent* a, const morap_dfa* t, const int32_t* lette
 void upload_models(morap_ctx* ctx);
 
 // solver.cpp
-void solve(morap_ctx* ctx, const double* W, int K, const morap_vi_opts& o, double* c_out, Stats& st);
+// warm (nullable, [K]): column of the previous solve each column starts from
+// (-1: from 0); used when the previous solve was FP32 with at least as many
+// padded columns, ignored otherwise
+void solve(morap_ctx* ctx, const double* W, int K, const morap_vi_opts& o, double* c_out, Stats& st,
+           const int32_t* warm = nullptr);
 void evaluate(morap_ctx* ctx, const int32_t* assign, int K, const morap_vi_opts& o, double* r_out, Stats& st);
 const std::vector<Variant>& variants();
 
@@ -465,6 +472,12 @@ struct InstArgs {
 };
 void gather_columns(hipStream_t s, const InstArgs& a, int prec, const void* x0, const void* x1,
                     const uint8_t* final_par, int Kp, double* xi);
+// start of an FP32 solve from the previous one's final values: out[s][k] =
+// a x_prev[s][map[k]] + b (the buffer its pair froze in; ab[m][k] = (a, b))
+// where map[k] >= 0 and a != 0, 0 elsewhere (and on the zero row)
+void warm_columns(hipStream_t s, int64_t S, int Kp, int K, const int32_t* map, const int32_t* state_model,
+                  const float* ab, const float* x0, const float* x1, const uint8_t* final_par, int Kp_old,
+                  float* out);
 // FP64 start of the instances from the FP32 solve's values, scaled by
 // scale[inst] (instances with a zero cost weight start from 0)
 void warm_start(hipStream_t s, const InstArgs& a, const void* x0, const void* x1, const uint8_t* final_par, int Kp,

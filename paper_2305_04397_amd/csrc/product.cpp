@@ -811,6 +811,13 @@ void upload_models(morap_ctx* c) {
     upload(c->d_rew64, hm.rew, s);
     upload(c->d_to_done, hm.to_done, s);
     upload(c->d_state_base, hm.state_base, s);
+    {
+        std::vector<int32_t> sm((size_t)c->S);
+        for (int m = 0; m < hm.M; ++m)
+            std::fill(sm.begin() + hm.state_base[m], sm.begin() + hm.state_base[m + 1], m);
+        upload(c->d_state_model, sm, s);
+        MORAP_HIP(hipStreamSynchronize(s));   // sm goes out of scope
+    }
     upload(c->d_init, hm.init, s);
     // FP32 copies for FP32 sweeps
     c->d_prob32.ensure((size_t)c->N * 4 + 16);

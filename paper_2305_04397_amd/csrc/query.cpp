@@ -10,6 +10,9 @@
 // UNDECIDED.
 #include "common.h"
 
+#include <cstdio>
+#include <cstdlib>
+
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -43,6 +46,7 @@ struct QState {
     std::vector<std::vector<int32_t>> Fs;   // assignment of every pass
     bool done = false, separated = false;
     int fallback = 0;
+    double latency_ms = -1.0;   // set when the query stops
     double gap = 0;
     int64_t backups = 0;
     double ms = 0;
@@ -135,92 +139,127 @@ void query_batch(morap_ctx* c, const double* T, const double* W0, int Q, const d
         }
     }
     morap_vi_opts vo = o.vi;
-    for (int it = 0; it < o.max_iter; ++it) {
-        std::vector<int> act;
-        for (int q = 0; q < Q; ++q)
-            if (!qs[q].done) act.push_back(q);
-        if (act.empty()) break;
-        for (size_t b = 0; b < act.size(); b += 64) {
-            const int K = (int)std::min<size_t>(64, act.size() - b);
-            std::vector<double> W((size_t)K * d), C((size_t)K * nI * nJ), R((size_t)K * d);
-            std::vector<int32_t> A((size_t)K * nJ);
-            for (int kk = 0; kk < K; ++kk) {
-                // re-normalise so the row sums to 1 to the last bit
-                const auto& w = qs[act[b + kk]].w;
-                double sum = 0;
-                for (double v : w) sum += v;
-                for (int q = 0; q < d; ++q) W[(size_t)kk * d + q] = w[q] / sum;
+    // MORAP_PROGRESS=1: one line per Alg. 1 pass on stderr (long lockstep
+    // batches report as they go)
+    static const bool progress = [] {
+        const char* p = std::getenv("MORAP_PROGRESS");
+        return p && *p && *p != '0';
+    }();
+    // groups of at most 64 queries, each run to its end before the next
+    // (a group's solves can then start from its previous pass's values)
+    std::vector<int> prev_col(Q, -1);
+    double last_ms[3] = {0, 0, 0};   // solve, assignment + evaluation, geometry of the last pass
+    int64_t last_sweeps = 0;
+    for (int g0 = 0; g0 < Q; g0 += 64) {
+        const int g1 = std::min(Q, g0 + 64);
+        for (int it = 0; it < o.max_iter; ++it) {
+            std::vector<int> act;
+            for (int q = g0; q < g1; ++q)
+                if (!qs[q].done) act.push_back(q);
+            if (act.empty()) break;
+            if (progress) {
+                std::fprintf(stderr,
+                             "[morap] Alg. 1 pass %d: %zu of %d queries running (%.0f ms; last pass: solve %.0f ms in %lld "
+                             "sweeps, assignment and evaluation %.0f, geometry %.0f ms)\n",
+                             it + 1, act.size(), g1 - g0,
+                             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start)
+                                 .count(),
+                             last_ms[0], (long long)last_sweeps, last_ms[1], last_ms[2]);
+                std::fflush(stderr);
             }
-            Stats st;
-            const auto t0 = std::chrono::steady_clock::now();
-            solve(c, W.data(), K, vo, C.data(), st);
-            assign_columns(nI, nJ, C.data(), K, A.data());
-            evaluate(c, A.data(), K, vo, R.data(), st);
-            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-            // the geometry of each query (both projections, the stop test and
-            // the next weight vector) on host threads: queries share nothing
-            parallel_for(K, [&](int kk) {
-                QState& s = qs[act[b + kk]];
-                s.backups += st.backups / K;
-                s.ms += ms / K;
-                std::vector<double> r(R.begin() + (size_t)kk * d, R.begin() + (size_t)(kk + 1) * d);
-                std::vector<double> w(W.begin() + (size_t)kk * d, W.begin() + (size_t)(kk + 1) * d);
-                s.Phi.push_back(r);
-                s.Ws.push_back(w);
-                s.Fs.emplace_back(A.begin() + (size_t)kk * nJ, A.begin() + (size_t)(kk + 1) * nJ);
-                double wr = 0, wt = 0;
-                for (int k = 0; k < d; ++k) {
-                    wr += w[k] * r[k];
-                    wt += w[k] * s.t_down[k];
+            {
+                const int K = (int)act.size();
+                std::vector<double> W((size_t)K * d), C((size_t)K * nI * nJ), R((size_t)K * d);
+                std::vector<int32_t> A((size_t)K * nJ), warm_map(K);
+                for (int kk = 0; kk < K; ++kk) {
+                    // re-normalise so the row sums to 1 to the last bit
+                    const auto& w = qs[act[kk]].w;
+                    double sum = 0;
+                    for (double v : w) sum += v;
+                    for (int q = 0; q < d; ++q) W[(size_t)kk * d + q] = w[q] / sum;
+                    warm_map[kk] = prev_col[act[kk]];
+                    prev_col[act[kk]] = kk;
                 }
-                const int n = (int)s.Phi.size();
-                std::vector<double> Pf((size_t)n * d), Wf((size_t)n * d);
-                for (int i = 0; i < n; ++i)
+                Stats st;
+                const auto t0 = std::chrono::steady_clock::now();
+                solve(c, W.data(), K, vo, C.data(), st, o.warm_start && it > 0 ? warm_map.data() : nullptr);
+                const auto t1 = std::chrono::steady_clock::now();
+                assign_columns(nI, nJ, C.data(), K, A.data());
+                evaluate(c, A.data(), K, vo, R.data(), st);
+                const auto t2 = std::chrono::steady_clock::now();
+                const double ms = std::chrono::duration<double, std::milli>(t2 - t0).count();
+                last_ms[0] = std::chrono::duration<double, std::milli>(t1 - t0).count();
+                last_sweeps = st.sweeps;
+                last_ms[1] = std::chrono::duration<double, std::milli>(t2 - t1).count();
+                // the geometry of each query (both projections, the stop test and
+                // the next weight vector) on host threads: queries share nothing
+                parallel_for(K, [&](int kk) {
+                    QState& s = qs[act[kk]];
+                    s.backups += st.backups / K;
+                    s.ms += ms / K;
+                    std::vector<double> r(R.begin() + (size_t)kk * d, R.begin() + (size_t)(kk + 1) * d);
+                    std::vector<double> w(W.begin() + (size_t)kk * d, W.begin() + (size_t)(kk + 1) * d);
+                    s.Phi.push_back(r);
+                    s.Ws.push_back(w);
+                    s.Fs.emplace_back(A.begin() + (size_t)kk * nJ, A.begin() + (size_t)(kk + 1) * nJ);
+                    double wr = 0, wt = 0;
                     for (int k = 0; k < d; ++k) {
-                        Pf[(size_t)i * d + k] = s.Phi[i][k];
-                        Wf[(size_t)i * d + k] = s.Ws[i][k];
+                        wr += w[k] * r[k];
+                        wt += w[k] * s.t_down[k];
                     }
-                if (wr < wt) {
-                    if (o.verification_only) s.separated = true;
-                    project_outer(Wf.data(), Pf.data(), n, d, s.t.data(), M, s.t_down.data());
-                }
-                s.lam.assign(n, 0.0);
-                project_inner(Pf.data(), n, d, s.t.data(), M, s.t_up.data(), s.lam.data());
-                std::vector<double> diff(d);
-                for (int k = 0; k < d; ++k) diff[k] = s.t_down[k] - s.t_up[k];
-                s.gap = mnorm(diff, M);
-                if (s.separated || s.gap <= o.eps) {
-                    s.done = true;
-                    return;
-                }
-                // w = M (t - t_up) / ||M (t - t_up)||_1.  Components at or
-                // below 1e-12 max(1, ||t||_inf) are rounding noise of the
-                // projection (like negative ones) and become 0: a positive
-                // noise entry would otherwise be the whole objective of the
-                // models it touches.
-                std::vector<double> v(d), mv(d, 0.0);
-                double tmax = 1.0;
-                for (int k = 0; k < d; ++k) {
-                    v[k] = s.t[k] - s.t_up[k];
-                    tmax = std::max(tmax, std::fabs(s.t[k]));
-                }
-                for (int k = 0; k < d; ++k) {
-                    if (!M) mv[k] = v[k];
-                    else
-                        for (int l = 0; l < d; ++l) mv[k] += M[(size_t)k * d + l] * v[l];
-                }
-                const double floor = 1e-12 * tmax;
-                double sum = 0;
-                for (int k = 0; k < d; ++k) {
-                    mv[k] = mv[k] > floor ? mv[k] : 0.0;
-                    sum += mv[k];
-                }
-                if (!(sum > 0)) {
-                    s.done = true;   // t_up == t up to rounding
-                    return;
-                }
-                for (int k = 0; k < d; ++k) s.w[k] = mv[k] / sum;
-            });
+                    const int n = (int)s.Phi.size();
+                    std::vector<double> Pf((size_t)n * d), Wf((size_t)n * d);
+                    for (int i = 0; i < n; ++i)
+                        for (int k = 0; k < d; ++k) {
+                            Pf[(size_t)i * d + k] = s.Phi[i][k];
+                            Wf[(size_t)i * d + k] = s.Ws[i][k];
+                        }
+                    if (wr < wt) {
+                        if (o.verification_only) s.separated = true;
+                        project_outer(Wf.data(), Pf.data(), n, d, s.t.data(), M, s.t_down.data());
+                    }
+                    s.lam.assign(n, 0.0);
+                    project_inner(Pf.data(), n, d, s.t.data(), M, s.t_up.data(), s.lam.data());
+                    std::vector<double> diff(d);
+                    for (int k = 0; k < d; ++k) diff[k] = s.t_down[k] - s.t_up[k];
+                    s.gap = mnorm(diff, M);
+                    if (s.separated || s.gap <= o.eps) {
+                        s.done = true;
+                        return;
+                    }
+                    // w = M (t - t_up) / ||M (t - t_up)||_1.  Components at or
+                    // below 1e-12 max(1, ||t||_inf) are rounding noise of the
+                    // projection (like negative ones) and become 0: a positive
+                    // noise entry would otherwise be the whole objective of the
+                    // models it touches.
+                    std::vector<double> v(d), mv(d, 0.0);
+                    double tmax = 1.0;
+                    for (int k = 0; k < d; ++k) {
+                        v[k] = s.t[k] - s.t_up[k];
+                        tmax = std::max(tmax, std::fabs(s.t[k]));
+                    }
+                    for (int k = 0; k < d; ++k) {
+                        if (!M) mv[k] = v[k];
+                        else
+                            for (int l = 0; l < d; ++l) mv[k] += M[(size_t)k * d + l] * v[l];
+                    }
+                    const double floor = 1e-12 * tmax;
+                    double sum = 0;
+                    for (int k = 0; k < d; ++k) {
+                        mv[k] = mv[k] > floor ? mv[k] : 0.0;
+                        sum += mv[k];
+                    }
+                    if (!(sum > 0)) {
+                        s.done = true;   // t_up == t up to rounding
+                        return;
+                    }
+                    for (int k = 0; k < d; ++k) s.w[k] = mv[k] / sum;
+                });
+                last_ms[2] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t2).count();
+            }
+            const double now = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+            for (int q : act)
+                if (qs[q].done && qs[q].latency_ms < 0) qs[q].latency_ms = now;
         }
     }
     const double total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
@@ -247,6 +286,7 @@ void query_batch(morap_ctx* c, const double* T, const double* W0, int Q, const d
         r.fallback = s.fallback;
         r.gap = s.gap;
         r.ms = Q == 1 ? total_ms : s.ms;
+        r.latency_ms = s.latency_ms < 0 ? total_ms : s.latency_ms;
         r.backups = s.backups;
         if (r.t_up) std::copy(s.t_up.begin(), s.t_up.end(), r.t_up);
         if (r.t_down) std::copy(s.t_down.begin(), s.t_down.end(), r.t_down);
@@ -265,3 +305,37 @@ void query_batch(morap_ctx* c, const double* T, const double* W0, int Q, const d
 }
 
 }  // namespace morap
+
+extern "C" int morap_proposer_target(const double* t, const double* t_down, const double* w_last, int d,
+                                     const double* M, double* w_out) {
+    if (!t || !t_down || !w_last || !w_out || d < 1) return MORAP_E_INVALID;
+    for (int k = 0; k < d; ++k)
+        if (!std::isfinite(t[k]) || !std::isfinite(t_down[k]) || !std::isfinite(w_last[k])) return MORAP_E_INVALID;
+    if (M)
+        for (int64_t k = 0; k < (int64_t)d * d; ++k)
+            if (!std::isfinite(M[k])) return MORAP_E_INVALID;
+    std::vector<double> diff(d), w(d);
+    double dmax = 0;
+    for (int k = 0; k < d; ++k) {
+        diff[k] = t[k] - t_down[k];
+        dmax = std::max(dmax, std::fabs(diff[k]));
+    }
+    if (dmax > 1e-9) {
+        for (int k = 0; k < d; ++k) {
+            double v = 0;
+            if (!M) v = diff[k];
+            else
+                for (int l = 0; l < d; ++l) v += M[(size_t)k * d + l] * diff[l];
+            w[k] = v;
+        }
+    } else {
+        w.assign(w_last, w_last + d);
+    }
+    double sum = 0;
+    for (int k = 0; k < d; ++k) {
+        w[k] = std::max(w[k], 0.0);
+        sum += w[k];
+    }
+    for (int k = 0; k < d; ++k) w_out[k] = sum > 0 ? w[k] / sum : 1.0 / d;
+    return MORAP_OK;
+}

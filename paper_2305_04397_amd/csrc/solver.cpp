@@ -422,12 +422,25 @@ static const Variant& choose_variant(morap_ctx* c, ValueSet& vs, const uint8_t* 
 }
 
 // Batched value iteration into `vs` until every (masked) pair has converged.
-static void run_vi(morap_ctx* c, int g, ValueSet& vs, const uint8_t* mask, const morap_vi_opts& o, Stats& st) {
+static void swap_buf(DevBuf& a, DevBuf& b) {
+    std::swap(a.p, b.p);
+    std::swap(a.bytes, b.bytes);
+    std::swap(a.meter, b.meter);
+}
+
+// warm: the solve starts from the values prepared in d_xwarm (they become
+// the first sweep's input buffer)
+static void run_vi(morap_ctx* c, int g, ValueSet& vs, const uint8_t* mask, const morap_vi_opts& o, Stats& st,
+                   bool warm = false) {
     const Variant& v = choose_variant(c, vs, mask, o.eps_vi, o.schedule);
     c->last_variant = v.id;
     const int chunk = std::max(2, (o.check_every + 1) / 2 * 2);
     EventPair wall;
     reset_solve(c, vs, mask, o.eps_vi, v);
+    if (warm) {
+        swap_buf(vs.x[0], c->d_xwarm);
+        ++c->buf_gen;   // graphs hold the value buffers' addresses
+    }
     MORAP_HIP(hipEventRecord(wall.a, c->stream));
     int64_t launched = 0;
     int64_t* h = c->h_counters.as<int64_t>();
@@ -505,13 +518,15 @@ static void add_stats(Stats& a, const Stats& b) {
     a.variant_refine = b.variant_refine ? b.variant_refine : a.variant_refine;
 }
 
-static void solve_impl(morap_ctx* c, const double* W, int K, const morap_vi_opts& o, double* c_out, Stats& st);
+static void solve_impl(morap_ctx* c, const double* W, int K, const morap_vi_opts& o, double* c_out, Stats& st,
+                       const int32_t* warm);
 static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const morap_vi_opts& o, double* r_out,
                           Stats& st);
 
-void solve(morap_ctx* c, const double* W, int K, const morap_vi_opts& o, double* c_out, Stats& st) {
+void solve(morap_ctx* c, const double* W, int K, const morap_vi_opts& o, double* c_out, Stats& st,
+           const int32_t* warm) {
     Stats local;
-    solve_impl(c, W, K, o, c_out, local);
+    solve_impl(c, W, K, o, c_out, local, warm);
     add_stats(st, local);
     add_stats(c->cum, local);
 }
@@ -523,7 +538,8 @@ void evaluate(morap_ctx* c, const int32_t* assign, int K, const morap_vi_opts& o
     add_stats(c->cum, local);
 }
 
-static void solve_impl(morap_ctx* c, const double* W, int K, const morap_vi_opts& o, double* c_out, Stats& st) {
+static void solve_impl(morap_ctx* c, const double* W, int K, const morap_vi_opts& o, double* c_out, Stats& st,
+                       const int32_t* warm) {
     MORAP_CHECK(c->loaded, MORAP_E_STATE, "no models loaded");
     MORAP_CHECK(W && K >= 1 && K <= 4096, MORAP_E_INVALID, "need 1 <= K <= 4096 weight vectors");
     MORAP_CHECK(o.precision == MORAP_F32 || o.precision == MORAP_F64, MORAP_E_INVALID, "bad precision");
@@ -542,10 +558,50 @@ static void solve_impl(morap_ctx* c, const double* W, int K, const morap_vi_opts
     const auto t0 = std::chrono::steady_clock::now();
     const int prec = o.precision;
     const int Kp = padded_k(K);
+    // a warm start needs the previous FP32 values in buffers that already
+    // fit this solve (they are read in place)
+    const size_t need = (size_t)(c->S + 1) * Kp * 4;
+    const bool warm_ok = warm && prec == MORAP_F32 && c->vmain.valid && c->vmain.prec == MORAP_F32 &&
+                         Kp <= c->vmain.Kp && c->vmain.x[0].bytes >= need && c->vmain.x[1].bytes >= need;
+    const int Kp_old = c->vmain.Kp, K_old = c->vmain.K;
+    // Per pair, the start a x_prev + b from the previous values x_prev, which
+    // are (up to the stop rule) the optimal values V = wc_o C + wp_o P of the
+    // previous weights, C <= 0 and P in [0, 1] the cost and probability
+    // values of the previous optimal policy.  Every start is below the new
+    // optimum V', so value iteration climbs to it as from 0 and zero-reward
+    // loops (which admit larger fixed points) cannot hold it above:
+    //  * probability only now and before: V' = (wp_n / wp_o) V exactly (the
+    //    optimal policies do not depend on the scale); a relative 1e-6 below
+    //    it covers the previous stop (FP32 stops at 8 2^-24 relative);
+    //  * a cost weight now and before: V' >= wc_n C >= (wc_n / wc_o)(V - wp_o),
+    //    the previous policy's value without its probability reward;
+    //  * otherwise from 0, as Alg. 3.
+    std::vector<float> warm_ab;
+    if (warm_ok) {
+        const std::vector<double>& Wp = c->W;   // the previous solve's weights [K_old][d]
+        warm_ab.assign((size_t)M * Kp * 2, 0.f);
+        for (int k = 0; k < K; ++k) {
+            MORAP_CHECK(warm[k] >= -1 && warm[k] < K_old, MORAP_E_INVALID, "warm-start column out of range");
+            if (warm[k] < 0) continue;
+            for (int m = 0; m < M; ++m) {
+                const int i = m / nJ, j = m % nJ;
+                const double wc_n = W[(size_t)k * d + i], wp_n = W[(size_t)k * d + nI + j];
+                const double wc_o = Wp[(size_t)warm[k] * d + i], wp_o = Wp[(size_t)warm[k] * d + nI + j];
+                double a = 0, b = 0;
+                if (wc_n == 0 && wc_o == 0 && wp_o > 0) {
+                    a = wp_n / wp_o * (1.0 - 1e-6);
+                } else if (wc_n > 0 && wc_o > 0) {
+                    a = wc_n / wc_o;
+                    b = -a * wp_o;
+                }
+                warm_ab[((size_t)m * Kp + k) * 2] = (float)a;
+                warm_ab[((size_t)m * Kp + k) * 2 + 1] = (float)b;
+            }
+        }
+    }
     c->solved = false;
     c->evaluated = false;
     ensure_scratch(c, Kp);
-    ensure_values(c, c->vmain, K, Kp, prec);
     c->K = K;
     c->Kp = Kp;
     c->prec = prec;
@@ -567,8 +623,21 @@ static void solve_impl(morap_ctx* c, const double* W, int K, const morap_vi_opts
     MORAP_HIP(hipMemcpyAsync(c->d_wp64.p, wp.data(), wp.size() * 8, hipMemcpyHostToDevice, c->stream));
     MORAP_HIP(hipMemcpyAsync(c->d_wc32.p, wc32.data(), wc32.size() * 4, hipMemcpyHostToDevice, c->stream));
     MORAP_HIP(hipMemcpyAsync(c->d_wp32.p, wp32.data(), wp32.size() * 4, hipMemcpyHostToDevice, c->stream));
+    if (warm_ok) {
+        c->d_warm_map.ensure((size_t)K * 4);
+        c->d_warm_ab.ensure(warm_ab.size() * 4);
+        c->d_xwarm.ensure(need);
+        MORAP_HIP(hipMemcpyAsync(c->d_warm_map.p, warm, (size_t)K * 4, hipMemcpyHostToDevice, c->stream));
+        MORAP_HIP(hipMemcpyAsync(c->d_warm_ab.p, warm_ab.data(), warm_ab.size() * 4, hipMemcpyHostToDevice,
+                                 c->stream));
+        k::warm_columns(c->stream, c->S, Kp, K, c->d_warm_map.as<int32_t>(), c->d_state_model.as<int32_t>(),
+                        c->d_warm_ab.as<float>(), c->vmain.x[0].as<float>(), c->vmain.x[1].as<float>(),
+                        c->vmain.final_par.as<uint8_t>(), Kp_old, c->d_xwarm.as<float>());
+    }
+    ensure_values(c, c->vmain, K, Kp, prec);
+    MORAP_HIP(hipStreamSynchronize(c->stream));   // the host weight vectors go out of scope
 
-    run_vi(c, 0, c->vmain, nullptr, o, st);
+    run_vi(c, 0, c->vmain, nullptr, o, st, warm_ok);
     if (c_out)
         MORAP_HIP(hipMemcpyAsync(c_out, c->vmain.c.p, (size_t)K * M * 8, hipMemcpyDeviceToHost, c->stream));
     MORAP_HIP(hipStreamSynchronize(c->stream));

@@ -551,6 +551,44 @@ __global__ void gather_kernel(InstArgs a, const T* x0, const T* x1, const uint8_
     xi[L.is] = (double)x[(int64_t)L.gs * Kp + k];
 }
 
+// Start of an FP32 solve from the previous solve's final values (the next
+// pass of the same queries: their weights moved a little): out[s][k] =
+// a[m][k] x_prev[s][map[k]] + b[m][k] from the buffer the pair froze in, 0
+// where map[k] < 0 or a[m][k] = 0, and on the zero row.  The host picks a
+// and b (see solve); ab holds the pairs (a, b).
+__global__ void warm_columns_kernel(int64_t n, int Kp, int K, const int32_t* __restrict__ map,
+                                    const int32_t* __restrict__ state_model, int64_t S,
+                                    const float2* __restrict__ ab, const float* __restrict__ x0,
+                                    const float* __restrict__ x1, const uint8_t* __restrict__ par, int Kp_old,
+                                    float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t s = i / Kp;
+    const int k = (int)(i % Kp);
+    float v = 0.f;
+    if (s < S && k < K) {
+        const int ko = map[k];
+        if (ko >= 0) {
+            const int m = state_model[s];
+            const float2 f = ab[(int64_t)m * Kp + k];
+            if (f.x != 0.f) {
+                const float* x = par[(int64_t)m * Kp_old + ko] ? x1 : x0;
+                v = fmaf(f.x, x[s * Kp_old + ko], f.y);
+            }
+        }
+    }
+    out[i] = v;
+}
+
+void warm_columns(hipStream_t s, int64_t S, int Kp, int K, const int32_t* map, const int32_t* state_model,
+                  const float* ab, const float* x0, const float* x1, const uint8_t* final_par, int Kp_old,
+                  float* out) {
+    const int64_t n = (S + 1) * Kp;
+    hipLaunchKernelGGL(warm_columns_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, Kp, K, map,
+                       state_model, S, reinterpret_cast<const float2*>(ab), x0, x1, final_par, Kp_old, out);
+    MORAP_HIP(hipGetLastError());
+}
+
 // Start of the FP64 re-solve of an instance from the FP32 solve's values of
 // its pair: the optimal values of the model scale with its two weights, so
 // x = x32 / (w_i + w_j) (scale[inst] = 1 / (w_i + w_j)).  Only instances

@@ -83,13 +83,15 @@ class Stats(C.Structure):
 
 class QueryOpts(C.Structure):
     _fields_ = [("eps", C.c_double), ("max_iter", C.c_int32), ("verification_only", C.c_int32),
-                ("use_proposer", C.c_int32), ("keep_trace", C.c_int32), ("vi", ViOpts)]
+                ("use_proposer", C.c_int32), ("keep_trace", C.c_int32), ("warm_start", C.c_int32),
+                ("vi", ViOpts)]
 
 
 class QueryResult(C.Structure):
     _fields_ = [("verdict", C.c_int32), ("iterations", C.c_int32), ("fallback", C.c_int32),
                 ("reserved", C.c_int32), ("gap", C.c_double), ("ms", C.c_double), ("backups", C.c_int64),
-                ("t_up", _p), ("t_down", _p), ("lam", _p), ("trace_w", _p), ("trace_r", _p), ("trace_f", _p)]
+                ("t_up", _p), ("t_down", _p), ("lam", _p), ("trace_w", _p), ("trace_r", _p), ("trace_f", _p),
+                ("latency_ms", C.c_double)]
 
 
 class TrainOpts(C.Structure):
@@ -132,6 +134,7 @@ _sig("morap_synthesize", C.c_int, _ctxp, _p, _p, _p, C.c_int, C.POINTER(ViOpts),
 _sig("morap_project_inner", C.c_int, _p, C.c_int, C.c_int, _p, _p, _p, _p)
 _sig("morap_project_outer", C.c_int, _p, _p, C.c_int, C.c_int, _p, _p, _p)
 _sig("morap_set_features", C.c_int, _ctxp, _p, C.c_int)
+_sig("morap_proposer_target", C.c_int, _p, _p, _p, C.c_int, _p, _p)
 _sig("morap_proposer_init", C.c_int, _ctxp, C.c_int, C.c_int, C.c_uint64)
 _sig("morap_proposer_num_params", C.c_int64, _ctxp)
 _sig("morap_proposer_get_params", C.c_int, _ctxp, _p)
@@ -178,6 +181,18 @@ class Options:
         o.use_graph = 1 if self.use_graph else 0
         o.time_kernels = 1 if self.time_kernels else 0
         return o
+
+
+def proposer_target(t, t_down, w_last, M=None) -> np.ndarray:
+    """morap_proposer_target: the weight vector a query should have started
+    from (host, no context)."""
+    t, t_down, w_last = _c(t, np.float64), _c(t_down, np.float64), _c(w_last, np.float64)
+    Mc = None if M is None else _c(M, np.float64)
+    out = np.zeros(t.size)
+    rc = lib.morap_proposer_target(_ptr(t), _ptr(t_down), _ptr(w_last), t.size, _ptr(Mc), _ptr(out))
+    if rc != 0:
+        raise MorapError(rc, "morap_proposer_target failed")
+    return out
 
 
 def product_host(agent, task, letters) -> dict:
@@ -440,7 +455,7 @@ class Context:
     # -- Alg. 1 ------------------------------------------------------------
     def query_batch(self, T, M=None, eps: float = 1e-3, max_iter: int = 64, opts: Options = Options(),
                     verification_only: bool = False, use_proposer: bool = False, trace: bool = False,
-                    W0=None):
+                    W0=None, warm_start: bool = True):
         T = _c(np.atleast_2d(T), np.float64)
         Q, d = T.shape
         W0c = None if W0 is None else _c(np.atleast_2d(W0), np.float64)
@@ -449,6 +464,7 @@ class Context:
         qo.verification_only = int(verification_only)
         qo.use_proposer = int(use_proposer)
         qo.keep_trace = int(trace)
+        qo.warm_start = int(warm_start)
         qo.vi = opts.to_c()
         res = (QueryResult * Q)()
         bufs = []
@@ -466,7 +482,8 @@ class Context:
         for q in range(Q):
             n = res[q].iterations
             out.append({"verdict": res[q].verdict, "iterations": n, "fallback": res[q].fallback,
-                        "gap": res[q].gap, "ms": res[q].ms, "backups": res[q].backups,
+                        "gap": res[q].gap, "ms": res[q].ms, "latency_ms": res[q].latency_ms,
+                        "backups": res[q].backups,
                         "t_up": bufs[q]["t_up"], "t_down": bufs[q]["t_down"], "lam": bufs[q]["lam"][:n],
                         "W": bufs[q]["trace_w"][:n], "R": bufs[q]["trace_r"][:n], "F": bufs[q]["trace_f"][:n]})
         return out

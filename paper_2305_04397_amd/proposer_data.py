@@ -49,14 +49,8 @@ def thresholds(rng, front: np.ndarray, n: int, nI: int) -> np.ndarray:
 
 
 def target_weight(t: np.ndarray, res: dict, M=None) -> np.ndarray:
-    diff = t - res["t_down"]
-    if np.abs(diff).max() > 1e-9:
-        w = diff if M is None else M @ diff
-    else:
-        w = res["W"][-1].copy()
-    w = np.maximum(w, 0.0)
-    s = w.sum()
-    return w / s if s > 0 else np.full(t.size, 1.0 / t.size)
+    from paper_2305_04397_amd.morap import proposer_target
+    return proposer_target(t, res["t_down"], res["W"][-1], M)
 
 
 def generate(ctx, wl, T: np.ndarray, phi: np.ndarray, opts, eps: float = 0.01, max_iter: int = 64,

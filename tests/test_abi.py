@@ -309,3 +309,25 @@ def test_host_team_model_rejects_unequal_counts():
     with pytest.raises(morap.MorapError) as e:
         morap.team_model_host(wl, np.full(5, 0.2))
     assert e.value.code == morap.E_INVALID
+
+
+def test_proposer_target_on_the_host():
+    """The proposer's training target (host only): the face normal
+    M (t - t_down) at the closest point for a threshold outside, the last
+    weight vector for one inside; clipped at 0, normalised to sum 1."""
+    from paper_2305_04397_amd import morap
+    t = np.array([-1.0, -2.0, 0.9])
+    t_down = np.array([-1.5, -2.0, 0.5])
+    w = morap.proposer_target(t, t_down, np.array([0.2, 0.3, 0.5]))
+    assert np.allclose(w, [0.5 / 0.9, 0.0, 0.4 / 0.9], atol=1e-15)
+    # negative parts of the normal are rounding noise and become 0
+    w = morap.proposer_target(t, t_down + np.array([0.0, 1e-3, 0.0]), np.ones(3) / 3)
+    assert w[1] == 0.0 and w.sum() == pytest.approx(1.0, abs=1e-15)
+    # inside: the last weight vector, normalised
+    w = morap.proposer_target(t, t, np.array([1.0, 1.0, 2.0]))
+    assert np.allclose(w, [0.25, 0.25, 0.5])
+    # a diagonal norm matrix scales the normal
+    w = morap.proposer_target(t, t_down, np.zeros(3), M=np.diag([2.0, 1.0, 1.0]))
+    assert np.allclose(w, [1.0 / 1.4, 0.0, 0.4 / 1.4])
+    with pytest.raises(morap.MorapError):
+        morap.proposer_target(np.array([np.nan, 0.0, 0.0]), t_down, np.ones(3))

@@ -346,6 +346,41 @@ def test_query_batch_equals_single_queries(ctx, morap):
         assert np.abs(b["t_up"] - s["t_up"]).max() <= 1e-9
 
 
+def test_warm_started_passes_agree_with_cold_ones(ctx, morap):
+    """Alg. 1 passes whose FP32 solves start from the previous pass's values
+    (pairs with a positive cost weight) against passes solved from 0: the same
+    verdicts, and final inner points within the stop rule's reach of each
+    other (each lies within sqrt(2 dist eps) of the exact projection, dist =
+    ||t - t_up||), on the 10 x 20 family (d = 30)."""
+    wl = make_workload(2)
+    ctx.build_products(wl)
+    nI, d = wl.n_agents, wl.n_agents + wl.n_tasks
+    rng = np.random.default_rng(12)
+    opts = morap.Options(eps_vi=1e-6, precision="f32")
+    front, _, _, _ = ctx.support(dirichlet_weights(rng, 8, d), opts)
+    T = []
+    for k in range(16):
+        u = front[k % 8]
+        hi = 0.0 if k % 2 else 0.3          # odd: inside (below a front point), even: mixed
+        t = u + rng.uniform(-0.3, hi, d) * np.abs(u)
+        t[nI:] = np.clip(t[nI:], 0.0, 1.0)
+        T.append(t)
+    T = np.array(T)
+    eps = 0.01
+    warm = ctx.query_batch(T, eps=eps, max_iter=200, opts=opts, warm_start=True)
+    cold = ctx.query_batch(T, eps=eps, max_iter=200, opts=opts, warm_start=False)
+    decided = 0
+    for t, a, b in zip(T, warm, cold):
+        assert a["verdict"] == b["verdict"]
+        decided += int(a["verdict"] != morap.UNDECIDED)
+        if a["gap"] <= eps and b["gap"] <= eps:
+            dist = max(np.linalg.norm(t - a["t_up"]), np.linalg.norm(t - b["t_up"]))
+            assert np.linalg.norm(a["t_up"] - b["t_up"]) <= 2 * np.sqrt(2 * dist * eps) + 1e-6
+    # thresholds within the loop's tolerance of the front may stay undecided
+    # (in both runs alike, checked above)
+    assert decided >= len(T) - 4
+
+
 def test_query_with_norm_matrix_matches_oracle(ctx, morap):
     """Alg. 1 with a diagonal SPD norm matrix M (the M-norm projections)."""
     wl = make_workload(1)
