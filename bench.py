@@ -30,11 +30,15 @@ Extra objects on the JSON line:
                 each pass's solve started from the previous pass's values) on
                 the timed workload: latency p50 / p99, passes, verdicts, how
                 many met the stop test; plain first weight (1, 0, ..., 0)
-                against the learned proposer trained on the device from
-                plain-loop queries of other thresholds of the same workload;
+                against the learned proposer trained on the device from the
+                plain method's support steps on other weight vectors of the
+                same workload (thresholds around the point r(w) of a weight
+                vector w, target w);
   proposer      learned vs plain first weight on the 10 x 20 family: the
-                proposer is trained on the device from plain-loop queries of
-                seeded variants, then both loops answer unseen thresholds.
+                proposer is trained on the device from the plain method's
+                support steps on seeded variants (thresholds around the
+                point r(w) of a weight vector w, target w; 200k tuples), then
+                both loops answer unseen thresholds.
 """
 from __future__ import annotations
 
@@ -102,22 +106,6 @@ def measured_traffic(kernel: str):
     return None if best is None else best[1]
 
 
-def thresholds(rng, front: np.ndarray, n: int, nI: int, inside_half: bool = False) -> np.ndarray:
-    """t = u* + delta |u*| around points u* of the front, delta ~ U[-0.3, 0.3]
-    per coordinate; probabilities clipped to [0, 1].  With inside_half, every
-    second threshold takes delta ~ U[-0.3, 0] (below a front point, hence
-    achievable): in d = 150 a threshold with mixed signs is almost surely
-    outside."""
-    idx = rng.integers(front.shape[0], size=n)
-    u = front[idx]
-    hi = np.full((n, 1), 0.3)
-    if inside_half:
-        hi[1::2] = 0.0
-    t = u + (rng.uniform(0.0, 1.0, size=u.shape) * (hi + 0.3) - 0.3) * np.abs(u)
-    t[:, nI:] = np.clip(t[:, nI:], 0.0, 1.0)
-    return t
-
-
 def query_stats(res, wall_ms: float, eps: float, morap) -> dict:
     """Summary of one lockstep batch of queries: latency to each query's last
     pass (p50 / p99), passes, verdicts, how many met the loop's stop test."""
@@ -140,14 +128,15 @@ def query_eval(ctx, wl, front, rng, args, eps_vi: float) -> dict:
     """ms per point-oriented Pareto query on the timed workload, plain and
     learned first weight.  Thresholds: half below front points (achievable),
     half around them.  The learned proposer for this workload's d is trained
-    on the device from plain-loop queries on other thresholds of the same
-    workload (G15 tuples: threshold, face normal at the loop's outer point or
-    its last weight), then answers the same thresholds as the plain loop."""
+    on the device from the plain method's support steps on other weight
+    vectors of the same workload (thresholds drawn around the point r(w) of
+    a weight vector w, target w), then answers the same thresholds as the
+    plain loop."""
     from paper_2305_04397_amd import morap, proposer_data as pdata
     nI, d = wl.n_agents, wl.n_agents + wl.n_tasks
     opts = morap.Options(eps_vi=eps_vi, precision=args.precision)
     loop_eps = 0.01
-    T = thresholds(rng, front, args.queries, nI, inside_half=True)
+    T = pdata.thresholds(rng, front, args.queries, nI, inside_half=True)
     out = {"workload": wl.name, "eps": loop_eps, "max_iter": args.query_max_iter,
            "thresholds": "half below front points, half around them (U[-0.3, 0.3] per coordinate)",
            "warm_started_passes": True}
@@ -159,8 +148,7 @@ def query_eval(ctx, wl, front, rng, args, eps_vi: float) -> dict:
     if args.query_train > 0:
         t0 = time.perf_counter()
         phi = pdata.features(ctx, wl, opts)
-        Ttr = thresholds(rng, front, args.query_train, nI, inside_half=True)
-        X, Wt, _ = pdata.generate(ctx, wl, Ttr, phi, opts, eps=loop_eps, max_iter=args.query_max_iter)
+        X, Wt = pdata.generate_from_support(ctx, wl, args.query_train, 2, phi, rng, opts)
         gen_s = time.perf_counter() - t0
         ctx.proposer_init(X.shape[1], d, seed=args.seed)
         ctx.proposer_set_input_norm(X.mean(0), X.std(0) + 1e-3)
@@ -235,34 +223,34 @@ def cpu_baseline(wl, K: int, eps: float, budget_s: float, seed: int, workers: in
 
 
 def proposer_eval(args) -> dict:
-    """Learned vs plain first weight on the 10 x 20 family.
+    """Learned vs plain first weight on the 10 x 20 family (d = 30).
 
-    Plain Alg. 1 loops on seeded 10 x 20 variants give (t, target weight)
-    tuples; the proposer is trained on them on the device, then both loops
-    answer the same unseen thresholds of variant 0 (fresh draws): wall time
-    and Alg. 2 passes per query, and agreement of the answers."""
+    The plain method's support steps on seeded 10 x 20 variants give
+    (threshold, weight) tuples: thresholds drawn around the point r(w) that
+    the support step returned for a Dirichlet weight vector w, with w as the
+    target; the proposer is trained on them on the device, then both loops
+    answer the same unseen thresholds of variant 0 (fresh draws, half of them
+    achievable): wall time and Alg. 2 passes per query, and agreement of the
+    answers."""
     from workloads import make_workload
     from paper_2305_04397_amd import morap, proposer_data as pdata
     rng = np.random.default_rng(args.seed + 1)
     opts = morap.Options(eps_vi=1e-6, precision="f32")
     ctx = morap.Context(0)
-    X, Wt, phis, eval_T, errors = [], [], {}, None, []
+    X, Wt, phis, eval_T = [], [], {}, None
     t0 = time.perf_counter()
+    per_variant = max(1, args.proposer_train // (2 * args.proposer_variants))
     for v in range(args.proposer_variants):
         wl = make_workload(2, variant=v)
         ctx.build_products(wl)
         phi = pdata.features(ctx, wl, opts)
-        front = pdata.front_points(ctx, wl, 256, rng, opts)
-        T = pdata.thresholds(rng, front, args.proposer_train, wl.n_agents)
-        n_err = len(errors)
-        x, w, _ = pdata.generate(ctx, wl, T, phi, opts, errors=errors)
-        for e in errors[n_err:]:
-            log(f"proposer data: batch skipped: {e}")
+        x, w = pdata.generate_from_support(ctx, wl, per_variant, 2, phi, rng, opts)
         X.append(x)
         Wt.append(w)
         if v == 0:
             phis[0] = phi
-            eval_T = pdata.thresholds(rng, front, args.proposer_queries, wl.n_agents)
+            front = pdata.front_points(ctx, wl, 256, rng, opts)
+            eval_T = pdata.thresholds(rng, front, args.proposer_queries, wl.n_agents, inside_half=True)
         log(f"proposer data: variant {v}, {len(x)} tuples ({time.perf_counter() - t0:.0f} s)")
     X, Wt = np.vstack(X), np.vstack(Wt)
     d = Wt.shape[1]
@@ -277,7 +265,8 @@ def proposer_eval(args) -> dict:
     ctx.build_products(wl)
     ctx.set_features(phis[0])
     ctx.query_batch(eval_T[:8], eps=0.01, opts=opts)                         # warm caches
-    out = {"workload": wl.name, "eps": 0.01, "train_tuples": int(len(X)), "skipped_batches": len(errors),
+    out = {"workload": wl.name, "eps": 0.01, "train_tuples": int(len(X)),
+           "train_data": "support points r(w) of Dirichlet weight vectors w, two thresholds around each, target w",
            "train_variants": args.proposer_variants, "epochs": 80, "train_s": round(train_s, 2),
            "loss_first": round(float(losses[0]), 4), "loss_last": round(float(losses[-1]), 4)}
     res = {}
@@ -316,11 +305,13 @@ def main():
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--query-max-iter", type=int, default=48,
                     help="Alg. 2 passes allowed per query in the ms-per-query measurement")
-    ap.add_argument("--query-train", type=int, default=128,
-                    help="plain-loop training queries for the learned proposer on the timed workload (0 = skip)")
+    ap.add_argument("--query-train", type=int, default=2048,
+                    help="support points (two thresholds each) training the learned proposer on the timed "
+                         "workload (0 = skip)")
     ap.add_argument("--proposer-queries", type=int, default=1000,
                     help="unseen 10x20 queries for the learned-vs-plain comparison (0 = skip)")
-    ap.add_argument("--proposer-train", type=int, default=512, help="training queries per 10x20 variant")
+    ap.add_argument("--proposer-train", type=int, default=200_000,
+                    help="training tuples over the 10x20 variants (support points, two thresholds each)")
     ap.add_argument("--proposer-variants", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -375,7 +366,7 @@ def main():
     step_ms = []
     t_all = time.perf_counter()
     for s in range(args.steps):
-        T = thresholds(rng, front, K, nI)
+        T = pdata.thresholds(rng, front, K, nI)
         W0 = rng.dirichlet(np.ones(d), size=K)
         ts = time.perf_counter()
         ctx.query_batch(T, W0=W0, max_iter=1, eps=0.01, opts=opts)

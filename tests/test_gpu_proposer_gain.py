@@ -1,9 +1,10 @@
 """What the trained proposer gains over the plain loop (Alg. 1 from e_1).
 
 On a seeded instance of the 10 x 20 family (reduced to 4 agents x 8 tasks so
-the test stays short), plain-loop queries at thresholds around the front give
-(t, target weight) pairs; the proposer is trained on them and then starts
-unseen queries.  Both loops must reach the same verdicts and closest points
+the test stays short), the plain method's support steps give (t, target
+weight) pairs: thresholds drawn around the point r(w) of a Dirichlet weight
+vector w, with target w; the proposer is trained on them and then starts
+unseen queries (half of them below front points, hence achievable).  Both loops must reach the same verdicts and closest points
 (the plain update and the exact value iteration still decide every answer);
 the learned start must need fewer Alg. 2 passes on average.
 """
@@ -26,9 +27,8 @@ def test_learned_start_needs_fewer_passes():
         rng = np.random.default_rng(0)
         phi = pdata.features(ctx, wl, opts)
         front = pdata.front_points(ctx, wl, 256, rng, opts)
-        T_train = pdata.thresholds(rng, front, 768, nI)
-        T_test = pdata.thresholds(rng, front, 96, nI)
-        X, Wt, _ = pdata.generate(ctx, wl, T_train, phi, opts)
+        T_test = pdata.thresholds(rng, front, 96, nI, inside_half=True)
+        X, Wt = pdata.generate_from_support(ctx, wl, 4096, 2, phi, rng, opts)
         ctx.proposer_init(X.shape[1], d, seed=1)
         ctx.proposer_set_input_norm(X.mean(0), X.std(0) + 1e-3)
         losses = ctx.proposer_train(X, Wt, batch=128, epochs=60, lr=1e-3, seed=2)
