@@ -302,6 +302,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="VI seconds per baseline process")
     ap.add_argument("--cpu-workers", type=int, default=8, help="baseline processes (at most the host's cores)")
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--schedule", type=int, default=0,
+                    help="sweep-kernel variant of the timed passes (0 = the autotuner's choice)")
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--query-max-iter", type=int, default=48,
                     help="Alg. 2 passes allowed per query in the ms-per-query measurement")
@@ -320,7 +322,7 @@ def main():
         sys.exit(2)
 
     from workloads import make_workload
-    from paper_2305_04397_amd import morap
+    from paper_2305_04397_amd import morap, proposer_data as pdata
 
     cfg = 3 if args.workload == "50x100" else 2
     K = 64 if cfg == 3 else 16
@@ -345,7 +347,7 @@ def main():
         info = ctx.model_info(m)
         S, R, N = S + info["n_states"], R + info["n_rows"], N + info["nnz"]
     log(f"{nI * nJ} products built and uploaded in {time.time() - t0:.1f} s: S={S} R={R} N={N}")
-    opts = morap.Options(eps_vi=eps, precision=args.precision, time_kernels=True)
+    opts = morap.Options(eps_vi=eps, precision=args.precision, time_kernels=True, schedule=args.schedule)
     rng = np.random.default_rng(args.seed)
 
     # warm-up (includes the sweep-kernel autotuning) and front points

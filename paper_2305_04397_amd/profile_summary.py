@@ -69,7 +69,7 @@ def summarize(d: str, delete_raw: bool) -> str:
     return text
 
 
-SWEEP_SOURCES = ("csrc/block.hip", "csrc/vi.hip", "csrc/kern.h")
+SWEEP_SOURCES = ("csrc/block.hip", "csrc/halo.hip", "csrc/vi.hip", "csrc/kern.h")
 
 
 def sources_hash() -> str:
