@@ -190,7 +190,9 @@ typedef struct {
     int64_t eval_sweeps;    /* sweeps of the policy evaluation                      */
     int64_t polish_sweeps;  /* FP64 sweeps after an FP32 solve (evaluate)          */
     int64_t rank_rounds;    /* attractor-rank relaxation sweeps (policy extraction)  */
-    int64_t excluded;       /* reserved                                             */
+    int64_t floor_stops;    /* FP32 pairs stopped at the rounding floor: no new     */
+                            /* smallest change in 64 sweeps, last change within     */
+                            /* 256 units in the last place of the largest value     */
     double  bytes;          /* algorithmic bytes moved by the sweep kernel          */
     double  ms_vi, ms_eval, ms_total;   /* device / host wall time of the phases   */
     double  ms_sweep_kernel;/* summed sweep-kernel time (time_kernels = 1)          */
@@ -221,7 +223,10 @@ int morap_solve(morap_ctx* ctx, const double* W, int K, const morap_vi_opts* opt
  * evaluated per objective (Alg. 4, FP64 Jacobi from 0, eps_eval).
  * r_out[K][d]: r[|I|+j] = completion probability of task j; r[i] = sum of the
  * cost values of the tasks assigned to i.  Each agent may receive at most
- * ceil(|J|/|I|) tasks.  Errors: INVALID, STATE, IMPROPER, NOT_CONVERGED, HIP. */
+ * ceil(|J|/|I|) tasks.  On a team model (morap_load_team_model) assign is
+ * ignored (may be NULL): the one policy of each column is evaluated on every
+ * objective into r_out[K][d], and morap_get_policy(k, 0) returns it.
+ * Errors: INVALID, STATE, IMPROPER, NOT_CONVERGED, HIP. */
 int morap_evaluate(morap_ctx* ctx, const int32_t* assign, int K, const morap_vi_opts* opts,
                    double* r_out, morap_stats* stats);
 
@@ -249,6 +254,33 @@ int morap_team_model_host(const morap_agent* agents, int n_agents, const morap_d
                           int n_tasks, const int32_t* const* letters, const double* w,
                           int32_t* sizes_out, int32_t* state_row, int32_t* row_ptr, int32_t* col,
                           double* prob, double* rew, uint8_t* to_done);
+
+/* The team MDP of Def. teamMDP for n agents and n tasks (n <= 16) with its
+ * d = 2n objectives, as one caller-built model for morap_load_team_model
+ * (host only, no context; two calls as morap_product_host, sizes_out = {S,
+ * R, N, init}): rew[r] = (-cost, mass entering acceptance) of agent i acting
+ * on task j, obj[r] = (i, n + j), the objectives the two rewards belong to;
+ * the zero-reward rows (commit, hand over, start the next task, empty) have
+ * obj[r] = (0, n).  Errors: as morap_team_model_host. */
+int morap_team_model_mo_host(const morap_agent* agents, int n_agents, const morap_dfa* tasks, int n_tasks,
+                             const int32_t* const* letters, int32_t* sizes_out, int32_t* state_row,
+                             int32_t* row_ptr, int32_t* col, double* prob, double* rew, int32_t* obj,
+                             uint8_t* to_done);
+
+/* Load a team MDP with d = n_agents + n_tasks objectives into the context
+ * (Def. teamMDP; replaces any loaded models): one model in the layout of
+ * morap_load_models (its agent and task fields 0) plus obj[R][2], the
+ * objective in [0, d) each of a row's two rewards belongs to.  On such a
+ * context morap_solve takes W[K][d] and scalarises every row with its own
+ * objectives (w[obj[r][0]] rew[r][0] + w[obj[r][1]] rew[r][1]); c_out[K]
+ * gets the value at the initial state; morap_support evaluates the policy of
+ * every column per objective (Alg. 4 on the d objectives) into r_out[K][d]
+ * (assign_out, if given, gets 0 per task); morap_query and morap_query_batch
+ * run Alg. 1 on it.  Its optimum for w equals the decentralised
+ * assignment's (Lemma lem:ct-mdp-prop).  Errors: INVALID (as
+ * morap_load_models, objective out of range), OOM, UNSUPPORTED. */
+int morap_load_team_model(morap_ctx* ctx, int n_agents, int n_tasks, const morap_model* model,
+                          const int32_t* obj);
 
 /* The same assignment without a context (host only, no device touched), for
  * c[K][n_agents][n_tasks] given by the caller: assign_out[K][n_tasks] holds
@@ -356,8 +388,8 @@ int morap_query_batch(morap_ctx* ctx, const double* T, const double* W0, int Q, 
  * serves task j, sum of v[i] over the picked passes with f(j) = i, divided by
  * the sum of their v.  Afterwards morap_get_policy(q, j) returns the
  * scheduler of task j in the q-th picked pass.  Errors: INVALID (no v > 0,
- * an agent index out of range, negative v), and those of morap_solve and
- * morap_evaluate. */
+ * an agent index out of range, negative v), UNSUPPORTED (a team model is
+ * loaded), and those of morap_solve and morap_evaluate. */
 int morap_synthesize(morap_ctx* ctx, const double* W, const int32_t* F, const double* v, int n,
                      const morap_vi_opts* opts, int32_t* n_picked, int32_t* picked_out, double* r_out,
                      double* matrix_out);

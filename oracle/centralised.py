@@ -117,6 +117,35 @@ def team_value(team: TeamMDP, w: np.ndarray, eps: float = 1e-12, max_sweeps: int
     raise RuntimeError("value iteration did not converge")
 
 
+def team_value_proper(team: TeamMDP, w: np.ndarray) -> float:
+    """Scalarised optimum over proper policies (those that finish every task
+    with probability 1) from the joint initial state.
+
+    Where an agent's steps weigh nothing, the team MDP admits an improper
+    optimum (that agent takes a task and never finishes it, so the agents
+    after it never spend anything); ``team_value`` returns that one.  The
+    proper optimum is the least solution v of v >= r_a + P_a v over every row
+    a (any such v bounds each proper policy's value from above, and the
+    proper optimum satisfies the system with equality), i.e. the linear
+    programme min sum_s v(s) over that system; states without rows have
+    v >= 0."""
+    from scipy.optimize import linprog
+    S = team.n_states
+    R = len(team.row_ptr) - 1
+    r = team.rew @ np.asarray(w, dtype=np.float64)
+    row_state = np.repeat(np.arange(S), np.diff(team.state_row))
+    P = sp.csr_matrix((team.prob, team.col, team.row_ptr), shape=(R, S))
+    own = sp.csr_matrix((np.ones(R), (np.arange(R), row_state)), shape=(R, S))
+    empty = np.flatnonzero(np.diff(team.state_row) == 0)
+    lone = sp.csr_matrix((np.ones(len(empty)), (np.arange(len(empty)), empty)), shape=(len(empty), S))
+    A = sp.vstack([-(own - P), -lone]).tocsr()
+    b = np.concatenate([-r, np.zeros(len(empty))])
+    res = linprog(np.ones(S), A_ub=A, b_ub=b, bounds=[(None, None)] * S, method="highs")
+    if res.status != 0:
+        raise RuntimeError("proper team optimum: " + res.message)
+    return float(res.x[team.init])
+
+
 def single_objective_model(team: TeamMDP, w: np.ndarray) -> dict:
     """The team MDP scalarised for one weight vector, laid out as a
     caller-built single-objective model (the reward in the cost column).

@@ -32,7 +32,7 @@ void to_abi(const Stats& s, morap_stats* out) {
     out->eval_sweeps = s.eval_sweeps;
     out->polish_sweeps = s.polish_sweeps;
     out->rank_rounds = s.rank_rounds;
-    out->excluded = s.excluded;
+    out->floor_stops = s.floor_stops;
     out->bytes = s.bytes;
     out->ms_vi = s.ms_vi;
     out->ms_eval = s.ms_eval;
@@ -214,6 +214,25 @@ int morap_team_model_host(const morap_agent* agents, int n_agents, const morap_d
     }
 }
 
+int morap_team_model_mo_host(const morap_agent* agents, int n_agents, const morap_dfa* tasks, int n_tasks,
+                             const int32_t* const* letters, int32_t* sizes_out, int32_t* state_row,
+                             int32_t* row_ptr, int32_t* col, double* prob, double* rew, int32_t* obj,
+                             uint8_t* to_done) {
+    try {
+        team_model_mo_host(agents, n_agents, tasks, n_tasks, letters, sizes_out, state_row, row_ptr, col, prob, rew,
+                           obj, to_done);
+        return MORAP_OK;
+    } catch (const MorapError& e) {
+        return e.code;
+    } catch (...) {
+        return MORAP_E_OOM;
+    }
+}
+
+int morap_load_team_model(morap_ctx* ctx, int n_agents, int n_tasks, const morap_model* model, const int32_t* obj) {
+    return guarded(ctx, [&] { load_team_model(ctx, n_agents, n_tasks, model, obj); });
+}
+
 int morap_assign_host(const double* c, int n_agents, int n_tasks, int K, int32_t* assign_out) {
     try {
         assign_columns(n_agents, n_tasks, c, K, assign_out);
@@ -235,9 +254,11 @@ int morap_support(morap_ctx* ctx, const double* W, int K, const morap_vi_opts* o
         std::vector<int32_t> A((size_t)std::max(K, 1) * nJ);
         Stats st;
         solve(ctx, W, K, *opts, C.data(), st);
-        assign_columns(nI, nJ, C.data(), K, A.data());
+        // a team model's policy does the assignment itself: no assignment step
+        if (!ctx->team) assign_columns(nI, nJ, C.data(), K, A.data());
         evaluate(ctx, A.data(), K, *opts, r_out, st);
-        if (assign_out) std::copy(A.begin(), A.begin() + (size_t)K * nJ, assign_out);
+        if (assign_out && ctx->team) std::fill(assign_out, assign_out + (size_t)K * n_tasks_of(ctx), 0);
+        else if (assign_out) std::copy(A.begin(), A.begin() + (size_t)K * nJ, assign_out);
         if (c_out) std::copy(C.begin(), C.begin() + (size_t)K * nI * nJ, c_out);
         to_abi(st, stats);
     });
@@ -252,6 +273,7 @@ int morap_synthesize(morap_ctx* ctx, const double* W, const int32_t* F, const do
         MORAP_CHECK(W && F && v && opts && n_picked && picked_out && r_out && n >= 1, MORAP_E_INVALID,
                     "bad synthesis arguments");
         MORAP_CHECK(ctx->loaded, MORAP_E_STATE, "no models loaded");
+        MORAP_CHECK(!ctx->team, MORAP_E_UNSUPPORTED, "synthesis needs the decentralised products");
         const int nI = ctx->hm.nI, nJ = ctx->hm.nJ, d = nI + nJ;
         std::vector<int32_t> pick;
         double vsum = 0;
@@ -304,9 +326,12 @@ int morap_get_policy(const morap_ctx* cctx, int k, int j, int8_t* mu_out) {
     morap_ctx* ctx = const_cast<morap_ctx*>(cctx);
     return guarded(ctx, [&] {
         MORAP_CHECK(ctx->evaluated, MORAP_E_STATE, "no morap_evaluate yet");
+        // a team model: one policy per column (j = 0), held by each of the
+        // column's (d + 1) / 2 evaluation instances
+        const int per_col = ctx->team ? (n_obj_of(ctx) + 1) / 2 : ctx->hm.nJ;
         MORAP_CHECK(mu_out && k >= 0 && k < ctx->eK && j >= 0 && j < ctx->hm.nJ, MORAP_E_INVALID,
                     "index out of range");
-        const int q = k * ctx->hm.nJ + j;
+        const int q = k * per_col + j;
         const int64_t b = ctx->inst_base[q], e = ctx->inst_base[q + 1];
         if (e > b)
             MORAP_HIP(hipMemcpy(mu_out, ctx->d_mu.as<int8_t>() + b, (size_t)(e - b), hipMemcpyDeviceToHost));

@@ -178,7 +178,7 @@ struct Variant {
 
 struct Stats {
     int64_t backups = 0, sweeps = 0, max_pair_sweeps = 0, eval_sweeps = 0, polish_sweeps = 0,
-            rank_rounds = 0, excluded = 0;
+            rank_rounds = 0, floor_stops = 0;
     double bytes = 0, ms_vi = 0, ms_eval = 0, ms_total = 0, ms_sweep_kernel = 0;
     int64_t sweep_launches = 0;
     double bytes_refine = 0, ms_sweep_kernel_refine = 0;
@@ -219,6 +219,13 @@ struct morap_ctx {
     int max_rows_per_state = 0;
     bool has_blocks = false;                        // the neighbourhood-block form exists
     morap::DevBuf d_blk_rec, d_blk32, d_blk64;
+    bool team = false;                              // a team MDP with per-row objectives is loaded
+    int team_nI = 0, team_nJ = 0;                   // its agents and tasks (d = team_nI + team_nJ)
+    morap::DevBuf d_obj;                            // [R][2] objective of each reward of a row
+    morap::DevBuf d_rewk32, d_rewk64, d_team_w;     // [R][Kp] scalarised rewards, [K][d] weights
+    morap::DevBuf d_inst_obj;                       // [instances][2] objectives an instance evaluates
+    morap::DevBuf d_team_pi;                        // [S] global row of a fixed proper policy
+    morap::DevBuf d_team_E;                         // [S][d] its value per objective (the start of a solve)
     bool has_halo = false;                          // halo tiles exist
     morap::DevBuf d_htiles, d_htile_base, d_hrec, d_hlist;
     int64_t n_htiles = 0;
@@ -248,7 +255,8 @@ struct morap_ctx {
     morap::DevBuf d_model_active;                   // [M] uint8
     morap::DevBuf d_act_models, d_act_prefix;       // compacted active model list
     morap::DevBuf d_act_tiles;                      // the active models' tiles, in order
-    morap::DevBuf d_counters;                       // int64 [8] (see the convergence kernel)
+    morap::DevBuf d_best_res, d_stall;              // [M][Kp] FP32 rounding-floor detection
+    morap::DevBuf d_counters;                       // int64 [9] (see the convergence kernel)
     morap::PinnedBuf h_counters;
     morap::PinnedBuf h_log;                         // per-launch tile counts (sweep log)
     std::vector<double> W;                          // [K][d] of the last solve
@@ -341,12 +349,22 @@ std::vector<uint8_t> dfa_done(const morap_dfa& t);
 void team_model_host(const morap_agent* agents, int n_agents, const morap_dfa* tasks, int n_tasks,
                      const int32_t* const* letters, const double* w, int32_t* sizes, int32_t* state_row,
                      int32_t* row_ptr, int32_t* col, double* prob, double* rew, uint8_t* to_done);
+// the team MDP with its d = 2n objectives: per row the two rewards and the
+// objective each belongs to (host only)
+void team_model_mo_host(const morap_agent* agents, int n_agents, const morap_dfa* tasks, int n_tasks,
+                        const int32_t* const* letters, int32_t* sizes, int32_t* state_row, int32_t* row_ptr,
+                        int32_t* col, double* prob, double* rew, int32_t* obj, uint8_t* to_done);
 // one product on the host (no context, no device): sizes = {S, R, N, init},
 // arrays filled where non-NULL
 void product_host(const morap_agent* a, const morap_dfa* t, const int32_t* letters, int32_t* sizes,
                   int32_t* state_row, int32_t* row_ptr, int32_t* col, double* prob, double* rew, uint8_t* to_done,
                   int32_t* states);
 void upload_models(morap_ctx* ctx);
+void load_team_model(morap_ctx* ctx, int n_agents, int n_tasks, const morap_model* model, const int32_t* obj);
+// agents, tasks and objectives of the loaded models (a team model: its own)
+inline int n_agents_of(const morap_ctx* c) { return c->team ? c->team_nI : c->hm.nI; }
+inline int n_tasks_of(const morap_ctx* c) { return c->team ? c->team_nJ : c->hm.nJ; }
+inline int n_obj_of(const morap_ctx* c) { return n_agents_of(c) + n_tasks_of(c); }
 
 // solver.cpp
 // warm (nullable, [K]): column of the previous solve each column starts from
@@ -409,6 +427,7 @@ struct SweepArgs {
     int32_t zero_row;       // S: the value row that always holds 0
     uint32_t pattern;       // union of the blocks' nonzero (action, slot) entries
     const int32_t* act_tiles;  // global index of every active tile, in order
+    const void* rewk;          // team models: scalarised reward of every (row, column) [R][Kp] (nullable)
     const HTile* htiles;       // halo tiles (LDS-staged sweep)
     const uint2* hrec;         // their records
     const int32_t* hlist;      // their halo lists
@@ -440,6 +459,12 @@ struct ConvergeArgs {
     int64_t* counters;
     int M, K, Kp, prec, out_par;
     double eps, unit;       // stop at res <= max(eps, unit * ymax)
+    // FP32 rounding floor: a pair whose change has set no new minimum for
+    // stall_sweeps sweeps (0: off) and is within floor * ymax stops too
+    double* best_res;       // [M][Kp] smallest change so far
+    int32_t* stall;         // [M][Kp] sweeps since it was set
+    int stall_sweeps;
+    double floor;
     const int32_t* tile_base;
     int32_t* act_models;
     int32_t* act_prefix;
@@ -469,7 +494,25 @@ struct InstArgs {
     const uint8_t* to_done;
     const int32_t* init;
     int cus;                       // compute units (resident-sized grids of the striding kernels)
+    // team models (nullable otherwise): FP64 scalarised reward of every
+    // (row, column) with its leading dimension, every row's two objectives
+    // and the two objectives each instance evaluates (-1: none)
+    const double* rewk;
+    int rewk_ld;
+    const int32_t* row_obj;
+    const int32_t* inst_obj;
 };
+// team models: one Jacobi sweep of the per-objective evaluation of the fixed
+// policy pi (E[s][o], res = max change as FP64 bits), and the start values
+// x[s][k] = sum_o W[k][o] E[s][o] minus a margin (FP32 or FP64 x, [S+1][Kp])
+void team_eval_sweep(hipStream_t s, int64_t S, int d, const int32_t* pi, const int32_t* row_ptr,
+                     const int32_t* col, const double* prob, const double* rew, const int32_t* obj,
+                     const double* E_in, double* E_out, unsigned long long* res);
+void team_start(hipStream_t s, int64_t S, int K, int Kp, int d, const double* W, const double* E, int prec,
+                void* x);
+// team models: out[r][k] = W[k][obj[r][0]] rew[r][0] + W[k][obj[r][1]] rew[r][1]
+void team_rewards(hipStream_t s, int64_t R, int K, int Kp, int d, const double* W, const int32_t* obj,
+                  const double* rew, double* out64, float* out32);
 void gather_columns(hipStream_t s, const InstArgs& a, int prec, const void* x0, const void* x1,
                     const uint8_t* final_par, int Kp, double* xi);
 // start of an FP32 solve from the previous one's final values: out[s][k] =

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cstring>
 #include <functional>
 #include <cmath>
 #include <thread>
@@ -796,6 +797,7 @@ void upload_models(morap_ctx* c) {
     c->loaded = false;
     c->solved = false;
     c->evaluated = false;
+    c->team = false;
     c->tuned.clear();
     c->resident.clear();
     // captured sweep graphs bake in the model buffers, the zero row and the
@@ -881,6 +883,122 @@ void upload_models(morap_ctx* c) {
         k::to_f32(s, c->d_blk64.as<double>(), c->d_blk32.as<float>(), (int64_t)hm.blk_agent.size());
     }
     MORAP_HIP(hipStreamSynchronize(s));
+    c->loaded = true;
+}
+
+// A team model's optimum from value iteration started at 0 can be improper:
+// where an agent's steps weigh nothing it may take a task and never finish
+// it, so the agents after it never start theirs (and spend nothing).  The
+// optimum over proper policies -- the assignment optimum of Lemma
+// lem:ct-mdp-prop -- is the least fixed point of the backup, and value
+// iteration reaches it from any start below it.  The start used: the values
+// of one fixed proper policy pi, per objective, E[s][o] (a solve starts each
+// column at sum_o w[o] E[s][o]).  pi is the attractor policy of all rows
+// (ranks are distances to done; each state takes the row moving the most
+// mass into done or lower ranks), E its Jacobi evaluation on the device.
+static void team_proper_start(morap_ctx* c, int d) {
+    const HostModels& hm = c->hm;
+    const int64_t S = hm.S();
+    // predecessors of every state (over all rows)
+    std::vector<int64_t> pstart(S + 1, 0);
+    for (int64_t s = 0; s < S; ++s)
+        for (int32_t r = hm.state_row[s]; r < hm.state_row[s + 1]; ++r)
+            for (int32_t e = hm.row_ptr[r]; e < hm.row_ptr[r + 1]; ++e) ++pstart[hm.col[e] + 1];
+    for (int64_t s = 0; s < S; ++s) pstart[s + 1] += pstart[s];
+    std::vector<int32_t> pred(pstart[S]);
+    {
+        std::vector<int64_t> fill(pstart.begin(), pstart.end() - 1);
+        for (int64_t s = 0; s < S; ++s)
+            for (int32_t r = hm.state_row[s]; r < hm.state_row[s + 1]; ++r)
+                for (int32_t e = hm.row_ptr[r]; e < hm.row_ptr[r + 1]; ++e) pred[fill[hm.col[e]]++] = (int32_t)s;
+    }
+    // BFS ranks from done
+    std::vector<int32_t> rank(S, -1), queue;
+    queue.reserve(S);
+    for (int64_t s = 0; s < S; ++s)
+        for (int32_t r = hm.state_row[s]; r < hm.state_row[s + 1]; ++r)
+            if (hm.to_done[r] && rank[s] < 0) {
+                rank[s] = 1;
+                queue.push_back((int32_t)s);
+            }
+    for (size_t h = 0; h < queue.size(); ++h) {
+        const int32_t t = queue[h];
+        for (int64_t p = pstart[t]; p < pstart[t + 1]; ++p)
+            if (rank[pred[p]] < 0) {
+                rank[pred[p]] = rank[t] + 1;
+                queue.push_back(pred[p]);
+            }
+    }
+    std::vector<int32_t> pi(S);
+    for (int64_t s = 0; s < S; ++s) {
+        MORAP_CHECK(rank[s] >= 0, MORAP_E_INVALID, "team model: a state cannot reach done");
+        int best = -1;
+        double best_m = -1.0;
+        for (int32_t r = hm.state_row[s]; r < hm.state_row[s + 1]; ++r) {
+            double m = 0.0, live = 0.0;
+            bool hit = hm.to_done[r] != 0;
+            for (int32_t e = hm.row_ptr[r]; e < hm.row_ptr[r + 1]; ++e) {
+                live += hm.prob[e];
+                if (rank[hm.col[e]] < rank[s]) {
+                    hit = true;
+                    m += hm.prob[e];
+                }
+            }
+            if (hm.to_done[r]) m += 1.0 - live;
+            if (hit && m > best_m + 1e-12) {
+                best_m = m;
+                best = r;
+            }
+        }
+        pi[s] = best;
+    }
+    upload(c->d_team_pi, pi, c->stream);
+    hipStream_t st = c->stream;
+    morap::DevBuf E1, res;
+    c->d_team_E.ensure((size_t)S * d * 8 + 8);
+    E1.ensure((size_t)S * d * 8 + 8);
+    res.ensure(8);
+    double* e0 = c->d_team_E.as<double>();
+    double* e1 = E1.as<double>();
+    k::fill_f64(st, e0, 0.0, S * d);
+    int64_t sweeps = 0;
+    while (true) {
+        unsigned long long r = 0;
+        for (int i = 0; i < 64; ++i) {
+            if (i == 63) MORAP_HIP(hipMemsetAsync(res.p, 0, 8, st));
+            k::team_eval_sweep(st, S, d, c->d_team_pi.as<int32_t>(), c->d_row_ptr.as<int32_t>(),
+                               c->d_col.as<int32_t>(), c->d_prob64.as<double>(), c->d_rew64.as<double>(),
+                               c->d_obj.as<int32_t>(), (i & 1) ? e1 : e0, (i & 1) ? e0 : e1,
+                               i == 63 ? res.as<unsigned long long>() : nullptr);
+        }
+        sweeps += 64;
+        MORAP_HIP(hipMemcpyAsync(&r, res.p, 8, hipMemcpyDeviceToHost, st));
+        MORAP_HIP(hipStreamSynchronize(st));
+        double change;
+        std::memcpy(&change, &r, 8);
+        if (change <= 1e-12) break;
+        MORAP_CHECK(sweeps < 10000000, MORAP_E_NOT_CONVERGED, "team model: evaluation of the start policy");
+    }
+}
+
+// A team MDP (Def. teamMDP) with its d objectives: one caller-built model
+// plus the objective of each of a row's two rewards.
+void load_team_model(morap_ctx* c, int nA, int nT, const morap_model* model, const int32_t* obj) {
+    MORAP_CHECK(model && obj && nA >= 1 && nT >= 1 && nA + nT <= 4096, MORAP_E_INVALID,
+                "bad team model arguments");
+    MORAP_CHECK(model->agent == 0 && model->task == 0, MORAP_E_INVALID, "a team model has agent = task = 0");
+    MORAP_CHECK(model->n_rows >= 0, MORAP_E_INVALID, "negative size");
+    const int d = nA + nT;
+    for (int64_t r = 0; r < 2 * (int64_t)model->n_rows; ++r)
+        MORAP_CHECK(obj[r] >= 0 && obj[r] < d, MORAP_E_INVALID, "objective index out of range");
+    load_models(c, model, 1, 1, 1);
+    c->loaded = false;
+    std::vector<int32_t> o(obj, obj + 2 * (size_t)model->n_rows);
+    upload(c->d_obj, o, c->stream);
+    team_proper_start(c, d);
+    c->team = true;
+    c->team_nI = nA;
+    c->team_nJ = nT;
     c->loaded = true;
 }
 

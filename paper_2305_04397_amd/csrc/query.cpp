@@ -86,7 +86,7 @@ void query_batch(morap_ctx* c, const double* T, const double* W0, int Q, const d
     MORAP_CHECK(c->loaded, MORAP_E_STATE, "no models loaded");
     MORAP_CHECK(T && res && Q >= 1, MORAP_E_INVALID, "bad query arguments");
     MORAP_CHECK(o.eps >= 0 && o.max_iter >= 1, MORAP_E_INVALID, "need eps >= 0 and max_iter >= 1");
-    const int nI = c->hm.nI, nJ = c->hm.nJ, d = nI + nJ;
+    const int nI = n_agents_of(c), nJ = n_tasks_of(c), d = nI + nJ;
     for (int64_t i = 0; i < (int64_t)Q * d; ++i) MORAP_CHECK(std::isfinite(T[i]), MORAP_E_INVALID, "t must be finite");
     std::vector<QState> qs(Q);
     const auto t_start = std::chrono::steady_clock::now();
@@ -184,7 +184,8 @@ void query_batch(morap_ctx* c, const double* T, const double* W0, int Q, const d
                 const auto t0 = std::chrono::steady_clock::now();
                 solve(c, W.data(), K, vo, C.data(), st, o.warm_start && it > 0 ? warm_map.data() : nullptr);
                 const auto t1 = std::chrono::steady_clock::now();
-                assign_columns(nI, nJ, C.data(), K, A.data());
+                // a team model's policy assigns by itself (A stays 0)
+                if (!c->team) assign_columns(nI, nJ, C.data(), K, A.data());
                 evaluate(c, A.data(), K, vo, R.data(), st);
                 const auto t2 = std::chrono::steady_clock::now();
                 const double ms = std::chrono::duration<double, std::milli>(t2 - t0).count();

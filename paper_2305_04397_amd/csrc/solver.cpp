@@ -98,8 +98,10 @@ static void ensure_scratch(morap_ctx* c, int Kp) {
     moved |= c->d_act_models.ensure((size_t)M * 4 + 4);
     moved |= c->d_act_prefix.ensure((size_t)(M + 1) * 4 + 4);
     moved |= c->d_act_tiles.ensure(std::max<size_t>(c->tiles.size(), (size_t)c->n_htiles) * 4 + 4);
-    moved |= c->d_counters.ensure(8 * 8);
-    c->h_counters.ensure(8 * 8);
+    moved |= c->d_best_res.ensure(pairs * 8);
+    moved |= c->d_stall.ensure(pairs * 4);
+    moved |= c->d_counters.ensure(9 * 8);
+    c->h_counters.ensure(9 * 8);
     // a captured sweep graph holds these addresses: it must not replay
     // after any of them moved
     if (moved) ++c->buf_gen;
@@ -145,6 +147,10 @@ static k::ConvergeArgs converge_args(morap_ctx* c, ValueSet& vs, const uint8_t* 
     // FP32 backups cannot resolve changes below a few units in the last
     // place of the values: stop there too (FP64: the bound is below eps)
     a.unit = vs.prec == MORAP_F32 ? 8.0 * std::ldexp(1.0, -24) : 8.0 * std::ldexp(1.0, -53);
+    a.best_res = c->d_best_res.as<double>();
+    a.stall = c->d_stall.as<int32_t>();
+    a.stall_sweeps = vs.prec == MORAP_F32 ? 64 : 0;
+    a.floor = 256.0 * std::ldexp(1.0, -24);
     a.tile_base = halo ? c->d_htile_base.as<int32_t>() : c->d_tile_base.as<int32_t>();
     a.act_models = c->d_act_models.as<int32_t>();
     a.act_prefix = c->d_act_prefix.as<int32_t>();
@@ -184,6 +190,7 @@ static k::SweepArgs sweep_args(morap_ctx* c, ValueSet& vs, int in_par) {
     a.htiles = c->has_halo ? c->d_htiles.as<HTile>() : nullptr;
     a.hrec = c->has_halo ? c->d_hrec.as<uint2>() : nullptr;
     a.hlist = c->has_halo ? c->d_hlist.as<int32_t>() : nullptr;
+    a.rewk = c->team ? (f32 ? c->d_rewk32.p : c->d_rewk64.p) : nullptr;
     return a;
 }
 
@@ -368,7 +375,7 @@ static void run_chunk(morap_ctx* c, int g, ValueSet& vs, const uint8_t* mask, co
 }
 
 static void read_counters(morap_ctx* c) {
-    MORAP_HIP(hipMemcpyAsync(c->h_counters.p, c->d_counters.p, 8 * 8, hipMemcpyDeviceToHost, c->stream));
+    MORAP_HIP(hipMemcpyAsync(c->h_counters.p, c->d_counters.p, 9 * 8, hipMemcpyDeviceToHost, c->stream));
     MORAP_HIP(hipStreamSynchronize(c->stream));
 }
 
@@ -428,6 +435,53 @@ static void swap_buf(DevBuf& a, DevBuf& b) {
     std::swap(a.meter, b.meter);
 }
 
+// For the message of a solve that hit its sweep limit: the first pairs still
+// active, each with its two weights and the change between the last two
+// iterates (the two value buffers) at its most-changing state.
+static std::string describe_active(morap_ctx* c, ValueSet& vs) {
+    const int M = c->hm.M, Kp = vs.Kp;
+    std::vector<uint8_t> act((size_t)M * Kp);
+    MORAP_HIP(hipMemcpy(act.data(), c->d_active.p, act.size(), hipMemcpyDeviceToHost));
+    const size_t el = vs.prec == MORAP_F32 ? 4 : 8;
+    std::string out;
+    int shown = 0;
+    for (int m = 0; m < M && shown < 4; ++m)
+        for (int k = 0; k < vs.K && shown < 4; ++k) {
+            if (!act[(size_t)m * Kp + k]) continue;
+            const int32_t s0 = c->hm.state_base[m], s1 = c->hm.state_base[m + 1];
+            std::vector<char> b0((size_t)(s1 - s0) * Kp * el + 8), b1(b0.size());
+            MORAP_HIP(hipMemcpy(b0.data(), vs.x[0].as<char>() + (size_t)s0 * Kp * el, b0.size() - 8,
+                                hipMemcpyDeviceToHost));
+            MORAP_HIP(hipMemcpy(b1.data(), vs.x[1].as<char>() + (size_t)s0 * Kp * el, b1.size() - 8,
+                                hipMemcpyDeviceToHost));
+            double dmax = -1, v0 = 0, v1 = 0;
+            int at = -1;
+            for (int32_t s = 0; s < s1 - s0; ++s) {
+                const size_t i = (size_t)s * Kp + k;
+                const double a = el == 4 ? reinterpret_cast<float*>(b0.data())[i] : reinterpret_cast<double*>(b0.data())[i];
+                const double b = el == 4 ? reinterpret_cast<float*>(b1.data())[i] : reinterpret_cast<double*>(b1.data())[i];
+                if (std::fabs(a - b) > dmax) {
+                    dmax = std::fabs(a - b);
+                    at = s;
+                    v0 = a;
+                    v1 = b;
+                }
+            }
+            const int d = n_obj_of(c);
+            const int i = m / c->hm.nJ, j = m % c->hm.nJ;
+            const double wc = c->team ? 1.0 : c->W[(size_t)k * d + i];
+            const double wp = c->team ? 0.0 : c->W[(size_t)k * d + c->hm.nI + j];
+            char buf[320];
+            std::snprintf(buf, sizeof buf,
+                          "%s (model %d, column %d: weights %.9g, %.9g; last change %.6g at state %d, %.9g -> "
+                          "%.9g)",
+                          shown ? "," : ":", m, k, wc, wp, dmax, at, v0, v1);
+            out += buf;
+            ++shown;
+        }
+    return out;
+}
+
 // warm: the solve starts from the values prepared in d_xwarm (they become
 // the first sweep's input buffer)
 static void run_vi(morap_ctx* c, int g, ValueSet& vs, const uint8_t* mask, const morap_vi_opts& o, Stats& st,
@@ -440,6 +494,12 @@ static void run_vi(morap_ctx* c, int g, ValueSet& vs, const uint8_t* mask, const
     if (warm) {
         swap_buf(vs.x[0], c->d_xwarm);
         ++c->buf_gen;   // graphs hold the value buffers' addresses
+    } else if (c->team) {
+        // a team model starts below its optimum over proper policies (the
+        // values of a fixed proper policy), which value iteration then
+        // reaches instead of an improper fixed point above it
+        k::team_start(c->stream, c->S, vs.K, vs.Kp, n_obj_of(c), c->d_team_w.as<double>(),
+                      c->d_team_E.as<double>(), vs.prec, vs.x[0].p);
     }
     MORAP_HIP(hipEventRecord(wall.a, c->stream));
     int64_t launched = 0;
@@ -475,7 +535,7 @@ static void run_vi(morap_ctx* c, int g, ValueSet& vs, const uint8_t* mask, const
         if (launched >= o.max_sweeps)
             fail(MORAP_E_NOT_CONVERGED, "value iteration: " + std::to_string(h[3]) +
                                             " (model, column) pairs still active after " +
-                                            std::to_string(launched) + " sweeps");
+                                            std::to_string(launched) + " sweeps" + describe_active(c, vs));
     }
     MORAP_HIP(hipEventRecord(wall.b, c->stream));
     MORAP_HIP(hipEventSynchronize(wall.b));
@@ -484,6 +544,7 @@ static void run_vi(morap_ctx* c, int g, ValueSet& vs, const uint8_t* mask, const
     MORAP_HIP(hipMemcpy(ps.data(), c->d_pair_sweeps.p, ps.size() * 4, hipMemcpyDeviceToHost));
     const size_t el = vs.prec == MORAP_F32 ? 4 : 8;
     st.backups += h[4];
+    st.floor_stops += h[8];
     if (mask) st.bytes_refine += (double)h[6] + 2.0 * el * (double)h[7];
     else st.bytes += (double)h[6] + 2.0 * el * (double)h[7];
     st.max_pair_sweeps = std::max<int64_t>(st.max_pair_sweeps, *std::max_element(ps.begin(), ps.end()));
@@ -505,6 +566,7 @@ static void add_stats(Stats& a, const Stats& b) {
     a.eval_sweeps += b.eval_sweeps;
     a.polish_sweeps += b.polish_sweeps;
     a.rank_rounds += b.rank_rounds;
+    a.floor_stops += b.floor_stops;
     a.bytes += b.bytes;
     a.ms_vi += b.ms_vi;
     a.ms_eval += b.ms_eval;
@@ -545,7 +607,7 @@ static void solve_impl(morap_ctx* c, const double* W, int K, const morap_vi_opts
     MORAP_CHECK(o.precision == MORAP_F32 || o.precision == MORAP_F64, MORAP_E_INVALID, "bad precision");
     MORAP_CHECK(o.eps_vi > 0 && std::isfinite(o.eps_vi), MORAP_E_INVALID, "eps_vi must be > 0");
     MORAP_CHECK(o.max_sweeps >= 1, MORAP_E_INVALID, "max_sweeps must be >= 1");
-    const int nI = c->hm.nI, nJ = c->hm.nJ, M = c->hm.M, d = nI + nJ;
+    const int nI = c->hm.nI, nJ = c->hm.nJ, M = c->hm.M, d = n_obj_of(c);
     for (int k = 0; k < K; ++k) {
         double s = 0;
         for (int q = 0; q < d; ++q) {
@@ -561,7 +623,7 @@ static void solve_impl(morap_ctx* c, const double* W, int K, const morap_vi_opts
     // a warm start needs the previous FP32 values in buffers that already
     // fit this solve (they are read in place)
     const size_t need = (size_t)(c->S + 1) * Kp * 4;
-    const bool warm_ok = warm && prec == MORAP_F32 && c->vmain.valid && c->vmain.prec == MORAP_F32 &&
+    const bool warm_ok = warm && !c->team && prec == MORAP_F32 && c->vmain.valid && c->vmain.prec == MORAP_F32 &&
                          Kp <= c->vmain.Kp && c->vmain.x[0].bytes >= need && c->vmain.x[1].bytes >= need;
     const int Kp_old = c->vmain.Kp, K_old = c->vmain.K;
     // Per pair, the start a x_prev + b from the previous values x_prev, which
@@ -607,14 +669,16 @@ static void solve_impl(morap_ctx* c, const double* W, int K, const morap_vi_opts
     c->prec = prec;
     c->W.assign(W, W + (size_t)K * d);
 
-    // per-(model, column) weights of the model's two objectives
+    // per-(model, column) weights of the model's two objectives (a team
+    // model: its rows are scalarised per column on the device instead, and
+    // (1, 0) marks the column in use)
     std::vector<double> wc((size_t)M * Kp, 0.0), wp((size_t)M * Kp, 0.0);
     std::vector<float> wc32((size_t)M * Kp, 0.f), wp32((size_t)M * Kp, 0.f);
     for (int m = 0; m < M; ++m) {
         const int i = m / nJ, j = m % nJ;
         for (int k = 0; k < K; ++k) {
-            wc[(size_t)m * Kp + k] = W[(size_t)k * d + i];
-            wp[(size_t)m * Kp + k] = W[(size_t)k * d + nI + j];
+            wc[(size_t)m * Kp + k] = c->team ? 1.0 : W[(size_t)k * d + i];
+            wp[(size_t)m * Kp + k] = c->team ? 0.0 : W[(size_t)k * d + nI + j];
             wc32[(size_t)m * Kp + k] = (float)wc[(size_t)m * Kp + k];
             wp32[(size_t)m * Kp + k] = (float)wp[(size_t)m * Kp + k];
         }
@@ -623,6 +687,17 @@ static void solve_impl(morap_ctx* c, const double* W, int K, const morap_vi_opts
     MORAP_HIP(hipMemcpyAsync(c->d_wp64.p, wp.data(), wp.size() * 8, hipMemcpyHostToDevice, c->stream));
     MORAP_HIP(hipMemcpyAsync(c->d_wc32.p, wc32.data(), wc32.size() * 4, hipMemcpyHostToDevice, c->stream));
     MORAP_HIP(hipMemcpyAsync(c->d_wp32.p, wp32.data(), wp32.size() * 4, hipMemcpyHostToDevice, c->stream));
+    if (c->team) {
+        // every (row, column)'s reward w[obj[r][0]] rew[r][0] + w[obj[r][1]] rew[r][1]
+        const int64_t R = c->hm.state_row.back();
+        bool moved = c->d_team_w.ensure((size_t)K * d * 8);
+        moved |= c->d_rewk64.ensure((size_t)R * Kp * 8 + 8);
+        moved |= c->d_rewk32.ensure((size_t)R * Kp * 4 + 8);
+        if (moved) ++c->buf_gen;
+        MORAP_HIP(hipMemcpyAsync(c->d_team_w.p, W, (size_t)K * d * 8, hipMemcpyHostToDevice, c->stream));
+        k::team_rewards(c->stream, R, K, Kp, d, c->d_team_w.as<double>(), c->d_obj.as<int32_t>(),
+                        c->d_rew64.as<double>(), c->d_rewk64.as<double>(), c->d_rewk32.as<float>());
+    }
     if (warm_ok) {
         c->d_warm_map.ensure((size_t)K * 4);
         c->d_warm_ab.ensure(warm_ab.size() * 4);
@@ -665,6 +740,12 @@ static k::InstArgs inst_args(morap_ctx* c, int n_tiles, int n_inst) {
     a.to_done = c->d_to_done.as<uint8_t>();
     a.init = c->d_init.as<int32_t>();
     a.cus = c->prop.multiProcessorCount;
+    if (c->team) {
+        a.rewk = c->d_rewk64.as<double>();
+        a.rewk_ld = c->Kp;
+        a.row_obj = c->d_obj.as<int32_t>();
+        a.inst_obj = c->d_inst_obj.as<int32_t>();
+    }
     return a;
 }
 
@@ -675,10 +756,18 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
                           Stats& st) {
     MORAP_CHECK(c->solved, MORAP_E_STATE, "morap_evaluate needs a morap_solve first");
     MORAP_CHECK(K == c->K, MORAP_E_INVALID, "K differs from the last morap_solve");
-    MORAP_CHECK(assign != nullptr, MORAP_E_INVALID, "assign is NULL");
+    MORAP_CHECK(assign != nullptr || c->team, MORAP_E_INVALID, "assign is NULL");
     MORAP_CHECK(o.eps_eval > 0 && o.eps_vi > 0 && o.tau >= 0, MORAP_E_INVALID, "bad tolerances");
-    const int nI = c->hm.nI, nJ = c->hm.nJ, d = nI + nJ;
-    const int cap = std::max(1, (nJ + nI - 1) / nI);
+    const bool team = c->team;
+    const int nI = c->hm.nI, nJ = team ? (n_obj_of(c) + 1) / 2 : c->hm.nJ, d = team ? n_obj_of(c) : nI + nJ;
+    // A team model has one policy per column; its instances (one per pair of
+    // objectives, nJ per column) evaluate that policy's objectives 2p, 2p+1.
+    std::vector<int32_t> team_assign;
+    if (team) {
+        team_assign.assign((size_t)K * nJ, 0);
+        assign = team_assign.data();
+    }
+    const int cap = team ? nJ : std::max(1, (nJ + nI - 1) / nI);
     for (int kk = 0; kk < K; ++kk) {
         std::vector<int> load(nI, 0);
         for (int j = 0; j < nJ; ++j) {
@@ -703,7 +792,7 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
         for (int j = 0; j < nJ; ++j) {
             const int q = kk * nJ + j;
             const int i = assign[q];
-            const int m = i * nJ + j;
+            const int m = team ? 0 : i * nJ + j;
             c->inst_k[q] = kk;
             c->inst_m[q] = m;
             const int S_m = c->hm.state_base[m + 1] - c->hm.state_base[m];
@@ -712,8 +801,8 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
                 tiles.push_back(q);
                 tiles.push_back(b);
             }
-            iwc[q] = c->W[(size_t)kk * d + i];
-            iwp[q] = c->W[(size_t)kk * d + nI + j];
+            iwc[q] = team ? 1.0 : c->W[(size_t)kk * d + i];
+            iwp[q] = team ? 0.0 : c->W[(size_t)kk * d + nI + j];
             const double sc = iwc[q] + iwp[q];   // policies come from the weights scaled to sum 1
             if (sc > 0) {
                 iwc[q] /= sc;
@@ -751,6 +840,17 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
     MORAP_HIP(hipMemcpyAsync(c->d_iwp.p, iwp.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
     MORAP_HIP(hipMemcpyAsync(c->d_iscale.p, iscale.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
     MORAP_HIP(hipMemcpyAsync(c->d_init_idx.p, init_idx.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+    std::vector<int32_t> iobj;
+    if (team) {
+        iobj.resize((size_t)2 * n);
+        for (int q = 0; q < n; ++q) {
+            const int p = q % nJ;
+            iobj[2 * q] = 2 * p;
+            iobj[2 * q + 1] = 2 * p + 1 < d ? 2 * p + 1 : -1;
+        }
+        c->d_inst_obj.ensure((size_t)2 * n * 4);
+        MORAP_HIP(hipMemcpyAsync(c->d_inst_obj.p, iobj.data(), iobj.size() * 4, hipMemcpyHostToDevice, s));
+    }
     const k::InstArgs a = inst_args(c, n_tiles, n);
     int64_t* dctr = c->d_counters.as<int64_t>();
     int64_t* h = c->h_counters.as<int64_t>();
@@ -860,8 +960,8 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
         std::vector<double> wc((size_t)M * Kp, 0.0), wp((size_t)M * Kp, 0.0);
         for (int kk = 0; kk < K; ++kk)
             for (int m = 0; m < M; ++m) {
-                const int i = m / nJ, j = m % nJ;
-                double a0 = c->W[(size_t)kk * d + i], a1 = c->W[(size_t)kk * d + nI + j];
+                const int i = m / c->hm.nJ, j = m % c->hm.nJ;
+                double a0 = team ? 1.0 : c->W[(size_t)kk * d + i], a1 = team ? 0.0 : c->W[(size_t)kk * d + nI + j];
                 const double sc = a0 + a1;
                 if (sc > 0) {
                     a0 /= sc;
@@ -999,6 +1099,11 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
         for (int kk = 0; kk < K; ++kk)
             for (int j = 0; j < nJ; ++j) {
                 const int q = kk * nJ + j;
+                if (team) {
+                    r_out[(size_t)kk * d + 2 * j] = vals[2 * q];
+                    if (2 * j + 1 < d) r_out[(size_t)kk * d + 2 * j + 1] = vals[2 * q + 1];
+                    continue;
+                }
                 r_out[(size_t)kk * d + nI + j] = vals[2 * q + 1];
                 r_out[(size_t)kk * d + assign[q]] += vals[2 * q];
             }

@@ -1,6 +1,8 @@
 // The team MDP of the decentralised model (Sec. 3.1, Def. teamMDP) for n
-// agents and n tasks, built on the host and scalarised for one weight vector
-// so that the device's CSR sweep can solve it as a single-objective model.
+// agents and n tasks, built on the host: scalarised for one weight vector (a
+// single-objective model for the device's CSR sweep), or with its d = 2n
+// objectives (the two rewards of every row and the objective each belongs
+// to) for the team mode of the library.
 //
 // A state is (agent i, task j, agent state s, task location q, committed set
 // U), numbered with U fastest, then q, s, j, i.  Rows, in this order:
@@ -22,15 +24,21 @@
 
 namespace morap {
 
-void team_model_host(const morap_agent* agents, int n_agents, const morap_dfa* tasks, int n_tasks,
-                     const int32_t* const* letters, const double* w, int32_t* sizes, int32_t* state_row,
-                     int32_t* row_ptr, int32_t* col, double* prob, double* rew, uint8_t* to_done) {
+// The team MDP with the two rewards of every row and the objective each one
+// belongs to: rew[r] = (-cost, mass entering acceptance), obj[r] = (i, n + j)
+// for agent i acting on task j (switch and empty rows: rewards 0, objectives
+// (0, n)).  w (nullable) scalarises instead: rew[r] = (w . objective vector, 0).
+static void team_build(const morap_agent* agents, int n_agents, const morap_dfa* tasks, int n_tasks,
+                       const int32_t* const* letters, const double* w, int32_t* sizes, int32_t* state_row,
+                       int32_t* row_ptr, int32_t* col, double* prob, double* rew, int32_t* obj,
+                       uint8_t* to_done) {
     const int n = n_agents;
-    MORAP_CHECK(agents && tasks && letters && w && sizes && n >= 1 && n <= 16 && n_tasks == n, MORAP_E_INVALID,
+    MORAP_CHECK(agents && tasks && letters && sizes && n >= 1 && n <= 16 && n_tasks == n, MORAP_E_INVALID,
                 "bad arguments (1 <= agents = tasks <= 16)");
     for (int i = 0; i < n; ++i) check_agent(agents[i], i);
     for (int j = 0; j < n; ++j) check_dfa(tasks[j], j);
-    for (int q = 0; q < 2 * n; ++q) MORAP_CHECK(std::isfinite(w[q]), MORAP_E_INVALID, "non-finite weight");
+    if (w)
+        for (int q = 0; q < 2 * n; ++q) MORAP_CHECK(std::isfinite(w[q]), MORAP_E_INVALID, "non-finite weight");
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) {
             const int32_t* l = letters[(size_t)i * n + j];
@@ -51,16 +59,21 @@ void team_model_host(const morap_agent* agents, int n_agents, const morap_dfa* t
     std::vector<std::vector<uint8_t>> done(n);
     for (int j = 0; j < n; ++j) done[j] = dfa_done(tasks[j]);
 
-    std::vector<int32_t> sr{0}, rp{0}, cl;
+    std::vector<int32_t> sr{0}, rp{0}, cl, ob;
     std::vector<double> pr, rw;
-    auto end_row = [&](double r) {
+    // a row with cost reward rc for agent oc and probability reward rq for
+    // objective oq
+    auto end_row = [&](double rc, double rq, int32_t oc, int32_t oq) {
         rp.push_back((int32_t)cl.size());
-        rw.push_back(r);
+        rw.push_back(rc);
+        rw.push_back(rq);
+        ob.push_back(oc);
+        ob.push_back(oq);
     };
     auto jump = [&](int32_t target) {
         cl.push_back(target);
         pr.push_back(1.0);
-        end_row(0.0);
+        end_row(0.0, 0.0, 0, n);
     };
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) {
@@ -85,7 +98,7 @@ void team_model_host(const morap_agent* agents, int n_agents, const morap_dfa* t
                                     cl.push_back(id(i, j, s2, q2, used));
                                     pr.push_back(ag.prob[e]);
                                 }
-                                end_row(-ag.cost[r] * w[i] + mass * w[n + j]);
+                                end_row(-ag.cost[r], mass, i, n + j);
                             }
                         }
                         if (s == ag.init && q == tk.q0 && !mine) {
@@ -99,7 +112,7 @@ void team_model_host(const morap_agent* agents, int n_agents, const morap_dfa* t
                             while (k < n && ((used >> k) & 1)) ++k;
                             if (k < n) jump(id(k, j + 1, agents[k].init, tasks[j + 1].q0, used)); // b3
                         }
-                        if (rp.size() == rows_before) end_row(0.0);
+                        if (rp.size() == rows_before) end_row(0.0, 0.0, 0, n);
                         sr.push_back((int32_t)rp.size() - 1);
                     }
         }
@@ -115,15 +128,38 @@ void team_model_host(const morap_agent* agents, int n_agents, const morap_dfa* t
     if (prob) std::copy(pr.begin(), pr.end(), prob);
     if (rew)
         for (int32_t r = 0; r < R; ++r) {
-            rew[2 * (size_t)r] = rw[r];
-            rew[2 * (size_t)r + 1] = 0.0;
+            if (w) {
+                // the objective vector of the row, dotted with w
+                rew[2 * (size_t)r] = w[ob[2 * (size_t)r]] * rw[2 * (size_t)r] +
+                                     w[ob[2 * (size_t)r + 1]] * rw[2 * (size_t)r + 1];
+                rew[2 * (size_t)r + 1] = 0.0;
+            } else {
+                rew[2 * (size_t)r] = rw[2 * (size_t)r];
+                rew[2 * (size_t)r + 1] = rw[2 * (size_t)r + 1];
+            }
         }
+    if (obj) std::copy(ob.begin(), ob.end(), obj);
     if (to_done)
         for (int32_t r = 0; r < R; ++r) {
             double sum = 0.0;
             for (int32_t e = rp[r]; e < rp[r + 1]; ++e) sum += pr[e];
             to_done[r] = sum < 1.0 - 1e-12 ? 1 : 0;
         }
+}
+
+void team_model_host(const morap_agent* agents, int n_agents, const morap_dfa* tasks, int n_tasks,
+                     const int32_t* const* letters, const double* w, int32_t* sizes, int32_t* state_row,
+                     int32_t* row_ptr, int32_t* col, double* prob, double* rew, uint8_t* to_done) {
+    MORAP_CHECK(w, MORAP_E_INVALID, "NULL weights");
+    team_build(agents, n_agents, tasks, n_tasks, letters, w, sizes, state_row, row_ptr, col, prob, rew, nullptr,
+               to_done);
+}
+
+void team_model_mo_host(const morap_agent* agents, int n_agents, const morap_dfa* tasks, int n_tasks,
+                        const int32_t* const* letters, int32_t* sizes, int32_t* state_row, int32_t* row_ptr,
+                        int32_t* col, double* prob, double* rew, int32_t* obj, uint8_t* to_done) {
+    team_build(agents, n_agents, tasks, n_tasks, letters, nullptr, sizes, state_row, row_ptr, col, prob, rew, obj,
+               to_done);
 }
 
 }  // namespace morap

@@ -129,7 +129,10 @@ bellman_sweep(const Tile* __restrict__ tiles, const int32_t* __restrict__ tile_b
               const uint8_t* __restrict__ active_all,
               const T* __restrict__ x_in, T* __restrict__ x_out,
               unsigned long long* __restrict__ res_all, unsigned long long* __restrict__ ymax_all,
-              int Kp) {
+              int Kp, const T* __restrict__ rewk) {
+    // rewk (nullable): the scalarised reward of every (row, column), [R][Kp]
+    // (team models, whose rows carry their own objectives), replacing
+    // wc rew.x + wp rew.y
     constexpr int KT = CPL * LPS;          // columns per k-tile
     constexpr int G = WG / LPS;            // states processed at once
     constexpr int NW = WG / 64;            // waves
@@ -228,7 +231,9 @@ bellman_sweep(const Tile* __restrict__ tiles, const int32_t* __restrict__ tile_b
                     if (l_rptr[r] == l_rptr[r + 1]) {
                         const T2 rw = l_rew[r];
 #pragma unroll
-                        for (int c = 0; c < CPL; ++c) best[c] = fmax(best[c], wc[c] * rw.x + wp[c] * rw.y);
+                        for (int c = 0; c < CPL; ++c)
+                            best[c] = fmax(best[c], rewk ? rewk[(int64_t)(r0 + r) * Kp + kc + c]
+                                                         : wc[c] * rw.x + wp[c] * rw.y);
                     }
                 }
                 const int le0 = l_rptr[lr0], le1 = l_rptr[lr1];
@@ -265,7 +270,9 @@ bellman_sweep(const Tile* __restrict__ tiles, const int32_t* __restrict__ tile_b
                                 cur = rr[u];
                                 const T2 rw = l_rew[cur];
 #pragma unroll
-                                for (int c = 0; c < CPL; ++c) acc[c] = wc[c] * rw.x + wp[c] * rw.y;
+                                for (int c = 0; c < CPL; ++c)
+                                    acc[c] = rewk ? rewk[(int64_t)(r0 + cur) * Kp + kc + c]
+                                                  : wc[c] * rw.x + wp[c] * rw.y;
                             }
 #pragma unroll
                             for (int c = 0; c < CPL; ++c) acc[c] = fma(pp[u], xv[u].v[c], acc[c]);
@@ -302,7 +309,8 @@ static void launch_sweep(hipStream_t s, int grid, int ktiles, const SweepArgs& a
     hipLaunchKernelGGL((bellman_sweep<T, T2, CPL, LPS, WG>), dim3(grid, ktiles), dim3(WG), 0, s,
                        a.tiles, a.tile_base, a.act_models, a.act_prefix, a.counters, a.state_row,
                        a.row_ptr, a.col, (const T*)a.prob, (const T2*)a.rew, (const T*)a.wc,
-                       (const T*)a.wp, a.active, (const T*)a.x_in, (T*)a.x_out, a.res, a.ymax, a.Kp);
+                       (const T*)a.wp, a.active, (const T*)a.x_in, (T*)a.x_out, a.res, a.ymax, a.Kp,
+                       (const T*)a.rewk);
 }
 
 template <class T, class T2>
@@ -343,13 +351,101 @@ void sweep(hipStream_t s, int prec, const Variant& v, int grid, int ktiles, cons
 }
 
 // ---------------------------------------------------------------------------
+// team models: the scalarised reward of every (row, column) from the row's
+// own objectives, out[r][k] = W[k][obj[r][0]] rew[r][0] + W[k][obj[r][1]]
+// rew[r][1] for k < K, 0 for the padding columns
+// ---------------------------------------------------------------------------
+__global__ void team_rewards_kernel(int64_t R, int K, int Kp, int d, const double* __restrict__ W,
+                                    const int32_t* __restrict__ obj, const double* __restrict__ rew,
+                                    double* __restrict__ out64, float* __restrict__ out32) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= R * Kp) return;
+    const int64_t r = i / Kp;
+    const int k = (int)(i % Kp);
+    double v = 0.0;
+    if (k < K) v = W[(int64_t)k * d + obj[2 * r]] * rew[2 * r] + W[(int64_t)k * d + obj[2 * r + 1]] * rew[2 * r + 1];
+    out64[i] = v;
+    out32[i] = (float)v;
+}
+
+__global__ void team_eval_kernel(int64_t S, int d, const int32_t* __restrict__ pi, const int32_t* __restrict__ row_ptr,
+                                 const int32_t* __restrict__ col, const double* __restrict__ prob,
+                                 const double* __restrict__ rew, const int32_t* __restrict__ obj,
+                                 const double* __restrict__ E_in, double* __restrict__ E_out,
+                                 unsigned long long* __restrict__ res) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double change = 0.0;
+    if (i < S * d) {
+        const int64_t s = i / d;
+        const int o = (int)(i % d);
+        const int row = pi[s];
+        double v = (obj[2 * row] == o ? rew[2 * row] : 0.0) + (obj[2 * row + 1] == o ? rew[2 * row + 1] : 0.0);
+        for (int e = row_ptr[row]; e < row_ptr[row + 1]; ++e) v = fma(prob[e], E_in[(int64_t)col[e] * d + o], v);
+        E_out[i] = v;
+        change = fabs(v - E_in[i]);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) change = fmax(change, __shfl_xor(change, off, 64));
+    if (res && (threadIdx.x & 63) == 0 && change > 0.0)
+        atomicMax(res, (unsigned long long)__double_as_longlong(change));
+}
+
+void team_eval_sweep(hipStream_t s, int64_t S, int d, const int32_t* pi, const int32_t* row_ptr, const int32_t* col,
+                     const double* prob, const double* rew, const int32_t* obj, const double* E_in, double* E_out,
+                     unsigned long long* res) {
+    const int64_t n = S * d;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(team_eval_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, S, d, pi, row_ptr, col,
+                       prob, rew, obj, E_in, E_out, res);
+    MORAP_HIP(hipGetLastError());
+}
+
+// The start lies below the optimum over proper policies (the fixed policy is
+// one); the margin covers the evaluation's stop and rounding.
+template <class T>
+__global__ void team_start_kernel(int64_t S, int K, int Kp, int d, const double* __restrict__ W,
+                                  const double* __restrict__ E, T* __restrict__ x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S * Kp) return;
+    const int64_t s = i / Kp;
+    const int k = (int)(i % Kp);
+    double v = 0.0;
+    if (k < K) {
+        for (int o = 0; o < d; ++o) v = fma(W[(int64_t)k * d + o], E[s * d + o], v);
+        v -= 1e-9 * (1.0 + fabs(v));
+    }
+    x[i] = (T)v;
+}
+
+void team_start(hipStream_t s, int64_t S, int K, int Kp, int d, const double* W, const double* E, int prec, void* x) {
+    const int64_t n = S * Kp;
+    if (n <= 0) return;
+    const dim3 g((unsigned)((n + 255) / 256));
+    if (prec == MORAP_F32)
+        hipLaunchKernelGGL(team_start_kernel<float>, g, dim3(256), 0, s, S, K, Kp, d, W, E, (float*)x);
+    else
+        hipLaunchKernelGGL(team_start_kernel<double>, g, dim3(256), 0, s, S, K, Kp, d, W, E, (double*)x);
+    MORAP_HIP(hipGetLastError());
+}
+
+void team_rewards(hipStream_t s, int64_t R, int K, int Kp, int d, const double* W, const int32_t* obj,
+                  const double* rew, double* out64, float* out32) {
+    const int64_t n = R * Kp;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(team_rewards_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, R, K, Kp, d, W, obj,
+                       rew, out64, out32);
+    MORAP_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
 // convergence of (model, column) pairs and compaction of the active tiles
 // ---------------------------------------------------------------------------
 // Threads stride over the (model, column) pairs of the models active in the
 // sweep just done.  counters: [0] active pairs (accumulating), [1] active
 // tiles, [2] active models, [3] active pairs after the last sweep, [4]
 // backups done, [5] sweeps done, [6] CSR bytes streamed, [7] state-columns
-// updated (each one value read and one written).  The three sums are reduced
+// updated (each one value read and one written), [8] pairs stopped at the
+// FP32 rounding floor.  The three sums are reduced
 // in the workgroup and added with one atomic each: thousands of atomics on
 // the same counters would serialise in L2.
 constexpr int kConvergeBlocks = 256;
@@ -367,7 +463,23 @@ __global__ void __launch_bounds__(256) converge_kernel(ConvergeArgs a) {
             const double r = __longlong_as_double((long long)a.res[i]);
             const double y = __longlong_as_double((long long)a.ymax[i]);
             const double tol = fmax(a.eps, a.unit * y);
-            if (r <= tol) {
+            // Jacobi sweeps in FP32 can settle into a cycle: the values of
+            // alternate sweeps form two chains (a state's new value reads its
+            // neighbours' old ones) that can come to rest on two different
+            // fixed points of the rounded backup, as far apart as a rounding
+            // error amplified by the expected number of visits.  The change
+            // then stays constant; such a pair stops at that floor.
+            bool floor_stop = false;
+            if (a.stall_sweeps > 0 && r > tol) {
+                if (r < a.best_res[i]) {
+                    a.best_res[i] = r;
+                    a.stall[i] = 0;
+                } else if (++a.stall[i] >= a.stall_sweeps && r <= a.floor * y) {
+                    floor_stop = true;
+                    atomicAdd((unsigned long long*)&a.counters[8], 1ull);
+                }
+            }
+            if (r <= tol || floor_stop) {
                 a.active[i] = 0;
                 a.final_par[i] = (uint8_t)a.out_par;
                 a.pair_sweeps[i] = next_sweep;
@@ -502,11 +614,13 @@ __global__ void init_solve_kernel(ConvergeArgs a) {
         a.pair_sweeps[i] = 0;
         a.res[i] = 0ull;
         a.ymax[i] = 0ull;
+        a.best_res[i] = INFINITY;
+        a.stall[i] = 0;
         if (on) a.model_active[m] = 1;
         if (k < a.K) a.c[(int64_t)k * a.M + m] = 0.0;
     }
     // the compaction that follows counts as no sweep: start the counter at -1
-    if (i < 8) a.counters[i] = (i == 5) ? -1 : 0;
+    if (i < 9) a.counters[i] = (i == 5) ? -1 : 0;
 }
 
 void init_solve(hipStream_t s, const ConvergeArgs& a) {
@@ -683,17 +797,23 @@ __global__ void __launch_bounds__(256) opt_mask_kernel(InstArgs a, const double*
     const int64_t ib = a.inst_base[L.inst];
     const double w0 = wc[L.inst], w1 = wp[L.inst];
     const int rb = a.state_row[L.gs], re = a.state_row[L.gs + 1];
+    const int kk = a.inst_k[L.inst];
+    // a row's scalarised reward: the instance's two weights, or for a team
+    // model the row's own objectives (rewk)
+    auto reward = [&](int row) {
+        return a.rewk ? a.rewk[(int64_t)row * a.rewk_ld + kk] : w0 * a.rew[2 * row] + w1 * a.rew[2 * row + 1];
+    };
     // two passes (max, then the tolerance test) keep Q out of scratch memory
     double qmax = -INFINITY;
     for (int row = rb; row < re; ++row) {
-        double acc = w0 * a.rew[2 * row] + w1 * a.rew[2 * row + 1];
+        double acc = reward(row);
         for (int e = a.row_ptr[row]; e < a.row_ptr[row + 1]; ++e)
             acc = fma(a.prob[e], x[ib + (a.col[e] - L.sb)], acc);
         qmax = fmax(qmax, acc);
     }
     uint32_t bits = 0;
     for (int row = rb; row < re; ++row) {
-        double acc = w0 * a.rew[2 * row] + w1 * a.rew[2 * row + 1];
+        double acc = reward(row);
         for (int e = a.row_ptr[row]; e < a.row_ptr[row + 1]; ++e)
             acc = fma(a.prob[e], x[ib + (a.col[e] - L.sb)], acc);
         if (acc >= qmax - tau) bits |= 1u << (row - rb);
@@ -875,6 +995,16 @@ __global__ void __launch_bounds__(256) eval_kernel(InstArgs a, const int8_t* mu,
             const int64_t ib = a.inst_base[L.inst];
             const int row = a.state_row[L.gs] + mu[L.is];
             double c0 = a.rew[2 * row], c1 = a.rew[2 * row + 1];
+            if (a.row_obj) {
+                // team model: the instance evaluates objectives o0 and o1;
+                // each of the row's rewards counts for the objective it
+                // belongs to
+                const int o0 = a.inst_obj[2 * L.inst], o1 = a.inst_obj[2 * L.inst + 1];
+                const int oc = a.row_obj[2 * row], op = a.row_obj[2 * row + 1];
+                const double rc = a.rew[2 * row], rp = a.rew[2 * row + 1];
+                c0 = (oc == o0 ? rc : 0.0) + (op == o0 ? rp : 0.0);
+                c1 = (oc == o1 ? rc : 0.0) + (op == o1 ? rp : 0.0);
+            }
             for (int e = a.row_ptr[row]; e < a.row_ptr[row + 1]; ++e) {
                 const int64_t j = ib + (a.col[e] - L.sb);
                 const double2 v = reinterpret_cast<const double2*>(x_in)[j];

@@ -71,7 +71,7 @@ class ViOpts(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("backups", C.c_int64), ("sweeps", C.c_int64), ("max_pair_sweeps", C.c_int64),
                 ("eval_sweeps", C.c_int64), ("polish_sweeps", C.c_int64), ("rank_rounds", C.c_int64),
-                ("excluded", C.c_int64), ("bytes", C.c_double), ("ms_vi", C.c_double),
+                ("floor_stops", C.c_int64), ("bytes", C.c_double), ("ms_vi", C.c_double),
                 ("ms_eval", C.c_double), ("ms_total", C.c_double), ("ms_sweep_kernel", C.c_double),
                 ("sweep_launches", C.c_int64), ("bytes_refine", C.c_double),
                 ("ms_sweep_kernel_refine", C.c_double), ("sweep_launches_refine", C.c_int64),
@@ -123,6 +123,9 @@ _sig("morap_assign_host", C.c_int, _p, C.c_int, C.c_int, C.c_int, _p)
 _sig("morap_product_host", C.c_int, C.POINTER(Agent), C.POINTER(Dfa), _p, _p, _p, _p, _p, _p, _p, _p, _p)
 _sig("morap_team_model_host", C.c_int, C.POINTER(Agent), C.c_int, C.POINTER(Dfa), C.c_int, C.POINTER(_p), _p, _p,
      _p, _p, _p, _p, _p, _p)
+_sig("morap_team_model_mo_host", C.c_int, C.POINTER(Agent), C.c_int, C.POINTER(Dfa), C.c_int, C.POINTER(_p), _p,
+     _p, _p, _p, _p, _p, _p, _p)
+_sig("morap_load_team_model", C.c_int, _ctxp, C.c_int, C.c_int, C.POINTER(Model), _p)
 _sig("morap_support", C.c_int, _ctxp, _p, C.c_int, C.POINTER(ViOpts), _p, _p, _p, C.POINTER(Stats))
 _sig("morap_get_policy", C.c_int, _ctxp, C.c_int, C.c_int, _p)
 _sig("morap_get_stats", C.c_int, _ctxp, C.POINTER(Stats))
@@ -259,6 +262,45 @@ def team_model_host(workload, w) -> dict:
     return out
 
 
+def team_model_mo_host(workload) -> dict:
+    """The team MDP of ``workload`` (|I| = |J|) with its d = 2n objectives
+    (Def. teamMDP), for ``Context.load_team_model``: rew [R, 2] = (-cost,
+    acceptance mass) and obj [R, 2] the objective each belongs to."""
+    n = workload.n_agents
+    keep = []
+    agents = (Agent * n)()
+    for i, a in enumerate(workload.agents):
+        arrs = [_c(a.sa_ptr, np.int32), _c(a.succ, np.int32), _c(a.prob, np.float64), _c(a.cost, np.float64)]
+        keep += arrs
+        agents[i] = Agent(a.n_states, a.n_actions, a.init, *[_ptr(x) for x in arrs])
+    tasks = (Dfa * workload.n_tasks)()
+    for j, t in enumerate(workload.tasks):
+        arrs = [_c(t.delta, np.int32), _c(t.accepting, np.uint8)]
+        keep += arrs
+        tasks[j] = Dfa(t.n_locs, t.n_letters, t.q0, *[_ptr(x) for x in arrs])
+    nJ = workload.n_tasks
+    lets = (_p * (n * nJ))()
+    for i in range(n):
+        for j in range(nJ):
+            arr = _c(workload.letters[i][j], np.int32)
+            keep.append(arr)
+            lets[i * nJ + j] = arr.ctypes.data
+    sizes = np.zeros(4, np.int32)
+    rc = lib.morap_team_model_mo_host(agents, n, tasks, nJ, lets, _ptr(sizes), *([None] * 7))
+    if rc:
+        raise MorapError(rc, "team MDP construction failed")
+    S, R, N, init = (int(v) for v in sizes)
+    out = {"state_row": np.zeros(S + 1, np.int32), "row_ptr": np.zeros(R + 1, np.int32),
+           "col": np.zeros(N, np.int32), "prob": np.zeros(N), "rew": np.zeros((R, 2)),
+           "obj": np.zeros((R, 2), np.int32), "to_done": np.zeros(R, np.uint8), "init": init}
+    rc = lib.morap_team_model_mo_host(agents, n, tasks, nJ, lets, _ptr(sizes),
+                                      *[_ptr(out[k]) for k in ("state_row", "row_ptr", "col", "prob", "rew", "obj",
+                                                               "to_done")])
+    if rc:
+        raise MorapError(rc, "team MDP construction failed")
+    return out
+
+
 def assign_host(c):
     """Alg. 2's assignment on the host, no context: c [K, nI, nJ] -> the
     agent of each task, [K, nJ]."""
@@ -313,6 +355,7 @@ class Context:
             raise MorapError(rc, f"morap_create(device={device}) failed")
         self._h = h
         self.nI = self.nJ = 0
+        self.team = False
         self._keep = []
 
     # -- plumbing ----------------------------------------------------------
@@ -365,6 +408,7 @@ class Context:
                 lets[i * nJ + j] = arr.ctypes.data
         self._check(lib.morap_build_products(self._h, agents, nI, tasks, nJ, lets), "morap_build_products")
         self.nI, self.nJ = nI, nJ
+        self.team = False
 
     def load_models(self, models: Sequence[dict], n_agents: int, n_tasks: int):
         """models[m]: dict with state_row, row_ptr, col, prob, rew [R,2], to_done, init."""
@@ -379,6 +423,23 @@ class Context:
                            *[_ptr(x) for x in a])
         self._check(lib.morap_load_models(self._h, arr, len(models), n_agents, n_tasks), "morap_load_models")
         self.nI, self.nJ = n_agents, n_tasks
+        self.team = False
+
+    def load_team_model(self, model: dict, n_agents: int, n_tasks: int):
+        """A team MDP with its d = n_agents + n_tasks objectives (from
+        ``team_model_mo_host``): solve takes W [K, d] and returns c [K] (the
+        value at the initial state), support returns r [K, d]."""
+        a = [_c(model["state_row"], np.int32), _c(model["row_ptr"], np.int32), _c(model["col"], np.int32),
+             _c(model["prob"], np.float64), _c(model["rew"], np.float64), _c(model["to_done"], np.uint8)]
+        obj = _c(model["obj"], np.int32)
+        md = Model(0, 0, len(a[0]) - 1, len(a[1]) - 1, len(a[2]), int(model["init"]), *[_ptr(x) for x in a])
+        self._check(lib.morap_load_team_model(self._h, n_agents, n_tasks, C.byref(md), _ptr(obj)),
+                    "morap_load_team_model")
+        self.nI, self.nJ = n_agents, n_tasks
+        self.team = True
+
+    def _c_shape(self, K):
+        return (K,) if self.team else (K, self.nI, self.nJ)
 
     def model_info(self, m: int) -> dict:
         s = np.zeros(5, np.int32)
@@ -401,19 +462,21 @@ class Context:
     def solve(self, W, opts: Options = Options()):
         W = _c(np.atleast_2d(W), np.float64)
         K = W.shape[0]
-        c = np.zeros((K, self.nI, self.nJ))
+        c = np.zeros(self._c_shape(K))
         st = Stats()
         o = opts.to_c()
         self._check(lib.morap_solve(self._h, _ptr(W), K, C.byref(o), _ptr(c), C.byref(st)), "morap_solve")
         return c, st.as_dict()
 
-    def evaluate(self, assign, opts: Options = Options()):
-        A = _c(np.atleast_2d(assign), np.int32)
-        K = A.shape[0]
+    def evaluate(self, assign, opts: Options = Options(), K: int = None):
+        """assign [K, nJ]; on a team model None (give K)."""
+        A = None if assign is None else _c(np.atleast_2d(assign), np.int32)
+        K = A.shape[0] if A is not None else int(K)
         r = np.zeros((K, self.d))
         st = Stats()
         o = opts.to_c()
-        self._check(lib.morap_evaluate(self._h, _ptr(A), K, C.byref(o), _ptr(r), C.byref(st)), "morap_evaluate")
+        self._check(lib.morap_evaluate(self._h, _ptr(A) if A is not None else None, K, C.byref(o), _ptr(r),
+                                       C.byref(st)), "morap_evaluate")
         return r, st.as_dict()
 
     def assign(self, c):
@@ -427,7 +490,7 @@ class Context:
         K = W.shape[0]
         r = np.zeros((K, self.d))
         A = np.zeros((K, self.nJ), np.int32)
-        c = np.zeros((K, self.nI, self.nJ))
+        c = np.zeros(self._c_shape(K))
         st = Stats()
         o = opts.to_c()
         self._check(lib.morap_support(self._h, _ptr(W), K, C.byref(o), _ptr(r), _ptr(A), _ptr(c), C.byref(st)),

@@ -302,6 +302,37 @@ def test_host_team_model_equals_the_oracle(n, seed):
         assert y[g["init"]] == pytest.approx(centralised.team_value(team, w), abs=1e-10)
 
 
+@pytest.mark.parametrize("n,seed", [(2, 41), (3, 42), (2, 43)])
+def test_host_team_mo_model_equals_the_oracle(n, seed):
+    """The team MDP with its d = 2n objectives (one reward pair and its two
+    objective indices per row): the same states, rows, successors and
+    probabilities as the scalarised layout, and each row's objective vector,
+    spread out from (rew, obj), is the oracle's exactly (states without rows
+    get one empty row with the zero vector)."""
+    from paper_2305_04397_amd import morap
+    from workloads import tiny_workload
+    from oracle import centralised
+    kinds = ("reach",) if seed != 43 else ("avoid", "reach")
+    wl = tiny_workload(seed, n, n, width=3, height=2, kinds=kinds, k=1, p_slip=0.25)
+    team = centralised.build_team_mdp(wl)
+    d = 2 * n
+    g = morap.team_model_mo_host(wl)
+    o = centralised.single_objective_model(team, np.full(d, 1.0 / d))
+    for k in ("state_row", "row_ptr", "col", "to_done"):
+        assert g[k].tolist() == o[k].tolist(), k
+    assert np.array_equal(g["prob"], o["prob"]) and g["init"] == o["init"]
+    R = len(g["row_ptr"]) - 1
+    assert g["obj"].shape == (R, 2) and g["obj"].min() >= 0 and g["obj"].max() < d
+    spread = np.zeros((R, d))
+    np.add.at(spread, (np.arange(R), g["obj"][:, 0]), g["rew"][:, 0])
+    np.add.at(spread, (np.arange(R), g["obj"][:, 1]), g["rew"][:, 1])
+    want = []
+    for s in range(team.n_states):
+        lo, hi = team.state_row[s], team.state_row[s + 1]
+        want.extend(team.rew[lo:hi] if hi > lo else [np.zeros(d)])
+    assert np.array_equal(spread, np.array(want))
+
+
 def test_host_team_model_rejects_unequal_counts():
     from paper_2305_04397_amd import morap
     from workloads import tiny_workload

@@ -479,6 +479,51 @@ def test_centralised_optimum_equals_decentralised_assignment(n, seed):
         assert centralised.team_value(team, w) == pytest.approx(w @ s.r, abs=1e-8)
 
 
+def test_team_optimum_at_a_zero_task_weight_corner_is_improper():
+    """Where every task's weight and agent 1's cost weight are 0 (w = e_0),
+    the team MDP lets agent 1 take the first task and never finish it: its
+    optimum, 0, lies above the best assignment's (agent 0 must serve a task
+    there) and no proper policy attains it.  The equality of Lemma
+    lem:ct-mdp-prop is read for weights whose team optimum is proper."""
+    from oracle.product import Product
+    wl = tiny_workload(41, 2, 2, width=3, height=2, kinds=("reach",), k=1, p_slip=0.25)
+    prods = product.build_all(wl)
+    team = centralised.build_team_mdp(wl)
+    w = np.eye(4)[0]
+    assert centralised.team_value(team, w) == 0.0
+    assert w @ alg.support(prods, 2, 2, w, 1e-13).r < -1e-3
+    g = centralised.single_objective_model(team, w)
+    S, R = len(g["state_row"]) - 1, len(g["row_ptr"]) - 1
+    p = Product(n_states=S, states=np.zeros((S, 2), np.int64), state_row=g["state_row"].astype(np.int64),
+                row_action=np.zeros(R, np.int64), row_ptr=g["row_ptr"].astype(np.int64),
+                col=g["col"].astype(np.int64), prob=g["prob"], to_done=g["to_done"].astype(bool),
+                rew_cost=g["rew"][:, 0].copy(), rew_prob=np.zeros(R), init=g["init"])
+    x = vi.value_iteration(p, 1.0, 0.0, 1e-12)[0][:, 0]
+    with pytest.raises(vi.ImproperPolicy):
+        vi.extract_policy(p, x, 1.0, 0.0)
+    # the optimum over proper policies is the assignment's
+    assert centralised.team_value_proper(team, w) == pytest.approx(w @ alg.support(prods, 2, 2, w, 1e-13).r,
+                                                                   abs=1e-8)
+
+
+@pytest.mark.parametrize("n,seed", [(2, 41), (3, 42)])
+def test_proper_team_optimum_equals_the_assignment_optimum(n, seed):
+    """The proper optimum (least solution of the Bellman inequalities, a
+    linear programme) equals the value iteration optimum at interior weights
+    and the best assignment's everywhere, corners included (Lemma
+    lem:ct-mdp-prop)."""
+    wl = tiny_workload(seed, n, n, width=3, height=2, kinds=("reach",), k=1, p_slip=0.25)
+    prods = product.build_all(wl)
+    team = centralised.build_team_mdp(wl)
+    rng = np.random.default_rng(seed + 3)
+    d = 2 * n
+    for w in [rng.dirichlet(np.ones(d)) for _ in range(2)] + [np.eye(d)[0], np.eye(d)[n], np.eye(d)[d - 1]]:
+        best = w @ alg.support(prods, n, n, w, 1e-13).r
+        assert centralised.team_value_proper(team, w) == pytest.approx(best, abs=1e-7)
+        if w.min() > 0:
+            assert centralised.team_value(team, w) == pytest.approx(best, abs=1e-8)
+
+
 # --------------------------------------------------------------------------
 # textbook reductions
 # --------------------------------------------------------------------------
