@@ -14,54 +14,71 @@
 
 namespace morap {
 
-// Minimum-cost perfect matching of a square n x n matrix by shortest
-// augmenting paths with row / column potentials.  Returns match[row] = col.
+// Minimum-cost perfect matching of a square n x n matrix (Kuhn-Munkres in
+// its successive-shortest-path form).  Dual potentials u (rows) and v
+// (columns) keep every reduced cost c(i,j) - u(i) - v(j) >= 0 and those of
+// matched pairs at 0.  Each row in turn is matched by a Dijkstra search over
+// alternating paths (a column leads on to the row matched to it at reduced
+// cost 0) until a free column is reached at distance D; the potentials of
+// the columns settled on the way, and of their rows, move by D minus their
+// distance (which keeps the reduced costs >= 0 and zeroes them along the
+// path), and the path is flipped.  Returns col_of_row.
 static std::vector<int> min_cost_matching(const std::vector<double>& cost, int n) {
     const double INF = std::numeric_limits<double>::infinity();
-    std::vector<double> u(n + 1, 0.0), v(n + 1, 0.0);
-    std::vector<int> p(n + 1, 0), way(n + 1, 0);   // p[col] = row matched to col (1-based)
-    for (int i = 1; i <= n; ++i) {
-        p[0] = i;
-        int j0 = 0;
-        std::vector<double> minv(n + 1, INF);
-        std::vector<char> used(n + 1, 0);
-        do {
-            used[j0] = 1;
-            const int i0 = p[j0];
-            double delta = INF;
-            int j1 = 0;
-            for (int j = 1; j <= n; ++j) {
-                if (used[j]) continue;
-                const double cur = cost[(size_t)(i0 - 1) * n + (j - 1)] - u[i0] - v[j];
-                if (cur < minv[j]) {
-                    minv[j] = cur;
-                    way[j] = j0;
+    std::vector<double> u(n, 0.0), v(n, 0.0), dist(n);
+    std::vector<int> row_of_col(n, -1), col_of_row(n, -1), pred_row(n), settled;
+    std::vector<char> done(n);
+    settled.reserve(n);
+    auto reduced = [&](int i, int j) { return cost[(size_t)i * n + j] - u[i] - v[j]; };
+    for (int r = 0; r < n; ++r) {
+        for (int j = 0; j < n; ++j) {
+            dist[j] = reduced(r, j);
+            pred_row[j] = r;
+            done[j] = 0;
+        }
+        settled.clear();
+        int sink = -1;
+        while (sink < 0) {
+            int j = -1;
+            double best = INF;
+            for (int k = 0; k < n; ++k)
+                if (!done[k] && (j < 0 || dist[k] < best)) {
+                    best = dist[k];
+                    j = k;
                 }
-                if (minv[j] < delta) {
-                    delta = minv[j];
-                    j1 = j;
+            done[j] = 1;
+            if (row_of_col[j] < 0) {
+                sink = j;
+                break;
+            }
+            settled.push_back(j);
+            const int i = row_of_col[j];
+            for (int k = 0; k < n; ++k) {
+                if (done[k]) continue;
+                const double via = dist[j] + reduced(i, k);
+                if (via < dist[k]) {
+                    dist[k] = via;
+                    pred_row[k] = i;
                 }
             }
-            for (int j = 0; j <= n; ++j) {
-                if (used[j]) {
-                    u[p[j]] += delta;
-                    v[j] -= delta;
-                } else {
-                    minv[j] -= delta;
-                }
-            }
-            j0 = j1;
-        } while (p[j0] != 0);
-        do {
-            const int j1 = way[j0];
-            p[j0] = p[j1];
-            j0 = j1;
-        } while (j0);
+        }
+        const double D = dist[sink];
+        for (int j : settled) {
+            const double shift = D - dist[j];
+            v[j] -= shift;
+            u[row_of_col[j]] += shift;
+        }
+        u[r] += D;
+        for (int k = sink;;) {
+            const int i = pred_row[k];
+            const int prev = col_of_row[i];
+            row_of_col[k] = i;
+            col_of_row[i] = k;
+            if (i == r) break;
+            k = prev;
+        }
     }
-    std::vector<int> match(n, -1);
-    for (int j = 1; j <= n; ++j)
-        if (p[j] > 0) match[p[j] - 1] = j - 1;
-    return match;
+    return col_of_row;
 }
 
 void assign_columns(int nI, int nJ, const double* c, int K, int32_t* out) {

@@ -470,17 +470,14 @@ def test_timed_solves_match_untimed(ctx, morap):
     assert s2["sweep_launches_refine"] > 0 and s2["ms_sweep_kernel_refine"] > 0
 
 
-def _team_model(team, w):
-    return centralised.single_objective_model(team, w)
-
-
 @pytest.mark.parametrize("n,seed", [(2, 41), (3, 42)])
 def test_team_mdp_on_the_device(ctx, morap, n, seed):
-    """The team MDP of Def. teamMDP (the centralised model), scalarised for
-    one weight vector and loaded as a caller-built model, solved by the
-    device's CSR sweep: its value at the joint initial state is the oracle's,
-    and the best assignment's that the device's own Alg. 2 finds on the
-    decentralised products (Lemma lem:ct-mdp-prop)."""
+    """The team MDP of Def. teamMDP (the centralised model), built by the
+    library's own builder scalarised for one weight vector and loaded as a
+    caller-built model, solved by the device's CSR sweep: its value at the
+    joint initial state is the oracle's, and the best assignment's that the
+    device's own Alg. 2 finds on the decentralised products (Lemma
+    lem:ct-mdp-prop; interior weights, where the optimum is proper)."""
     wl = tiny_workload(seed, n, n, width=3, height=2, kinds=("reach",), k=1, p_slip=0.25)
     team = centralised.build_team_mdp(wl)
     o = morap.Options(eps_vi=1e-12, precision="f64")
@@ -489,7 +486,7 @@ def test_team_mdp_on_the_device(ctx, morap, n, seed):
         w = rng.dirichlet(np.ones(2 * n))
         ctx.build_products(wl)
         r, _, _, _ = ctx.support(w[None, :], o)
-        ctx.load_models([_team_model(team, w)], 1, 1)
+        ctx.load_models([morap.team_model_host(wl, w)], 1, 1)
         cv, st = ctx.solve(np.array([[1.0, 0.0]]), o)
         assert st["variant"] <= 18
         assert cv[0, 0, 0] == pytest.approx(centralised.team_value(team, w), abs=1e-9)
