@@ -76,7 +76,11 @@ bellman_block(const Tile* __restrict__ tiles,
     // tiles than waves
     const int n_tiles = (int)counters[1];
     const int n_waves = gridDim.x * NW;
-    const int sub = n_tiles * 4 <= n_waves ? 4 : (n_tiles * 2 <= n_waves ? 2 : 1);
+    // few active tiles (the last large models of a solve): cut each tile into
+    // up to 16 units so that every wave has few states in sequence -- the
+    // launch then takes about one round of gather latency per U states
+    int sub = 1;
+    while (sub < 16 && n_tiles * sub * 2 <= n_waves) sub *= 2;
     const int n_units = n_tiles * sub;
     // XCD x takes the units [xb, xe); its waves take every count-th unit of
     // it, so neighbouring units (which share successor rows) are in flight
@@ -222,7 +226,7 @@ bellman_block(const Tile* __restrict__ tiles,
                 for (int c = 0; c < CPL; ++c) {
                     if (act[c]) {
                         x_out[o + c] = best[c];
-                        res[c] = fmax(res[c], fabs((double)best[c] - (double)old.v[c]));
+                        res[c] = fmax(res[c], (double)fabs(best[c] - old.v[c]));
                         if (want_ymax) ym[c] = fmax(ym[c], fabs((double)best[c]));
                     }
                 }
@@ -264,7 +268,11 @@ bellman_block_wave(const Tile* __restrict__ tiles,
 
     const int n_tiles = (int)counters[1];
     const int n_waves = gridDim.x * NW;
-    const int sub = n_tiles * 4 <= n_waves ? 4 : (n_tiles * 2 <= n_waves ? 2 : 1);
+    // few active tiles (the last large models of a solve): cut each tile into
+    // up to 16 units so that every wave has few states in sequence -- the
+    // launch then takes about one round of gather latency per U states
+    int sub = 1;
+    while (sub < 16 && n_tiles * sub * 2 <= n_waves) sub *= 2;
     const int n_units = n_tiles * sub;
     // XCD x takes the units [xb, xe); its waves take every count-th unit of
     // it, so neighbouring units (which share successor rows) are in flight
@@ -300,12 +308,14 @@ bellman_block_wave(const Tile* __restrict__ tiles,
     int cur_m = -1;
     bool on = false, act = false;
     T wc = 0, wp = 0;
-    double res = 0.0, ym = 0.0;
+    // the change |y - x| in T: for FP32 exact whenever y and x are within a
+    // factor of two of each other (Sterbenz), as near the stop test
+    T res = 0, ym = 0;
     auto flush = [&](int m) {
         const int64_t idx = (int64_t)m * Kp + kc;
-        max_flush(&res_all[idx], res);
-        if (want_ymax) max_flush(&ymax_all[idx], ym);
-        res = ym = 0.0;
+        max_flush(&res_all[idx], (double)res);
+        if (want_ymax) max_flush(&ymax_all[idx], (double)ym);
+        res = ym = 0;
     };
 
     UnitDesc nd = describe(u_begin);
@@ -403,8 +413,8 @@ bellman_block_wave(const Tile* __restrict__ tiles,
                 if (act) {
                     // the new values are read only by the next sweep: stream them out
                     __builtin_nontemporal_store(best, (x_out + (int64_t)gs[q] * Kp) + kc);
-                    res = fmax(res, fabs((double)best - (double)old));
-                    if (want_ymax) ym = fmax(ym, fabs((double)best));
+                    res = fmax(res, fabs(best - old));
+                    if (want_ymax) ym = fmax(ym, fabs(best));
                 }
             }
         }

@@ -87,13 +87,14 @@ bellman_halo(const HTile* __restrict__ tiles, const int32_t* __restrict__ act_ti
     int cur_m = -1;
     bool act = false;
     float wc = 0.f, wp = 0.f;
-    double res = 0.0;
-    float ym = 0.f;
+    // the change |y - x| in FP32: exact whenever y and x are within a factor
+    // of two of each other (Sterbenz), as near the stop test
+    float res = 0.f, ym = 0.f;
     auto flush = [&](int m) {
         const int64_t idx = (int64_t)m * Kp + kc;
-        max_flush(&res_all[idx], res);
+        max_flush(&res_all[idx], (double)res);
         max_flush(&ymax_all[idx], (double)ym);
-        res = 0.0;
+        res = 0.f;
         ym = 0.f;
     };
 
@@ -111,14 +112,19 @@ bellman_halo(const HTile* __restrict__ tiles, const int32_t* __restrict__ act_ti
         rec = hrec[dd.rec_begin + p];
         gsv = hl[p];
     };
-    HTile d = tiles[act_tiles[t]];
+    // tile descriptors are wave-uniform: keep them in scalar registers
+    auto uniform = [](const HTile& h) {
+        return HTile{__builtin_amdgcn_readfirstlane(h.model), __builtin_amdgcn_readfirstlane(h.rec_begin),
+                     __builtin_amdgcn_readfirstlane(h.n), __builtin_amdgcn_readfirstlane(h.halo_begin)};
+    };
+    HTile d = uniform(tiles[act_tiles[t]]);
     int g[ROUNDS];
     uint2 rec;
     int gsv;
     fetch(d, g, rec, gsv);
     while (true) {
         const int tn = t + step;
-        const HTile dn = tiles[act_tiles[tn < xe ? tn : t]];
+        const HTile dn = uniform(tiles[act_tiles[tn < xe ? tn : t]]);
         const int n = d.n & 0xffff, H = d.n >> 16;
         // this wave's rows straight into LDS
 #pragma unroll
@@ -207,7 +213,7 @@ bellman_halo(const HTile* __restrict__ tiles, const int32_t* __restrict__ act_ti
                 }
                 if (act) {
                     __builtin_nontemporal_store(best, (x_out + (int64_t)gs[q] * Kp) + kc);
-                    res = fmax(res, fabs((double)best - (double)xo[q]));
+                    res = fmaxf(res, fabsf(best - xo[q]));
                     ym = fmaxf(ym, fabsf(best));
                 }
             }

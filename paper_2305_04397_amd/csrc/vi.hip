@@ -289,7 +289,7 @@ bellman_sweep(const Tile* __restrict__ tiles, const int32_t* __restrict__ tile_b
                 for (int c = 0; c < CPL; ++c) {
                     if (act[c]) {
                         x_out[gs * Kp + kc + c] = best[c];
-                        res[c] = fmax(res[c], fabs((double)best[c] - (double)old.v[c]));
+                        res[c] = fmax(res[c], (double)fabs(best[c] - old.v[c]));
                         if (want_ymax) ym[c] = fmax(ym[c], fabs((double)best[c]));
                     }
                 }
