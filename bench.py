@@ -14,12 +14,16 @@ value iteration of all 5,000 models for the 64 columns to convergence (Alg. 3
 and the stop test), the assignment (Alg. 2), FP64 polish, policy extraction
 and per-objective evaluation of the assigned models (Alg. 4), and both
 projections of Alg. 1 for every query.  `value` is state-action backups per
-second over the timed steps (inputs resident on the device).
+second over the timed steps (inputs resident on the device), which replay
+captured graphs of sweep chunks; the kernel figures come from one more pass of
+the same kind with HIP events around the sweep launches (eager launches).
 
 Extra objects on the JSON line:
   roofline      the Bellman sweep kernel: algorithmic bytes (CSR of active
                 models + one FP32 read and one write per active state-column)
-                over its summed HIP-event durations, against 8 TB/s HBM;
+                over its summed HIP-event durations, against 8 TB/s HBM; the
+                last sweeps of a solve (under 20 % of the tiles active) run the
+                LDS-staged kernel, reported apart as `tail_kernel`;
                 `traffic` = HBM bytes per launch from the committed rocprofv3
                 counter summary (profiles/sweep_traffic_50x100.txt), null when
                 the sweep sources changed since it was taken;
@@ -162,7 +166,7 @@ def query_eval(ctx, wl, front, rng, args, eps_vi: float) -> dict:
         out["learned"].update({"train_tuples": int(len(X)), "data_s": round(gen_s, 1),
                                "train_s": round(train_s, 2), "loss_first": round(float(losses[0]), 4),
                                "loss_last": round(float(losses[-1]), 4),
-                               "fallbacks": int(sum(q["fallback"] for q in learned))})
+                               "fallbacks": int(sum(q["fallback"] == 1 for q in learned))})
         decided = [(p, q) for p, q in zip(plain, learned)
                    if p["verdict"] != morap.UNDECIDED and q["verdict"] != morap.UNDECIDED]
         out["learned_vs_plain_verdicts"] = f"{sum(p['verdict'] == q['verdict'] for p, q in decided)}/{len(decided)}"
@@ -270,14 +274,21 @@ def proposer_eval(args) -> dict:
            "train_variants": args.proposer_variants, "epochs": 80, "train_s": round(train_s, 2),
            "loss_first": round(float(losses[0]), 4), "loss_last": round(float(losses[-1]), 4)}
     res = {}
-    for name, use in (("plain", False), ("learned", True)):
+    # plain; the proposer's first weight vector; the proposer's weight vector
+    # at every pass (input t_down after the first; a query keeps Alg. 1's
+    # update once a proposal is invalid, repeats a weight vector or the
+    # previous learned pass did not shrink the gap by 1 %)
+    for name, use, passes in (("plain", False, 1), ("learned", True, 1), ("learned_every_pass", True, 64)):
         ts = time.perf_counter()
-        r = ctx.query_batch(eval_T, eps=0.01, opts=opts, use_proposer=use)
+        r = ctx.query_batch(eval_T, eps=0.01, opts=opts, use_proposer=use, proposer_passes=passes)
         ms = (time.perf_counter() - ts) * 1e3
         its = np.array([q["iterations"] for q in r])
         res[name] = r
         out[name] = {"queries": len(r), "wall_ms": round(ms, 1), "ms_per_query": round(ms / len(r), 3),
                      "passes_mean": round(float(its.mean()), 3), "passes_max": int(its.max())}
+        if use:
+            out[name]["first_weight_fallbacks"] = int(sum(q["fallback"] == 1 for q in r))
+            out[name]["later_weight_fallbacks"] = int(sum(q["fallback"] == 2 for q in r))
         log(f"proposer eval {name}: {ms / len(r):.2f} ms/query, passes mean {its.mean():.2f}")
     # verdicts are compared where both loops decided; a threshold within eps
     # of the front may end UNDECIDED in one loop and decided in the other
@@ -286,7 +297,9 @@ def proposer_eval(args) -> dict:
     agree = sum(p["verdict"] == q["verdict"] for p, q in decided)
     out["verdict_agreement"] = f"{agree}/{len(decided)}"
     out["undecided_in_either"] = len(eval_T) - len(decided)
-    out["fallbacks"] = int(sum(q["fallback"] for q in res["learned"]))
+    decided3 = [(p, q) for p, q in zip(res["plain"], res["learned_every_pass"])
+                if p["verdict"] != morap.UNDECIDED and q["verdict"] != morap.UNDECIDED]
+    out["verdict_agreement_every_pass"] = f"{sum(p['verdict'] == q['verdict'] for p, q in decided3)}/{len(decided3)}"
     ctx.close()
     return out
 
@@ -347,7 +360,10 @@ def main():
         info = ctx.model_info(m)
         S, R, N = S + info["n_states"], R + info["n_rows"], N + info["nnz"]
     log(f"{nI * nJ} products built and uploaded in {time.time() - t0:.1f} s: S={S} R={R} N={N}")
-    opts = morap.Options(eps_vi=eps, precision=args.precision, time_kernels=True, schedule=args.schedule)
+    # the timed steps replay captured graphs of sweep chunks; one extra pass
+    # with HIP events around the sweep launches (eager) gives the kernel figures
+    opts = morap.Options(eps_vi=eps, precision=args.precision, schedule=args.schedule)
+    opts_timed = morap.Options(eps_vi=eps, precision=args.precision, time_kernels=True, schedule=args.schedule)
     rng = np.random.default_rng(args.seed)
 
     # warm-up (includes the sweep-kernel autotuning) and front points
@@ -375,12 +391,23 @@ def main():
         step_ms.append((time.perf_counter() - ts) * 1e3)
         log(f"step {s + 1}/{args.steps}: {step_ms[-1]:.0f} ms")
     wall = time.perf_counter() - t_all
+    st_graph = ctx.stats()
+    value = st_graph["backups"] / wall
+    # one more pass of the same kind with HIP events on the library's stream
+    # around every 4th sweep launch (a uniform sample; eager launches)
+    ctx.reset_stats()
+    T = pdata.thresholds(rng, front, K, nI)
+    W0 = rng.dirichlet(np.ones(d), size=K)
+    ts = time.perf_counter()
+    ctx.query_batch(T, W0=W0, max_iter=1, eps=0.01, opts=opts_timed)
+    timed_pass_ms = (time.perf_counter() - ts) * 1e3
     st = ctx.stats()
-    value = st["backups"] / wall
+    log(f"kernel-timed pass (eager launches): {timed_pass_ms:.0f} ms")
     # dominant kernel: the FP32 batched sweep over all (model, column) pairs
-    # every 4th sweep launch is timed (a uniform sample): bytes per launch over
-    # all launches, duration averaged over the timed ones
-    per_launch_bytes = st["bytes"] / max(1, st["sweeps"])
+    # until few tiles stay active: bytes per launch over its launches,
+    # duration averaged over its timed ones
+    main_sweeps = st["sweeps"] - st["sweeps_tail"]
+    per_launch_bytes = st["bytes"] / max(1, main_sweeps)
     avg_s = st["ms_sweep_kernel"] / 1e3 / max(1, st["sweep_launches"])
     achieved = per_launch_bytes / avg_s / 1e9 if st["ms_sweep_kernel"] > 0 else 0.0
     kname = kernel_name(st["variant"], args.precision)
@@ -388,10 +415,21 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if tb is None else round(tb, 0),
-                "kernel": kname, "variant": st["variant"], "launches": st["sweeps"],
+                "kernel": kname, "variant": st["variant"], "launches": main_sweeps,
                 "launches_timed": st["sweep_launches"],
                 "avg_launch_us": round(st["ms_sweep_kernel"] * 1e3 / max(1, st["sweep_launches"]), 2),
-                "bytes_per_launch": round(per_launch_bytes, 0)}
+                "bytes_per_launch": round(per_launch_bytes, 0),
+                "timing": "HIP events on every 4th sweep launch of one extra pass (eager launches); value and "
+                          "ms_per_step come from the timed steps, which replay captured graphs"}
+    if st["sweeps_tail"]:
+        avg_t = st["ms_sweep_kernel_tail"] / 1e3 / max(1, st["sweep_launches_tail"])
+        bt = st["bytes_tail"] / st["sweeps_tail"]
+        roofline["tail_kernel"] = {
+            "kernel": kernel_name(st["variant_tail"], args.precision), "variant": st["variant_tail"],
+            "launches": st["sweeps_tail"], "launches_timed": st["sweep_launches_tail"],
+            "avg_launch_us": round(avg_t * 1e6, 2), "bytes_per_launch": round(bt, 0),
+            "achieved": round(bt / avg_t / 1e9, 1) if avg_t > 0 else None,
+            "note": "the last sweeps of each solve (under 20 % of the tiles active) run the LDS-staged kernel"}
     if st["sweep_launches_refine"]:
         avg_r = st["ms_sweep_kernel_refine"] / 1e3 / st["sweep_launches_refine"]
         ach_r = st["bytes_refine"] / max(1, st["polish_sweeps"]) / avg_r / 1e9
@@ -399,8 +437,9 @@ def main():
             "achieved": round(ach_r, 1), "launches": st["polish_sweeps"],
             "launches_timed": st["sweep_launches_refine"], "avg_launch_us": round(avg_r * 1e6, 2),
             "kernel": kernel_name(st["variant_refine"], "f64")}
-    log(f"timed: {value:.3e} backups/s, sweep kernel {achieved:.0f} GB/s "
-        f"({st['sweeps']} launches, {st['sweep_launches']} timed, {st['ms_sweep_kernel']:.0f} ms); FP64 re-solve "
+    log(f"timed: {value:.3e} backups/s, {float(np.mean(step_ms)):.0f} ms per step; sweep kernel {achieved:.0f} GB/s "
+        f"({main_sweeps} launches, {st['sweep_launches']} timed, {st['ms_sweep_kernel']:.0f} ms; then "
+        f"{st['sweeps_tail']} of the tail kernel, {st['ms_sweep_kernel_tail']:.0f} ms); FP64 re-solve "
         f"{st['ms_sweep_kernel_refine']:.0f} ms over {st['sweep_launches_refine']} timed launches; "
         f"VI {st['ms_vi']:.0f} ms, evaluation {st['ms_eval']:.0f} ms")
 
@@ -422,9 +461,10 @@ def main():
                        "parallelism": "1 GPU"},
             "roofline": roofline, "cpu_baseline": cpu, "ms_per_query": per_query,
             "proposer": learned,
-            "stats": {k: st[k] for k in ("backups", "sweeps", "eval_sweeps", "polish_sweeps", "rank_rounds",
-                                         "ms_vi", "ms_eval", "variant", "variant_refine", "bytes",
-                                         "bytes_refine")}}
+            "stats": {k: st_graph[k] for k in ("backups", "sweeps", "sweeps_tail", "eval_sweeps", "polish_sweeps",
+                                               "rank_rounds", "floor_stops", "ms_vi", "ms_eval", "variant",
+                                               "variant_tail", "variant_refine", "bytes", "bytes_tail",
+                                               "bytes_refine")}}
     print(json.dumps(line), flush=True)
 
 

@@ -202,6 +202,14 @@ typedef struct {
     int64_t sweep_launches_refine;
     int32_t variant;        /* sweep-kernel variant of the last batched solve       */
     int32_t variant_refine; /* variant of the last FP64 re-solve of assigned pairs  */
+    int64_t sweeps_tail;    /* sweeps of batched solves run by the LDS-staged kernel */
+                            /* once few tiles stay active (included in sweeps;      */
+                            /* bytes, ms_sweep_kernel, sweep_launches: main kernel) */
+    int64_t sweep_launches_tail; /* their timed launches, bytes and kernel time     */
+    double  bytes_tail;
+    double  ms_sweep_kernel_tail;
+    int32_t variant_tail;   /* that kernel's variant (0: no switch)                 */
+    int32_t reserved;
 } morap_stats;
 
 /* Alg. 2 first loop / Alg. 3 for K weight vectors W[K][d] at once: for every
@@ -321,6 +329,16 @@ typedef struct {
     int32_t warm_start;      /* 1 = after the first pass, each FP32 solve starts a
                                 query's column from its values of the previous
                                 pass (pairs with a zero cost weight from 0)     */
+    int32_t proposer_passes; /* with use_proposer: the proposer gives the weight
+                                vector of the first max(1, proposer_passes)
+                                passes; after the first its input is t_down (the
+                                closest point to t that the separating hyperplanes
+                                found so far allow) in place of t.  A later
+                                proposal is kept only if it is finite, on the
+                                simplex, unlike every earlier weight vector of
+                                the query, and the previous learned pass shrank
+                                the gap by 1 %; otherwise that query takes Alg.
+                                1's own update from then on (fallback = 2)     */
     morap_vi_opts vi;
 } morap_query_opts;
 

@@ -13,7 +13,7 @@ thread_local AllocMeter* g_meter = nullptr;
 }
 
 morap_ctx::~morap_ctx() {
-    for (int g = 0; g < 2; ++g) {
+    for (int g = 0; g < 3; ++g) {
         if (chunk_exec[g]) (void)hipGraphExecDestroy(chunk_exec[g]);
         if (chunk_graph[g]) (void)hipGraphDestroy(chunk_graph[g]);
     }
@@ -44,6 +44,12 @@ void to_abi(const Stats& s, morap_stats* out) {
     out->sweep_launches_refine = s.sweep_launches_refine;
     out->variant = s.variant;
     out->variant_refine = s.variant_refine;
+    out->sweeps_tail = s.sweeps_tail;
+    out->sweep_launches_tail = s.sweep_launches_tail;
+    out->bytes_tail = s.bytes_tail;
+    out->ms_sweep_kernel_tail = s.ms_sweep_kernel_tail;
+    out->variant_tail = s.variant_tail;
+    out->reserved = 0;
 }
 
 }  // namespace

@@ -184,6 +184,10 @@ struct Stats {
     double bytes_refine = 0, ms_sweep_kernel_refine = 0;
     int64_t sweep_launches_refine = 0;
     int variant = 0, variant_refine = 0;
+    // the last sweeps of batched solves, run by the LDS-staged kernel
+    int64_t sweeps_tail = 0, sweep_launches_tail = 0;
+    double bytes_tail = 0, ms_sweep_kernel_tail = 0;
+    int variant_tail = 0;
 };
 
 // Values of one batched value iteration: two Jacobi buffers [S][Kp], the
@@ -262,9 +266,11 @@ struct morap_ctx {
     std::vector<double> W;                          // [K][d] of the last solve
     int last_variant = 0;
     std::vector<hipEvent_t> event_pool;             // reusable per-launch timing events
-    hipGraph_t chunk_graph[2] = {nullptr, nullptr}; // captured chunks of sweeps (main, FP64 refine)
-    hipGraphExec_t chunk_exec[2] = {nullptr, nullptr};
-    std::string graph_key[2];
+    // captured chunks of sweeps: main, FP64 refine, and main again for the
+    // sweep kernel of a solve's last, small active sets
+    hipGraph_t chunk_graph[3] = {nullptr, nullptr, nullptr};
+    hipGraphExec_t chunk_exec[3] = {nullptr, nullptr, nullptr};
+    std::string graph_key[3];
     uint64_t load_gen = 0;                          // bumped by every model upload (graph keys)
     uint64_t buf_gen = 0;                           // bumped when a solve buffer moves (graph keys)
 
@@ -472,9 +478,13 @@ struct ConvergeArgs {
     const int32_t* states_per_model; // [M] states (value traffic per active column)
     const int64_t* csr_bytes;        // [M] CSR bytes read per sweep of an active model
     int32_t* act_tiles;              // [tiles] global index of every active tile, in order
+    int relist;                      // compaction only re-lists the active models (no sweep is counted)
 };
 void converge(hipStream_t s, const ConvergeArgs& a);
 void compact(hipStream_t s, const ConvergeArgs& a);
+// the same active models listed over the tiles of a.tile_base (a change of
+// sweep kernel between the gather and the LDS-staged tiles)
+void relist(hipStream_t s, ConvergeArgs a);
 void init_solve(hipStream_t s, const ConvergeArgs& a);
 
 // instances (polish, policy extraction, evaluation)

@@ -46,6 +46,8 @@ struct QState {
     std::vector<std::vector<int32_t>> Fs;   // assignment of every pass
     bool done = false, separated = false;
     int fallback = 0;
+    int learned_passes = 0;      // passes whose weight vector the proposer gave
+    double gap_before = -1.0;    // the gap when the last learned weight was set
     double latency_ms = -1.0;   // set when the query stops
     double gap = 0;
     int64_t backups = 0;
@@ -77,6 +79,55 @@ void parallel_for(int n, F f) {
     for (int t = 0; t < nt; ++t) th.emplace_back(worker);
     for (auto& t : th) t.join();
     if (err) std::rethrow_exception(err);
+}
+
+// The proposer's weight vectors after the first pass (morap_query_opts,
+// proposer_passes): input [t_down; phi]; a proposal replaces Alg. 1's update
+// only while it is valid, new to the query, and the previous learned pass
+// shrank the gap by 1 %, else the query keeps the update from then on.
+void propose_later(morap_ctx* c, std::vector<QState>& qs, const std::vector<int>& act, int d, int passes) {
+    std::vector<int> ask;
+    for (int q : act) {
+        const QState& s = qs[q];
+        if (!s.done && s.fallback == 0 && s.learned_passes > 0 && s.learned_passes < passes) ask.push_back(q);
+    }
+    if (ask.empty()) return;
+    const int nfeat = (int)c->features.size();
+    std::vector<float> X(ask.size() * (size_t)(d + nfeat)), out(ask.size() * (size_t)d);
+    for (size_t a = 0; a < ask.size(); ++a) {
+        const QState& s = qs[ask[a]];
+        for (int k = 0; k < d; ++k) X[a * (d + nfeat) + k] = (float)s.t_down[k];
+        for (int k = 0; k < nfeat; ++k) X[a * (d + nfeat) + d + k] = (float)c->features[k];
+    }
+    proposer_infer_host(c, X.data(), (int)ask.size(), out.data());
+    for (size_t a = 0; a < ask.size(); ++a) {
+        QState& s = qs[ask[a]];
+        std::vector<double> w(d);
+        double sum = 0;
+        bool ok = !(s.gap >= 0.99 * s.gap_before);
+        for (int k = 0; k < d; ++k) {
+            const double v = out[a * d + k];
+            ok &= std::isfinite(v) && v >= 0;
+            w[k] = v;
+            sum += v;
+        }
+        ok &= std::fabs(sum - 1.0) <= 1e-3 && sum > 0;
+        if (ok) {
+            for (auto& v : w) v /= sum;
+            for (const auto& prev : s.Ws) {
+                double diff = 0;
+                for (int k = 0; k < d; ++k) diff = std::max(diff, std::fabs(prev[k] - w[k]));
+                ok &= diff > 1e-6;
+            }
+        }
+        if (ok) {
+            s.gap_before = s.gap;
+            s.w = w;
+            ++s.learned_passes;
+        } else {
+            s.fallback = 2;
+        }
+    }
 }
 
 }  // namespace
@@ -133,6 +184,8 @@ void query_batch(morap_ctx* c, const double* T, const double* W0, int Q, const d
             if (ok) {
                 for (auto& v : w) v /= sum;
                 s.w = w;
+                s.learned_passes = 1;
+                s.gap_before = INFINITY;
             } else {
                 s.fallback = 1;   // plain rule: start from (1, 0, ..., 0)
             }
@@ -258,6 +311,7 @@ void query_batch(morap_ctx* c, const double* T, const double* W0, int Q, const d
                 });
                 last_ms[2] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t2).count();
             }
+            if (learned && o.proposer_passes > 1) propose_later(c, qs, act, d, o.proposer_passes);
             const double now = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
             for (int q : act)
                 if (qs[q].done && qs[q].latency_ms < 0) qs[q].latency_ms = now;

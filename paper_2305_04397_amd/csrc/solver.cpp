@@ -484,13 +484,30 @@ static std::string describe_active(morap_ctx* c, ValueSet& vs) {
 
 // warm: the solve starts from the values prepared in d_xwarm (they become
 // the first sweep's input buffer)
+// The LDS-staged sweep for the last sweeps of a solve whose kernel is the
+// wave-per-state gather sweep: the two give identical values, and once few
+// tiles stay active (the last large models) the staged one is faster.
+static const Variant* tail_variant(morap_ctx* c, const ValueSet& vs, const uint8_t* mask, const Variant& v,
+                                   int schedule) {
+    if (mask || schedule != 0 || !c->has_halo || vs.prec != MORAP_F32 || vs.Kp % 64 != 0) return nullptr;
+    if (v.kind != SWEEP_BLOCK || v.cpl != 1 || v.lps != 64) return nullptr;
+    for (const auto& t : variants())
+        if (t.kind == SWEEP_HALO && t.unroll == 2) return &t;
+    return nullptr;
+}
+constexpr int kTailPercent = 20;   // switch below this share of the tiles
+
 static void run_vi(morap_ctx* c, int g, ValueSet& vs, const uint8_t* mask, const morap_vi_opts& o, Stats& st,
                    bool warm = false) {
-    const Variant& v = choose_variant(c, vs, mask, o.eps_vi, o.schedule);
-    c->last_variant = v.id;
+    const Variant& v0 = choose_variant(c, vs, mask, o.eps_vi, o.schedule);
+    c->last_variant = v0.id;
+    const Variant* vt = tail_variant(c, vs, mask, v0, o.schedule);
+    const Variant* vp = &v0;   // the kernel of the next chunk
+    double bytes_at_switch = -1;
+    int64_t sweeps_at_switch = 0;
     const int chunk = std::max(2, (o.check_every + 1) / 2 * 2);
     EventPair wall;
-    reset_solve(c, vs, mask, o.eps_vi, v);
+    reset_solve(c, vs, mask, o.eps_vi, v0);
     if (warm) {
         swap_buf(vs.x[0], c->d_xwarm);
         ++c->buf_gen;   // graphs hold the value buffers' addresses
@@ -513,10 +530,13 @@ static void run_vi(morap_ctx* c, int g, ValueSet& vs, const uint8_t* mask, const
             MORAP_HIP(hipEventElapsedTime(&t, e.first, e.second));
             if (sweep_log() && i < 4096)
                 std::fprintf(sweep_log(), "sweep prec=%d mask=%d variant=%d tiles=%lld ms=%.4f\n", vs.prec,
-                             mask != nullptr, v.id, (long long)c->h_log.as<int64_t>()[i], t);
+                             mask != nullptr, vp->id, (long long)c->h_log.as<int64_t>()[i], t);
             if (mask) {
                 st.ms_sweep_kernel_refine += t;
                 st.sweep_launches_refine += 1;
+            } else if (vp != &v0) {
+                st.ms_sweep_kernel_tail += t;
+                st.sweep_launches_tail += 1;
             } else {
                 st.ms_sweep_kernel += t;
                 st.sweep_launches += 1;
@@ -526,12 +546,22 @@ static void run_vi(morap_ctx* c, int g, ValueSet& vs, const uint8_t* mask, const
         }
         ev.clear();
     };
+    const size_t el = vs.prec == MORAP_F32 ? 4 : 8;
+    const int64_t main_tiles = (int64_t)c->tiles.size();
     while (true) {
-        run_chunk(c, g, vs, mask, v, o.eps_vi, chunk, o.use_graph != 0, o.time_kernels ? &ev : nullptr);
+        run_chunk(c, vp == &v0 ? g : 2, vs, mask, *vp, o.eps_vi, chunk, o.use_graph != 0,
+                  o.time_kernels ? &ev : nullptr);
         launched += chunk;
         read_counters(c);
         harvest();
         if (h[3] == 0) break;
+        if (vt && vp == &v0 && h[1] * 100 < main_tiles * kTailPercent) {
+            // the same active models listed over the halo tiles
+            bytes_at_switch = (double)h[6] + 2.0 * el * (double)h[7];
+            sweeps_at_switch = h[5];
+            vp = vt;
+            k::relist(c->stream, converge_args(c, vs, mask, o.eps_vi, 0, true));
+        }
         if (launched >= o.max_sweeps)
             fail(MORAP_E_NOT_CONVERGED, "value iteration: " + std::to_string(h[3]) +
                                             " (model, column) pairs still active after " +
@@ -542,15 +572,23 @@ static void run_vi(morap_ctx* c, int g, ValueSet& vs, const uint8_t* mask, const
     const float ms = wall.elapsed_ms();
     std::vector<int32_t> ps((size_t)c->hm.M * vs.Kp);
     MORAP_HIP(hipMemcpy(ps.data(), c->d_pair_sweeps.p, ps.size() * 4, hipMemcpyDeviceToHost));
-    const size_t el = vs.prec == MORAP_F32 ? 4 : 8;
     st.backups += h[4];
     st.floor_stops += h[8];
-    if (mask) st.bytes_refine += (double)h[6] + 2.0 * el * (double)h[7];
-    else st.bytes += (double)h[6] + 2.0 * el * (double)h[7];
+    const double bytes = (double)h[6] + 2.0 * el * (double)h[7];
+    if (mask) {
+        st.bytes_refine += bytes;
+    } else if (bytes_at_switch >= 0) {
+        st.bytes += bytes_at_switch;
+        st.bytes_tail += bytes - bytes_at_switch;
+        st.sweeps_tail += h[5] - sweeps_at_switch;
+        st.variant_tail = vt->id;
+    } else {
+        st.bytes += bytes;
+    }
     st.max_pair_sweeps = std::max<int64_t>(st.max_pair_sweeps, *std::max_element(ps.begin(), ps.end()));
     st.ms_vi += ms;
-    if (mask) st.variant_refine = v.id;
-    else st.variant = v.id;
+    if (mask) st.variant_refine = v0.id;
+    else st.variant = v0.id;
     if (mask) st.polish_sweeps += h[5];
     else st.sweeps += h[5];
     vs.valid = true;
@@ -576,6 +614,11 @@ static void add_stats(Stats& a, const Stats& b) {
     a.bytes_refine += b.bytes_refine;
     a.ms_sweep_kernel_refine += b.ms_sweep_kernel_refine;
     a.sweep_launches_refine += b.sweep_launches_refine;
+    a.sweeps_tail += b.sweeps_tail;
+    a.sweep_launches_tail += b.sweep_launches_tail;
+    a.bytes_tail += b.bytes_tail;
+    a.ms_sweep_kernel_tail += b.ms_sweep_kernel_tail;
+    a.variant_tail = b.variant_tail ? b.variant_tail : a.variant_tail;
     a.variant = b.variant ? b.variant : a.variant;
     a.variant_refine = b.variant_refine ? b.variant_refine : a.variant_refine;
 }

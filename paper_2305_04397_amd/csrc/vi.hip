@@ -550,7 +550,7 @@ __global__ void __launch_bounds__(1024) compact_kernel(ConvergeArgs a) {
         }
     part[tid] = sum;
     partm[tid] = cnt;
-    if (bytes) atomicAdd((unsigned long long*)&a.counters[6], bytes);
+    if (bytes && !a.relist) atomicAdd((unsigned long long*)&a.counters[6], bytes);
     __syncthreads();
     // inclusive scan (Hillis-Steele)
     for (int o = 1; o < 1024; o <<= 1) {
@@ -576,9 +576,11 @@ __global__ void __launch_bounds__(1024) compact_kernel(ConvergeArgs a) {
         a.act_prefix[offm] = off;
         a.counters[1] = off;
         a.counters[2] = offm;
-        a.counters[3] = a.counters[0];
-        a.counters[0] = 0;
-        a.counters[5] += 1;
+        if (!a.relist) {
+            a.counters[3] = a.counters[0];
+            a.counters[0] = 0;
+            a.counters[5] += 1;
+        }
     }
 }
 
@@ -591,6 +593,19 @@ __global__ void __launch_bounds__(64) expand_kernel(ConvergeArgs a) {
     const int base = a.act_prefix[b];
     const int t0 = a.tile_base[m], nt = a.tile_base[m + 1] - t0;
     for (int i = threadIdx.x; i < nt; i += 64) a.act_tiles[base + i] = t0 + i;
+}
+
+// the active models of the current lists, flagged again (for relist)
+__global__ void remark_kernel(ConvergeArgs a) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < (int)a.counters[2]) a.model_active[a.act_models[b]] = 1;
+}
+
+void relist(hipStream_t s, ConvergeArgs a) {
+    hipLaunchKernelGGL(remark_kernel, dim3((unsigned)((a.M + 255) / 256)), dim3(256), 0, s, a);
+    MORAP_HIP(hipGetLastError());
+    a.relist = 1;
+    compact(s, a);
 }
 
 void compact(hipStream_t s, const ConvergeArgs& a) {

@@ -75,7 +75,9 @@ class Stats(C.Structure):
                 ("ms_eval", C.c_double), ("ms_total", C.c_double), ("ms_sweep_kernel", C.c_double),
                 ("sweep_launches", C.c_int64), ("bytes_refine", C.c_double),
                 ("ms_sweep_kernel_refine", C.c_double), ("sweep_launches_refine", C.c_int64),
-                ("variant", C.c_int32), ("variant_refine", C.c_int32)]
+                ("variant", C.c_int32), ("variant_refine", C.c_int32), ("sweeps_tail", C.c_int64),
+                ("sweep_launches_tail", C.c_int64), ("bytes_tail", C.c_double),
+                ("ms_sweep_kernel_tail", C.c_double), ("variant_tail", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -84,7 +86,7 @@ class Stats(C.Structure):
 class QueryOpts(C.Structure):
     _fields_ = [("eps", C.c_double), ("max_iter", C.c_int32), ("verification_only", C.c_int32),
                 ("use_proposer", C.c_int32), ("keep_trace", C.c_int32), ("warm_start", C.c_int32),
-                ("vi", ViOpts)]
+                ("proposer_passes", C.c_int32), ("vi", ViOpts)]
 
 
 class QueryResult(C.Structure):
@@ -518,7 +520,7 @@ class Context:
     # -- Alg. 1 ------------------------------------------------------------
     def query_batch(self, T, M=None, eps: float = 1e-3, max_iter: int = 64, opts: Options = Options(),
                     verification_only: bool = False, use_proposer: bool = False, trace: bool = False,
-                    W0=None, warm_start: bool = True):
+                    W0=None, warm_start: bool = True, proposer_passes: int = 1):
         T = _c(np.atleast_2d(T), np.float64)
         Q, d = T.shape
         W0c = None if W0 is None else _c(np.atleast_2d(W0), np.float64)
@@ -528,6 +530,7 @@ class Context:
         qo.use_proposer = int(use_proposer)
         qo.keep_trace = int(trace)
         qo.warm_start = int(warm_start)
+        qo.proposer_passes = int(proposer_passes)
         qo.vi = opts.to_c()
         res = (QueryResult * Q)()
         bufs = []

@@ -101,3 +101,26 @@ def test_proposer_nan_output_falls_back_to_the_plain_rule(ctx, morap):
     assert learned["fallback"] == 1 and plain["fallback"] == 0
     assert learned["verdict"] == plain["verdict"] and learned["iterations"] == plain["iterations"]
     assert np.array_equal(learned["t_up"], plain["t_up"])
+
+
+def test_later_proposal_that_repeats_a_weight_falls_back(ctx, morap):
+    """With the proposer giving later weight vectors too (proposer_passes), a
+    proposal equal to an earlier weight vector of the query (a network with
+    zero parameters proposes the uniform vector for every input) is refused:
+    the query takes Alg. 1's update from then on (fallback 2) and runs
+    exactly as with the proposer's first weight vector alone."""
+    wl = make_workload(1)
+    ctx.build_products(wl)
+    d, nfeat = 4, 2
+    ctx.set_features(np.array([0.1, 0.2]))
+    ctx.proposer_init(d + nfeat, d, seed=5)
+    ctx.proposer_set_params(np.zeros(ctx.proposer_num_params(), dtype=np.float32))
+    # an infeasible threshold just above the front (several passes from any start)
+    t = np.array([-16.4670084, -6.32019845, 1.0, 1.0])
+    opts = morap.Options(eps_vi=1e-8, precision="f64")
+    every = ctx.query(t, eps=1e-3, max_iter=32, opts=opts, use_proposer=True, proposer_passes=32)
+    first = ctx.query(t, eps=1e-3, max_iter=32, opts=opts, use_proposer=True, proposer_passes=1)
+    assert first["fallback"] == 0 and every["fallback"] == 2
+    assert every["iterations"] >= 2
+    assert every["verdict"] == first["verdict"] and every["iterations"] == first["iterations"]
+    assert np.array_equal(every["t_up"], first["t_up"]) and np.array_equal(every["t_down"], first["t_down"])

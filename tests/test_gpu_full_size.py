@@ -54,6 +54,30 @@ def test_full_size_solve_sampled(full):
             assert abs(c[k, i, j] - ref) <= 2e-4 * max(1.0, abs(ref)), (i, j, k, c[k, i, j], ref)
 
 
+def test_tail_kernel_switch_keeps_the_values(full):
+    """An autotuned solve whose kernel is the wave-per-state gather sweep
+    runs its last sweeps (under 20 % of the tiles active) with the LDS-staged
+    kernel; the values, the stop sweeps and the backups are those of the same
+    solve with the gather sweep throughout (a fixed schedule never
+    switches), bit for bit."""
+    morap, ctx, wl = full
+    nI, nJ = wl.n_agents, wl.n_tasks
+    W = dirichlet_weights(np.random.default_rng(5), 64, nI + nJ)
+    c1, st1 = ctx.solve(W, morap.Options(eps_vi=1e-6, precision="f32"))
+    if st1["variant"] not in (34, 37, 38):
+        pytest.skip(f"the autotuner chose variant {st1['variant']}, not a wave-per-state gather sweep")
+    assert st1["variant_tail"] == 39 and 0 < st1["sweeps_tail"] < st1["sweeps"]
+    big = [m for m in range(nI * nJ) if ctx.model_info(m)["n_states"] > 100_000][:2]
+    v1 = {(k, m): ctx.get_values(k, m) for m in big for k in (0, 63)}
+    c2, st2 = ctx.solve(W, morap.Options(eps_vi=1e-6, precision="f32", schedule=st1["variant"]))
+    assert st2["sweeps_tail"] == 0 and st2["variant_tail"] == 0
+    assert np.array_equal(c1, c2)
+    assert st1["sweeps"] == st2["sweeps"] and st1["backups"] == st2["backups"]
+    assert st1["bytes"] + st1["bytes_tail"] == pytest.approx(st2["bytes"], rel=1e-12)
+    for (k, m), x in v1.items():
+        assert np.array_equal(x, ctx.get_values(k, m)), (k, m)
+
+
 @pytest.mark.parametrize("kind", ["avoid", "reach"])
 def test_full_size_largest_product_sampled(full, kind):
     """The products of maximum size class: the 128 x 128 agent with a
