@@ -76,11 +76,7 @@ bellman_block(const Tile* __restrict__ tiles,
     // tiles than waves
     const int n_tiles = (int)counters[1];
     const int n_waves = gridDim.x * NW;
-    // few active tiles (the last large models of a solve): cut each tile into
-    // up to 16 units so that every wave has few states in sequence -- the
-    // launch then takes about one round of gather latency per U states
-    int sub = 1;
-    while (sub < 16 && n_tiles * sub * 2 <= n_waves) sub *= 2;
+    const int sub = n_tiles * 4 <= n_waves ? 4 : (n_tiles * 2 <= n_waves ? 2 : 1);
     const int n_units = n_tiles * sub;
     // XCD x takes the units [xb, xe); its waves take every count-th unit of
     // it, so neighbouring units (which share successor rows) are in flight
@@ -268,11 +264,7 @@ bellman_block_wave(const Tile* __restrict__ tiles,
 
     const int n_tiles = (int)counters[1];
     const int n_waves = gridDim.x * NW;
-    // few active tiles (the last large models of a solve): cut each tile into
-    // up to 16 units so that every wave has few states in sequence -- the
-    // launch then takes about one round of gather latency per U states
-    int sub = 1;
-    while (sub < 16 && n_tiles * sub * 2 <= n_waves) sub *= 2;
+    const int sub = n_tiles * 4 <= n_waves ? 4 : (n_tiles * 2 <= n_waves ? 2 : 1);
     const int n_units = n_tiles * sub;
     // XCD x takes the units [xb, xe); its waves take every count-th unit of
     // it, so neighbouring units (which share successor rows) are in flight
