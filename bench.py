@@ -220,7 +220,8 @@ def cpu_baseline(wl, K: int, eps: float, budget_s: float, seed: int, workers: in
     rate = sum(b / e for b, e, _ in res if e > 0)
     done = sum(d for _, _, d in res)
     return {"value": rate, "unit": "backups/s", "cores": workers, "kind": "oracle",
-            "per_core": rate / workers,
+            "per_core": rate / workers, "host_cpus": os.cpu_count(),
+            "cpus_available": len(os.sched_getaffinity(0)),
             "sample": f"{done} models drawn at random from the workload (agents of at most 2,000 cells) by {workers} "
                       f"processes, K={K} Dirichlet weight columns, eps {eps:g}, FP64 Jacobi value iteration "
                       f"(numpy/scipy), about {budget_s:.0f} s of VI per process"}
@@ -313,7 +314,8 @@ def main():
     ap.add_argument("--queries", type=int, default=64, help="queries for the ms-per-query measurement (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="VI seconds per baseline process")
-    ap.add_argument("--cpu-workers", type=int, default=8, help="baseline processes (at most the host's cores)")
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="baseline processes (at most the cores this process may run on)")
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--schedule", type=int, default=0,
                     help="sweep-kernel variant of the timed passes (0 = the autotuner's choice)")
@@ -348,7 +350,7 @@ def main():
     # the CPU baseline first: its worker processes fork before the GPU is used
     cpu = None
     if not args.no_cpu_baseline:
-        workers = max(1, min(args.cpu_workers, os.cpu_count() or 1))
+        workers = max(1, min(args.cpu_workers, len(os.sched_getaffinity(0))))
         cpu = cpu_baseline(wl, K, eps, args.cpu_seconds, args.seed, workers)
         log(f"cpu baseline: {cpu['value']:.3e} backups/s on {workers} processes")
     ctx = morap.Context(0)

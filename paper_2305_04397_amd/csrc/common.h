@@ -285,6 +285,14 @@ struct morap_ctx {
     morap::DevBuf d_ires, d_iactive, d_ipar;        // per (instance, objective)
     morap::DevBuf d_mask, d_rank, d_mu;             // per instance state
     morap::DevBuf d_xe[2];                          // evaluation values [inst states][2]
+    // the last evaluation's final values and instance layout (a warm start
+    // of the next one)
+    morap::DevBuf d_xe_prev, d_warm_copy;
+    std::vector<int64_t> prev_inst_base;
+    std::vector<int32_t> prev_inst_m;
+    int prev_per_col = 0;
+    bool eval_prev_valid = false;
+    uint64_t prev_eval_gen = 0;
     morap::DevBuf d_iwc, d_iwp;                     // per instance FP64 weights
     morap::DevBuf d_iscale;                         // per instance 1 / (w_i + w_j) (warm start)
     morap::DevBuf d_ichanged;                       // per instance: ranks changed in the last round
@@ -378,7 +386,11 @@ inline int n_obj_of(const morap_ctx* c) { return n_agents_of(c) + n_tasks_of(c);
 // padded columns, ignored otherwise
 void solve(morap_ctx* ctx, const double* W, int K, const morap_vi_opts& o, double* c_out, Stats& st,
            const int32_t* warm = nullptr);
-void evaluate(morap_ctx* ctx, const int32_t* assign, int K, const morap_vi_opts& o, double* r_out, Stats& st);
+// warm (nullable): per column, the column of the previous evaluation whose
+// instance of the same task on the same model starts the policy evaluation
+// from its final values (-1: from 0, as Alg. 4)
+void evaluate(morap_ctx* ctx, const int32_t* assign, int K, const morap_vi_opts& o, double* r_out, Stats& st,
+              const int32_t* warm = nullptr);
 const std::vector<Variant>& variants();
 
 // assign.cpp
@@ -520,6 +532,8 @@ void team_eval_sweep(hipStream_t s, int64_t S, int d, const int32_t* pi, const i
                      const double* E_in, double* E_out, unsigned long long* res);
 void team_start(hipStream_t s, int64_t S, int K, int Kp, int d, const double* W, const double* E, int prec,
                 void* x);
+// runs (dst, src, length) of instance states [.][2] copied from prev to x
+void copy_runs(hipStream_t s, const int64_t* runs, int n_runs, const double* prev, double* x);
 // team models: out[r][k] = W[k][obj[r][0]] rew[r][0] + W[k][obj[r][1]] rew[r][1]
 void team_rewards(hipStream_t s, int64_t R, int K, int Kp, int d, const double* W, const int32_t* obj,
                   const double* rew, double* out64, float* out32);

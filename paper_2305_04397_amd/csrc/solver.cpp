@@ -626,7 +626,7 @@ static void add_stats(Stats& a, const Stats& b) {
 static void solve_impl(morap_ctx* c, const double* W, int K, const morap_vi_opts& o, double* c_out, Stats& st,
                        const int32_t* warm);
 static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const morap_vi_opts& o, double* r_out,
-                          Stats& st);
+                          Stats& st, const int32_t* warm);
 
 void solve(morap_ctx* c, const double* W, int K, const morap_vi_opts& o, double* c_out, Stats& st,
            const int32_t* warm) {
@@ -636,9 +636,16 @@ void solve(morap_ctx* c, const double* W, int K, const morap_vi_opts& o, double*
     add_stats(c->cum, local);
 }
 
-void evaluate(morap_ctx* c, const int32_t* assign, int K, const morap_vi_opts& o, double* r_out, Stats& st) {
+void evaluate(morap_ctx* c, const int32_t* assign, int K, const morap_vi_opts& o, double* r_out, Stats& st,
+              const int32_t* warm) {
     Stats local;
-    evaluate_impl(c, assign, K, o, r_out, local);
+    c->eval_prev_valid = c->eval_prev_valid && c->prev_eval_gen == c->load_gen;
+    try {
+        evaluate_impl(c, assign, K, o, r_out, local, warm);
+    } catch (...) {
+        c->eval_prev_valid = false;
+        throw;
+    }
     add_stats(st, local);
     add_stats(c->cum, local);
 }
@@ -796,7 +803,7 @@ static k::InstArgs inst_args(morap_ctx* c, int n_tiles, int n_inst) {
 constexpr int kTauSteps = 6;
 
 static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const morap_vi_opts& o, double* r_out,
-                          Stats& st) {
+                          Stats& st, const int32_t* warm) {
     MORAP_CHECK(c->solved, MORAP_E_STATE, "morap_evaluate needs a morap_solve first");
     MORAP_CHECK(K == c->K, MORAP_E_INVALID, "K differs from the last morap_solve");
     MORAP_CHECK(assign != nullptr || c->team, MORAP_E_INVALID, "assign is NULL");
@@ -1071,11 +1078,36 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
         fail(MORAP_E_IMPROPER, std::to_string(h[0]) + " states cannot reach done through tau-optimal actions");
     }
 
-    // Alg. 4 per objective
+    // Alg. 4 per objective, from 0, or (warm) each instance whose column's
+    // previous column had an instance of the same task on the same model from
+    // that instance's final values: the evaluation of a proper policy reaches
+    // its values from any start
     double* xe0 = c->d_xe[0].as<double>();
     double* xe1 = c->d_xe[1].as<double>();
     k::fill_f64(s, xe0, 0.0, 2 * NS);
     k::fill_f64(s, xe1, 0.0, 2 * NS);
+    if (warm && c->eval_prev_valid && c->prev_per_col == nJ) {
+        std::vector<int64_t> runs;
+        const int K_prev = (int)(c->prev_inst_m.size() / std::max(1, nJ));
+        for (int kk = 0; kk < K; ++kk) {
+            const int kp = warm[kk];
+            MORAP_CHECK(kp >= -1, MORAP_E_INVALID, "warm-start column out of range");
+            if (kp < 0 || kp >= K_prev) continue;
+            for (int j = 0; j < nJ; ++j) {
+                const int q = kk * nJ + j, qp = kp * nJ + j;
+                if (c->prev_inst_m[qp] != c->inst_m[q]) continue;
+                runs.push_back(c->inst_base[q]);
+                runs.push_back(c->prev_inst_base[qp]);
+                runs.push_back(c->inst_base[q + 1] - c->inst_base[q]);
+            }
+        }
+        if (!runs.empty()) {
+            c->d_warm_copy.ensure(runs.size() * 8);
+            MORAP_HIP(hipMemcpyAsync(c->d_warm_copy.p, runs.data(), runs.size() * 8, hipMemcpyHostToDevice, s));
+            k::copy_runs(s, c->d_warm_copy.as<int64_t>(), (int)(runs.size() / 3), c->d_xe_prev.as<double>(), xe0);
+            MORAP_HIP(hipStreamSynchronize(s));   // the host run list goes out of scope
+        }
+    }
     k::set_active(s, n, a, iact, ires, ipar, 2);
     int64_t esweeps = 0;
     k::InstArgs ae = a;
@@ -1153,6 +1185,15 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
     }
     c->eK = K;
     c->evaluated = true;
+    // keep the final values and the layout for a warm start of the next one
+    std::swap(c->d_xe_prev.p, c->d_xe[0].p);
+    std::swap(c->d_xe_prev.bytes, c->d_xe[0].bytes);
+    std::swap(c->d_xe_prev.meter, c->d_xe[0].meter);
+    c->prev_inst_base = c->inst_base;
+    c->prev_inst_m = c->inst_m;
+    c->prev_per_col = nJ;
+    c->prev_eval_gen = c->load_gen;
+    c->eval_prev_valid = true;
     st.ms_eval += ms;
     st.ms_total += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }

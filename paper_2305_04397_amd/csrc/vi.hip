@@ -1072,6 +1072,21 @@ __global__ void select_final_kernel(InstArgs a, double* x0, const double* x1, co
         if (par[(int64_t)L.inst * width + o]) x0[L.is * width + o] = x1[L.is * width + o];
 }
 
+// runs (dst, src, length) of instance states: x[dst + i][2] = prev[src + i][2]
+__global__ void copy_runs_kernel(const int64_t* __restrict__ runs, int n_runs, const double* __restrict__ prev,
+                                 double* __restrict__ x) {
+    const int r = blockIdx.x;
+    if (r >= n_runs) return;
+    const int64_t dst = runs[3 * r], src = runs[3 * r + 1], len = runs[3 * r + 2];
+    for (int64_t i = threadIdx.x; i < 2 * len; i += blockDim.x) x[2 * dst + i] = prev[2 * src + i];
+}
+
+void copy_runs(hipStream_t s, const int64_t* runs, int n_runs, const double* prev, double* x) {
+    if (n_runs <= 0) return;
+    hipLaunchKernelGGL(copy_runs_kernel, dim3(n_runs), dim3(256), 0, s, runs, n_runs, prev, x);
+    MORAP_HIP(hipGetLastError());
+}
+
 void select_final(hipStream_t s, const InstArgs& a, double* x0, const double* x1, const uint8_t* par,
                   int width) {
     if (a.n_tiles <= 0) return;

@@ -515,7 +515,10 @@ def test_synthesis_matches_oracle(ctx, morap, cfg):
     infeasible_t = mix + 0.05 * np.abs(mix)
     infeasible_t[nI:] = np.minimum(infeasible_t[nI:], 1.0)
     for t, feasible in ((feasible_t, True), (infeasible_t, False)):
-        g = ctx.query(t, eps=1e-6, max_iter=200, opts=o, trace=True)
+        # cold passes: the synthesis re-solves and re-evaluates from 0, so the
+        # points are reproduced to rounding (warm-started passes stop their
+        # evaluations elsewhere, within eps_eval)
+        g = ctx.query(t, eps=1e-6, max_iter=200, opts=o, trace=True, warm_start=False)
         syn = ctx.synthesize(g, o)
         picked = syn["picked"]
         assert len(picked) >= 1 and (g["lam"][picked] > 0).all()
