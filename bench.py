@@ -320,6 +320,8 @@ def main():
     ap.add_argument("--schedule", type=int, default=0,
                     help="sweep-kernel variant of the timed passes (0 = the autotuner's choice)")
     ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--no-graph", action="store_true",
+                    help="timed steps enqueue every launch instead of replaying captured graphs (profiler runs)")
     ap.add_argument("--query-max-iter", type=int, default=48,
                     help="Alg. 2 passes allowed per query in the ms-per-query measurement")
     ap.add_argument("--query-train", type=int, default=2048,
@@ -364,7 +366,7 @@ def main():
     log(f"{nI * nJ} products built and uploaded in {time.time() - t0:.1f} s: S={S} R={R} N={N}")
     # the timed steps replay captured graphs of sweep chunks; one extra pass
     # with HIP events around the sweep launches (eager) gives the kernel figures
-    opts = morap.Options(eps_vi=eps, precision=args.precision, schedule=args.schedule)
+    opts = morap.Options(eps_vi=eps, precision=args.precision, schedule=args.schedule, use_graph=not args.no_graph)
     opts_timed = morap.Options(eps_vi=eps, precision=args.precision, time_kernels=True, schedule=args.schedule)
     rng = np.random.default_rng(args.seed)
 
@@ -431,6 +433,7 @@ def main():
             "launches": st["sweeps_tail"], "launches_timed": st["sweep_launches_tail"],
             "avg_launch_us": round(avg_t * 1e6, 2), "bytes_per_launch": round(bt, 0),
             "achieved": round(bt / avg_t / 1e9, 1) if avg_t > 0 else None,
+            "traffic": measured_traffic(kernel_name(st["variant_tail"], args.precision)),
             "note": "the last sweeps of each solve (under 20 % of the tiles active) run the LDS-staged kernel"}
     if st["sweep_launches_refine"]:
         avg_r = st["ms_sweep_kernel_refine"] / 1e3 / st["sweep_launches_refine"]

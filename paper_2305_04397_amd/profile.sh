@@ -15,7 +15,10 @@ REPO=$(cd "$(dirname "$0")/.." && pwd)
 mkdir -p "$OUT"
 OUT=$(cd "$OUT" && pwd)
 cd /tmp && export TMPDIR=/tmp
-ARGS="$REPO/bench.py --steps 1 --warmup 1 --queries 0 --proposer-queries 0 --no-cpu-baseline $EXTRA"
+# --no-graph: launches are enqueued one by one (rocprofv3's kernel tracing
+# crashed the process replaying captured graphs); kernel durations do not
+# depend on how the launches are submitted
+ARGS="$REPO/bench.py --steps 1 --warmup 1 --queries 0 --proposer-queries 0 --no-cpu-baseline --no-graph $EXTRA"
 SUM="python3 -m paper_2305_04397_amd.profile_summary"
 echo "profile: kernel trace" && \
 timeout -k 10 600 rocprofv3 --kernel-trace --stats -d "$OUT/trace" -o run --output-format csv -- python3 $ARGS \
