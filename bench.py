@@ -469,7 +469,7 @@ def main():
             "stats": {k: st_graph[k] for k in ("backups", "sweeps", "sweeps_tail", "eval_sweeps", "polish_sweeps",
                                                "rank_rounds", "floor_stops", "ms_vi", "ms_eval", "variant",
                                                "variant_tail", "variant_refine", "bytes", "bytes_tail",
-                                               "bytes_refine")}}
+                                               "bytes_refine", "refine_pairs", "refine_columns")}}
     print(json.dumps(line), flush=True)
 
 

@@ -210,6 +210,10 @@ typedef struct {
     double  ms_sweep_kernel_tail;
     int32_t variant_tail;   /* that kernel's variant (0: no switch)                 */
     int32_t reserved;
+    int64_t refine_pairs;   /* support / query after FP32 solves: unassigned pairs   */
+                            /* within the FP32 error of the assignment re-solved in  */
+                            /* FP64 ...                                              */
+    int64_t refine_columns; /* ... and columns whose assignment they improved        */
 } morap_stats;
 
 /* Alg. 2 first loop / Alg. 3 for K weight vectors W[K][d] at once: for every
@@ -297,8 +301,14 @@ int morap_load_team_model(morap_ctx* ctx, int n_agents, int n_tasks, const morap
 int morap_assign_host(const double* c, int n_agents, int n_tasks, int K, int32_t* assign_out);
 
 /* Alg. 2 whole, for K weight vectors: solve -> assignment -> evaluate.
- * r_out[K][d], assign_out[K][|J|] (nullable), c_out[K][|I|][|J|] (nullable).
- * Errors: as morap_solve and morap_evaluate. */
+ * After an FP32 solve the assignment is checked on FP64 values: the FP64
+ * re-solve of the assigned pairs measures each column's FP32 error e; every
+ * other pair whose slack against the assignment (from the optimal duals) is
+ * at most 2e is re-solved in FP64 as well, the column is assigned again with
+ * these values, and it takes the new assignment when its value rises (stats:
+ * refine_pairs, refine_columns).  r_out[K][d], assign_out[K][|J|] (nullable;
+ * the assignment evaluated), c_out[K][|I|][|J|] (nullable; the solve's
+ * values).  Errors: as morap_solve and morap_evaluate. */
 int morap_support(morap_ctx* ctx, const double* W, int K, const morap_vi_opts* opts,
                   double* r_out, int32_t* assign_out, double* c_out, morap_stats* stats);
 

@@ -50,6 +50,8 @@ void to_abi(const Stats& s, morap_stats* out) {
     out->ms_sweep_kernel_tail = s.ms_sweep_kernel_tail;
     out->variant_tail = s.variant_tail;
     out->reserved = 0;
+    out->refine_pairs = s.refine_pairs;
+    out->refine_columns = s.refine_columns;
 }
 
 }  // namespace
@@ -262,7 +264,10 @@ int morap_support(morap_ctx* ctx, const double* W, int K, const morap_vi_opts* o
         solve(ctx, W, K, *opts, C.data(), st);
         // a team model's policy does the assignment itself: no assignment step
         if (!ctx->team) assign_columns(nI, nJ, C.data(), K, A.data());
-        evaluate(ctx, A.data(), K, *opts, r_out, st);
+        // after an FP32 solve the assignment is checked on FP64 values
+        std::vector<int32_t> F(A);
+        evaluate(ctx, A.data(), K, *opts, r_out, st, nullptr, ctx->team ? nullptr : F.data());
+        if (!ctx->team) A = F;
         if (assign_out && ctx->team) std::fill(assign_out, assign_out + (size_t)K * n_tasks_of(ctx), 0);
         else if (assign_out) std::copy(A.begin(), A.begin() + (size_t)K * nJ, assign_out);
         if (c_out) std::copy(C.begin(), C.begin() + (size_t)K * nI * nJ, c_out);

@@ -22,8 +22,10 @@ namespace morap {
 // cost 0) until a free column is reached at distance D; the potentials of
 // the columns settled on the way, and of their rows, move by D minus their
 // distance (which keeps the reduced costs >= 0 and zeroes them along the
-// path), and the path is flipped.  Returns col_of_row.
-static std::vector<int> min_cost_matching(const std::vector<double>& cost, int n) {
+// path), and the path is flipped.  Returns col_of_row; u_out / v_out
+// (nullable) receive the final potentials.
+static std::vector<int> min_cost_matching(const std::vector<double>& cost, int n, std::vector<double>* u_out = nullptr,
+                                          std::vector<double>* v_out = nullptr) {
     const double INF = std::numeric_limits<double>::infinity();
     std::vector<double> u(n, 0.0), v(n, 0.0), dist(n);
     std::vector<int> row_of_col(n, -1), col_of_row(n, -1), pred_row(n), settled;
@@ -78,7 +80,20 @@ static std::vector<int> min_cost_matching(const std::vector<double>& cost, int n
             k = prev;
         }
     }
+    if (u_out) *u_out = u;
+    if (v_out) *v_out = v;
     return col_of_row;
+}
+
+// The replicated square problem of one column (every agent row repeated
+// ceil(|J|/|I|) times, zero-value dummy tasks), as costs -c.
+static void column_costs(int nI, int nJ, int cap, const double* ck, std::vector<double>& cost) {
+    const int n = nI * cap;
+    cost.assign((size_t)n * n, 0.0);
+    for (int r = 0; r < n; ++r) {
+        const int i = r / cap;
+        for (int j = 0; j < nJ; ++j) cost[(size_t)r * n + j] = -ck[(size_t)i * nJ + j];
+    }
 }
 
 void assign_columns(int nI, int nJ, const double* c, int K, int32_t* out) {
@@ -93,11 +108,7 @@ void assign_columns(int nI, int nJ, const double* c, int K, int32_t* out) {
     auto worker = [&] {
         std::vector<double> cost((size_t)n * n);
         for (int k; (k = next++) < K;) {
-            const double* ck = c + (size_t)k * nI * nJ;
-            for (int r = 0; r < n; ++r) {
-                const int i = r / cap;
-                for (int j = 0; j < n; ++j) cost[(size_t)r * n + j] = j < nJ ? -ck[(size_t)i * nJ + j] : 0.0;
-            }
+            column_costs(nI, nJ, cap, c + (size_t)k * nI * nJ, cost);
             const auto match = min_cost_matching(cost, n);
             for (int r = 0; r < n; ++r)
                 if (match[r] >= 0 && match[r] < nJ) out[(size_t)k * nJ + match[r]] = r / cap;
@@ -111,6 +122,30 @@ void assign_columns(int nI, int nJ, const double* c, int K, int32_t* out) {
     std::vector<std::thread> th;
     for (int t = 0; t < nt; ++t) th.emplace_back(worker);
     for (auto& t : th) t.join();
+}
+
+// Slack of every (agent, task) pair against an optimal assignment of column
+// c[nI][nJ]: with the optimal dual potentials u (agent rows) and v (tasks)
+// of the cost form -c, slack(i, j) = min over agent i's rows r of
+// -c(i, j) - u(r) - v(j) >= 0, zero on the assigned pairs.  Any other
+// assignment's value falls short of the optimum by the sum of its pairs'
+// slacks.  Returns the assignment (agent of each task).
+std::vector<int32_t> assignment_slack(int nI, int nJ, const double* ck, double* slack) {
+    const int cap = std::max(1, (nJ + nI - 1) / nI);
+    const int n = nI * cap;
+    std::vector<double> cost, u, v;
+    column_costs(nI, nJ, cap, ck, cost);
+    const auto match = min_cost_matching(cost, n, &u, &v);
+    std::vector<int32_t> f(nJ, -1);
+    for (int r = 0; r < n; ++r)
+        if (match[r] >= 0 && match[r] < nJ) f[match[r]] = r / cap;
+    for (int i = 0; i < nI; ++i)
+        for (int j = 0; j < nJ; ++j) {
+            double best = INFINITY;
+            for (int r = i * cap; r < (i + 1) * cap; ++r) best = std::min(best, cost[(size_t)r * n + j] - u[r] - v[j]);
+            slack[(size_t)i * nJ + j] = std::max(0.0, best);
+        }
+    return f;
 }
 
 }  // namespace morap

@@ -188,6 +188,8 @@ struct Stats {
     int64_t sweeps_tail = 0, sweep_launches_tail = 0;
     double bytes_tail = 0, ms_sweep_kernel_tail = 0;
     int variant_tail = 0;
+    // the assignment check after FP32 solves: pairs re-solved, columns reassigned
+    int64_t refine_pairs = 0, refine_columns = 0;
 };
 
 // Values of one batched value iteration: two Jacobi buffers [S][Kp], the
@@ -293,6 +295,13 @@ struct morap_ctx {
     int prev_per_col = 0;
     bool eval_prev_valid = false;
     uint64_t prev_eval_gen = 0;
+    // FP64 values at the initial states of the assigned pairs of the last
+    // evaluation after an FP32 solve (valid when set), and the buffers of
+    // the re-solve of other pairs for the assignment check
+    std::vector<double> last_c64;
+    bool last_c64_valid = false;
+    morap::DevBuf d_cand_model, d_cand_k, d_cand_base, d_cand_tiles, d_cand_iwc, d_cand_iwp, d_cand_iscale;
+    morap::DevBuf d_cand_x0, d_cand_x1, d_cand_res, d_cand_act, d_cand_par, d_cand_init, d_cand_val;
     morap::DevBuf d_iwc, d_iwp;                     // per instance FP64 weights
     morap::DevBuf d_iscale;                         // per instance 1 / (w_i + w_j) (warm start)
     morap::DevBuf d_ichanged;                       // per instance: ranks changed in the last round
@@ -389,12 +398,21 @@ void solve(morap_ctx* ctx, const double* W, int K, const morap_vi_opts& o, doubl
 // warm (nullable): per column, the column of the previous evaluation whose
 // instance of the same task on the same model starts the policy evaluation
 // from its final values (-1: from 0, as Alg. 4)
+//
+// refine (nullable, FP32 solves of block-form products): the assignment
+// (assign) is checked against FP64 values -- every pair whose slack lies
+// within twice the column's largest FP32 error on its assigned pairs is
+// re-solved in FP64, the column is assigned again on the FP64 values, and a
+// column whose value rises takes the new assignment, which is then
+// evaluated; refine receives the assignment evaluated
 void evaluate(morap_ctx* ctx, const int32_t* assign, int K, const morap_vi_opts& o, double* r_out, Stats& st,
-              const int32_t* warm = nullptr);
+              const int32_t* warm = nullptr, int32_t* refine = nullptr);
 const std::vector<Variant>& variants();
 
 // assign.cpp
 void assign_columns(int nI, int nJ, const double* c, int K, int32_t* out);
+// one column's optimal assignment and the slack of every pair against it
+std::vector<int32_t> assignment_slack(int nI, int nJ, const double* ck, double* slack);
 
 // qp.cpp
 void project_inner(const double* Phi, int m, int d, const double* t, const double* M, double* x,
@@ -532,6 +550,8 @@ void team_eval_sweep(hipStream_t s, int64_t S, int d, const int32_t* pi, const i
                      const double* E_in, double* E_out, unsigned long long* res);
 void team_start(hipStream_t s, int64_t S, int K, int Kp, int d, const double* W, const double* E, int prec,
                 void* x);
+// out[q] = x[idx[q]] (0 where idx[q] < 0): one value per instance state
+void gather_values(hipStream_t s, int n, const int64_t* idx, const double* x, double* out);
 // runs (dst, src, length) of instance states [.][2] copied from prev to x
 void copy_runs(hipStream_t s, const int64_t* runs, int n_runs, const double* prev, double* x);
 // team models: out[r][k] = W[k][obj[r][0]] rew[r][0] + W[k][obj[r][1]] rew[r][1]

@@ -239,7 +239,11 @@ void query_batch(morap_ctx* c, const double* T, const double* W0, int Q, const d
                 const auto t1 = std::chrono::steady_clock::now();
                 // a team model's policy assigns by itself (A stays 0)
                 if (!c->team) assign_columns(nI, nJ, C.data(), K, A.data());
-                evaluate(c, A.data(), K, vo, R.data(), st, o.warm_start && it > 0 ? warm_map.data() : nullptr);
+                // after an FP32 solve the assignment is checked on FP64 values
+                std::vector<int32_t> F(A);
+                evaluate(c, A.data(), K, vo, R.data(), st, o.warm_start && it > 0 ? warm_map.data() : nullptr,
+                         c->team ? nullptr : F.data());
+                if (!c->team) A = F;
                 const auto t2 = std::chrono::steady_clock::now();
                 const double ms = std::chrono::duration<double, std::milli>(t2 - t0).count();
                 last_ms[0] = std::chrono::duration<double, std::milli>(t1 - t0).count();

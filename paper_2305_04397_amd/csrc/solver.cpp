@@ -10,7 +10,9 @@
 #include "common.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <thread>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -619,6 +621,8 @@ static void add_stats(Stats& a, const Stats& b) {
     a.bytes_tail += b.bytes_tail;
     a.ms_sweep_kernel_tail += b.ms_sweep_kernel_tail;
     a.variant_tail = b.variant_tail ? b.variant_tail : a.variant_tail;
+    a.refine_pairs += b.refine_pairs;
+    a.refine_columns += b.refine_columns;
     a.variant = b.variant ? b.variant : a.variant;
     a.variant_refine = b.variant_refine ? b.variant_refine : a.variant_refine;
 }
@@ -636,12 +640,28 @@ void solve(morap_ctx* c, const double* W, int K, const morap_vi_opts& o, double*
     add_stats(c->cum, local);
 }
 
+static std::vector<double> resolve_pairs(morap_ctx* c, const std::vector<int32_t>& pk,
+                                         const std::vector<int32_t>& pm, const morap_vi_opts& o, Stats& st);
+static int refine_assignment(morap_ctx* c, const int32_t* assign, int K, const morap_vi_opts& o, Stats& st,
+                             int32_t* out);
+
 void evaluate(morap_ctx* c, const int32_t* assign, int K, const morap_vi_opts& o, double* r_out, Stats& st,
-              const int32_t* warm) {
+              const int32_t* warm, int32_t* refine) {
     Stats local;
     c->eval_prev_valid = c->eval_prev_valid && c->prev_eval_gen == c->load_gen;
     try {
         evaluate_impl(c, assign, K, o, r_out, local, warm);
+        if (refine) {
+            std::copy(assign, assign + (size_t)K * c->hm.nJ, refine);
+            if (!c->team && c->prec == MORAP_F32 && c->has_blocks && c->last_c64_valid &&
+                refine_assignment(c, assign, K, o, local, refine) > 0) {
+                // again with the new assignment, each instance started from
+                // the first evaluation's values where the pair is unchanged
+                std::vector<int32_t> same(K);
+                for (int k = 0; k < K; ++k) same[k] = k;
+                evaluate_impl(c, refine, K, o, r_out, local, same.data());
+            }
+        }
     } catch (...) {
         c->eval_prev_valid = false;
         throw;
@@ -1005,6 +1025,18 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
         st.ms_vi += wall.elapsed_ms();
         st.polish_sweeps += vsweeps;
         st.variant_refine = -1;   // instance-major block iteration
+        // the assigned pairs' FP64 values at their initial states, for the
+        // weights of the column (the re-solve scaled them to sum 1)
+        c->last_c64_valid = false;
+        if (c->prec == MORAP_F32 && !team) {
+            double* v = c->d_init_val.as<double>();
+            k::gather_values(s, n, c->d_init_idx.as<int64_t>(), x0, v);
+            c->last_c64.resize(n);
+            MORAP_HIP(hipMemcpyAsync(c->last_c64.data(), v, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+            MORAP_HIP(hipStreamSynchronize(s));
+            for (int q = 0; q < n; ++q) c->last_c64[q] = iscale[q] > 0 ? c->last_c64[q] / iscale[q] : 0.0;
+            c->last_c64_valid = true;
+        }
     } else {
         const int M = c->hm.M, Kp = c->Kp;
         std::vector<double> wc((size_t)M * Kp, 0.0), wp((size_t)M * Kp, 0.0);
@@ -1196,6 +1228,187 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
     c->eval_prev_valid = true;
     st.ms_eval += ms;
     st.ms_total += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// ---------------------------------------------------------------------------
+// the assignment check after an FP32 solve
+// ---------------------------------------------------------------------------
+// FP64 value iteration (to eps_vi, instance-major over the block form, from
+// the FP32 values) of the (column k, model m) pairs listed; returns each
+// pair's value at its model's initial state for the column's own weights.
+// Uses buffers of its own: the last evaluation stays readable.
+static std::vector<double> resolve_pairs(morap_ctx* c, const std::vector<int32_t>& pk,
+                                         const std::vector<int32_t>& pm, const morap_vi_opts& o, Stats& st) {
+    const int n = (int)pk.size();
+    const int nI = c->hm.nI, nJ = c->hm.nJ, d = nI + nJ;
+    hipStream_t s = c->stream;
+    std::vector<int64_t> base(n + 1, 0), init_idx(n, -1);
+    std::vector<int32_t> tiles;
+    std::vector<double> iwc(n), iwp(n), iscale(n, 0.0);
+    for (int q = 0; q < n; ++q) {
+        const int m = pm[q], i = m / nJ, j = m % nJ;
+        const int S_m = c->hm.state_base[m + 1] - c->hm.state_base[m];
+        base[q + 1] = base[q] + S_m;
+        for (int b = 0; b < S_m; b += 256) {
+            tiles.push_back(q);
+            tiles.push_back(b);
+        }
+        iwc[q] = c->W[(size_t)pk[q] * d + i];
+        iwp[q] = c->W[(size_t)pk[q] * d + nI + j];
+        const double sc = iwc[q] + iwp[q];
+        if (sc > 0) {
+            iwc[q] /= sc;
+            iwp[q] /= sc;
+            iscale[q] = 1.0 / sc;
+        }
+        if (c->hm.init[m] >= 0) init_idx[q] = base[q] + (c->hm.init[m] - c->hm.state_base[m]);
+    }
+    const int64_t NS = base[n];
+    c->d_cand_model.ensure((size_t)n * 4);
+    c->d_cand_k.ensure((size_t)n * 4);
+    c->d_cand_base.ensure((size_t)(n + 1) * 8);
+    c->d_cand_tiles.ensure(tiles.size() * 4 + 8);
+    c->d_cand_iwc.ensure((size_t)n * 8);
+    c->d_cand_iwp.ensure((size_t)n * 8);
+    c->d_cand_iscale.ensure((size_t)n * 8);
+    c->d_cand_x0.ensure((size_t)NS * 8 + 8);
+    c->d_cand_x1.ensure((size_t)NS * 8 + 8);
+    c->d_cand_res.ensure((size_t)n * 8);
+    c->d_cand_act.ensure((size_t)n);
+    c->d_cand_par.ensure((size_t)n);
+    c->d_cand_init.ensure((size_t)n * 8);
+    c->d_cand_val.ensure((size_t)n * 8);
+    MORAP_HIP(hipMemcpyAsync(c->d_cand_model.p, pm.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+    MORAP_HIP(hipMemcpyAsync(c->d_cand_k.p, pk.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+    MORAP_HIP(hipMemcpyAsync(c->d_cand_base.p, base.data(), (size_t)(n + 1) * 8, hipMemcpyHostToDevice, s));
+    MORAP_HIP(hipMemcpyAsync(c->d_cand_tiles.p, tiles.data(), tiles.size() * 4, hipMemcpyHostToDevice, s));
+    MORAP_HIP(hipMemcpyAsync(c->d_cand_iwc.p, iwc.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+    MORAP_HIP(hipMemcpyAsync(c->d_cand_iwp.p, iwp.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+    MORAP_HIP(hipMemcpyAsync(c->d_cand_iscale.p, iscale.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+    MORAP_HIP(hipMemcpyAsync(c->d_cand_init.p, init_idx.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+    k::InstArgs a = inst_args(c, (int)(tiles.size() / 2), n);
+    a.inst_model = c->d_cand_model.as<int32_t>();
+    a.inst_k = c->d_cand_k.as<int32_t>();
+    a.inst_base = c->d_cand_base.as<int64_t>();
+    a.inst_tiles = c->d_cand_tiles.as<int32_t>();
+    double* x0 = c->d_cand_x0.as<double>();
+    double* x1 = c->d_cand_x1.as<double>();
+    unsigned long long* res = c->d_cand_res.as<unsigned long long>();
+    uint8_t* act = c->d_cand_act.as<uint8_t>();
+    uint8_t* par = c->d_cand_par.as<uint8_t>();
+    int64_t* dctr = c->d_counters.as<int64_t>();
+    int64_t* h = c->h_counters.as<int64_t>();
+    k::warm_start(s, a, c->vmain.x[0].p, c->vmain.x[1].p, c->vmain.final_par.as<uint8_t>(), c->vmain.Kp,
+                  c->d_cand_iscale.as<double>(), c->d_cand_iwc.as<double>(), x0);
+    k::fill_f64(s, x1, 0.0, NS);
+    k::set_active(s, n, a, act, res, par, 1);
+    const int chunk = std::max(2, (o.check_every + 1) / 2 * 2);
+    int64_t sweeps = 0;
+    while (true) {
+        for (int i = 0; i < chunk; ++i) {
+            const bool even = (i & 1) == 0;
+            k::inst_vi_sweep(s, a, c->d_blk_rec.as<int32_t>(), c->d_blk64.as<double>(), c->d_cand_iwc.as<double>(),
+                             c->d_cand_iwp.as<double>(), act, even ? x0 : x1, even ? x1 : x0, res, (int32_t)c->S,
+                             c->hm.blk_pattern);
+            k::inst_converge(s, n, res, act, par, even ? 1 : 0, o.eps_vi, dctr);
+        }
+        sweeps += chunk;
+        read_counters(c);
+        if (h[0] == 0) break;
+        MORAP_CHECK(sweeps < o.max_sweeps, MORAP_E_NOT_CONVERGED,
+                    "value iteration of the pairs of the assignment check did not converge");
+    }
+    k::select_final(s, a, x0, x1, par, 1);
+    k::gather_values(s, n, c->d_cand_init.as<int64_t>(), x0, c->d_cand_val.as<double>());
+    std::vector<double> out(n);
+    MORAP_HIP(hipMemcpyAsync(out.data(), c->d_cand_val.p, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+    MORAP_HIP(hipStreamSynchronize(s));
+    for (int q = 0; q < n; ++q) out[q] = iscale[q] > 0 ? out[q] / iscale[q] : 0.0;
+    st.polish_sweeps += sweeps;
+    return out;
+}
+
+// The assignment of each column was taken on FP32 values c.  Their error on
+// the column's assigned pairs, e_k, is known from the FP64 re-solve; every
+// unassigned pair whose slack (the value an assignment using it gives up,
+// from the optimal duals) is at most 2 e_k could enter a better assignment
+// once corrected by that much, so it is re-solved in FP64 too.  The column
+// is then assigned again on c with the FP64 values of all these pairs; it
+// takes the new assignment when that raises its value by more than 1e-9 of
+// it.
+// Returns the number of columns that changed (their assignments in out).
+static int refine_assignment(morap_ctx* c, const int32_t* assign, int K, const morap_vi_opts& o, Stats& st,
+                             int32_t* out) {
+    const int nI = c->hm.nI, nJ = c->hm.nJ, M = c->hm.M;
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<double> C((size_t)K * M);
+    MORAP_HIP(hipMemcpy(C.data(), c->vmain.c.p, C.size() * 8, hipMemcpyDeviceToHost));   // [K][M]
+    // the pairs to re-solve, per column (columns on host threads)
+    std::vector<std::vector<int32_t>> cand(K);
+    std::atomic<int> next{0};
+    auto worker = [&] {
+        std::vector<double> slack((size_t)M);
+        for (int k; (k = next++) < K;) {
+            const double* ck = C.data() + (size_t)k * M;
+            double e = 0, cmax = 0;
+            for (int j = 0; j < nJ; ++j) {
+                const int m = assign[(size_t)k * nJ + j] * nJ + j;
+                e = std::max(e, std::fabs(ck[m] - c->last_c64[(size_t)k * nJ + j]));
+            }
+            for (int m = 0; m < M; ++m) cmax = std::max(cmax, std::fabs(ck[m]));
+            const double theta = 2.0 * e + 1e-12 * std::max(1.0, cmax);
+            assignment_slack(nI, nJ, ck, slack.data());
+            for (int i = 0; i < nI; ++i)
+                for (int j = 0; j < nJ; ++j)
+                    if (assign[(size_t)k * nJ + j] != i && slack[(size_t)i * nJ + j] <= theta)
+                        cand[k].push_back(i * nJ + j);
+        }
+    };
+    {
+        const int nt = std::max(1, std::min<int>(K, (int)std::min(16u, std::thread::hardware_concurrency())));
+        std::vector<std::thread> th;
+        for (int t = 1; t < nt; ++t) th.emplace_back(worker);
+        worker();
+        for (auto& t : th) t.join();
+    }
+    std::vector<int32_t> pk, pm;
+    for (int k = 0; k < K; ++k)
+        for (int32_t m : cand[k]) {
+            pk.push_back(k);
+            pm.push_back(m);
+        }
+    st.refine_pairs += (int64_t)pk.size();
+    const auto t1 = std::chrono::steady_clock::now();
+    if (pk.empty()) return 0;
+    const std::vector<double> v = resolve_pairs(c, pk, pm, o, st);
+    if (std::getenv("MORAP_PROGRESS"))
+        std::fprintf(stderr, "[morap] assignment check: %zu pairs re-solved; slacks %.1f ms, re-solve %.1f ms\n",
+                     pk.size(), std::chrono::duration<double, std::milli>(t1 - t0).count(),
+                     std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count());
+    // c with the FP64 values of the assigned and the re-solved pairs
+    for (int k = 0; k < K; ++k)
+        for (int j = 0; j < nJ; ++j)
+            C[(size_t)k * M + assign[(size_t)k * nJ + j] * nJ + j] = c->last_c64[(size_t)k * nJ + j];
+    for (size_t q = 0; q < pk.size(); ++q) C[(size_t)pk[q] * M + pm[q]] = v[q];
+    std::vector<int32_t> A((size_t)K * nJ);
+    assign_columns(nI, nJ, C.data(), K, A.data());
+    int changed = 0;
+    for (int k = 0; k < K; ++k) {
+        const double* ck = C.data() + (size_t)k * M;
+        double v_old = 0, v_new = 0;
+        for (int j = 0; j < nJ; ++j) {
+            v_old += ck[assign[(size_t)k * nJ + j] * nJ + j];
+            v_new += ck[A[(size_t)k * nJ + j] * nJ + j];
+        }
+        // gains below 1e-9 of the column's value are under the accuracy of
+        // the FP64 values themselves (each stops at eps_vi)
+        if (v_new > v_old + 1e-9 * std::max(1.0, std::fabs(v_old))) {
+            std::copy(A.begin() + (size_t)k * nJ, A.begin() + (size_t)(k + 1) * nJ, out + (size_t)k * nJ);
+            ++changed;
+        }
+    }
+    st.refine_columns += changed;
+    return changed;
 }
 
 }  // namespace morap

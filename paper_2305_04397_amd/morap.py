@@ -77,7 +77,8 @@ class Stats(C.Structure):
                 ("ms_sweep_kernel_refine", C.c_double), ("sweep_launches_refine", C.c_int64),
                 ("variant", C.c_int32), ("variant_refine", C.c_int32), ("sweeps_tail", C.c_int64),
                 ("sweep_launches_tail", C.c_int64), ("bytes_tail", C.c_double),
-                ("ms_sweep_kernel_tail", C.c_double), ("variant_tail", C.c_int32), ("reserved", C.c_int32)]
+                ("ms_sweep_kernel_tail", C.c_double), ("variant_tail", C.c_int32), ("reserved", C.c_int32),
+                ("refine_pairs", C.c_int64), ("refine_columns", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}

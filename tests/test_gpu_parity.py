@@ -620,3 +620,53 @@ def test_f32_solve_more_than_64_columns(ctx, morap, K):
     assert st["variant"] > 18
     co, _, _ = _oracle_c(prods, nI, nJ, W, eps)
     assert (np.abs(c - co) <= 2e-4 * np.maximum(1.0, np.abs(co))).all()
+
+
+def test_assignment_check_after_fp32_solves(ctx, morap):
+    """After an FP32 solve the support step checks its assignment on FP64
+    values: pairs whose slack lies within twice the column's FP32 error are
+    re-solved in FP64 and the column reassigned if that raises its value.
+    With agent 1 a copy of agent 0, every task ties between the two: the tied
+    pairs are re-solved (refine_pairs > 0) and no column changes (the values
+    stay equal); on every column the assignment is optimal for the FP64
+    values of a full FP64 solve to rounding, and the evaluated point is the
+    one morap_evaluate gives for that assignment."""
+    import dataclasses
+    base = make_workload(1)
+    agents = [base.agents[0], base.agents[0]]
+    letters = [base.letters[0], base.letters[0]]
+    wl = dataclasses.replace(base, agents=agents, letters=letters)
+    ctx.build_products(wl)
+    nI, nJ = wl.n_agents, wl.n_tasks
+    W = dirichlet_weights(np.random.default_rng(8), 16, nI + nJ)
+    W[:, 1] = W[:, 0]           # the two agents' costs weigh the same: exact ties
+    W /= W.sum(axis=1, keepdims=True)
+    o = morap.Options(eps_vi=1e-6, eps_eval=1e-10, precision="f32")
+    r, A, c, st = ctx.support(W, o)
+    assert st["refine_pairs"] > 0 and st["refine_columns"] == 0
+    c64, _ = ctx.solve(W, morap.Options(eps_vi=1e-12, precision="f64"))
+    for k in range(len(W)):
+        opt = max(sum(c64[k][f[j], j] for j in range(nJ)) for f in ([0, 1], [1, 0], [0, 0], [1, 1])
+                  if max(np.bincount(f, minlength=nI)) <= 1)
+        val = sum(c64[k][A[k][j], j] for j in range(nJ))
+        assert val >= opt - 1e-9 * max(1.0, abs(opt)), k
+    ctx.solve(W, o)
+    r2, _ = ctx.evaluate(A, o)
+    assert np.abs(r2 - r).max() <= 1e-9 * max(1.0, np.abs(r).max())
+
+
+def test_assignment_check_keeps_parity_on_cfg2(ctx, morap):
+    """The 10 x 20 family in FP32: every column's assignment is optimal for
+    the values of a full FP64 solve within the FP64 solve's accuracy."""
+    wl = make_workload(2)
+    ctx.build_products(wl)
+    nI, nJ = wl.n_agents, wl.n_tasks
+    W = dirichlet_weights(np.random.default_rng(9), 32, nI + nJ)
+    r, A, c, st = ctx.support(W, morap.Options(eps_vi=1e-6, precision="f32"))
+    c64, _ = ctx.solve(W, morap.Options(eps_vi=1e-12, precision="f64"))
+    A64 = ctx.assign(c64)
+    for k in range(len(W)):
+        opt = sum(c64[k][A64[k][j], j] for j in range(nJ))
+        val = sum(c64[k][A[k][j], j] for j in range(nJ))
+        assert val >= opt - 1e-9 * max(1.0, abs(opt)), (k, val, opt)
+    assert st["refine_pairs"] >= 0 and st["refine_columns"] >= 0
