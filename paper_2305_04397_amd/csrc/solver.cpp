@@ -1358,9 +1358,12 @@ static int refine_assignment(morap_ctx* c, const int32_t* assign, int K, const m
             for (int m = 0; m < M; ++m) cmax = std::max(cmax, std::fabs(ck[m]));
             const double theta = 2.0 * e + 1e-12 * std::max(1.0, cmax);
             assignment_slack(nI, nJ, ck, slack.data());
+            // pairs whose two weights are 0 have the value 0 in any precision
+            const double* w = c->W.data() + (size_t)k * (nI + nJ);
             for (int i = 0; i < nI; ++i)
                 for (int j = 0; j < nJ; ++j)
-                    if (assign[(size_t)k * nJ + j] != i && slack[(size_t)i * nJ + j] <= theta)
+                    if (assign[(size_t)k * nJ + j] != i && slack[(size_t)i * nJ + j] <= theta &&
+                        w[i] + w[nI + j] > 0)
                         cand[k].push_back(i * nJ + j);
         }
     };
