@@ -497,7 +497,15 @@ static const Variant* tail_variant(morap_ctx* c, const ValueSet& vs, const uint8
         if (t.kind == SWEEP_HALO && t.unroll == 2) return &t;
     return nullptr;
 }
-constexpr int kTailPercent = 20;   // switch below this share of the tiles
+// switch below this share of the tiles (MORAP_TAIL_PERCENT overrides it,
+// 0 never switches)
+static int tail_percent() {
+    static const int p = [] {
+        const char* e = std::getenv("MORAP_TAIL_PERCENT");
+        return e && *e ? std::max(0, std::min(100, std::atoi(e))) : 20;
+    }();
+    return p;
+}
 
 static void run_vi(morap_ctx* c, int g, ValueSet& vs, const uint8_t* mask, const morap_vi_opts& o, Stats& st,
                    bool warm = false) {
@@ -557,7 +565,7 @@ static void run_vi(morap_ctx* c, int g, ValueSet& vs, const uint8_t* mask, const
         read_counters(c);
         harvest();
         if (h[3] == 0) break;
-        if (vt && vp == &v0 && h[1] * 100 < main_tiles * kTailPercent) {
+        if (vt && vp == &v0 && h[1] * 100 < main_tiles * tail_percent()) {
             // the same active models listed over the halo tiles
             bytes_at_switch = (double)h[6] + 2.0 * el * (double)h[7];
             sweeps_at_switch = h[5];
