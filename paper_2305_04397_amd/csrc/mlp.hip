@@ -9,7 +9,7 @@
 // the batch; optimiser Adam with bias correction.
 //
 // Precision: BF16 weights, inputs, activations and back-propagated gradients,
-// FP32 accumulation on the matrix cores (v_mfma_f32_16x16x16bf16_1k), FP32
+// FP32 accumulation on the matrix cores (v_mfma_f32_16x16x32_bf16), FP32
 // biases, logits, softmax, weight gradients and Adam state, FP32 master
 // weights (the BF16 copies are refreshed by every Adam step).
 //
@@ -34,7 +34,8 @@ namespace morap {
 
 namespace {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));          // BF16 bits
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int HID = 256;
@@ -77,30 +78,32 @@ __global__ void __launch_bounds__(256) gemm_bf16(GemmArgs g) {
     const int tiles_n = (g.N + 63) / 64;
     const int tm = wave / tiles_n, tn = wave - tm * tiles_n;
     if (tm * 16 >= g.M) return;
-    // operand layout of the 16x16x16 BF16 MFMA: lane l holds A[l % 16][4 (l / 16) + e]
-    // and B[4 (l / 16) + e][l % 16] for e = 0..3; the result D[4 (l / 16) + e][l % 16]
+    // operand layout of gfx950's 16x16x32 BF16 MFMA: lane l holds
+    // A[l % 16][8 (l / 16) + e] and B[8 (l / 16) + e][l % 16] for e = 0..7;
+    // the result D[4 (l / 16) + e][l % 16] for e = 0..3
     const int r = lane & 15, kg = lane >> 4;
     const int m = tm * 16 + r;
     f32x4 acc[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < g.K; k0 += 16) {
-        bf16x4 a;
+    for (int k0 = 0; k0 < g.K; k0 += 32) {
+        s16x8 a;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int k = k0 + 4 * kg + e;
+        for (int e = 0; e < 8; ++e) {
+            const int k = k0 + 8 * kg + e;
             a[e] = (m < g.M && k < g.K) ? (short)g.A[m * g.sam + k * g.sak] : (short)0;
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int n = tn * 64 + j * 16 + r;
-            bf16x4 b;
+            s16x8 b;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int k = k0 + 4 * kg + e;
+            for (int e = 0; e < 8; ++e) {
+                const int k = k0 + 8 * kg + e;
                 b[e] = (n < g.N && k < g.K) ? (short)g.B[k * g.sbk + n * g.sbn] : (short)0;
             }
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[j], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                             __builtin_bit_cast(bf16x8, b), acc[j], 0, 0, 0);
         }
     }
 #pragma unroll
