@@ -128,6 +128,48 @@ def query_stats(res, wall_ms: float, eps: float, morap) -> dict:
             "backups": int(sum(q["backups"] for q in res))}
 
 
+_SINGLE_CORE = r'''
+import json, os, sys, time
+os.sched_setaffinity(0, {sorted(os.sched_getaffinity(0))[0]})
+sys.path.insert(0, sys.argv[1])
+import numpy as np
+from workloads import make_workload, dirichlet_weights
+from oracle import product, alg
+out = {}
+for cfg, name in ((1, "2x2"), (2, "10x20")):
+    wl = make_workload(cfg)
+    t0 = time.perf_counter()
+    prods = product.build_all(wl)
+    build = time.perf_counter() - t0
+    nI, nJ = wl.n_agents, wl.n_tasks
+    W = dirichlet_weights(np.random.default_rng(3), 4, nI + nJ)
+    t0 = time.perf_counter()
+    for w in W:
+        r = alg.support(prods, nI, nJ, w, 1e-6).r
+    per = (time.perf_counter() - t0) / len(W)
+    t = r - 0.05 * np.abs(r)
+    t0 = time.perf_counter()
+    q = alg.query(prods, nI, nJ, t, 0.01, 1e-6)
+    out[name] = {"product_build_s": round(build, 3), "support_s_per_weight_vector": round(per, 3),
+                 "query_s": round(time.perf_counter() - t0, 3), "query_passes": int(q.iterations)}
+print(json.dumps(out))
+'''
+
+
+def oracle_single_core() -> dict:
+    """The FP64 oracle on one host core (one thread: BLAS threads 1, the
+    process pinned to one core), on the 2 x 2 and 10 x 20 workloads in full:
+    product construction, one support step (Alg. 2) per Dirichlet weight
+    vector, and one query (Alg. 1, eps 0.01) just below a support point."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", _SINGLE_CORE, ROOT], capture_output=True, text=True, env=env,
+                       timeout=1200)
+    if r.returncode != 0:
+        raise RuntimeError("single-core oracle run failed: " + r.stderr[-2000:])
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def query_eval(ctx, wl, front, rng, args, eps_vi: float) -> dict:
     """ms per point-oriented Pareto query on the timed workload, plain and
     learned first weight.  Thresholds: half below front points (achievable),
@@ -332,6 +374,8 @@ def main():
     ap.add_argument("--proposer-train", type=int, default=200_000,
                     help="training tuples over the 10x20 variants (support points, two thresholds each)")
     ap.add_argument("--proposer-variants", type=int, default=4)
+    ap.add_argument("--oracle-single-core", action="store_true",
+                    help="also time the FP64 oracle on one core on the 2x2 and 10x20 workloads in full (~2 min)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path runs on a single MI355X (multi-GPU sharding is "
@@ -355,6 +399,12 @@ def main():
         workers = max(1, min(args.cpu_workers, len(os.sched_getaffinity(0))))
         cpu = cpu_baseline(wl, K, eps, args.cpu_seconds, args.seed, workers)
         log(f"cpu baseline: {cpu['value']:.3e} backups/s on {workers} processes")
+    if args.oracle_single_core:
+        single = oracle_single_core()
+        log(f"oracle on one core: {single}")
+        if cpu is None:
+            cpu = {"kind": "oracle"}
+        cpu["single_core_full_workloads"] = single
     ctx = morap.Context(0)
     t0 = time.time()
     ctx.build_products(wl)
