@@ -144,14 +144,16 @@ for cfg, name in ((1, "2x2"), (2, "10x20")):
     nI, nJ = wl.n_agents, wl.n_tasks
     W = dirichlet_weights(np.random.default_rng(3), 4, nI + nJ)
     t0 = time.perf_counter()
-    for w in W:
+    for k, w in enumerate(W):
         r = alg.support(prods, nI, nJ, w, 1e-6).r
+        print(f"[bench] single-core oracle {name}: support step {k + 1}/{len(W)} done", file=sys.stderr, flush=True)
     per = (time.perf_counter() - t0) / len(W)
     t = r - 0.05 * np.abs(r)
     t0 = time.perf_counter()
     q = alg.query(prods, nI, nJ, t, 0.01, 1e-6)
     out[name] = {"product_build_s": round(build, 3), "support_s_per_weight_vector": round(per, 3),
                  "query_s": round(time.perf_counter() - t0, 3), "query_passes": int(q.iterations)}
+    print(f"[bench] single-core oracle {name}: {out[name]}", file=sys.stderr, flush=True)
 print(json.dumps(out))
 '''
 
@@ -163,10 +165,10 @@ def oracle_single_core() -> dict:
     vector, and one query (Alg. 1, eps 0.01) just below a support point."""
     import subprocess
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    r = subprocess.run([sys.executable, "-c", _SINGLE_CORE, ROOT], capture_output=True, text=True, env=env,
+    r = subprocess.run([sys.executable, "-c", _SINGLE_CORE, ROOT], stdout=subprocess.PIPE, text=True, env=env,
                        timeout=1200)
     if r.returncode != 0:
-        raise RuntimeError("single-core oracle run failed: " + r.stderr[-2000:])
+        raise RuntimeError(f"single-core oracle run failed with status {r.returncode} (its stderr is above)")
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
