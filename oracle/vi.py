@@ -8,6 +8,10 @@ Readings taken here:
     computes y = T(x_{n-1}) from x_0 = 0 and stops at the first n with
     max_s |y - x_{n-1}| <= eps, returning that sweep's y.  The fixed point is
     the same; only where the iteration stops changes.
+  * Stage retirement inside the iteration (``stage_retired_value_iteration``):
+    a stage (height of its location group in the product's location DAG)
+    stops being backed up in a column once every lower stage has stopped and
+    its own largest change is <= eps; its values stay those of that sweep.
   * The policy is extracted from the final values, not along the trajectory
     (the trajectory rule of Alg. 3 is kept as ``policy_rule="paper"``, parity
     unpinned).
@@ -158,6 +162,59 @@ def stage_ordered_value_iteration(prod: Product, wc, wp, eps: float, max_sweeps:
             sweeps[g, cols[done]] = n
             active[cols[done]] = False
     return x, sweeps
+
+
+def stage_retired_value_iteration(prod: Product, wc, wp, eps: float, max_sweeps: int = 1_000_000):
+    """Value iteration in which stages retire inside the Jacobi iteration
+    (the staged form of Alg. 3 that keeps the plain sweep count).
+
+    Every sweep backs up the states of the stages still active in a column
+    (``location_stages``) from the previous sweep's values, exactly as
+    ``value_iteration``; the states of a retired stage keep their values.
+    After the sweep the stages of each column are taken in increasing order:
+    a stage retires when every lower stage has retired (in an earlier sweep or
+    in this one) and the largest change over its own states in this sweep is
+    <= eps.  A column is done when all its stages have retired; with one
+    stage this is ``value_iteration`` itself.  The fixed point is the one of
+    Alg. 3; the stopping points differ.
+
+    Returns (y [S, K], retired [n_stages, K] = the sweep in which each stage
+    retired, backups = the rows backed up over all sweeps and columns)."""
+    r = scalarised_rewards(prod, wc, wp)
+    K = r.shape[1]
+    S = prod.n_states
+    x = np.zeros((S, K))
+    if S == 0:
+        return x, np.zeros((0, K), dtype=np.int64), 0
+    stage = location_stages(prod)
+    n_stages = int(stage.max()) + 1
+    rows_of_stage = np.bincount(stage, weights=np.diff(prod.state_row), minlength=n_stages).astype(np.int64)
+    retired = np.zeros((n_stages, K), dtype=np.int64)   # 0 = not yet
+    P = prod.P()
+    backups = 0
+    n = 0
+    while (retired == 0).any():
+        n += 1
+        if n > max_sweeps:
+            raise RuntimeError("value iteration did not converge")
+        live = retired == 0                       # [n_stages, K] stages swept now
+        y = _state_max(prod, r + P @ x)
+        swept = live[stage]                       # [S, K]
+        y = np.where(swept, y, x)
+        change = np.abs(y - x)
+        backups += int((rows_of_stage[:, None] * live).sum())
+        for k in range(K):
+            lower_done = True
+            for g in range(n_stages):
+                if retired[g, k]:
+                    continue
+                res = change[stage == g, k].max()
+                if lower_done and res <= eps:
+                    retired[g, k] = n
+                else:
+                    lower_done = False
+        x = y
+    return x, retired, backups
 
 
 def q_values(prod: Product, x: np.ndarray, wc, wp) -> np.ndarray:

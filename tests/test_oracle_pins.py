@@ -928,6 +928,57 @@ def test_stage_ordered_vi_trades_updates_for_sweeps():
     assert np.abs(xs - xp).max() <= 1e-4
 
 
+def test_stage_retired_vi_on_one_location_is_plain_vi():
+    """With one stage the in-iteration retirement is Alg. 3's iteration, bit
+    for bit and sweep for sweep, and backs up every row in every sweep."""
+    wl = tiny_workload(72, 1, 1, width=4, height=4, kinds=("avoid",), k=1, p_slip=0.2)
+    p = product.build_all(wl)[0]
+    W = np.random.default_rng(72).dirichlet(np.ones(2), size=4)
+    xr, ret, backups = vi.stage_retired_value_iteration(p, W[:, 0], W[:, 1], 1e-9)
+    xp, sp_ = vi.value_iteration(p, W[:, 0], W[:, 1], 1e-9)
+    assert ret.shape == (1, 4)
+    assert np.array_equal(xr, xp) and np.array_equal(ret[0], sp_)
+    assert backups == p.n_rows * sp_.max() * 4 - p.n_rows * (sp_.max() - sp_).sum()
+
+
+@pytest.mark.parametrize("seed", [73, 74])
+def test_stage_retired_vi_reaches_the_lp_optimum(seed):
+    """Four stages retiring inside the iteration reach the occupation-measure
+    LP's optimum at the initial state and plain VI's values everywhere; the
+    stages retire lowest first."""
+    wl = tiny_workload(seed, 1, 1, width=3, height=3, kinds=("reach",), k=4, p_slip=0.2)
+    prods = product.build_all(wl)
+    p = prods[0]
+    Aeq, beq, obj = _mo_lp(prods, 1, 1)
+    W = np.vstack([np.random.default_rng(seed).dirichlet(np.ones(2), size=3), [[0.0, 1.0]]])
+    xr, ret, _ = vi.stage_retired_value_iteration(p, W[:, 0], W[:, 1], 1e-12)
+    assert ret.shape[0] == 4 and (ret > 0).all()
+    assert (np.diff(ret, axis=0) >= 0).all()
+    xp, _ = vi.value_iteration(p, W[:, 0], W[:, 1], 1e-12)
+    assert np.abs(xr - xp).max() <= 1e-9 * max(1.0, np.abs(xp).max())
+    for col, w in enumerate(W):
+        lp = linprog(-(w @ obj), A_eq=Aeq, b_eq=beq, bounds=[(0, None)] * Aeq.shape[1], method="highs")
+        assert lp.status == 0
+        assert xr[p.init, col] == pytest.approx(-lp.fun, abs=1e-7)
+
+
+def test_stage_retired_vi_keeps_the_sweep_count_and_saves_updates():
+    """On the reach-seq(7) product the lower stages retire early while the
+    sweep count stays plain VI's (within a sweep or two), so fewer rows are
+    backed up; the values stay within eps-scale of plain VI's."""
+    wl = make_workload(2, n_agents=1, n_tasks=20)
+    j = next(b for b, t in enumerate(wl.tasks) if t.kind == "reach" and t.n_locs == 8)
+    p = product.build_product(wl.agents[0], wl.tasks[j], wl.letters[0][j])
+    W = np.array([[0.3, 0.7], [0.05, 0.95]])
+    xr, ret, backups = vi.stage_retired_value_iteration(p, W[:, 0], W[:, 1], 1e-6)
+    xp, sp_ = vi.value_iteration(p, W[:, 0], W[:, 1], 1e-6)
+    assert ret.shape[0] == 7
+    assert (ret.max(axis=0) <= sp_ + 2).all()
+    assert (ret[0] < ret[-1]).all()
+    assert backups < p.n_rows * sp_.sum()
+    assert np.abs(xr - xp).max() <= 1e-4
+
+
 # --------------------------------------------------------------------------
 # the pins have teeth: a plausible mistake planted in the oracle (on the CPU,
 # through monkeypatch) makes the independent check disagree far beyond its
@@ -992,6 +1043,22 @@ def test_mutation_reversed_stage_order_fails_the_plain_vi_pin(monkeypatch):
     monkeypatch.setattr(vi, "location_stages", lambda q: real(q).max() - real(q))
     xs, _ = vi.stage_ordered_value_iteration(p, W[:, 0], W[:, 1], 1e-12)
     assert np.abs(xs - xp).max() > 1e-3
+
+
+def test_mutation_reversed_retirement_order_fails_the_plain_vi_pin(monkeypatch):
+    """Retiring the stage of the initial state first (stage order reversed)
+    freezes it at 0 under probability-only weights: its states see no reward
+    until the lower stages' values arrive."""
+    wl = tiny_workload(73, 1, 1, width=3, height=3, kinds=("reach",), k=4, p_slip=0.2)
+    p = product.build_all(wl)[0]
+    W = np.array([[0.0, 1.0]])
+    xp, _ = vi.value_iteration(p, W[:, 0], W[:, 1], 1e-12)
+    xr, _, _ = vi.stage_retired_value_iteration(p, W[:, 0], W[:, 1], 1e-12)
+    assert np.abs(xr - xp).max() <= 1e-9
+    real = vi.location_stages
+    monkeypatch.setattr(vi, "location_stages", lambda q: real(q).max() - real(q))
+    xr, _, _ = vi.stage_retired_value_iteration(p, W[:, 0], W[:, 1], 1e-12)
+    assert np.abs(xr - xp).max() > 1e-3
 
 
 def test_mutation_frozen_weight_update_fails_the_projection_pin(monkeypatch):
