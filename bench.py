@@ -172,6 +172,30 @@ def oracle_single_core() -> dict:
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
+def stage_retirement_eval(ctx, rng, K: int, d: int, eps: float) -> dict:
+    """FP64 value iteration of K Dirichlet weight columns on the loaded
+    products, plain (morap_solve, graphs) and with stage retirement
+    (morap_solve_staged, eager launches): wall time of the second of two
+    runs each, sweeps, backups and algorithmic bytes, and the largest change
+    of a value at an initial state."""
+    from paper_2305_04397_amd import morap
+    W = rng.dirichlet(np.ones(d), size=K)
+    o = morap.Options(eps_vi=eps, precision="f64")
+    out = {"precision": "f64", "K": K, "eps_vi": eps}
+    c = {}
+    for name, fn in (("plain", ctx.solve), ("staged", ctx.solve_staged)):
+        for _ in range(2):
+            t0 = time.perf_counter()
+            c[name], st = fn(W, o)
+            ms = (time.perf_counter() - t0) * 1e3
+        out[name] = {"ms": round(ms, 1), "sweeps": st["sweeps"], "backups": st["backups"],
+                     "bytes": st["bytes"], "variant": st["variant"]}
+        log(f"stage retirement: {name} {ms:.0f} ms, {st['sweeps']} sweeps, {st['backups']:.4e} backups")
+    out["backups_saved"] = round(1.0 - out["staged"]["backups"] / out["plain"]["backups"], 4)
+    out["max_rel_change_c"] = float(np.abs(c["staged"] - c["plain"]).max() / max(1.0, np.abs(c["plain"]).max()))
+    return out
+
+
 def query_eval(ctx, wl, front, rng, args, eps_vi: float) -> dict:
     """ms per point-oriented Pareto query on the timed workload, plain and
     learned first weight.  Thresholds: half below front points (achievable),
@@ -376,6 +400,8 @@ def main():
     ap.add_argument("--proposer-train", type=int, default=200_000,
                     help="training tuples over the 10x20 variants (support points, two thresholds each)")
     ap.add_argument("--proposer-variants", type=int, default=4)
+    ap.add_argument("--stage-retirement", action="store_true",
+                    help="also compare FP64 value iteration with and without stage retirement on the workload")
     ap.add_argument("--oracle-single-core", action="store_true",
                     help="also time the FP64 oracle on one core on the 2x2 and 10x20 workloads in full (~2 min)")
     args = ap.parse_args()
@@ -502,6 +528,7 @@ def main():
 
     # full queries on the timed workload: plain and learned first weight
     per_query = query_eval(ctx, wl, front, rng, args, eps) if args.queries > 0 else None
+    staged = stage_retirement_eval(ctx, rng, K, d, eps) if args.stage_retirement else None
 
     ctx.close()
     learned = None
@@ -517,7 +544,7 @@ def main():
                        "states": S, "rows": R, "nnz": N, "K": K, "eps_vi": eps, "seed": args.seed,
                        "parallelism": "1 GPU"},
             "roofline": roofline, "cpu_baseline": cpu, "ms_per_query": per_query,
-            "proposer": learned,
+            "proposer": learned, "stage_retirement": staged,
             "stats": {k: st_graph[k] for k in ("backups", "sweeps", "sweeps_tail", "eval_sweeps", "polish_sweeps",
                                                "rank_rounds", "floor_stops", "ms_vi", "ms_eval", "variant",
                                                "variant_tail", "variant_refine", "bytes", "bytes_tail",

@@ -227,6 +227,25 @@ typedef struct {
 int morap_solve(morap_ctx* ctx, const double* W, int K, const morap_vi_opts* opts,
                 double* c_out, morap_stats* stats);
 
+/* Alg. 3 as morap_solve, with stages retiring inside the Jacobi iteration
+ * (the staged form of value iteration that ordering by strongly connected
+ * components allows, Sec. 6).  A state's stage is the height of its DFA
+ * location group (a strongly connected set of locations) in the DAG those
+ * groups form in its product; every transition leads to the same or a lower
+ * stage.  Each sweep backs up the stages still active in a column; after it,
+ * a stage retires in that column when every lower stage has retired and the
+ * largest change over its own states is <= eps_vi, and keeps the values of
+ * that sweep from then on.  A pair is done when the stage of its initial
+ * state retires; c_out as morap_solve.  Products built by
+ * morap_build_products (block form) only, FP64 only (precision must be
+ * MORAP_F64); opts.schedule, when > 0, must name a neighbourhood-block sweep
+ * (ids 19-38).  The values stay on the device as after morap_solve.
+ * stats->backups counts the rows of the active stages only.
+ * Errors: INVALID, STATE, UNSUPPORTED (team model, caller-loaded models,
+ * FP32), OOM, NOT_CONVERGED, HIP. */
+int morap_solve_staged(morap_ctx* ctx, const double* W, int K, const morap_vi_opts* opts,
+                       double* c_out, morap_stats* stats);
+
 /* Alg. 2 second loop for the columns of the last morap_solve: assign[K][|J|]
  * gives the agent of every task per column.  For each (k, j) the policy of
  * model (assign[k][j], j) is extracted from that column's final values (FP32

@@ -178,6 +178,16 @@ int morap_solve(morap_ctx* ctx, const double* W, int K, const morap_vi_opts* opt
     });
 }
 
+int morap_solve_staged(morap_ctx* ctx, const double* W, int K, const morap_vi_opts* opts, double* c_out,
+                       morap_stats* stats) {
+    return guarded(ctx, [&] {
+        MORAP_CHECK(opts, MORAP_E_INVALID, "opts is NULL");
+        Stats st;
+        solve_staged(ctx, W, K, *opts, c_out, st);
+        to_abi(st, stats);
+    });
+}
+
 int morap_evaluate(morap_ctx* ctx, const int32_t* assign, int K, const morap_vi_opts* opts, double* r_out,
                    morap_stats* stats) {
     return guarded(ctx, [&] {

@@ -205,6 +205,25 @@ struct ValueSet {
 
 struct Proposer;  // mlp.hip
 
+// Stage retirement inside the iteration (the staged form of Alg. 3): the
+// states of every model split by stage (the height of their location group
+// in the product's location DAG) into units, lowest stage first, with the
+// neighbourhood-block records reordered inside each tile so that a unit's
+// records form runs; the tiles of a unit are consecutive.
+struct StagedLayout {
+    uint64_t gen = ~0ull;                 // model upload the layout belongs to
+    int U = 0;                            // units
+    int64_t n_tiles = 0;
+    std::vector<int32_t> unit_base;       // [M+1] first unit of each model
+    DevBuf tiles, tile_base, rec;         // unit tiles, [U+1], records [8S]
+    DevBuf rows, states, csr, live;       // [U] rows, states, CSR bytes (FP64), 0 / -1 (dead model)
+    DevBuf unit_base_d, init_unit;        // [M+1], [M] unit of the initial state (-1: done)
+    // solve state
+    DevBuf active, res, ymax, wc, wp, final_par, pair_sweeps, best_res, stall;   // [U][Kp]
+    DevBuf c_units;                       // [K][U] (cleared at the start, unused)
+    DevBuf model_active, act_models, act_prefix, act_tiles, retired, counters;
+};
+
 }  // namespace morap
 
 // ---------------------------------------------------------------------------
@@ -311,6 +330,9 @@ struct morap_ctx {
     morap::DevBuf d_live_tiles;
     std::vector<int8_t> h_mu;                       // policies of the last evaluate
 
+    // units of the stage-retiring solve (built on first use per upload)
+    morap::StagedLayout staged;
+
     // autotuner cache: key (prec, Kp) -> variant id
     std::vector<std::pair<int64_t, int>> tuned;
     // resident workgroups per compute unit: key (variant, prec) -> count
@@ -395,6 +417,8 @@ inline int n_obj_of(const morap_ctx* c) { return n_agents_of(c) + n_tasks_of(c);
 // padded columns, ignored otherwise
 void solve(morap_ctx* ctx, const double* W, int K, const morap_vi_opts& o, double* c_out, Stats& st,
            const int32_t* warm = nullptr);
+// the same value iteration with stage retirement inside it (FP64, block form)
+void solve_staged(morap_ctx* ctx, const double* W, int K, const morap_vi_opts& o, double* c_out, Stats& st);
 // warm (nullable): per column, the column of the previous evaluation whose
 // instance of the same task on the same model starts the policy evaluation
 // from its final values (-1: from 0, as Alg. 4)
@@ -516,6 +540,33 @@ void compact(hipStream_t s, const ConvergeArgs& a);
 // sweep kernel between the gather and the LDS-staged tiles)
 void relist(hipStream_t s, ConvergeArgs a);
 void init_solve(hipStream_t s, const ConvergeArgs& a);
+
+// stage retirement (staged.hip)
+struct StageArgs {
+    const int32_t* unit_base;   // [M+1]
+    const int32_t* init_unit;   // [M] unit of the initial state, -1 if done
+    const int32_t* init;        // [M] initial state
+    const int32_t* rows;        // [U] rows (backups per active column)
+    const int32_t* states;      // [U] states
+    uint8_t* active;            // [U][Kp]
+    unsigned long long* res;    // [U][Kp]
+    unsigned long long* ymax;   // [U][Kp]
+    uint8_t* model_active;      // [U]
+    double* c;                  // [K][M] values at the initial states
+    uint8_t* final_par;         // [M][Kp]
+    int32_t* pair_sweeps;       // [M][Kp] sweep in which the initial state's unit retired
+    int64_t* retired;           // [U * Kp] (unit, column) pairs retired in this sweep
+    int64_t* counters;          // as the convergence kernel's, [9] / [10] the list counts
+    const Tile* tiles;          // unit tiles
+    const int32_t* tile_base;   // [U+1]
+    const int32_t* rec;         // reordered block records [8S]
+    const double* x_out;        // the buffer the sweep wrote
+    double* x_in;               // the buffer it read
+    int M, K, Kp, out_par, slot;   // slot: 9 or 10, the list count of this sweep
+    double eps, unit;
+};
+void stage_converge(hipStream_t s, const StageArgs& a);
+void stage_copy(hipStream_t s, const StageArgs& a);
 
 // instances (polish, policy extraction, evaluation)
 struct InstArgs {

@@ -1422,4 +1422,368 @@ static int refine_assignment(morap_ctx* c, const int32_t* assign, int K, const m
     return changed;
 }
 
+// ---------------------------------------------------------------------------
+// stage retirement inside the iteration (the staged form of Alg. 3)
+// ---------------------------------------------------------------------------
+template <class T>
+static void upload_vec(DevBuf& d, const std::vector<T>& h, hipStream_t s) {
+    d.ensure(h.size() * sizeof(T) + 16);
+    if (!h.empty()) MORAP_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+// Stage of every state of model m: the location graph has an edge q -> q'
+// for every live transition from a state at q to one at q'; its strongly
+// connected groups form a DAG, and a group's stage is its height there (0
+// for a group with no other group below it).  Every transition therefore
+// leads to the same or a lower stage.
+static int model_stages(const HostModels& hm, int m, std::vector<int32_t>& stage) {
+    const int32_t s0 = hm.state_base[m], s1 = hm.state_base[m + 1];
+    std::vector<int32_t> locs;
+    for (int32_t g = s0; g < s1; ++g) locs.push_back(hm.states_sq[(size_t)2 * g + 1]);
+    std::sort(locs.begin(), locs.end());
+    locs.erase(std::unique(locs.begin(), locs.end()), locs.end());
+    const int L = (int)locs.size();
+    if (L == 0) return 0;
+    auto idx = [&](int32_t g) {
+        return (int)(std::lower_bound(locs.begin(), locs.end(), hm.states_sq[(size_t)2 * g + 1]) - locs.begin());
+    };
+    // reachability between locations (a handful per product)
+    std::vector<uint8_t> reach((size_t)L * L, 0);
+    for (int a = 0; a < L; ++a) reach[(size_t)a * L + a] = 1;
+    for (int32_t g = s0; g < s1; ++g) {
+        const int a = idx(g);
+        for (int32_t r = hm.state_row[g]; r < hm.state_row[g + 1]; ++r)
+            for (int32_t e = hm.row_ptr[r]; e < hm.row_ptr[r + 1]; ++e) {
+                const int32_t h = hm.col[e];
+                MORAP_CHECK(h >= s0 && h < s1, MORAP_E_STATE, "a transition leaves its model");
+                reach[(size_t)a * L + idx(h)] = 1;
+            }
+    }
+    for (int q = 0; q < L; ++q)
+        for (int a = 0; a < L; ++a)
+            if (reach[(size_t)a * L + q])
+                for (int b = 0; b < L; ++b)
+                    if (reach[(size_t)q * L + b]) reach[(size_t)a * L + b] = 1;
+    // heights: a location reaches strictly more locations than every
+    // location strictly below it, so count order is a topological order
+    std::vector<int> n_reach(L, 0), order(L), height(L, 0);
+    for (int a = 0; a < L; ++a)
+        for (int b = 0; b < L; ++b) n_reach[a] += reach[(size_t)a * L + b];
+    for (int a = 0; a < L; ++a) order[a] = a;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return n_reach[x] < n_reach[y]; });
+    int top = 0;
+    for (int a : order) {
+        for (int b = 0; b < L; ++b)
+            if (reach[(size_t)a * L + b] && !reach[(size_t)b * L + a]) height[a] = std::max(height[a], height[b] + 1);
+        top = std::max(top, height[a]);
+    }
+    for (int32_t g = s0; g < s1; ++g) stage[g] = height[idx(g)];
+    return top + 1;
+}
+
+static void build_stage_layout(morap_ctx* c) {
+    StagedLayout& L = c->staged;
+    if (L.gen == c->load_gen) return;
+    const HostModels& hm = c->hm;
+    const int M = hm.M;
+    const int64_t S = hm.S();
+    MORAP_CHECK(c->has_blocks, MORAP_E_UNSUPPORTED,
+                "stage retirement runs on the neighbourhood-block form (products built by morap_build_products)");
+    MORAP_CHECK((int64_t)hm.states_sq.size() == 2 * S, MORAP_E_UNSUPPORTED,
+                "stage retirement needs the DFA location of every state");
+    std::vector<int32_t> stage((size_t)S, 0);
+    L.unit_base.assign(M + 1, 0);
+    std::vector<int32_t> init_unit(M, -1);
+    for (int m = 0; m < M; ++m) {
+        L.unit_base[m + 1] = L.unit_base[m] + model_stages(hm, m, stage);
+        if (hm.init[m] >= 0) init_unit[m] = L.unit_base[m] + stage[hm.init[m]];
+    }
+    const int U = L.unit_base[M];
+    std::vector<int32_t> rows(U, 0), states(U, 0), live(U, -1);
+    std::vector<int64_t> csr(U, 0);
+    for (int m = 0; m < M; ++m)
+        for (int32_t g = hm.state_base[m]; g < hm.state_base[m + 1]; ++g) {
+            const int u = L.unit_base[m] + stage[g];
+            const int32_t nr = hm.state_row[g + 1] - hm.state_row[g];
+            const int64_t nnz = hm.row_ptr[hm.state_row[g + 1]] - hm.row_ptr[hm.state_row[g]];
+            rows[u] += nr;
+            states[u] += 1;
+            // state_row + row_ptr + col (int32) + prob and two rewards (FP64)
+            csr[u] += 4 + 4 * (int64_t)nr + 12 * nnz + 16 * (int64_t)nr;
+            live[u] = hm.init[m] >= 0 ? 0 : -1;
+        }
+    // records regrouped by unit inside every tile (stable), and the unit
+    // tiles, consecutive per unit
+    std::vector<int32_t> rec(hm.blk_rec.size());
+    std::vector<std::vector<Tile>> per_unit(U);
+    for (int m = 0; m < M; ++m) {
+        const int nst = L.unit_base[m + 1] - L.unit_base[m];
+        std::vector<int> cnt(nst + 1);
+        for (int t = c->tile_base[m]; t < c->tile_base[m + 1]; ++t) {
+            const Tile& tl = c->tiles[t];
+            std::fill(cnt.begin(), cnt.end(), 0);
+            for (int p = tl.s_begin; p < tl.s_end; ++p) ++cnt[stage[hm.blk_rec[(size_t)p * 8 + 7]] + 1];
+            for (int q = 0; q < nst; ++q) cnt[q + 1] += cnt[q];
+            for (int q = 0; q < nst; ++q)
+                if (cnt[q + 1] > cnt[q])
+                    per_unit[L.unit_base[m] + q].push_back(
+                        Tile{L.unit_base[m] + q, tl.s_begin + cnt[q], tl.s_begin + cnt[q + 1], 0});
+            for (int p = tl.s_begin; p < tl.s_end; ++p) {
+                const int q = stage[hm.blk_rec[(size_t)p * 8 + 7]];
+                std::copy(&hm.blk_rec[(size_t)p * 8], &hm.blk_rec[(size_t)p * 8 + 8],
+                          &rec[(size_t)(tl.s_begin + cnt[q]++) * 8]);
+            }
+        }
+    }
+    std::vector<Tile> tiles;
+    std::vector<int32_t> tile_base(U + 1, 0);
+    for (int u = 0; u < U; ++u) {
+        tile_base[u] = (int32_t)tiles.size();
+        tiles.insert(tiles.end(), per_unit[u].begin(), per_unit[u].end());
+    }
+    tile_base[U] = (int32_t)tiles.size();
+    hipStream_t s = c->stream;
+    upload_vec(L.tiles, tiles, s);
+    upload_vec(L.tile_base, tile_base, s);
+    upload_vec(L.rec, rec, s);
+    upload_vec(L.rows, rows, s);
+    upload_vec(L.states, states, s);
+    upload_vec(L.csr, csr, s);
+    upload_vec(L.live, live, s);
+    upload_vec(L.unit_base_d, L.unit_base, s);
+    upload_vec(L.init_unit, init_unit, s);
+    MORAP_HIP(hipStreamSynchronize(s));
+    L.U = U;
+    L.n_tiles = (int64_t)tiles.size();
+    L.gen = c->load_gen;
+}
+
+// Alg. 3 for K columns with stage retirement (FP64): each sweep backs up the
+// units still active, then per (model, column) the units are taken lowest
+// first and a unit retires when all lower ones have and its own change is
+// <= eps_vi; its values are copied into the other buffer.  A pair's value at
+// the initial state is final when the initial state's unit retires.
+static void solve_staged_impl(morap_ctx* c, const double* W, int K, const morap_vi_opts& o, double* c_out,
+                              Stats& st) {
+    MORAP_CHECK(c->loaded, MORAP_E_STATE, "no models loaded");
+    MORAP_CHECK(!c->team, MORAP_E_UNSUPPORTED, "stage retirement runs on the decentralised products");
+    MORAP_CHECK(o.precision == MORAP_F64, MORAP_E_UNSUPPORTED, "stage retirement runs FP64 values");
+    MORAP_CHECK(W && K >= 1 && K <= 4096, MORAP_E_INVALID, "need 1 <= K <= 4096 weight vectors");
+    MORAP_CHECK(o.eps_vi > 0 && std::isfinite(o.eps_vi), MORAP_E_INVALID, "eps_vi must be > 0");
+    MORAP_CHECK(o.max_sweeps >= 1, MORAP_E_INVALID, "max_sweeps must be >= 1");
+    const int nI = c->hm.nI, nJ = c->hm.nJ, M = c->hm.M, d = nI + nJ;
+    for (int k = 0; k < K; ++k) {
+        double sum = 0;
+        for (int q = 0; q < d; ++q) {
+            const double w = W[(size_t)k * d + q];
+            MORAP_CHECK(std::isfinite(w) && w >= 0, MORAP_E_INVALID, "weights must be finite and >= 0");
+            sum += w;
+        }
+        MORAP_CHECK(std::fabs(sum - 1.0) <= 1e-9, MORAP_E_INVALID, "weight rows must sum to 1");
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    build_stage_layout(c);
+    StagedLayout& L = c->staged;
+    const int U = L.U, Kp = padded_k(K);
+    // a neighbourhood-block sweep: the one the autotuner chose for plain FP64
+    // solves of this width if it is one, else the first with k-tiles of
+    // min(Kp, 64) columns (the wave-per-state one where it fits)
+    const Variant* v = nullptr;
+    if (o.schedule > 0) {
+        MORAP_CHECK(o.schedule <= (int)variants().size(), MORAP_E_INVALID, "unknown sweep variant");
+        v = &variants()[o.schedule - 1];
+        MORAP_CHECK(v->kind == SWEEP_BLOCK && Kp % kt_of(*v) == 0, MORAP_E_UNSUPPORTED,
+                    "stage retirement runs a neighbourhood-block sweep whose k-tile divides the padded width");
+    } else {
+        const int64_t key = ((int64_t)MORAP_F64 << 40) | Kp;
+        for (auto& t : c->tuned)
+            if (t.first == key && variant_by_id(t.second).kind == SWEEP_BLOCK) v = &variant_by_id(t.second);
+        if (!v)
+            for (const auto& x : variants())
+                if (x.kind == SWEEP_BLOCK && kt_of(x) == std::min(Kp, 64) &&
+                    (!v || (x.cpl == 1 && x.lps == 64 && x.unroll == 2)))
+                    v = &x;
+    }
+    MORAP_CHECK(v, MORAP_E_UNSUPPORTED, "no neighbourhood-block sweep for this width");
+    hipStream_t s = c->stream;
+    c->solved = false;
+    c->evaluated = false;
+    ensure_scratch(c, Kp);
+    c->K = K;
+    c->Kp = Kp;
+    c->prec = MORAP_F64;
+    c->W.assign(W, W + (size_t)K * d);
+    ValueSet& vs = c->vmain;
+    ensure_values(c, vs, K, Kp, MORAP_F64);
+
+    const size_t pairs = (size_t)U * Kp;
+    L.active.ensure(pairs);
+    L.res.ensure(pairs * 8);
+    L.ymax.ensure(pairs * 8);
+    L.wc.ensure(pairs * 8);
+    L.wp.ensure(pairs * 8);
+    L.final_par.ensure(pairs);
+    L.pair_sweeps.ensure(pairs * 4);
+    L.best_res.ensure(pairs * 8);
+    L.stall.ensure(pairs * 4);
+    L.c_units.ensure((size_t)K * U * 8);
+    L.model_active.ensure(U);
+    L.act_models.ensure((size_t)U * 4 + 4);
+    L.act_prefix.ensure((size_t)(U + 1) * 4 + 4);
+    L.act_tiles.ensure((size_t)L.n_tiles * 4 + 4);
+    L.retired.ensure(pairs * 8);
+    L.counters.ensure(11 * 8);
+    {
+        std::vector<double> wc(pairs, 0.0), wp(pairs, 0.0);
+        for (int m = 0; m < M; ++m) {
+            const int i = m / nJ, j = m % nJ;
+            for (int u = L.unit_base[m]; u < L.unit_base[m + 1]; ++u)
+                for (int k = 0; k < K; ++k) {
+                    wc[(size_t)u * Kp + k] = W[(size_t)k * d + i];
+                    wp[(size_t)u * Kp + k] = W[(size_t)k * d + nI + j];
+                }
+        }
+        MORAP_HIP(hipMemcpyAsync(L.wc.p, wc.data(), pairs * 8, hipMemcpyHostToDevice, s));
+        MORAP_HIP(hipMemcpyAsync(L.wp.p, wp.data(), pairs * 8, hipMemcpyHostToDevice, s));
+        MORAP_HIP(hipStreamSynchronize(s));
+    }
+    const int64_t nx = (c->S + 1) * Kp;
+    k::fill_f64(s, vs.x[0].as<double>(), 0.0, nx);
+    k::fill_f64(s, vs.x[1].as<double>(), 0.0, nx);
+    k::fill_f64(s, vs.c.as<double>(), 0.0, (int64_t)K * M);
+    k::fill_u8(s, vs.final_par.as<uint8_t>(), 0, (int64_t)M * Kp);
+    k::fill_i32(s, c->d_pair_sweeps.as<int32_t>(), 0, (int64_t)M * Kp);
+    k::fill_i64(s, L.counters.as<int64_t>(), 0, 11);
+
+    // the units as models of the active-set machinery
+    k::ConvergeArgs ca{};
+    ca.res = L.res.as<unsigned long long>();
+    ca.ymax = L.ymax.as<unsigned long long>();
+    ca.active = L.active.as<uint8_t>();
+    ca.final_par = L.final_par.as<uint8_t>();
+    ca.pair_sweeps = L.pair_sweeps.as<int32_t>();
+    ca.model_active = L.model_active.as<uint8_t>();
+    ca.c = L.c_units.as<double>();
+    ca.init = L.live.as<int32_t>();
+    ca.x_out = vs.x[1].p;
+    ca.counters = L.counters.as<int64_t>();
+    ca.M = U;
+    ca.K = K;
+    ca.Kp = Kp;
+    ca.prec = MORAP_F64;
+    ca.out_par = 1;
+    ca.eps = o.eps_vi;
+    ca.unit = 8.0 * std::ldexp(1.0, -53);
+    ca.best_res = L.best_res.as<double>();
+    ca.stall = L.stall.as<int32_t>();
+    ca.tile_base = L.tile_base.as<int32_t>();
+    ca.act_models = L.act_models.as<int32_t>();
+    ca.act_prefix = L.act_prefix.as<int32_t>();
+    ca.rows_per_model = L.rows.as<int32_t>();
+    ca.states_per_model = L.states.as<int32_t>();
+    ca.csr_bytes = L.csr.as<int64_t>();
+    ca.act_tiles = L.act_tiles.as<int32_t>();
+    k::init_solve(s, ca);
+
+    k::StageArgs sa{};
+    sa.unit_base = L.unit_base_d.as<int32_t>();
+    sa.init_unit = L.init_unit.as<int32_t>();
+    sa.init = c->d_init.as<int32_t>();
+    sa.rows = L.rows.as<int32_t>();
+    sa.states = L.states.as<int32_t>();
+    sa.active = ca.active;
+    sa.res = ca.res;
+    sa.ymax = ca.ymax;
+    sa.model_active = ca.model_active;
+    sa.c = vs.c.as<double>();
+    sa.final_par = vs.final_par.as<uint8_t>();
+    sa.pair_sweeps = c->d_pair_sweeps.as<int32_t>();
+    sa.retired = L.retired.as<int64_t>();
+    sa.counters = ca.counters;
+    sa.tiles = L.tiles.as<Tile>();
+    sa.tile_base = ca.tile_base;
+    sa.rec = L.rec.as<int32_t>();
+    sa.M = M;
+    sa.K = K;
+    sa.Kp = Kp;
+    sa.eps = o.eps_vi;
+    sa.unit = ca.unit;
+
+    k::SweepArgs a = sweep_args(c, vs, 0);
+    a.tiles = L.tiles.as<Tile>();
+    a.tile_base = ca.tile_base;
+    a.act_models = ca.act_models;
+    a.act_prefix = ca.act_prefix;
+    a.counters = ca.counters;
+    a.wc = L.wc.p;
+    a.wp = L.wp.p;
+    a.active = ca.active;
+    a.res = ca.res;
+    a.ymax = ca.ymax;
+    a.rec = sa.rec;
+    a.act_tiles = ca.act_tiles;
+    const int grid = persistent_grid(c, MORAP_F64, *v);
+    const int ktiles = Kp / kt_of(*v);
+    const int check = std::max(2, o.check_every);
+    int64_t h[11] = {0};
+    EventPair wall;
+    MORAP_HIP(hipEventRecord(wall.a, s));
+    for (int n = 0;; ++n) {
+        const int in_par = n & 1;
+        a.x_in = vs.x[in_par].p;
+        a.x_out = vs.x[1 - in_par].p;
+        EventPair* ev = nullptr;
+        std::unique_ptr<EventPair> timed;
+        if (o.time_kernels) {
+            timed.reset(new EventPair());
+            ev = timed.get();
+            MORAP_HIP(hipEventRecord(ev->a, s));
+        }
+        k::sweep_block(s, MORAP_F64, *v, grid, ktiles, a);
+        if (ev) MORAP_HIP(hipEventRecord(ev->b, s));
+        sa.x_in = vs.x[in_par].as<double>();
+        sa.x_out = vs.x[1 - in_par].as<double>();
+        sa.out_par = 1 - in_par;
+        sa.slot = 9 + (n & 1);
+        k::stage_converge(s, sa);
+        k::stage_copy(s, sa);
+        k::compact(s, ca);
+        if (ev) {
+            MORAP_HIP(hipEventSynchronize(ev->b));
+            st.ms_sweep_kernel += ev->elapsed_ms();
+            st.sweep_launches += 1;
+        }
+        if ((n + 1) % check == 0 || n + 1 >= o.max_sweeps) {
+            MORAP_HIP(hipMemcpyAsync(h, L.counters.p, sizeof(h), hipMemcpyDeviceToHost, s));
+            MORAP_HIP(hipStreamSynchronize(s));
+            if (h[3] == 0) break;
+            if (n + 1 >= o.max_sweeps)
+                fail(MORAP_E_NOT_CONVERGED, "value iteration with stage retirement: " + std::to_string(h[3]) +
+                                                " (unit, column) pairs still active after " +
+                                                std::to_string(n + 1) + " sweeps");
+        }
+    }
+    MORAP_HIP(hipEventRecord(wall.b, s));
+    MORAP_HIP(hipEventSynchronize(wall.b));
+    std::vector<int32_t> ps((size_t)M * Kp);
+    MORAP_HIP(hipMemcpy(ps.data(), c->d_pair_sweeps.p, ps.size() * 4, hipMemcpyDeviceToHost));
+    st.backups += h[4];
+    st.sweeps += h[5];
+    st.bytes += (double)h[6] + 16.0 * (double)h[7];
+    st.max_pair_sweeps = std::max<int64_t>(st.max_pair_sweeps, *std::max_element(ps.begin(), ps.end()));
+    st.ms_vi += wall.elapsed_ms();
+    st.variant = v->id;
+    if (c_out) MORAP_HIP(hipMemcpy(c_out, vs.c.p, (size_t)K * M * 8, hipMemcpyDeviceToHost));
+    st.ms_total += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    vs.valid = true;
+    c->solved = true;
+}
+
+void solve_staged(morap_ctx* c, const double* W, int K, const morap_vi_opts& o, double* c_out, Stats& st) {
+    Stats local;
+    solve_staged_impl(c, W, K, o, c_out, local);
+    add_stats(st, local);
+    add_stats(c->cum, local);
+}
+
 }  // namespace morap

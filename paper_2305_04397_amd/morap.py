@@ -120,6 +120,7 @@ _sig("morap_model_info", C.c_int, _ctxp, C.c_int, _p)
 _sig("morap_get_model", C.c_int, _ctxp, C.c_int, _p, _p, _p, _p, _p, _p, _p)
 _sig("morap_default_opts", None, C.POINTER(ViOpts))
 _sig("morap_solve", C.c_int, _ctxp, _p, C.c_int, C.POINTER(ViOpts), _p, C.POINTER(Stats))
+_sig("morap_solve_staged", C.c_int, _ctxp, _p, C.c_int, C.POINTER(ViOpts), _p, C.POINTER(Stats))
 _sig("morap_evaluate", C.c_int, _ctxp, _p, C.c_int, C.POINTER(ViOpts), _p, C.POINTER(Stats))
 _sig("morap_assign", C.c_int, _ctxp, _p, C.c_int, _p)
 _sig("morap_assign_host", C.c_int, _p, C.c_int, C.c_int, C.c_int, _p)
@@ -469,6 +470,17 @@ class Context:
         st = Stats()
         o = opts.to_c()
         self._check(lib.morap_solve(self._h, _ptr(W), K, C.byref(o), _ptr(c), C.byref(st)), "morap_solve")
+        return c, st.as_dict()
+
+    def solve_staged(self, W, opts: Options = Options(precision="f64")):
+        """morap_solve with stages retiring inside the iteration (FP64)."""
+        W = _c(np.atleast_2d(W), np.float64)
+        K = W.shape[0]
+        c = np.zeros(self._c_shape(K))
+        st = Stats()
+        o = opts.to_c()
+        self._check(lib.morap_solve_staged(self._h, _ptr(W), K, C.byref(o), _ptr(c), C.byref(st)),
+                    "morap_solve_staged")
         return c, st.as_dict()
 
     def evaluate(self, assign, opts: Options = Options(), K: int = None):

@@ -1,0 +1,123 @@
+"""Value iteration with stage retirement inside the Jacobi iteration
+(morap_solve_staged) against the oracle's iteration of the same form.
+
+A stage is the height of a state's DFA location group in its product's
+location DAG; after every sweep a stage retires in a column once every lower
+stage has and its own change is within eps.  The oracle
+(``vi.stage_retired_value_iteration``) is pinned to plain value iteration,
+the LP optimum and a reversed-order mutation; here the device must stop
+every stage in the same sweep (the same backups) with the same values, up to
+FP64 rounding of the backups' sums."""
+import numpy as np
+import pytest
+
+from workloads import make_workload, tiny_workload, dirichlet_weights
+from oracle import product, vi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def morap():
+    from paper_2305_04397_amd import morap as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(morap):
+    c = morap.Context(0)
+    yield c
+    c.close()
+
+
+def _f64(morap, eps):
+    return morap.Options(eps_vi=eps, precision="f64")
+
+
+@pytest.mark.parametrize("seed,kinds,k", [(81, ("reach",), 4), (82, ("reach", "avoid"), 3), (83, ("avoid",), 1)])
+def test_staged_solve_equals_the_oracle(ctx, morap, seed, kinds, k):
+    """Every (model, column): the value at the initial state and every state's
+    value equal the oracle's stage-retiring iteration; the rows backed up over
+    the solve equal the oracle's count (the same stopping sweep per stage)."""
+    wl = tiny_workload(seed, 3, 3, width=4, height=3, kinds=kinds, k=k, p_slip=0.2)
+    ctx.build_products(wl)
+    nI, nJ = wl.n_agents, wl.n_tasks
+    W = dirichlet_weights(np.random.default_rng(seed), 5, nI + nJ)
+    W[0] = 0.0
+    W[0, nI] = 1.0          # probability of task 0 only: the upper stages see no reward at first
+    eps = 1e-9
+    c, st = ctx.solve_staged(W, _f64(morap, eps))
+    prods = product.build_all(wl)
+    backups = 0
+    for m, p in enumerate(prods):
+        i, j = divmod(m, nJ)
+        if p.init < 0:
+            assert (c[:, i, j] == 0).all()
+            continue
+        y, ret, b = vi.stage_retired_value_iteration(p, W[:, i], W[:, nI + j], eps)
+        backups += b
+        assert np.abs(c[:, i, j] - y[p.init]).max() <= 1e-12 * max(1.0, np.abs(y).max())
+        for col in (0, len(W) - 1):
+            x = ctx.get_values(col, m)
+            assert np.abs(x - y[:, col]).max() <= 1e-12 * max(1.0, np.abs(y).max())
+    assert st["backups"] == backups
+    assert st["variant"] in range(19, 39)
+
+
+def test_staged_solve_on_cfg2_keeps_the_fixed_point_and_saves_backups(ctx, morap):
+    """10 x 20 (tasks of 3-8 locations): the staged solve's values are those
+    of the plain FP64 solve within the stop rule's reach, it needs at most a
+    couple of sweeps more, and it backs up fewer rows."""
+    wl = make_workload(2)
+    ctx.build_products(wl)
+    nI, nJ = wl.n_agents, wl.n_tasks
+    W = dirichlet_weights(np.random.default_rng(84), 16, nI + nJ)
+    eps = 1e-8
+    c0, st0 = ctx.solve(W, _f64(morap, eps))
+    c1, st1 = ctx.solve_staged(W, _f64(morap, eps))
+    assert np.abs(c1 - c0).max() <= 1e-5 * max(1.0, np.abs(c0).max())
+    assert st1["sweeps"] <= st0["sweeps"] + 2
+    assert st1["backups"] < st0["backups"]
+    # against the oracle's iteration of the same form on a few products
+    prods = product.build_all(wl)
+    for m in (0, 57, 133, 199):
+        i, j = divmod(m, nJ)
+        p = prods[m]
+        if p.init < 0:
+            continue
+        y, _, _ = vi.stage_retired_value_iteration(p, W[:, i], W[:, nI + j], eps)
+        assert np.abs(c1[:, i, j] - y[p.init]).max() <= 1e-10 * max(1.0, np.abs(y).max())
+
+
+def test_staged_solve_then_support_step(ctx, morap):
+    """The staged solve leaves its values where morap_evaluate reads them: the
+    support step from them gives the plain solve's points."""
+    wl = tiny_workload(85, 2, 2, width=4, height=3, kinds=("reach",), k=3, p_slip=0.2)
+    ctx.build_products(wl)
+    W = dirichlet_weights(np.random.default_rng(85), 4, 4)
+    o = morap.Options(eps_vi=1e-12, eps_eval=1e-12, precision="f64")
+    r0, A0, _, _ = ctx.support(W, o)
+    c1, _ = ctx.solve_staged(W, o)
+    A1 = ctx.assign(c1)
+    assert np.array_equal(A0, A1)
+    r1, _ = ctx.evaluate(A1, o)
+    assert np.abs(r1 - r0).max() <= 1e-9
+
+
+def test_staged_solve_rejects_what_it_does_not_run(ctx, morap):
+    wl = tiny_workload(86, 2, 2, width=3, height=2, kinds=("reach",), k=2)
+    ctx.build_products(wl)
+    W = np.full((1, 4), 0.25)
+    with pytest.raises(morap.MorapError) as e:
+        ctx.solve_staged(W, morap.Options(eps_vi=1e-6, precision="f32"))
+    assert e.value.code == morap.E_UNSUPPORTED
+    with pytest.raises(morap.MorapError) as e:
+        ctx.solve_staged(W, morap.Options(eps_vi=1e-6, precision="f64", schedule=5))
+    assert e.value.code == morap.E_UNSUPPORTED
+    with pytest.raises(morap.MorapError) as e:
+        ctx.solve_staged(np.full((1, 4), 0.3), morap.Options(eps_vi=1e-6, precision="f64"))
+    assert e.value.code == morap.E_INVALID
+    ctx.load_team_model(morap.team_model_mo_host(wl), 2, 2)
+    with pytest.raises(morap.MorapError) as e:
+        ctx.solve_staged(W, morap.Options(eps_vi=1e-6, precision="f64"))
+    assert e.value.code == morap.E_UNSUPPORTED
