@@ -206,7 +206,7 @@ def query_eval(ctx, wl, front, rng, args, eps_vi: float) -> dict:
     plain loop."""
     from paper_2305_04397_amd import morap, proposer_data as pdata
     nI, d = wl.n_agents, wl.n_agents + wl.n_tasks
-    opts = morap.Options(eps_vi=eps_vi, precision=args.precision)
+    opts = morap.Options(eps_vi=eps_vi, precision=args.precision, eval_from_values=not args.eval_from_zero)
     loop_eps = 0.01
     T = pdata.thresholds(rng, front, args.queries, nI, inside_half=True)
     out = {"workload": wl.name, "eps": loop_eps, "max_iter": args.query_max_iter,
@@ -308,7 +308,7 @@ def proposer_eval(args) -> dict:
     from workloads import make_workload
     from paper_2305_04397_amd import morap, proposer_data as pdata
     rng = np.random.default_rng(args.seed + 1)
-    opts = morap.Options(eps_vi=1e-6, precision="f32")
+    opts = morap.Options(eps_vi=1e-6, precision="f32", eval_from_values=not args.eval_from_zero)
     ctx = morap.Context(0)
     X, Wt, phis, eval_T = [], [], {}, None
     t0 = time.perf_counter()
@@ -400,6 +400,8 @@ def main():
     ap.add_argument("--proposer-train", type=int, default=200_000,
                     help="training tuples over the 10x20 variants (support points, two thresholds each)")
     ap.add_argument("--proposer-variants", type=int, default=4)
+    ap.add_argument("--eval-from-zero", action="store_true",
+                    help="start every policy evaluation (Alg. 4) from 0 instead of the solve's values")
     ap.add_argument("--stage-retirement", action="store_true",
                     help="also compare FP64 value iteration with and without stage retirement on the workload")
     ap.add_argument("--oracle-single-core", action="store_true",
@@ -444,8 +446,12 @@ def main():
     log(f"{nI * nJ} products built and uploaded in {time.time() - t0:.1f} s: S={S} R={R} N={N}")
     # the timed steps replay captured graphs of sweep chunks; one extra pass
     # with HIP events around the sweep launches (eager) gives the kernel figures
-    opts = morap.Options(eps_vi=eps, precision=args.precision, schedule=args.schedule, use_graph=not args.no_graph)
-    opts_timed = morap.Options(eps_vi=eps, precision=args.precision, time_kernels=True, schedule=args.schedule)
+    # Alg. 4 starts from the solve's scalarised values (--eval-from-zero: from 0)
+    efv = not args.eval_from_zero
+    opts = morap.Options(eps_vi=eps, precision=args.precision, schedule=args.schedule, use_graph=not args.no_graph,
+                         eval_from_values=efv)
+    opts_timed = morap.Options(eps_vi=eps, precision=args.precision, time_kernels=True, schedule=args.schedule,
+                               eval_from_values=efv)
     rng = np.random.default_rng(args.seed)
 
     # warm-up (includes the sweep-kernel autotuning) and front points
@@ -542,6 +548,7 @@ def main():
             "data": "synthetic: seeded grid-world agents and reach/avoid task automata",
             "config": {"workload": f"{wl.name}: {nI * nJ} product MDPs, K={K} weight columns per pass",
                        "states": S, "rows": R, "nnz": N, "K": K, "eps_vi": eps, "seed": args.seed,
+                       "eval_start": "from 0" if args.eval_from_zero else "from the solve's values",
                        "parallelism": "1 GPU"},
             "roofline": roofline, "cpu_baseline": cpu, "ms_per_query": per_query,
             "proposer": learned, "stage_retirement": staged,

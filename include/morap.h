@@ -177,10 +177,13 @@ typedef struct {
     int32_t schedule;     /* 0 = autotuned sweep kernel, > 0 = fixed variant id     */
     int32_t use_graph;    /* 1 = replay sweep chunks as a captured hipGraph         */
     int32_t time_kernels; /* 1 = time every sweep kernel with HIP events (eager)    */
+    int32_t eval_start;   /* Alg. 4 start: 0 = from 0; 1 = from the scalarised      */
+                          /* values of the policy's solve (probability 1, or the    */
+                          /* warm value, and cost (V - w_p P) / w_c; same stop rule)*/
 } morap_vi_opts;
 
 /* Fill `opts` with the defaults: eps 1e-6, tau 1e-9, FP32, 1e6 sweeps, check
- * every 32 sweeps, autotuned, graphs on, no kernel timing. */
+ * every 32 sweeps, autotuned, graphs on, no kernel timing, Alg. 4 from 0. */
 void morap_default_opts(morap_vi_opts* opts);
 
 typedef struct {
@@ -251,8 +254,12 @@ int morap_solve_staged(morap_ctx* ctx, const double* W, int K, const morap_vi_op
  * model (assign[k][j], j) is extracted from that column's final values (FP32
  * solves are first refined by FP64 value iteration of that model and column to
  * eps_vi), with the attractor tie rule on the tau-optimal action sets, then
- * evaluated per objective (Alg. 4, FP64 Jacobi from 0, eps_eval).
- * r_out[K][d]: r[|I|+j] = completion probability of task j; r[i] = sum of the
+ * evaluated per objective (Alg. 4, FP64 Jacobi from 0, eps_eval; with
+ * opts->eval_start = 1 from the values the policy was chosen from: the
+ * probability objective at 1, the cost objective at (V - w_p) / w_c with the
+ * pair's weights scaled to sum 1 where w_c >= 1e-3; a proper policy's
+ * evaluation reaches its values from any start, and the stop rule bounds the
+ * error of the result alike).  r_out[K][d]: r[|I|+j] = completion probability of task j; r[i] = sum of the
  * cost values of the tasks assigned to i.  Each agent may receive at most
  * ceil(|J|/|I|) tasks.  On a team model (morap_load_team_model) assign is
  * ignored (may be NULL): the one policy of each column is evaluated on every

@@ -166,6 +166,7 @@ void morap_default_opts(morap_vi_opts* o) {
     o->schedule = 0;
     o->use_graph = 1;
     o->time_kernels = 0;
+    o->eval_start = 0;
 }
 
 int morap_solve(morap_ctx* ctx, const double* W, int K, const morap_vi_opts* opts, double* c_out,

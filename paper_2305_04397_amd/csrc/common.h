@@ -309,6 +309,7 @@ struct morap_ctx {
     // the last evaluation's final values and instance layout (a warm start
     // of the next one)
     morap::DevBuf d_xe_prev, d_warm_copy;
+    morap::DevBuf d_iwarm;                          // per instance: warm-started (evaluation start)
     std::vector<int64_t> prev_inst_base;
     std::vector<int32_t> prev_inst_m;
     int prev_per_col = 0;
@@ -605,6 +606,10 @@ void team_start(hipStream_t s, int64_t S, int K, int Kp, int d, const double* W,
 void gather_values(hipStream_t s, int n, const int64_t* idx, const double* x, double* out);
 // runs (dst, src, length) of instance states [.][2] copied from prev to x
 void copy_runs(hipStream_t s, const int64_t* runs, int n_runs, const double* prev, double* x);
+// evaluation start from the instances' scalarised values xi (iwarm: per
+// instance, 1 where its values were warm-started)
+void eval_start(hipStream_t s, const InstArgs& a, const double* xi, const double* iwc, const double* iwp,
+                const uint8_t* iwarm, double* xe);
 // team models: out[r][k] = W[k][obj[r][0]] rew[r][0] + W[k][obj[r][1]] rew[r][1]
 void team_rewards(hipStream_t s, int64_t R, int K, int Kp, int d, const double* W, const int32_t* obj,
                   const double* rew, double* out64, float* out32);

@@ -1120,12 +1120,14 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
 
     // Alg. 4 per objective, from 0, or (warm) each instance whose column's
     // previous column had an instance of the same task on the same model from
-    // that instance's final values: the evaluation of a proper policy reaches
-    // its values from any start
+    // that instance's final values, and (eval_start) from the scalarised
+    // values: the evaluation of a proper policy reaches its values from any
+    // start, with the same bound on the error at its stop
     double* xe0 = c->d_xe[0].as<double>();
     double* xe1 = c->d_xe[1].as<double>();
     k::fill_f64(s, xe0, 0.0, 2 * NS);
     k::fill_f64(s, xe1, 0.0, 2 * NS);
+    std::vector<uint8_t> iwarm(n, 0);
     if (warm && c->eval_prev_valid && c->prev_per_col == nJ) {
         std::vector<int64_t> runs;
         const int K_prev = (int)(c->prev_inst_m.size() / std::max(1, nJ));
@@ -1136,6 +1138,7 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
             for (int j = 0; j < nJ; ++j) {
                 const int q = kk * nJ + j, qp = kp * nJ + j;
                 if (c->prev_inst_m[qp] != c->inst_m[q]) continue;
+                iwarm[q] = 1;
                 runs.push_back(c->inst_base[q]);
                 runs.push_back(c->prev_inst_base[qp]);
                 runs.push_back(c->inst_base[q + 1] - c->inst_base[q]);
@@ -1147,6 +1150,13 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
             k::copy_runs(s, c->d_warm_copy.as<int64_t>(), (int)(runs.size() / 3), c->d_xe_prev.as<double>(), xe0);
             MORAP_HIP(hipStreamSynchronize(s));   // the host run list goes out of scope
         }
+    }
+    if (o.eval_start && !team) {
+        // from the scalarised values the policies were chosen from (R15)
+        c->d_iwarm.ensure((size_t)n + 16);
+        MORAP_HIP(hipMemcpyAsync(c->d_iwarm.p, iwarm.data(), (size_t)n, hipMemcpyHostToDevice, s));
+        k::eval_start(s, a, xi, c->d_iwc.as<double>(), c->d_iwp.as<double>(), c->d_iwarm.as<uint8_t>(), xe0);
+        MORAP_HIP(hipStreamSynchronize(s));   // iwarm goes out of scope
     }
     k::set_active(s, n, a, iact, ires, ipar, 2);
     int64_t esweeps = 0;

@@ -1087,6 +1087,31 @@ void copy_runs(hipStream_t s, const int64_t* runs, int n_runs, const double* pre
     MORAP_HIP(hipGetLastError());
 }
 
+// Start of the per-objective evaluation from the instance's scalarised
+// values V = w_c C + w_p P (weights scaled to sum 1, the values its policy
+// was chosen from): the probability objective at its warm value where the
+// instance was warm-started, else 1 (its value under any proper policy of a
+// task without a trap); the cost objective at (V - w_p P0) / w_c where
+// w_c >= 1e-3 (below, the division would magnify V's own error), else as it
+// was.  For a policy greedy for V the start is its value up to V's error.
+__global__ void eval_start_kernel(InstArgs a, const double* __restrict__ xi, const double* __restrict__ iwc,
+                                  const double* __restrict__ iwp, const uint8_t* __restrict__ iwarm,
+                                  double* __restrict__ xe) {
+    InstLoc L;
+    if (!inst_locate(a, L)) return;
+    const double wc = iwc[L.inst], wp = iwp[L.inst];
+    const double p0 = iwarm[L.inst] ? xe[2 * L.is + 1] : 1.0;
+    xe[2 * L.is + 1] = p0;
+    if (wc >= 1e-3) xe[2 * L.is] = (xi[L.is] - wp * p0) / wc;
+}
+
+void eval_start(hipStream_t s, const InstArgs& a, const double* xi, const double* iwc, const double* iwp,
+                const uint8_t* iwarm, double* xe) {
+    if (a.n_tiles <= 0) return;
+    hipLaunchKernelGGL(eval_start_kernel, dim3(a.n_tiles), dim3(256), 0, s, a, xi, iwc, iwp, iwarm, xe);
+    MORAP_HIP(hipGetLastError());
+}
+
 void select_final(hipStream_t s, const InstArgs& a, double* x0, const double* x1, const uint8_t* par,
                   int width) {
     if (a.n_tiles <= 0) return;

@@ -65,7 +65,8 @@ class Model(C.Structure):
 class ViOpts(C.Structure):
     _fields_ = [("eps_vi", C.c_double), ("eps_eval", C.c_double), ("tau", C.c_double),
                 ("precision", C.c_int32), ("max_sweeps", C.c_int32), ("check_every", C.c_int32),
-                ("schedule", C.c_int32), ("use_graph", C.c_int32), ("time_kernels", C.c_int32)]
+                ("schedule", C.c_int32), ("use_graph", C.c_int32), ("time_kernels", C.c_int32),
+                ("eval_start", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -175,6 +176,7 @@ class Options:
     schedule: int = 0
     use_graph: bool = True
     time_kernels: bool = False
+    eval_from_values: bool = False   # Alg. 4 starts from the solve's scalarised values
 
     def to_c(self) -> ViOpts:
         o = ViOpts()
@@ -187,6 +189,7 @@ class Options:
         o.schedule = self.schedule
         o.use_graph = 1 if self.use_graph else 0
         o.time_kernels = 1 if self.time_kernels else 0
+        o.eval_start = 1 if self.eval_from_values else 0
         return o
 
 
