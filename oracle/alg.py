@@ -68,8 +68,21 @@ def policy_for(prod, wi: float, wj: float, eps_vi: float, tau: float = 1e-9) -> 
     sc = wi + wj
     if sc > 0:
         wi, wj = wi / sc, wj / sc
-    x, _ = vi.value_iteration(prod, np.array([wi]), np.array([wj]), eps_vi)
+    x, _ = vi.value_iteration(prod, np.array([wi]), np.array([wj]), policy_eps(eps_vi, wi, wj))
     return vi.extract_policy(prod, x[:, 0], wi, wj, tau)
+
+
+def policy_eps(eps_vi: float, wi: float, wj: float) -> float:
+    """Stop of the values a policy is chosen from (weights scaled to sum 1):
+    eps_vi, or eps_vi * 1e-4 (not below 1e-12, never above eps_vi) when the
+    cost weight vanishes.  Every action that completes the task as surely as
+    the best is then optimal, and values stopped at eps_vi differ between
+    such actions by their own error, far above the tie tolerance: the greedy
+    choice among them would be decided by that error and can progress only
+    through a slip (hundreds of thousands of expected steps)."""
+    if wi < 1e-6 and wj > 0:
+        return min(eps_vi, max(eps_vi * 1e-4, 1e-12))
+    return eps_vi
 
 
 def support(products, nI: int, nJ: int, w: np.ndarray, eps_vi: float,

@@ -310,6 +310,7 @@ struct morap_ctx {
     // of the next one)
     morap::DevBuf d_xe_prev, d_warm_copy;
     morap::DevBuf d_iwarm;                          // per instance: warm-started (evaluation start)
+    morap::DevBuf d_ieps;                           // per instance: stop of the FP64 policy values
     std::vector<int64_t> prev_inst_base;
     std::vector<int32_t> prev_inst_m;
     int prev_per_col = 0;
@@ -625,8 +626,9 @@ void warm_columns(hipStream_t s, int64_t S, int Kp, int K, const int32_t* map, c
 // scale[inst] (instances with a zero cost weight start from 0)
 void warm_start(hipStream_t s, const InstArgs& a, const void* x0, const void* x1, const uint8_t* final_par, int Kp,
                 const double* scale, const double* iwc, double* xi);
+// stop test of n entries: residual <= eps, or <= eps_i[i] where eps_i is given
 void inst_converge(hipStream_t s, int n, unsigned long long* res, uint8_t* active, uint8_t* par, int out_par,
-                   double eps, int64_t* counter);
+                   double eps, int64_t* counter, const double* eps_i = nullptr);
 void opt_mask(hipStream_t s, const InstArgs& a, const double* wc, const double* wp, const double* x,
               double tau, uint32_t* mask, int32_t* rank, int8_t* mu, bool only_unranked);
 void eval_sweep(hipStream_t s, const InstArgs& a, const int8_t* mu, const uint8_t* active,

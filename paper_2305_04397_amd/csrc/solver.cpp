@@ -830,6 +830,19 @@ static k::InstArgs inst_args(morap_ctx* c, int n_tiles, int n_inst) {
 // widenings of the tie tolerance in policy extraction (tau * 10^k, k <= 6)
 constexpr int kTauSteps = 6;
 
+// Stop of the FP64 values a pair's policy is chosen from (R16): eps_vi, or
+// 1e-4 eps_vi (not below 1e-12, never above eps_vi) when the scaled cost
+// weight vanishes.  Then every action that completes the task as surely as
+// the best is optimal, and values stopped at eps_vi differ between such
+// actions by their own error, far above the tie tolerance: the greedy
+// choice among them is decided by that error and can be an action that
+// progresses only through a slip (hundreds of thousands of expected steps,
+// which no evaluation finishes).
+static double policy_eps(double eps_vi, double wc, double wp) {
+    if (wc < 1e-6 && wp > 0) return std::min(eps_vi, std::max(eps_vi * 1e-4, 1e-12));
+    return eps_vi;
+}
+
 static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const morap_vi_opts& o, double* r_out,
                           Stats& st, const int32_t* warm) {
     MORAP_CHECK(c->solved, MORAP_E_STATE, "morap_evaluate needs a morap_solve first");
@@ -917,6 +930,14 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
     MORAP_HIP(hipMemcpyAsync(c->d_iwc.p, iwc.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
     MORAP_HIP(hipMemcpyAsync(c->d_iwp.p, iwp.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
     MORAP_HIP(hipMemcpyAsync(c->d_iscale.p, iscale.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+    std::vector<double> ieps(n);
+    double eps_pol = o.eps_vi;
+    for (int q = 0; q < n; ++q) {
+        ieps[q] = team ? o.eps_vi : policy_eps(o.eps_vi, iwc[q], iwp[q]);
+        eps_pol = std::min(eps_pol, ieps[q]);
+    }
+    c->d_ieps.ensure((size_t)n * 8 + 8);
+    MORAP_HIP(hipMemcpyAsync(c->d_ieps.p, ieps.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
     MORAP_HIP(hipMemcpyAsync(c->d_init_idx.p, init_idx.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
     std::vector<int32_t> iobj;
     if (team) {
@@ -1006,7 +1027,7 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
                                  c->d_iwp.as<double>(), iact, even ? x0 : x1, even ? x1 : x0, ires, (int32_t)c->S,
                                  c->hm.blk_pattern);
                 if (timed) MORAP_HIP(hipEventRecord(ev.back().second, s));
-                k::inst_converge(s, n, ires, iact, ipar, even ? 1 : 0, o.eps_vi, dctr);
+                k::inst_converge(s, n, ires, iact, ipar, even ? 1 : 0, o.eps_vi, dctr, c->d_ieps.as<double>());
             }
             vsweeps += chunk;
             // record + own value read + write per live instance state
@@ -1067,7 +1088,10 @@ static void evaluate_impl(morap_ctx* c, const int32_t* assign, int K, const mora
         uint8_t* pm = c->d_pair_mask.as<uint8_t>();
         k::fill_u8(s, pm, 0, (int64_t)c->hm.M * c->Kp);
         k::mark_pairs(s, a, c->Kp, pm);
-        run_vi(c, 1, c->vref, pm, o, st);
+        // one stop for the masked batched re-solve: the tightest any pair needs
+        morap_vi_opts op = o;
+        op.eps_vi = eps_pol;
+        run_vi(c, 1, c->vref, pm, op, st);
         k::gather_columns(s, a, MORAP_F64, c->vref.x[0].p, c->vref.x[1].p, c->vref.final_par.as<uint8_t>(),
                           c->vref.Kp, xi);
     }

@@ -763,12 +763,12 @@ void gather_columns(hipStream_t s, const InstArgs& a, int prec, const void* x0, 
 // number still running written to *counter (no separate clearing launch).
 __global__ void __launch_bounds__(1024) inst_converge_kernel(int n, unsigned long long* res, uint8_t* active,
                                                              uint8_t* par, int out_par, double eps,
-                                                             int64_t* counter) {
+                                                             int64_t* counter, const double* eps_i) {
     unsigned long long still = 0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         if (!active[i]) continue;
         const double r = __longlong_as_double((long long)res[i]);
-        if (r <= eps) {
+        if (r <= (eps_i ? eps_i[i] : eps)) {
             active[i] = 0;
             par[i] = (uint8_t)out_par;
         } else {
@@ -789,13 +789,13 @@ __global__ void __launch_bounds__(1024) inst_converge_kernel(int n, unsigned lon
 }
 
 void inst_converge(hipStream_t s, int n, unsigned long long* res, uint8_t* active, uint8_t* par,
-                   int out_par, double eps, int64_t* counter) {
+                   int out_par, double eps, int64_t* counter, const double* eps_i) {
     if (n <= 0) {
         fill_i64(s, counter, 0, 1);
         return;
     }
     hipLaunchKernelGGL(inst_converge_kernel, dim3(1), dim3(1024), 0, s, n, res, active, par, out_par, eps,
-                       counter);
+                       counter, eps_i);
     MORAP_HIP(hipGetLastError());
 }
 

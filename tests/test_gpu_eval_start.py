@@ -124,3 +124,37 @@ def test_eval_start_in_query_passes(ctx, morap):
     for a, b in zip(qa, qb):
         assert a["verdict"] == b["verdict"]
         assert np.abs(a["t_up"] - b["t_up"]).max() <= 1e-4 * max(1.0, np.abs(a["t_up"]).max())
+
+
+def test_vanishing_cost_weight_gives_a_policy_that_evaluates(ctx, morap):
+    """A column whose weight on agent 46's cost is 0 (as Alg. 1's later
+    weight vectors often are): the policy of its pair with task 61 (an avoid
+    task on a 48 x 48 grid) comes from values stopped 1e-4 tighter than
+    eps_vi, keeps the completion probability at the optimum (1 everywhere)
+    and finishes fast, so its cost evaluates in a bounded number of sweeps;
+    from values stopped at eps_vi the tie rule would pick a policy with
+    ~4e5 expected steps that no evaluation finishes."""
+    wl = make_workload(3)
+    nI, nJ = wl.n_agents, wl.n_tasks
+    i0, j0 = 46, 61
+    p = product.build_product(wl.agents[i0], wl.tasks[j0], wl.letters[i0][j0])
+    ctx.build_products(wl)
+    W = np.full((2, nI + nJ), 1.0)
+    W[:, i0] = 0.0
+    W[1, :nI] = 0.0
+    W /= W.sum(axis=1, keepdims=True)
+    A = np.array([[j // 2 for j in range(nJ)]] * 2, dtype=np.int32)
+    other = [j for j in range(nJ) if A[0, j] == i0][0]
+    A[:, j0] = i0
+    A[:, other] = j0 // 2
+    for prec in ("f32", "f64"):
+        o = morap.Options(eps_vi=1e-6, precision=prec, eval_from_values=True, max_sweeps=100_000)
+        ctx.solve(W, o)
+        r, st = ctx.evaluate(A, o)
+        assert st["eval_sweeps"] < 20_000
+        for k in range(2):
+            mu = ctx.get_policy(k, j0, p.n_states).astype(np.int64)
+            x, steps = _exact_and_steps(p, mu)
+            assert steps < 1e3
+            assert np.abs(x[:, 1] - 1.0).max() <= 1e-9
+            assert abs(r[k, nI + j0] - x[p.init, 1]) <= 1e-6 * steps + 1e-9

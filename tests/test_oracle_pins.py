@@ -1126,3 +1126,36 @@ def test_exact_policy_iteration_pin_catches_a_minimising_improvement(monkeypatch
         assert abs(v[prod.init] - (pts @ wv).max()) > 1e-3
     except (RuntimeError, vi.ImproperPolicy):
         pass   # or it fails outright: either way the planted mistake is caught
+
+
+# --------------------------------------------------------------------------
+# the values a policy is chosen from when the cost weight vanishes
+# --------------------------------------------------------------------------
+def test_policy_values_for_a_vanishing_cost_weight_give_a_fast_optimal_policy():
+    """Probability-only weights on a 48 x 48 agent with an avoid task: from
+    values stopped at 1e-6 the tie rule picks, among actions that all keep
+    the completion probability at 1, one decided by the values' own error
+    (394,543 expected steps at the worst state, beyond any evaluation); from
+    the tighter values of policy_eps the policy is as sure (probability 1
+    everywhere, the exact optimum) and finishes in ~10^2 expected steps."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    wl = make_workload(3)
+    i, j = 46, 61
+    p = product.build_product(wl.agents[i], wl.tasks[j], wl.letters[i][j])
+
+    def steps(mu):
+        rows = vi.policy_rows(p, mu)
+        A = sp.identity(p.n_states, format="csc") - p.P()[rows].tocsc()
+        return spla.spsolve(A, np.ones(p.n_states))
+
+    x, _ = vi.value_iteration(p, 0.0, 1.0, 1e-6)
+    slow = vi.extract_policy(p, x[:, 0], 0.0, 1.0)
+    assert steps(slow).max() > 1e5
+    assert alg.policy_eps(1e-6, 0.0, 1.0) == pytest.approx(1e-10)
+    assert alg.policy_eps(1e-6, 0.5, 0.5) == 1e-6 and alg.policy_eps(1e-13, 0.0, 1.0) == 1e-13
+    fast = alg.policy_for(p, 0.0, 0.7, 1e-6)
+    assert steps(fast).max() < 1e3
+    ex = vi.evaluate_exact(p, fast)
+    v_opt, _, _ = vi.optimal_exact(p, 0.0, 1.0)
+    assert np.abs(ex[:, 1] - v_opt).max() <= 1e-9
