@@ -57,9 +57,9 @@ def test_full_size_solve_sampled(full):
 def test_tail_kernel_switch_keeps_the_values(full):
     """An autotuned solve whose kernel is the wave-per-state gather sweep
     runs its last sweeps (under 20 % of the tiles active) with the LDS-staged
-    kernel; the values, the stop sweeps and the backups are those of the same
-    solve with the gather sweep throughout (a fixed schedule never
-    switches), bit for bit."""
+    kernel; the values, the stop sweeps, the backups, the bytes and the floor
+    stops are those of the same solve with the gather sweep throughout (a
+    fixed schedule never switches), bit for bit."""
     morap, ctx, wl = full
     nI, nJ = wl.n_agents, wl.n_tasks
     W = dirichlet_weights(np.random.default_rng(5), 64, nI + nJ)
@@ -74,6 +74,7 @@ def test_tail_kernel_switch_keeps_the_values(full):
     assert np.array_equal(c1, c2)
     assert st1["sweeps"] == st2["sweeps"] and st1["backups"] == st2["backups"]
     assert st1["bytes"] + st1["bytes_tail"] == pytest.approx(st2["bytes"], rel=1e-12)
+    assert st1["floor_stops"] == st2["floor_stops"] and st1["max_pair_sweeps"] == st2["max_pair_sweeps"]
     for (k, m), x in v1.items():
         assert np.array_equal(x, ctx.get_values(k, m)), (k, m)
 
