@@ -678,6 +678,19 @@ void evaluate(morap_ctx* c, const int32_t* assign, int K, const morap_vi_opts& o
     add_stats(c->cum, local);
 }
 
+// rows of W[K][d] on the simplex: finite, >= 0, summing to 1 (1e-9)
+static void check_weight_rows(const double* W, int K, int d) {
+    for (int k = 0; k < K; ++k) {
+        double sum = 0;
+        for (int q = 0; q < d; ++q) {
+            const double w = W[(size_t)k * d + q];
+            MORAP_CHECK(std::isfinite(w) && w >= 0, MORAP_E_INVALID, "weights must be finite and >= 0");
+            sum += w;
+        }
+        MORAP_CHECK(std::fabs(sum - 1.0) <= 1e-9, MORAP_E_INVALID, "weight rows must sum to 1");
+    }
+}
+
 static void solve_impl(morap_ctx* c, const double* W, int K, const morap_vi_opts& o, double* c_out, Stats& st,
                        const int32_t* warm) {
     MORAP_CHECK(c->loaded, MORAP_E_STATE, "no models loaded");
@@ -686,15 +699,7 @@ static void solve_impl(morap_ctx* c, const double* W, int K, const morap_vi_opts
     MORAP_CHECK(o.eps_vi > 0 && std::isfinite(o.eps_vi), MORAP_E_INVALID, "eps_vi must be > 0");
     MORAP_CHECK(o.max_sweeps >= 1, MORAP_E_INVALID, "max_sweeps must be >= 1");
     const int nI = c->hm.nI, nJ = c->hm.nJ, M = c->hm.M, d = n_obj_of(c);
-    for (int k = 0; k < K; ++k) {
-        double s = 0;
-        for (int q = 0; q < d; ++q) {
-            const double w = W[(size_t)k * d + q];
-            MORAP_CHECK(std::isfinite(w) && w >= 0, MORAP_E_INVALID, "weights must be finite and >= 0");
-            s += w;
-        }
-        MORAP_CHECK(std::fabs(s - 1.0) <= 1e-9, MORAP_E_INVALID, "weight rows must sum to 1");
-    }
+    check_weight_rows(W, K, d);
     const auto t0 = std::chrono::steady_clock::now();
     const int prec = o.precision;
     const int Kp = padded_k(K);
@@ -1606,15 +1611,7 @@ static void solve_staged_impl(morap_ctx* c, const double* W, int K, const morap_
     MORAP_CHECK(o.eps_vi > 0 && std::isfinite(o.eps_vi), MORAP_E_INVALID, "eps_vi must be > 0");
     MORAP_CHECK(o.max_sweeps >= 1, MORAP_E_INVALID, "max_sweeps must be >= 1");
     const int nI = c->hm.nI, nJ = c->hm.nJ, M = c->hm.M, d = nI + nJ;
-    for (int k = 0; k < K; ++k) {
-        double sum = 0;
-        for (int q = 0; q < d; ++q) {
-            const double w = W[(size_t)k * d + q];
-            MORAP_CHECK(std::isfinite(w) && w >= 0, MORAP_E_INVALID, "weights must be finite and >= 0");
-            sum += w;
-        }
-        MORAP_CHECK(std::fabs(sum - 1.0) <= 1e-9, MORAP_E_INVALID, "weight rows must sum to 1");
-    }
+    check_weight_rows(W, K, d);
     const auto t0 = std::chrono::steady_clock::now();
     build_stage_layout(c);
     StagedLayout& L = c->staged;
