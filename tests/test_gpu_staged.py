@@ -121,3 +121,23 @@ def test_staged_solve_rejects_what_it_does_not_run(ctx, morap):
     with pytest.raises(morap.MorapError) as e:
         ctx.solve_staged(W, morap.Options(eps_vi=1e-6, precision="f64"))
     assert e.value.code == morap.E_UNSUPPORTED
+
+
+def test_staged_solve_with_several_column_tiles(ctx, morap):
+    """70 columns (padded to 128, two k-tiles of 64): every column's values
+    against the oracle's retiring iteration on sampled products."""
+    wl = make_workload(2, n_agents=4, n_tasks=8)
+    ctx.build_products(wl)
+    nI, nJ = wl.n_agents, wl.n_tasks
+    W = dirichlet_weights(np.random.default_rng(87), 70, nI + nJ)
+    eps = 1e-9
+    c, st = ctx.solve_staged(W, _f64(morap, eps))
+    assert c.shape == (70, nI, nJ)
+    prods = product.build_all(wl)
+    for m in (0, 9, 22, 31):
+        i, j = divmod(m, nJ)
+        p = prods[m]
+        if p.init < 0:
+            continue
+        y, _, _ = vi.stage_retired_value_iteration(p, W[:, i], W[:, nI + j], eps)
+        assert np.abs(c[:, i, j] - y[p.init]).max() <= 1e-12 * max(1.0, np.abs(y).max())
