@@ -173,26 +173,28 @@ def oracle_single_core() -> dict:
 
 
 def stage_retirement_eval(ctx, rng, K: int, d: int, eps: float) -> dict:
-    """FP64 value iteration of K Dirichlet weight columns on the loaded
-    products, plain (morap_solve, graphs) and with stage retirement
-    (morap_solve_staged, eager launches): wall time of the second of two
-    runs each, sweeps, backups and algorithmic bytes, and the largest change
-    of a value at an initial state."""
+    """Value iteration of K Dirichlet weight columns on the loaded products,
+    plain (morap_solve, graphs) and with stage retirement (morap_solve_staged,
+    eager launches), in FP64 and in FP32: wall time of the second of two runs
+    each, sweeps, backups and algorithmic bytes, and the largest change of a
+    value at an initial state."""
     from paper_2305_04397_amd import morap
     W = rng.dirichlet(np.ones(d), size=K)
-    o = morap.Options(eps_vi=eps, precision="f64")
-    out = {"precision": "f64", "K": K, "eps_vi": eps}
-    c = {}
-    for name, fn in (("plain", ctx.solve), ("staged", ctx.solve_staged)):
-        for _ in range(2):
-            t0 = time.perf_counter()
-            c[name], st = fn(W, o)
-            ms = (time.perf_counter() - t0) * 1e3
-        out[name] = {"ms": round(ms, 1), "sweeps": st["sweeps"], "backups": st["backups"],
-                     "bytes": st["bytes"], "variant": st["variant"]}
-        log(f"stage retirement: {name} {ms:.0f} ms, {st['sweeps']} sweeps, {st['backups']:.4e} backups")
-    out["backups_saved"] = round(1.0 - out["staged"]["backups"] / out["plain"]["backups"], 4)
-    out["max_rel_change_c"] = float(np.abs(c["staged"] - c["plain"]).max() / max(1.0, np.abs(c["plain"]).max()))
+    out = {"K": K, "eps_vi": eps}
+    for prec in ("f64", "f32"):
+        o = morap.Options(eps_vi=eps, precision=prec)
+        res, c = {}, {}
+        for name, fn in (("plain", ctx.solve), ("staged", ctx.solve_staged)):
+            for _ in range(2):
+                t0 = time.perf_counter()
+                c[name], st = fn(W, o)
+                ms = (time.perf_counter() - t0) * 1e3
+            res[name] = {"ms": round(ms, 1), "sweeps": st["sweeps"], "backups": st["backups"],
+                         "bytes": st["bytes"] + st["bytes_tail"], "variant": st["variant"]}
+            log(f"stage retirement {prec}: {name} {ms:.0f} ms, {st['sweeps']} sweeps, {st['backups']:.4e} backups")
+        res["backups_saved"] = round(1.0 - res["staged"]["backups"] / res["plain"]["backups"], 4)
+        res["max_rel_change_c"] = float(np.abs(c["staged"] - c["plain"]).max() / max(1.0, np.abs(c["plain"]).max()))
+        out[prec] = res
     return out
 
 

@@ -239,13 +239,14 @@ int morap_solve(morap_ctx* ctx, const double* W, int K, const morap_vi_opts* opt
  * a stage retires in that column when every lower stage has retired and the
  * largest change over its own states is <= eps_vi, and keeps the values of
  * that sweep from then on.  A pair is done when the stage of its initial
- * state retires; c_out as morap_solve.  Products built by
- * morap_build_products (block form) only, FP64 only (precision must be
- * MORAP_F64); opts.schedule, when > 0, must name a neighbourhood-block sweep
- * (ids 19-38).  The values stay on the device as after morap_solve.
+ * state retires; c_out as morap_solve.  The stop rule is morap_solve's per
+ * stage (FP32: also the rounding floor of a stage whose change has stopped
+ * falling).  Products built by morap_build_products (block form) only;
+ * opts.schedule, when > 0, must name a neighbourhood-block sweep (ids
+ * 19-38).  The values stay on the device as after morap_solve.
  * stats->backups counts the rows of the active stages only.
- * Errors: INVALID, STATE, UNSUPPORTED (team model, caller-loaded models,
- * FP32), OOM, NOT_CONVERGED, HIP. */
+ * Errors: INVALID, STATE, UNSUPPORTED (team model, caller-loaded models),
+ * OOM, NOT_CONVERGED, HIP. */
 int morap_solve_staged(morap_ctx* ctx, const double* W, int K, const morap_vi_opts* opts,
                        double* c_out, morap_stats* stats);
 

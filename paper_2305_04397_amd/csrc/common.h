@@ -562,9 +562,13 @@ struct StageArgs {
     const Tile* tiles;          // unit tiles
     const int32_t* tile_base;   // [U+1]
     const int32_t* rec;         // reordered block records [8S]
-    const double* x_out;        // the buffer the sweep wrote
-    double* x_in;               // the buffer it read
-    int M, K, Kp, out_par, slot;   // slot: 9 or 10, the list count of this sweep
+    const void* x_out;          // the buffer the sweep wrote (precision prec)
+    void* x_in;                 // the buffer it read
+    double* best_res;           // [U][Kp] FP32 rounding floor: smallest change so far
+    int32_t* stall;             // [U][Kp] sweeps since it was set
+    int stall_sweeps;           // 0: no floor stop (FP64)
+    double floor;
+    int M, K, Kp, out_par, slot, prec;   // slot: 9 or 10, the list count of this sweep
     double eps, unit;
 };
 void stage_converge(hipStream_t s, const StageArgs& a);

@@ -1597,7 +1597,7 @@ static void build_stage_layout(morap_ctx* c) {
     L.gen = c->load_gen;
 }
 
-// Alg. 3 for K columns with stage retirement (FP64): each sweep backs up the
+// Alg. 3 for K columns with stage retirement: each sweep backs up the
 // units still active, then per (model, column) the units are taken lowest
 // first and a unit retires when all lower ones have and its own change is
 // <= eps_vi; its values are copied into the other buffer.  A pair's value at
@@ -1606,7 +1606,7 @@ static void solve_staged_impl(morap_ctx* c, const double* W, int K, const morap_
                               Stats& st) {
     MORAP_CHECK(c->loaded, MORAP_E_STATE, "no models loaded");
     MORAP_CHECK(!c->team, MORAP_E_UNSUPPORTED, "stage retirement runs on the decentralised products");
-    MORAP_CHECK(o.precision == MORAP_F64, MORAP_E_UNSUPPORTED, "stage retirement runs FP64 values");
+    MORAP_CHECK(o.precision == MORAP_F32 || o.precision == MORAP_F64, MORAP_E_INVALID, "bad precision");
     MORAP_CHECK(W && K >= 1 && K <= 4096, MORAP_E_INVALID, "need 1 <= K <= 4096 weight vectors");
     MORAP_CHECK(o.eps_vi > 0 && std::isfinite(o.eps_vi), MORAP_E_INVALID, "eps_vi must be > 0");
     MORAP_CHECK(o.max_sweeps >= 1, MORAP_E_INVALID, "max_sweeps must be >= 1");
@@ -1615,7 +1615,8 @@ static void solve_staged_impl(morap_ctx* c, const double* W, int K, const morap_
     const auto t0 = std::chrono::steady_clock::now();
     build_stage_layout(c);
     StagedLayout& L = c->staged;
-    const int U = L.U, Kp = padded_k(K);
+    const int U = L.U, Kp = padded_k(K), prec = o.precision;
+    const size_t el = prec == MORAP_F32 ? 4 : 8;
     // a neighbourhood-block sweep: the one the autotuner chose for plain FP64
     // solves of this width if it is one, else the first with k-tiles of
     // min(Kp, 64) columns (the wave-per-state one where it fits)
@@ -1626,7 +1627,7 @@ static void solve_staged_impl(morap_ctx* c, const double* W, int K, const morap_
         MORAP_CHECK(v->kind == SWEEP_BLOCK && Kp % kt_of(*v) == 0, MORAP_E_UNSUPPORTED,
                     "stage retirement runs a neighbourhood-block sweep whose k-tile divides the padded width");
     } else {
-        const int64_t key = ((int64_t)MORAP_F64 << 40) | Kp;
+        const int64_t key = ((int64_t)prec << 40) | Kp;
         for (auto& t : c->tuned)
             if (t.first == key && variant_by_id(t.second).kind == SWEEP_BLOCK) v = &variant_by_id(t.second);
         if (!v)
@@ -1642,17 +1643,17 @@ static void solve_staged_impl(morap_ctx* c, const double* W, int K, const morap_
     ensure_scratch(c, Kp);
     c->K = K;
     c->Kp = Kp;
-    c->prec = MORAP_F64;
+    c->prec = prec;
     c->W.assign(W, W + (size_t)K * d);
     ValueSet& vs = c->vmain;
-    ensure_values(c, vs, K, Kp, MORAP_F64);
+    ensure_values(c, vs, K, Kp, prec);
 
     const size_t pairs = (size_t)U * Kp;
     L.active.ensure(pairs);
     L.res.ensure(pairs * 8);
     L.ymax.ensure(pairs * 8);
-    L.wc.ensure(pairs * 8);
-    L.wp.ensure(pairs * 8);
+    L.wc.ensure(pairs * el);
+    L.wp.ensure(pairs * el);
     L.final_par.ensure(pairs);
     L.pair_sweeps.ensure(pairs * 4);
     L.best_res.ensure(pairs * 8);
@@ -1674,13 +1675,25 @@ static void solve_staged_impl(morap_ctx* c, const double* W, int K, const morap_
                     wp[(size_t)u * Kp + k] = W[(size_t)k * d + nI + j];
                 }
         }
-        MORAP_HIP(hipMemcpyAsync(L.wc.p, wc.data(), pairs * 8, hipMemcpyHostToDevice, s));
-        MORAP_HIP(hipMemcpyAsync(L.wp.p, wp.data(), pairs * 8, hipMemcpyHostToDevice, s));
+        std::vector<float> wc32, wp32;
+        if (prec == MORAP_F32) {
+            wc32.assign(wc.begin(), wc.end());
+            wp32.assign(wp.begin(), wp.end());
+        }
+        MORAP_HIP(hipMemcpyAsync(L.wc.p, prec == MORAP_F32 ? (const void*)wc32.data() : (const void*)wc.data(),
+                                 pairs * el, hipMemcpyHostToDevice, s));
+        MORAP_HIP(hipMemcpyAsync(L.wp.p, prec == MORAP_F32 ? (const void*)wp32.data() : (const void*)wp.data(),
+                                 pairs * el, hipMemcpyHostToDevice, s));
         MORAP_HIP(hipStreamSynchronize(s));
     }
     const int64_t nx = (c->S + 1) * Kp;
-    k::fill_f64(s, vs.x[0].as<double>(), 0.0, nx);
-    k::fill_f64(s, vs.x[1].as<double>(), 0.0, nx);
+    if (prec == MORAP_F32) {
+        k::fill_f32(s, vs.x[0].as<float>(), 0.f, nx);
+        k::fill_f32(s, vs.x[1].as<float>(), 0.f, nx);
+    } else {
+        k::fill_f64(s, vs.x[0].as<double>(), 0.0, nx);
+        k::fill_f64(s, vs.x[1].as<double>(), 0.0, nx);
+    }
     k::fill_f64(s, vs.c.as<double>(), 0.0, (int64_t)K * M);
     k::fill_u8(s, vs.final_par.as<uint8_t>(), 0, (int64_t)M * Kp);
     k::fill_i32(s, c->d_pair_sweeps.as<int32_t>(), 0, (int64_t)M * Kp);
@@ -1701,10 +1714,12 @@ static void solve_staged_impl(morap_ctx* c, const double* W, int K, const morap_
     ca.M = U;
     ca.K = K;
     ca.Kp = Kp;
-    ca.prec = MORAP_F64;
+    ca.prec = prec;
     ca.out_par = 1;
     ca.eps = o.eps_vi;
-    ca.unit = 8.0 * std::ldexp(1.0, -53);
+    // the stop rule of the plain solve (FP32: a few units in the last place,
+    // and the rounding floor, R12)
+    ca.unit = prec == MORAP_F32 ? 8.0 * std::ldexp(1.0, -24) : 8.0 * std::ldexp(1.0, -53);
     ca.best_res = L.best_res.as<double>();
     ca.stall = L.stall.as<int32_t>();
     ca.tile_base = L.tile_base.as<int32_t>();
@@ -1739,6 +1754,11 @@ static void solve_staged_impl(morap_ctx* c, const double* W, int K, const morap_
     sa.Kp = Kp;
     sa.eps = o.eps_vi;
     sa.unit = ca.unit;
+    sa.prec = prec;
+    sa.best_res = ca.best_res;
+    sa.stall = ca.stall;
+    sa.stall_sweeps = prec == MORAP_F32 ? 64 : 0;
+    sa.floor = 256.0 * std::ldexp(1.0, -24);
 
     k::SweepArgs a = sweep_args(c, vs, 0);
     a.tiles = L.tiles.as<Tile>();
@@ -1753,7 +1773,7 @@ static void solve_staged_impl(morap_ctx* c, const double* W, int K, const morap_
     a.ymax = ca.ymax;
     a.rec = sa.rec;
     a.act_tiles = ca.act_tiles;
-    const int grid = persistent_grid(c, MORAP_F64, *v);
+    const int grid = persistent_grid(c, prec, *v);
     const int ktiles = Kp / kt_of(*v);
     const int check = std::max(2, o.check_every);
     int64_t h[11] = {0};
@@ -1770,10 +1790,10 @@ static void solve_staged_impl(morap_ctx* c, const double* W, int K, const morap_
             ev = timed.get();
             MORAP_HIP(hipEventRecord(ev->a, s));
         }
-        k::sweep_block(s, MORAP_F64, *v, grid, ktiles, a);
+        k::sweep_block(s, prec, *v, grid, ktiles, a);
         if (ev) MORAP_HIP(hipEventRecord(ev->b, s));
-        sa.x_in = vs.x[in_par].as<double>();
-        sa.x_out = vs.x[1 - in_par].as<double>();
+        sa.x_in = vs.x[in_par].p;
+        sa.x_out = vs.x[1 - in_par].p;
         sa.out_par = 1 - in_par;
         sa.slot = 9 + (n & 1);
         k::stage_converge(s, sa);
@@ -1800,7 +1820,8 @@ static void solve_staged_impl(morap_ctx* c, const double* W, int K, const morap_
     MORAP_HIP(hipMemcpy(ps.data(), c->d_pair_sweeps.p, ps.size() * 4, hipMemcpyDeviceToHost));
     st.backups += h[4];
     st.sweeps += h[5];
-    st.bytes += (double)h[6] + 16.0 * (double)h[7];
+    st.bytes += (double)h[6] + 2.0 * (double)el * (double)h[7];
+    st.floor_stops += h[8];
     st.max_pair_sweeps = std::max<int64_t>(st.max_pair_sweeps, *std::max_element(ps.begin(), ps.end()));
     st.ms_vi += wall.elapsed_ms();
     st.variant = v->id;

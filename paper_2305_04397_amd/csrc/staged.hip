@@ -23,6 +23,7 @@ namespace k {
 // ([0] active pairs, [4] backups, [7] state-columns updated), with the
 // (unit, column) pairs retired in this sweep appended to a.retired and
 // counted in counters[a.slot].
+template <class T>
 __global__ void __launch_bounds__(256) stage_converge_kernel(StageArgs a) {
     const int64_t n = (int64_t)a.M * a.Kp;
     const int32_t next_sweep = (int32_t)(a.counters[5] + 1);
@@ -41,14 +42,28 @@ __global__ void __launch_bounds__(256) stage_converge_kernel(StageArgs a) {
             a.ymax[j] = 0ull;
             bk += (unsigned long long)a.rows[u];
             sc += (unsigned long long)a.states[u];
-            if (lower_done && r <= fmax(a.eps, a.unit * y)) {
+            const double tol = fmax(a.eps, a.unit * y);
+            // FP32: a unit whose change has set no new minimum for
+            // stall_sweeps sweeps and is within the rounding floor has
+            // settled as far as FP32 backups go (as a pair of the plain solve)
+            bool floor_stop = false;
+            if (a.stall_sweeps > 0 && r > tol) {
+                if (r < a.best_res[j]) {
+                    a.best_res[j] = r;
+                    a.stall[j] = 0;
+                } else if (++a.stall[j] >= a.stall_sweeps && r <= a.floor * y) {
+                    floor_stop = true;
+                }
+            }
+            if (lower_done && (r <= tol || floor_stop)) {
+                if (floor_stop) atomicAdd((unsigned long long*)&a.counters[8], 1ull);
                 a.active[j] = 0;
                 const unsigned long long p = atomicAdd((unsigned long long*)&a.counters[a.slot], 1ull);
                 a.retired[p] = j;
                 if (u == a.init_unit[m]) {
                     // the initial state's value is final
                     const int64_t i = (int64_t)m * a.Kp + k;
-                    a.c[(int64_t)k * a.M + m] = a.x_out[(int64_t)a.init[m] * a.Kp + k];
+                    a.c[(int64_t)k * a.M + m] = (double)((const T*)a.x_out)[(int64_t)a.init[m] * a.Kp + k];
                     a.final_par[i] = (uint8_t)a.out_par;
                     a.pair_sweeps[i] = next_sweep;
                 }
@@ -85,6 +100,7 @@ __global__ void __launch_bounds__(256) stage_converge_kernel(StageArgs a) {
 // from the buffer the sweep wrote into the one it read: one workgroup per
 // retired pair at a time, its threads over the unit's records (each names
 // its state).  The list count of the next sweep starts at 0 here.
+template <class T>
 __global__ void __launch_bounds__(256) stage_copy_kernel(StageArgs a) {
     if (blockIdx.x == 0 && threadIdx.x == 0) a.counters[a.slot == 9 ? 10 : 9] = 0;
     const int64_t n = a.counters[a.slot];
@@ -96,7 +112,7 @@ __global__ void __launch_bounds__(256) stage_copy_kernel(StageArgs a) {
             const Tile tl = a.tiles[tt];
             for (int p = tl.s_begin + (int)threadIdx.x; p < tl.s_end; p += blockDim.x) {
                 const int64_t g = a.rec[(int64_t)p * 8 + 7];
-                a.x_in[g * a.Kp + k] = a.x_out[g * a.Kp + k];
+                ((T*)a.x_in)[g * a.Kp + k] = ((const T*)a.x_out)[g * a.Kp + k];
             }
         }
     }
@@ -105,12 +121,14 @@ __global__ void __launch_bounds__(256) stage_copy_kernel(StageArgs a) {
 void stage_converge(hipStream_t s, const StageArgs& a) {
     const int64_t n = (int64_t)a.M * a.Kp;
     const unsigned blocks = (unsigned)std::min<int64_t>(256, std::max<int64_t>(1, (n + 255) / 256));
-    hipLaunchKernelGGL(stage_converge_kernel, dim3(blocks), dim3(256), 0, s, a);
+    if (a.prec == MORAP_F32) hipLaunchKernelGGL(stage_converge_kernel<float>, dim3(blocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(stage_converge_kernel<double>, dim3(blocks), dim3(256), 0, s, a);
     MORAP_HIP(hipGetLastError());
 }
 
 void stage_copy(hipStream_t s, const StageArgs& a) {
-    hipLaunchKernelGGL(stage_copy_kernel, dim3(256), dim3(256), 0, s, a);
+    if (a.prec == MORAP_F32) hipLaunchKernelGGL(stage_copy_kernel<float>, dim3(256), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(stage_copy_kernel<double>, dim3(256), dim3(256), 0, s, a);
     MORAP_HIP(hipGetLastError());
 }
 

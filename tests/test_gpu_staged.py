@@ -109,9 +109,6 @@ def test_staged_solve_rejects_what_it_does_not_run(ctx, morap):
     ctx.build_products(wl)
     W = np.full((1, 4), 0.25)
     with pytest.raises(morap.MorapError) as e:
-        ctx.solve_staged(W, morap.Options(eps_vi=1e-6, precision="f32"))
-    assert e.value.code == morap.E_UNSUPPORTED
-    with pytest.raises(morap.MorapError) as e:
         ctx.solve_staged(W, morap.Options(eps_vi=1e-6, precision="f64", schedule=5))
     assert e.value.code == morap.E_UNSUPPORTED
     with pytest.raises(morap.MorapError) as e:
@@ -141,3 +138,32 @@ def test_staged_solve_with_several_column_tiles(ctx, morap):
             continue
         y, _, _ = vi.stage_retired_value_iteration(p, W[:, i], W[:, nI + j], eps)
         assert np.abs(c[:, i, j] - y[p.init]).max() <= 1e-12 * max(1.0, np.abs(y).max())
+
+
+def test_staged_solve_in_fp32_cfg2(ctx, morap):
+    """FP32 values (the stop rule of the plain FP32 solve per stage, with its
+    rounding floor): the values at the initial states within the FP32 stop
+    error of the FP64 fixed point, the same sweep count as the plain FP32
+    solve within a few sweeps, fewer backups, and a support step from its
+    values as from the plain solve's."""
+    wl = make_workload(2)
+    ctx.build_products(wl)
+    nI, nJ = wl.n_agents, wl.n_tasks
+    W = dirichlet_weights(np.random.default_rng(88), 64, nI + nJ)
+    o32 = morap.Options(eps_vi=1e-6, precision="f32")
+    c0, st0 = ctx.solve(W, o32)
+    c64, _ = ctx.solve(W, _f64(morap, 1e-10))
+    c1, st1 = ctx.solve_staged(W, o32)
+    tol = 2e-4 * np.maximum(1.0, np.abs(c64))
+    assert (np.abs(c1 - c64) <= tol).all()
+    assert (np.abs(c0 - c64) <= tol).all()
+    assert st1["backups"] < st0["backups"]
+    assert st1["sweeps"] <= st0["sweeps"] + 4
+    A1 = ctx.assign(c1)
+    r1, _ = ctx.evaluate(A1, morap.Options(eps_vi=1e-6, eps_eval=1e-10, precision="f32"))
+    r0, A0, _, _ = ctx.support(W, morap.Options(eps_vi=1e-6, eps_eval=1e-10, precision="f32"))
+    same = (A0 == A1).all(axis=1)
+    assert same.mean() >= 0.9
+    # the support values w . r (the points may differ only between tied policies)
+    v0, v1 = (W * r0).sum(axis=1), (W * r1).sum(axis=1)
+    assert (np.abs(v1[same] - v0[same]) <= 1e-5 * np.maximum(1.0, np.abs(v0[same]))).all()
